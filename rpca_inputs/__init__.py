@@ -1,0 +1,225 @@
+"""Seeded synthetic RPCA instances shared by the FP64 oracle and the GPU path.
+
+This module only draws random inputs. It holds none of the method's arithmetic:
+it builds M = L* + S* from planted factors and a planted sparse matrix, the way
+the paper's experiments do (Section 4.1, "Problem Generation"), and it draws
+the initial factor U^(0) that Algorithm 1 leaves to the implementer.
+
+Every array that either side consumes is rounded to FP32 once, here, and then
+handed out as float64 arrays whose values are exactly representable in FP32.
+The oracle computes in FP64 on those values; the GPU path uploads the same
+values as FP32, so the two start from bit-identical inputs.
+
+Recipes (all seeded; independent streams for factors, support, values and U^(0)):
+
+* planted low-rank part: L* = U* V*^T with i.i.d. N(0,1) factors (Section 4.1),
+  or, for the geometric-spectrum workload, L* = Q_U diag(sigma) Q_V^T with
+  orthonormal Q from the QR factorisation of Gaussian matrices;
+* planted sparse part: an exact count round(s*m*n) of positions drawn without
+  replacement (Section 4.1 draws "smn random nonzero entries"), or an
+  independent Bernoulli(s) mask for instances too large to permute;
+* corruption values: uniform on [-a, a] ("uniform") or a uniform magnitude on
+  [lo, hi] with a fair random sign ("signed");
+* client widths: equal blocks, or log-uniform widths in [lo, hi] rounded to
+  integers (the uneven-client workload).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "Instance",
+    "planted_instance",
+    "equal_widths",
+    "loguniform_widths",
+    "gaussian_init",
+    "recipe",
+    "RECIPES",
+]
+
+# Stream identifiers for numpy SeedSequence spawning; fixed so that a change to
+# one recipe field never shifts the random numbers drawn for another.
+_STREAM_FACTORS = 1
+_STREAM_SUPPORT = 2
+_STREAM_VALUES = 3
+_STREAM_SIGNS = 4
+_STREAM_INIT = 5
+_STREAM_WIDTHS = 6
+
+
+def _rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(seed), int(stream)]))
+
+
+def _f32(x: np.ndarray) -> np.ndarray:
+    """Round to FP32 once and return float64 holding exactly those values."""
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+@dataclasses.dataclass
+class Instance:
+    """One synthetic RPCA problem, M = L* + S*, split column-wise over clients.
+
+    M is (m, n) float64 with FP32-representable values; the block of client i
+    is M[:, offsets[i]:offsets[i+1]] (Section 2.1: each client holds a
+    contiguous set of columns). Ustar @ Vstar.T is the planted low-rank part
+    before the FP32 rounding of M.
+    """
+
+    M: np.ndarray
+    widths: List[int]
+    Ustar: np.ndarray
+    Vstar: np.ndarray
+    Sstar: np.ndarray
+    seed: int
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.M.shape[0])
+
+    @property
+    def n(self) -> int:
+        return int(self.M.shape[1])
+
+    @property
+    def E(self) -> int:
+        return len(self.widths)
+
+    @property
+    def offsets(self) -> List[int]:
+        off = [0]
+        for w in self.widths:
+            off.append(off[-1] + int(w))
+        return off
+
+    def blocks(self) -> List[np.ndarray]:
+        off = self.offsets
+        return [self.M[:, off[i]:off[i + 1]] for i in range(self.E)]
+
+    @property
+    def Lstar(self) -> np.ndarray:
+        return self.Ustar @ self.Vstar.T
+
+
+def equal_widths(n: int, E: int) -> List[int]:
+    """E contiguous blocks whose widths differ by at most one column."""
+    base, extra = divmod(int(n), int(E))
+    return [base + (1 if i < extra else 0) for i in range(E)]
+
+
+def loguniform_widths(E: int, lo: int, hi: int, seed: int) -> List[int]:
+    """E widths round(exp(U[ln lo, ln hi])), clipped to [lo, hi]."""
+    rng = _rng(seed, _STREAM_WIDTHS)
+    w = np.exp(rng.uniform(math.log(lo), math.log(hi), size=E))
+    return [int(min(max(int(round(x)), lo), hi)) for x in w]
+
+
+def gaussian_init(m: int, r: int, seed: int) -> np.ndarray:
+    """U^(0) with i.i.d. N(0,1) entries, FP32-rounded (Algorithm 1 leaves the
+    distribution open; a Gaussian start avoids the stationary point U = 0)."""
+    return _f32(_rng(seed, _STREAM_INIT).standard_normal((m, r)))
+
+
+def planted_instance(
+    m: int,
+    widths: Sequence[int],
+    rstar: int,
+    s: float,
+    values: str = "signed",
+    lo: float = 5.0,
+    hi: float = 20.0,
+    seed: int = 0,
+    spectrum: str = "gaussian",
+    sigma_hi: float = 100.0,
+    sigma_lo: float = 1.0,
+    support: str = "exact",
+    name: str = "",
+) -> Instance:
+    """Draw M = L* + S* with a planted rank-rstar part and a fraction s of
+    corrupted entries.
+
+    values="uniform": corruption ~ U[-hi, hi]; values="signed": magnitude
+    ~ U[lo, hi] with a fair random sign. spectrum="gaussian": L* = U* V*^T with
+    N(0,1) factors; spectrum="geometric": singular values geometric from
+    sigma_hi down to sigma_lo on orthonormal random singular vectors.
+    """
+    widths = [int(w) for w in widths]
+    n = int(sum(widths))
+    frng = _rng(seed, _STREAM_FACTORS)
+    if spectrum == "gaussian":
+        Ustar = frng.standard_normal((m, rstar))
+        Vstar = frng.standard_normal((n, rstar))
+    elif spectrum == "geometric":
+        qu, _ = np.linalg.qr(frng.standard_normal((m, rstar)))
+        qv, _ = np.linalg.qr(frng.standard_normal((n, rstar)))
+        if rstar > 1:
+            k = np.arange(rstar, dtype=np.float64)
+            sig = sigma_hi * (sigma_lo / sigma_hi) ** (k / (rstar - 1))
+        else:
+            sig = np.array([sigma_hi])
+        Ustar = qu * np.sqrt(sig)[None, :]
+        Vstar = qv * np.sqrt(sig)[None, :]
+    else:
+        raise ValueError(f"unknown spectrum {spectrum!r}")
+
+    total = m * n
+    srng = _rng(seed, _STREAM_SUPPORT)
+    if support == "exact":
+        count = int(round(s * total))
+        flat = srng.choice(total, size=count, replace=False)
+    elif support == "bernoulli":
+        flat = np.flatnonzero(srng.random(total) < s)
+        count = flat.size
+    else:
+        raise ValueError(f"unknown support {support!r}")
+    vrng = _rng(seed, _STREAM_VALUES)
+    if values == "uniform":
+        vals = vrng.uniform(-hi, hi, size=count)
+    elif values == "signed":
+        mag = vrng.uniform(lo, hi, size=count)
+        sign = np.where(_rng(seed, _STREAM_SIGNS).random(count) < 0.5, -1.0, 1.0)
+        vals = sign * mag
+    else:
+        raise ValueError(f"unknown values {values!r}")
+    Sstar = np.zeros(total, dtype=np.float64)
+    Sstar[flat] = vals
+    # Column-major flattening: flat index = row + m * col, matching the
+    # column-major device layout (the choice does not affect the law).
+    Sstar = Sstar.reshape(n, m).T.copy()
+    M = _f32(Ustar @ Vstar.T + Sstar)
+    return Instance(M=M, widths=widths, Ustar=Ustar, Vstar=Vstar, Sstar=Sstar,
+                    seed=int(seed), name=name)
+
+
+# Named workloads. Each entry gives the instance recipe and the solver
+# parameters the workload is quoted with (lambda = 1/sqrt(n), rho = 0.1).
+RECIPES = {
+    # m = n = 500, rank 5, 5% of entries corrupted uniformly in [-10, 10],
+    # five clients of 100 columns, r = 5, 100 rounds.
+    "plain_500x500_r5": dict(m=500, n=500, E=5, rstar=5, s=0.05, values="uniform",
+                             lo=0.0, hi=10.0, r=5, rho=0.1, T=100),
+    # m = 4000, n = 8000, rank 20, 10% corrupted with magnitude U[5, 20],
+    # sixteen clients of 500 columns, r = 20, 200 rounds.
+    "plain_4000x8000_r20": dict(m=4000, n=8000, E=16, rstar=20, s=0.10, values="signed",
+                                lo=5.0, hi=20.0, r=20, rho=0.1, T=200),
+    # A 2000 x 2000 single-client instance with the large workload's recipe
+    # (rank 64, geometric spectrum 100 -> 1, 5% corrupted, magnitude U[1, 100]).
+    "geom_2000x2000_r64": dict(m=2000, n=2000, E=1, rstar=64, s=0.05, values="signed",
+                               lo=1.0, hi=100.0, r=64, rho=0.1, T=100,
+                               spectrum="geometric"),
+}
+
+
+def recipe(name: str, seed: int = 0, E: Optional[int] = None) -> Instance:
+    """Instantiate a named workload (see RECIPES)."""
+    cfg = dict(RECIPES[name])
+    E = int(E if E is not None else cfg["E"])
+    widths = equal_widths(cfg["n"], E)
+    return planted_instance(cfg["m"], widths, cfg["rstar"], cfg["s"], values=cfg["values"],
+                            lo=cfg["lo"], hi=cfg["hi"], seed=seed,
+                            spectrum=cfg.get("spectrum", "gaussian"), name=name)
