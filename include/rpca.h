@@ -1,0 +1,179 @@
+/*
+ * rpca.h -- C ABI of the MI355X (gfx950) DCF-PCA library.
+ *
+ * DCF-PCA (arXiv 2207.11669, Algorithm 1 in Section 2.2) minimises
+ *
+ *     1/2 ||U V^T + S - M||_F^2 + rho/2 (||U||_F^2 + ||V||_F^2) + lambda ||S||_1
+ *
+ * (Section 1, the nonconvex factorised objective) with M = [M_1 ... M_E] split
+ * column-wise over E clients (Section 2.1). Every round broadcasts U, lets each
+ * client take K local steps -- the (V_i, S_i) argmin of eq. "VS_arg" followed by
+ * a U step (eq. "U_local") -- and replaces U by the mean of the client factors
+ * (eq. "U_agg"). All clients live on one GPU; the mean is a device reduction.
+ *
+ * Conventions shared by every entry point:
+ *  - All matrices are column-major FP32 in device memory unless stated.
+ *  - Status codes: RPCA_OK (0) on success, negative on error, positive for a
+ *    warning on an otherwise successful call. rpca_last_error() gives text.
+ *  - A context is bound to one HIP stream; every call enqueues on that stream
+ *    and is asynchronous unless it says it synchronises. A context is not
+ *    thread-safe.
+ *  - Device errors poison the context: later calls return RPCA_ESTATE.
+ */
+#ifndef RPCA_H_
+#define RPCA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rpca_ctx rpca_ctx;
+
+typedef enum {
+  RPCA_OK = 0,
+  RPCA_EINVAL = -1,      /* bad argument; nothing was enqueued */
+  RPCA_EWORKSPACE = -2,  /* workspace missing, too small or misaligned */
+  RPCA_EDEVICE = -3,     /* a HIP call failed; the context is poisoned */
+  RPCA_ENONFINITE = -4,  /* a non-finite objective was observed; poisoned */
+  RPCA_ESTATE = -5,      /* the context is poisoned or not initialised */
+  RPCA_WARN_THM2 = 1     /* rho^2 > lambda^2 m n: by Theorem 2 (Section 3.3) the
+                            iterates can only reach U = 0 */
+} rpca_status;
+
+/* U step taken by each client after its (V_i, S_i) update. */
+typedef enum {
+  RPCA_U_GRAD = 0,   /* U_i <- U_i - eta grad_U L_i (eq. "U_local", Lemma 2) */
+  RPCA_U_CLOSED = 1  /* U_i <- argmin_U L_i(U, V_i, S_i)
+                        = (M_i - S_i) V_i (V_i^T V_i + rho n_i/n I)^{-1} */
+} rpca_u_mode;
+
+/* Step-size schedule for RPCA_U_GRAD (indexed by round t = 0, 1, ...). */
+typedef enum {
+  RPCA_ETA_CONST = 0,  /* eta_t = eta0 */
+  RPCA_ETA_SQRT = 1    /* eta_t = eta0 / sqrt(t + 1): a decaying rate (Section 4.2) */
+} rpca_eta_sched;
+
+typedef struct {
+  int64_t m;               /* rows of M (all clients share them), m >= 1 */
+  int32_t E;               /* number of clients, 1 <= E <= 4096 */
+  const int64_t* n_cols;   /* host array [E]: n_i >= 1 columns of client i */
+  int32_t r;               /* factor rank, 1 <= r <= 64 */
+  double rho;              /* rho > 0 (Frobenius penalty on U and V) */
+  double lambda;           /* lambda >= 0 (l1 penalty on S) */
+  int32_t K;               /* local steps per round, K >= 1 (Algorithm 1) */
+  int32_t inner;           /* (V, S) alternations per local step, >= 1 */
+  int32_t u_mode;          /* rpca_u_mode */
+  double eta0;             /* step size for RPCA_U_GRAD (> 0 there) */
+  int32_t eta_sched;       /* rpca_eta_sched */
+  uint32_t flags;          /* reserved, must be 0 */
+} rpca_params;
+
+/* Per-round statistics, FP64, recorded at the last local step of round t:
+ * objective = sum_i L_i(U_i, V_i, S_i) with U_i the client factor that the
+ * (V_i, S_i) update used (Section 2.2 local objectives; for K = 1 this is the
+ * global objective at (U^(t), V^(t+1), S^(t+1))); lambda_fro_sq =
+ * ||M - U V^T - S||_F^2; nnz = number of nonzeros of S; du_sq =
+ * ||U^(t+1) - U^(t)||_F^2; u_sq = ||U^(t+1)||_F^2; v_sq = ||V||_F^2;
+ * l1 = ||S||_1. */
+typedef struct {
+  double t, objective, lambda_fro_sq, nnz, du_sq, u_sq, v_sq, l1;
+} rpca_stats;
+
+/* NULL when the parameters are valid, else a static text naming the first
+ * violated condition (the checks rpca_init and rpca_workspace_bytes apply). */
+const char* rpca_params_error(const rpca_params* p);
+
+/* Bytes of device workspace rpca_init needs for these parameters.
+ * Returns RPCA_EINVAL for invalid parameters (same checks as rpca_init). */
+rpca_status rpca_workspace_bytes(const rpca_params* p, size_t* bytes);
+
+/* Create a context (Algorithm 1, initialisation step).
+ *  M_blocks: host array [E] of device pointers; M_blocks[i] is client i's
+ *            m x n_i block, column-major with leading dimension ldm[i].
+ *            Borrowed, read-only, and must stay valid while the context
+ *            lives. Each pointer must be 16-byte aligned, ldm[i] >= m and
+ *            ldm[i] % 4 == 0.
+ *  U0:       device m x r column-major start U^(0) with leading dimension
+ *            ldu >= m (copied; not retained).
+ *  workspace/ws_bytes: caller-owned device memory of at least
+ *            rpca_workspace_bytes() bytes, 256-byte aligned; the library
+ *            allocates no device memory of its own.
+ *  stream:   hipStream_t (as void*) all work is enqueued on; NULL = default.
+ * S_i^(0) = 0. Returns RPCA_WARN_THM2 (context still valid) when
+ * rho^2 > lambda^2 m n. On error *out is NULL. */
+rpca_status rpca_init(rpca_ctx** out, const rpca_params* p,
+                      const float* const* M_blocks, const int64_t* ldm,
+                      const float* U0, int64_t ldu,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* Enqueue `rounds` rounds of Algorithm 1 (rounds >= 0). Asynchronous. */
+rpca_status rpca_step(rpca_ctx* c, int32_t rounds);
+
+/* Run rounds until the stopping metric is <= tol or max_rounds rounds are
+ * done, checking every check_every rounds (synchronises at each check).
+ * The metric is ||L^(t) - L_ref||_F / ||L_ref||_F computed from factor Gram
+ * matrices: L_ref is the planted target when rpca_set_target was called,
+ * else the L of the previous check (relative change). *rounds_done and
+ * *metric (both optional) receive the rounds run by this call and the last
+ * metric. Returns RPCA_ENONFINITE if the objective became non-finite. */
+rpca_status rpca_solve(rpca_ctx* c, int32_t max_rounds, double tol, int32_t check_every,
+                       int32_t* rounds_done, double* metric);
+
+/* Register a planted low-rank target L* = Ustar Vstar^T for the solve metric
+ * (Section 4.1 evaluation). Ustar: device m x rstar column-major (ld ldus);
+ * Vstar: device n x rstar column-major (ld ldvs), rows ordered as the
+ * clients' columns. Copied into the workspace. 1 <= rstar <= 64. */
+rpca_status rpca_set_target(rpca_ctx* c, const float* Ustar, int64_t ldus,
+                            const float* Vstar, int64_t ldvs, int32_t rstar);
+
+/* Relative error ||U V^T - L_ref||_F / ||L_ref||_F of the current iterate
+ * against the target (or, with no target, NaN). Synchronises. */
+rpca_status rpca_target_error(rpca_ctx* c, double* relerr);
+
+/* Algorithm 1's output for client `client` (or all clients when client = -1):
+ * L_i = U^(T) V_i^T and S_i, written column-major into device buffers L and S
+ * with leading dimensions ldl, lds >= m (either pointer may be NULL to skip).
+ * For client = -1 the buffers hold all n columns in client order. Async. */
+rpca_status rpca_get_LS(rpca_ctx* c, int32_t client, float* L, int64_t ldl,
+                        float* S, int64_t lds);
+
+/* Current factors: U (m x r, ld ldu) and V (n x r, ld ldv), both column-major
+ * device buffers; either may be NULL. V's rows follow the clients' columns. */
+rpca_status rpca_get_factors(rpca_ctx* c, float* U, int64_t ldu, float* V, int64_t ldv);
+
+/* Statistics of round `round` (0-based; -1 = the last finished round); only
+ * the last 4096 rounds are kept. Synchronises. */
+rpca_status rpca_get_stats(rpca_ctx* c, int64_t round, rpca_stats* out);
+
+/* Kernel phases of one local step, for rpca_profile. */
+typedef enum {
+  RPCA_PHASE_VPASS = 0,          /* V_i ridge solve: W = (M_i - S_i)^T U, V = W G^{-1} */
+  RPCA_PHASE_SPASS = 1,          /* fused U V_i^T, soft-threshold into S_i, Lambda V_i */
+  RPCA_PHASE_CLIENT_FACTOR = 2,  /* per-client r x r factors of the closed U step */
+  RPCA_PHASE_UUPDATE = 3,        /* U step and consensus mean, Gram partials */
+  RPCA_PHASE_FINALIZE = 4,       /* r x r Gram, FP64 Cholesky inverse, statistics */
+  RPCA_NUM_PHASES = 5
+} rpca_phase;
+
+/* Measurement hook: run `rounds` rounds like rpca_step, with a HIP event pair
+ * around every kernel launch, synchronise, and return per phase the average
+ * launch duration in milliseconds (avg_ms[RPCA_NUM_PHASES]) and the number of
+ * launches (launches[RPCA_NUM_PHASES]). The rounds count as real rounds. */
+rpca_status rpca_profile(rpca_ctx* c, int32_t rounds, double* avg_ms, int64_t* launches);
+
+/* Rounds enqueued so far. */
+int64_t rpca_rounds(const rpca_ctx* c);
+
+/* Text of the last error on this context (never NULL). */
+const char* rpca_last_error(const rpca_ctx* c);
+
+/* Destroy a context (does not free the workspace or M). NULL is a no-op. */
+void rpca_destroy(rpca_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPCA_H_ */

@@ -1,0 +1,537 @@
+// C ABI of the DCF-PCA library: argument checks, workspace carving, the
+// per-round launch sequence of Algorithm 1 (Section 2.2) and the solve loop.
+#include "../../include/rpca.h"
+#include "rpca_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace rpca;
+
+struct rpca_ctx {
+  DevParams p{};
+  std::vector<ClientDev> clients;
+  std::vector<VGroup> vgroups;
+  std::vector<int64_t> col_off;  // first global column of each client, [E + 1]
+  hipStream_t stream = nullptr;
+  int64_t rounds = 0;
+  int cur = 0;  // consensus U buffer holding U^(t)
+  int inner = 1;
+  bool poisoned = false;
+  std::string err;
+  float* U[2] = {nullptr, nullptr};
+  float* Uc[2] = {nullptr, nullptr};
+  double* Ginv = nullptr;  // slot 0: consensus; slots 1..E: per-client (K > 1)
+  float* Uprev = nullptr;
+  float* Vprev = nullptr;
+  bool have_prev = false;
+  float* Ut = nullptr;
+  float* Vt = nullptr;
+  int RPT = 0;
+  bool have_target = false;
+  double* dpart = nullptr;
+  double* dpart2 = nullptr;
+  double* dout = nullptr;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  size_t S, U0, U1, Uc0, Uc1, Vrow, Vcol, P, gv, Af, Bf, gram, spart, upart, ucl, Ginv, dstate,
+      hist, clients, vgroups, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout, total;
+  int32_t MP, RP, NS, NVP, nrb, nub, ngroups;
+  int64_t lds, n, Sfloats;
+};
+
+const char* check_params(const rpca_params* p) {
+  if (!p) return "params is NULL";
+  if (p->m < 1 || p->m > (int64_t)1 << 30) return "m must be in [1, 2^30]";
+  if (p->E < 1 || p->E > 4096) return "E must be in [1, 4096]";
+  if (!p->n_cols) return "n_cols is NULL";
+  int64_t n = 0;
+  for (int i = 0; i < p->E; ++i) {
+    if (p->n_cols[i] < 1 || p->n_cols[i] > (int64_t)1 << 30) return "every n_i must be in [1, 2^30]";
+    n += p->n_cols[i];
+  }
+  if (n > (int64_t)1 << 31) return "total columns n must be <= 2^31";
+  if (p->r < 1 || p->r > kMaxRank) return "r must be in [1, 64]";
+  if (!(p->rho > 0.0) || !std::isfinite(p->rho)) return "rho must be finite and > 0";
+  if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return "lambda must be finite and >= 0";
+  if (p->K < 1 || p->K > 1024) return "K must be in [1, 1024]";
+  if (p->inner < 1 || p->inner > 1024) return "inner must be in [1, 1024]";
+  if (p->u_mode != RPCA_U_GRAD && p->u_mode != RPCA_U_CLOSED) return "unknown u_mode";
+  if (p->u_mode == RPCA_U_GRAD && (!(p->eta0 > 0.0) || !std::isfinite(p->eta0)))
+    return "eta0 must be finite and > 0 for RPCA_U_GRAD";
+  if (p->eta_sched != RPCA_ETA_CONST && p->eta_sched != RPCA_ETA_SQRT) return "unknown eta_sched";
+  if (p->flags != 0) return "flags must be 0";
+  return nullptr;
+}
+
+Layout make_layout(const rpca_params* p) {
+  Layout L{};
+  L.MP = (int32_t)round_up(p->m, kSRows);
+  L.RP = (int32_t)round_up(p->r, 16);
+  L.NS = (p->r + 3) / 4;
+  L.lds = round_up(p->m, 4);
+  L.nrb = L.MP / kSRows;
+  L.nub = L.MP / kURows;
+  int64_t nvp = 0, ng = 0, n = 0;
+  for (int i = 0; i < p->E; ++i) {
+    nvp += round_up(p->n_cols[i], kVCols);
+    ng += (p->n_cols[i] + kVCols - 1) / kVCols;
+    n += p->n_cols[i];
+  }
+  L.NVP = (int32_t)nvp;
+  L.ngroups = (int32_t)ng;
+  L.n = n;
+  L.Sfloats = L.lds * n;
+  const int E = p->E;
+  const bool multi = p->K > 1;
+  const size_t f = sizeof(float), d = sizeof(double);
+  const size_t RR = (size_t)L.RP * L.RP;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.S = take((size_t)L.Sfloats * f);
+  L.U0 = take((size_t)L.RP * L.MP * f);
+  L.U1 = take((size_t)L.RP * L.MP * f);
+  L.Uc0 = take(multi ? (size_t)E * L.RP * L.MP * f : 0);
+  L.Uc1 = take(multi ? (size_t)E * L.RP * L.MP * f : 0);
+  L.Vrow = take((size_t)L.NVP * L.RP * f);
+  L.Vcol = take((size_t)L.NVP * L.RP * f);
+  L.P = take((size_t)E * L.RP * L.MP * f);
+  L.gv = take((size_t)L.ngroups * RR * d);
+  L.Af = take((size_t)E * RR * d);
+  L.Bf = take((size_t)E * RR * d);
+  L.gram = take((size_t)(multi ? E : 1) * L.nub * RR * d);
+  L.spart = take((size_t)E * L.nrb * 4 * d);
+  L.upart = take((size_t)L.nub * d);
+  L.ucl = take((size_t)E * d);
+  L.Ginv = take((size_t)(1 + (multi ? E : 0)) * RR * d);
+  L.dstate = take(sizeof(DevState));
+  L.hist = take((size_t)kHist * sizeof(StatsRec));
+  L.clients = take((size_t)E * sizeof(ClientDev));
+  L.vgroups = take((size_t)L.ngroups * sizeof(VGroup));
+  L.Uprev = take((size_t)L.RP * L.MP * f);
+  L.Vprev = take((size_t)L.NVP * L.RP * f);
+  L.Ut = take((size_t)kMaxRank * L.MP * f);
+  L.Vt = take((size_t)L.NVP * kMaxRank * f);
+  L.dpart = take((size_t)2 * kDistBlocks * 3 * kMaxRank * kMaxRank * d);
+  L.dpart2 = take((size_t)48 * d);
+  L.dout = take((size_t)2 * d);
+  L.total = o;
+  return L;
+}
+
+rpca_status fail(rpca_ctx* c, rpca_status st, const std::string& msg) {
+  if (c) {
+    c->err = msg;
+    if (st == RPCA_EDEVICE || st == RPCA_ENONFINITE) c->poisoned = true;
+  }
+  return st;
+}
+
+rpca_status dev_fail(rpca_ctx* c, hipError_t e, const char* where) {
+  return fail(c, RPCA_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define RPCA_HIP(c, call, where)                 \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return dev_fail((c), e_, (where)); \
+  } while (0)
+
+double eta_at(const rpca_ctx* c) {
+  if (c->p.u_mode != RPCA_U_GRAD) return 0.0;
+  if (c->p.eta_sched == RPCA_ETA_SQRT) return c->p.eta0 / std::sqrt((double)c->rounds + 1.0);
+  return c->p.eta0;
+}
+
+// Optional per-kernel event timing (rpca_profile): a pair of events around
+// every launch, grouped by phase.
+struct Profiler {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> phase;
+  hipError_t begin(hipStream_t st, int ph) {
+    hipEvent_t a;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    ev.push_back(a);
+    phase.push_back(ph);
+    return hipEventRecord(a, st);
+  }
+  hipError_t end(hipStream_t st) {
+    hipEvent_t b;
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) return e;
+    ev.push_back(b);
+    return hipEventRecord(b, st);
+  }
+  ~Profiler() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+#define RPCA_LAUNCH(c, prof, ph, call, where)                      \
+  do {                                                              \
+    if (prof) RPCA_HIP(c, (prof)->begin((c)->stream, (ph)), "event"); \
+    RPCA_HIP(c, (call), (where));                                   \
+    if (prof) RPCA_HIP(c, (prof)->end((c)->stream), "event");         \
+  } while (0)
+
+// One round of Algorithm 1: K local steps (each: `inner` V/S alternations,
+// then the U step) and the consensus mean at the last one.
+rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
+  const DevParams& p = c->p;
+  hipStream_t st = c->stream;
+  const double eta = eta_at(c);
+  const int64_t ustride = (int64_t)p.RP * p.MP;
+  const int64_t gstride = (int64_t)p.RP * p.RP;
+  const float* Ucons = c->U[c->cur];
+  for (int k = 0; k < p.K; ++k) {
+    const float* Uin = k == 0 ? Ucons : c->Uc[(k - 1) & 1];
+    const int64_t us = k == 0 ? 0 : ustride;
+    const double* Gin = k == 0 ? c->Ginv : c->Ginv + gstride;
+    const int64_t gs = k == 0 ? 0 : gstride;
+    for (int q = 0; q < c->inner; ++q) {
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS, launch_vpass(p, Uin, us, Gin, gs, st), "V-pass launch");
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_SPASS, launch_spass(p, Uin, us, st), "S-pass launch");
+    }
+    if (p.u_mode == RPCA_U_CLOSED)
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(p, st), "client factor launch");
+    if (k == p.K - 1) {
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE,
+                  launch_uupdate(p, Uin, us, c->U[c->cur ^ 1], 0, Ucons, 1, eta, st), "U update launch");
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_FINALIZE, launch_finalize(p, c->Ginv, 0, 0, 1, st), "finalize launch");
+    } else {
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE,
+                  launch_uupdate(p, Uin, us, c->Uc[k & 1], ustride, nullptr, 0, eta, st), "U update launch");
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_FINALIZE, launch_finalize(p, c->Ginv + gstride, gstride, 1, 0, st),
+                  "finalize launch");
+    }
+  }
+  c->cur ^= 1;
+  c->rounds += 1;
+  return RPCA_OK;
+}
+
+}  // namespace
+
+namespace {
+
+rpca_status guard(rpca_ctx* c) {
+  if (!c) return RPCA_EINVAL;
+  if (c->poisoned) return RPCA_ESTATE;
+  return RPCA_OK;
+}
+
+// ||U V^T - X2 Y2^T||_F^2 and ||X2 Y2^T||_F^2 into c->dout (device).
+rpca_status enqueue_distance(rpca_ctx* c, const float* X2, const float* Y2, int rp2) {
+  RPCA_HIP(c,
+           launch_factor_distance(c->p, c->U[c->cur], c->p.Vcol, c->p.RP, X2, Y2, rp2, c->dpart,
+                                  c->dpart2, c->dout, c->stream),
+           "factor distance launch");
+  return RPCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rpca_params_error(const rpca_params* p) { return check_params(p); }
+
+rpca_status rpca_workspace_bytes(const rpca_params* p, size_t* bytes) {
+  if (check_params(p) || !bytes) return RPCA_EINVAL;
+  *bytes = make_layout(p).total;
+  return RPCA_OK;
+}
+
+rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const* M_blocks,
+                      const int64_t* ldm, const float* U0, int64_t ldu, void* workspace,
+                      size_t ws_bytes, void* stream) {
+  if (!out) return RPCA_EINVAL;
+  *out = nullptr;
+  if (check_params(prm)) return RPCA_EINVAL;
+  if (!M_blocks || !ldm || !U0 || ldu < prm->m) return RPCA_EINVAL;
+  for (int i = 0; i < prm->E; ++i) {
+    if (!M_blocks[i] || ldm[i] < prm->m || ldm[i] % 4 != 0 ||
+        reinterpret_cast<uintptr_t>(M_blocks[i]) % 16 != 0)
+      return RPCA_EINVAL;
+  }
+  const Layout L = make_layout(prm);
+  if (!workspace || ws_bytes < L.total || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return RPCA_EWORKSPACE;
+
+  rpca_ctx* c = new rpca_ctx();
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->inner = prm->inner;
+  char* ws = static_cast<char*>(workspace);
+  DevParams& p = c->p;
+  p.m = (int32_t)prm->m;
+  p.MP = L.MP;
+  p.r = prm->r;
+  p.RP = L.RP;
+  p.NS = L.NS;
+  p.E = prm->E;
+  p.K = prm->K;
+  p.NVP = L.NVP;
+  p.n = L.n;
+  p.lds = L.lds;
+  p.nrb = L.nrb;
+  p.nub = L.nub;
+  p.ngroups = L.ngroups;
+  p.u_mode = prm->u_mode;
+  p.eta_sched = prm->eta_sched;
+  p.lam = (float)prm->lambda;
+  p.rho = prm->rho;
+  p.eta0 = prm->eta0;
+  p.clients = reinterpret_cast<const ClientDev*>(ws + L.clients);
+  p.vgroups = reinterpret_cast<const VGroup*>(ws + L.vgroups);
+  p.S = reinterpret_cast<float*>(ws + L.S);
+  p.Vrow = reinterpret_cast<float*>(ws + L.Vrow);
+  p.Vcol = reinterpret_cast<float*>(ws + L.Vcol);
+  p.P = reinterpret_cast<float*>(ws + L.P);
+  p.gv_part = reinterpret_cast<double*>(ws + L.gv);
+  p.Afac = reinterpret_cast<double*>(ws + L.Af);
+  p.Bfac = reinterpret_cast<double*>(ws + L.Bf);
+  p.gram_part = reinterpret_cast<double*>(ws + L.gram);
+  p.spart = reinterpret_cast<double*>(ws + L.spart);
+  p.upart = reinterpret_cast<double*>(ws + L.upart);
+  p.ucl_sq = reinterpret_cast<double*>(ws + L.ucl);
+  p.dstate = reinterpret_cast<DevState*>(ws + L.dstate);
+  p.hist = reinterpret_cast<StatsRec*>(ws + L.hist);
+  c->U[0] = reinterpret_cast<float*>(ws + L.U0);
+  c->U[1] = reinterpret_cast<float*>(ws + L.U1);
+  c->Uc[0] = reinterpret_cast<float*>(ws + L.Uc0);
+  c->Uc[1] = reinterpret_cast<float*>(ws + L.Uc1);
+  c->Ginv = reinterpret_cast<double*>(ws + L.Ginv);
+  c->Uprev = reinterpret_cast<float*>(ws + L.Uprev);
+  c->Vprev = reinterpret_cast<float*>(ws + L.Vprev);
+  c->Ut = reinterpret_cast<float*>(ws + L.Ut);
+  c->Vt = reinterpret_cast<float*>(ws + L.Vt);
+  c->dpart = reinterpret_cast<double*>(ws + L.dpart);
+  c->dpart2 = reinterpret_cast<double*>(ws + L.dpart2);
+  c->dout = reinterpret_cast<double*>(ws + L.dout);
+
+  // Client table (Section 2.1: client i holds columns [col_off[i], col_off[i+1])).
+  c->clients.resize(prm->E);
+  c->col_off.resize(prm->E + 1);
+  int64_t col = 0, vrow = 0;
+  int32_t g = 0;
+  for (int i = 0; i < prm->E; ++i) {
+    ClientDev& cd = c->clients[i];
+    const int32_t ni = (int32_t)prm->n_cols[i];
+    cd.M = M_blocks[i];
+    cd.ldm = ldm[i];
+    cd.s_off = L.lds * col;
+    cd.n = ni;
+    cd.vrow0 = (int32_t)vrow;
+    cd.g0 = g;
+    for (int32_t j0 = 0; j0 < ni; j0 += kVCols) {
+      c->vgroups.push_back(VGroup{i, j0, ni - j0 < kVCols ? ni - j0 : kVCols, 0});
+      ++g;
+    }
+    cd.g1 = g;
+    cd.c = prm->rho * (double)ni / (double)L.n;
+    c->col_off[i] = col;
+    col += ni;
+    vrow += round_up(ni, kVCols);
+  }
+  c->col_off[prm->E] = col;
+
+  hipStream_t st = c->stream;
+  hipError_t e = hipMemsetAsync(workspace, 0, L.total, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.clients, c->clients.data(), c->clients.size() * sizeof(ClientDev),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.vgroups, c->vgroups.data(), c->vgroups.size() * sizeof(VGroup),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_copy_in_U(p, U0, ldu, c->U[0], st);
+  if (e == hipSuccess) e = launch_gram_init(p, c->U[0], st);
+  if (e == hipSuccess) e = launch_finalize(p, c->Ginv, 0, 0, 0, st);
+  // The host tables must outlive the asynchronous copies above.
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete c;
+    return RPCA_EDEVICE;
+  }
+  *out = c;
+  const double mn = (double)prm->m * (double)L.n;
+  if (prm->rho * prm->rho > prm->lambda * prm->lambda * mn) {
+    c->err = "rho^2 > lambda^2 m n: only U = 0 is stationary (Theorem 2)";
+    return RPCA_WARN_THM2;
+  }
+  return RPCA_OK;
+}
+
+rpca_status rpca_step(rpca_ctx* c, int32_t rounds) {
+  if (rpca_status s = guard(c)) return s;
+  if (rounds < 0) return fail(c, RPCA_EINVAL, "rounds must be >= 0");
+  for (int32_t t = 0; t < rounds; ++t)
+    if (rpca_status s = enqueue_round(c)) return s;
+  return RPCA_OK;
+}
+
+rpca_status rpca_set_target(rpca_ctx* c, const float* Ustar, int64_t ldus, const float* Vstar,
+                            int64_t ldvs, int32_t rstar) {
+  if (rpca_status s = guard(c)) return s;
+  if (!Ustar || !Vstar || rstar < 1 || rstar > kMaxRank || ldus < c->p.m || ldvs < c->p.n)
+    return fail(c, RPCA_EINVAL, "invalid target factors");
+  c->RPT = (int)round_up(rstar, 16);
+  RPCA_HIP(c,
+           launch_pack_target(c->p, c->clients.data(), c->col_off.data(), Ustar, ldus, Vstar,
+                              ldvs, rstar, c->Ut, c->Vt, c->RPT, c->stream),
+           "target pack launch");
+  c->have_target = true;
+  return RPCA_OK;
+}
+
+rpca_status rpca_target_error(rpca_ctx* c, double* relerr) {
+  if (rpca_status s = guard(c)) return s;
+  if (!relerr) return fail(c, RPCA_EINVAL, "relerr is NULL");
+  if (!c->have_target) {
+    *relerr = NAN;
+    return RPCA_OK;
+  }
+  if (rpca_status s = enqueue_distance(c, c->Ut, c->Vt, c->RPT)) return s;
+  double h[2];
+  RPCA_HIP(c, hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream), "copy");
+  RPCA_HIP(c, hipStreamSynchronize(c->stream), "synchronize");
+  *relerr = std::sqrt(std::fmax(h[0], 0.0) / h[1]);
+  return RPCA_OK;
+}
+
+rpca_status rpca_solve(rpca_ctx* c, int32_t max_rounds, double tol, int32_t check_every,
+                       int32_t* rounds_done, double* metric) {
+  if (rpca_status s = guard(c)) return s;
+  if (max_rounds < 0 || check_every < 1) return fail(c, RPCA_EINVAL, "bad solve arguments");
+  int32_t done = 0;
+  double last = INFINITY;
+  const size_t ubytes = (size_t)c->p.RP * c->p.MP * sizeof(float);
+  const size_t vbytes = (size_t)c->p.RP * c->p.NVP * sizeof(float);
+  rpca_status result = RPCA_OK;
+  while (done < max_rounds) {
+    const int32_t nr = max_rounds - done < check_every ? max_rounds - done : check_every;
+    if (rpca_status s = rpca_step(c, nr)) return s;
+    done += nr;
+    bool have_metric = false;
+    if (c->have_target) {
+      if (rpca_status s = enqueue_distance(c, c->Ut, c->Vt, c->RPT)) return s;
+      have_metric = true;
+    } else if (c->have_prev) {
+      if (rpca_status s = enqueue_distance(c, c->Uprev, c->Vprev, c->p.RP)) return s;
+      have_metric = true;
+    }
+    if (!c->have_target) {
+      RPCA_HIP(c, hipMemcpyAsync(c->Uprev, c->U[c->cur], ubytes, hipMemcpyDeviceToDevice, c->stream),
+               "copy U");
+      RPCA_HIP(c, hipMemcpyAsync(c->Vprev, c->p.Vcol, vbytes, hipMemcpyDeviceToDevice, c->stream),
+               "copy V");
+      c->have_prev = true;
+    }
+    double h[2] = {0.0, 1.0};
+    StatsRec rec;
+    if (have_metric)
+      RPCA_HIP(c, hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream), "copy");
+    RPCA_HIP(c,
+             hipMemcpyAsync(&rec, c->p.hist + (c->rounds - 1) % kHist, sizeof(rec),
+                            hipMemcpyDeviceToHost, c->stream),
+             "copy stats");
+    RPCA_HIP(c, hipStreamSynchronize(c->stream), "synchronize");
+    if (!std::isfinite(rec.objective)) {
+      result = fail(c, RPCA_ENONFINITE, "non-finite objective");
+      break;
+    }
+    if (have_metric) {
+      last = h[1] > 0.0 ? std::sqrt(std::fmax(h[0], 0.0) / h[1]) : INFINITY;
+      if (last <= tol) break;
+    }
+  }
+  if (rounds_done) *rounds_done = done;
+  if (metric) *metric = last;
+  return result;
+}
+
+rpca_status rpca_get_LS(rpca_ctx* c, int32_t client, float* L, int64_t ldl, float* S,
+                        int64_t lds) {
+  if (rpca_status s = guard(c)) return s;
+  if (client < -1 || client >= c->p.E) return fail(c, RPCA_EINVAL, "client out of range");
+  if ((L && ldl < c->p.m) || (S && lds < c->p.m)) return fail(c, RPCA_EINVAL, "leading dimension < m");
+  const int b = client < 0 ? 0 : client, e = client < 0 ? c->p.E : client + 1;
+  RPCA_HIP(c,
+           launch_materialize(c->p, c->clients.data(), c->col_off.data(), c->U[c->cur], b, e, L,
+                              ldl, S, lds, c->stream),
+           "materialize launch");
+  return RPCA_OK;
+}
+
+rpca_status rpca_get_factors(rpca_ctx* c, float* U, int64_t ldu, float* V, int64_t ldv) {
+  if (rpca_status s = guard(c)) return s;
+  if ((U && ldu < c->p.m) || (V && ldv < c->p.n)) return fail(c, RPCA_EINVAL, "leading dimension too small");
+  RPCA_HIP(c,
+           launch_get_factors(c->p, c->clients.data(), c->col_off.data(), c->U[c->cur], U, ldu, V,
+                              ldv, c->stream),
+           "factor copy launch");
+  return RPCA_OK;
+}
+
+rpca_status rpca_get_stats(rpca_ctx* c, int64_t round, rpca_stats* out) {
+  if (rpca_status s = guard(c)) return s;
+  if (!out) return fail(c, RPCA_EINVAL, "out is NULL");
+  if (round < 0) round = c->rounds - 1;
+  if (round < 0 || round >= c->rounds || round < c->rounds - kHist)
+    return fail(c, RPCA_EINVAL, "round not available");
+  StatsRec rec;
+  RPCA_HIP(c,
+           hipMemcpyAsync(&rec, c->p.hist + round % kHist, sizeof(rec), hipMemcpyDeviceToHost,
+                          c->stream),
+           "copy stats");
+  RPCA_HIP(c, hipStreamSynchronize(c->stream), "synchronize");
+  std::memcpy(out, &rec, sizeof(rec));
+  return RPCA_OK;
+}
+
+rpca_status rpca_profile(rpca_ctx* c, int32_t rounds, double* avg_ms, int64_t* launches) {
+  if (rpca_status s = guard(c)) return s;
+  if (rounds < 1 || !avg_ms || !launches) return fail(c, RPCA_EINVAL, "bad profile arguments");
+  Profiler prof;
+  for (int32_t t = 0; t < rounds; ++t)
+    if (rpca_status s = enqueue_round(c, &prof)) return s;
+  RPCA_HIP(c, hipStreamSynchronize(c->stream), "synchronize");
+  double tot[RPCA_NUM_PHASES] = {0};
+  int64_t cnt[RPCA_NUM_PHASES] = {0};
+  for (size_t k = 0; k < prof.phase.size(); ++k) {
+    float ms = 0.f;
+    RPCA_HIP(c, hipEventElapsedTime(&ms, prof.ev[2 * k], prof.ev[2 * k + 1]), "elapsed time");
+    tot[prof.phase[k]] += ms;
+    cnt[prof.phase[k]] += 1;
+  }
+  for (int k = 0; k < RPCA_NUM_PHASES; ++k) {
+    avg_ms[k] = cnt[k] ? tot[k] / (double)cnt[k] : 0.0;
+    launches[k] = cnt[k];
+  }
+  return RPCA_OK;
+}
+
+int64_t rpca_rounds(const rpca_ctx* c) { return c ? c->rounds : -1; }
+
+const char* rpca_last_error(const rpca_ctx* c) {
+  if (!c) return "context is NULL";
+  return c->err.c_str();
+}
+
+void rpca_destroy(rpca_ctx* c) { delete c; }
+
+}  // extern "C"

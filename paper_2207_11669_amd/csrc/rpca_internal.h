@@ -1,0 +1,105 @@
+// Internal definitions shared by the DCF-PCA kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rpca {
+
+constexpr int kMaxRank = 64;     // largest supported factor rank r
+constexpr int kHist = 4096;      // per-round statistics kept in a ring
+constexpr int kVCols = 32;       // columns per V-pass work-group
+constexpr int kVWaves = 8;       // waves per V-pass work-group (split over rows)
+constexpr int kSRows = 128;      // rows per S-pass work-group (4 waves x 32 rows)
+constexpr int kURows = 32;       // rows per U-update work-group
+
+// One client (Section 2.1): its borrowed block M_i and where its private
+// state lives in the workspace.
+struct ClientDev {
+  const float* M;   // column-major m x n_i, leading dimension ldm
+  int64_t ldm;
+  int64_t s_off;    // first float of S_i in the S buffer (leading dimension lds)
+  int32_t n;        // n_i
+  int32_t vrow0;    // first row of V_i in the padded V buffers (multiple of 32)
+  int32_t g0, g1;   // V-pass work-groups [g0, g1) that cover this client
+  double c;         // rho * n_i / n
+};
+
+// A V-pass work unit: up to 32 consecutive columns of one client.
+struct VGroup {
+  int32_t client, j0, ncols, pad;
+};
+
+// Device-resident scalars carried from round to round.
+struct DevState {
+  int64_t t;                 // rounds finished
+  double u_sq;               // ||U^(t)||_F^2 (trace of the current Gram)
+  double pad[6];
+};
+
+struct StatsRec {  // mirrors rpca_stats
+  double t, objective, lambda_fro_sq, nnz, du_sq, u_sq, v_sq, l1;
+};
+
+struct DevParams {
+  int32_t m, MP, r, RP, NS, E, K;
+  int32_t NVP;           // padded rows of the V buffers
+  int64_t n;             // total columns
+  int64_t lds;           // leading dimension of S (= m rounded up to 4)
+  int32_t nrb;           // S-pass row blocks (MP / kSRows)
+  int32_t nub;           // U-update row blocks (MP / kURows)
+  int32_t ngroups;       // V-pass work-groups
+  int32_t u_mode, eta_sched;
+  float lam;
+  double rho, eta0;
+  const ClientDev* clients;
+  const VGroup* vgroups;
+  float* S;              // all clients' S_i
+  float* Vrow;           // V, row-major NVP x RP
+  float* Vcol;           // V, column-major NVP x RP (leading dimension NVP)
+  float* P;              // per-client Lambda_i V_i, column-major MP x RP each
+  double* gv_part;       // per V-group partial V^T V, RP x RP
+  double* Afac;          // per-client (V_i^T V_i + c_i I)^{-1}, RP x RP
+  double* Bfac;          // per-client V_i^T V_i (V_i^T V_i + c_i I)^{-1}
+  double* gram_part;     // per (client,) U row block partial U^T U, RP x RP
+  double* spart;         // per S-pass work-group: 1/2-free sums (l2, l1, nnz, 0)
+  double* upart;         // per U row block: ||dU||^2
+  double* ucl_sq;        // per-client ||U_i||^2 of the current local factors
+  DevState* dstate;
+  StatsRec* hist;
+};
+
+// Launch helpers (kernels live in rpca_kernels.hip).
+constexpr int kDistBlocks = 64;  // work-groups per side of the factor-distance kernel
+hipError_t launch_vpass(const DevParams& p, const float* U, int64_t u_stride, const double* Ginv,
+                        int64_t g_stride, hipStream_t st);
+hipError_t launch_client_factor(const DevParams& p, hipStream_t st);
+hipError_t launch_spass(const DevParams& p, const float* U, int64_t u_stride, hipStream_t st);
+hipError_t launch_uupdate(const DevParams& p, const float* Uin, int64_t uin_stride, float* Uout,
+                          int64_t uout_stride, const float* Uprev_cons, int final_step,
+                          double eta, hipStream_t st);
+hipError_t launch_finalize(const DevParams& p, double* Ginv, int64_t g_stride, int per_client,
+                           int record, hipStream_t st);
+hipError_t launch_gram_init(const DevParams& p, const float* U, hipStream_t st);
+hipError_t launch_copy_in_U(const DevParams& p, const float* U0, int64_t ldu, float* Ucol,
+                            hipStream_t st);
+hipError_t launch_materialize(const DevParams& p, const ClientDev* host_clients,
+                              const int64_t* col_off, const float* Ucol, int client_begin,
+                              int client_end, float* L, int64_t ldl, float* S, int64_t lds,
+                              hipStream_t st);
+hipError_t launch_get_factors(const DevParams& p, const ClientDev* host_clients,
+                              const int64_t* col_off, const float* Ucol, float* U, int64_t ldu,
+                              float* V, int64_t ldv, hipStream_t st);
+hipError_t launch_pack_target(const DevParams& p, const ClientDev* host_clients,
+                              const int64_t* col_off, const float* Us, int64_t ldus,
+                              const float* Vs, int64_t ldvs, int rs, float* Ut, float* Vt,
+                              int RPT, hipStream_t st);
+// ||X1 Y1^T - X2 Y2^T||_F^2 -> out2[0] and ||X2 Y2^T||_F^2 -> out2[1], from
+// Gram matrices (FP64). X*: column-major, MP rows (ld MP); Y*: column-major,
+// NVP rows (ld NVP); widths rp1, rp2 <= 64. part: 2*kDistBlocks*3*64*64
+// doubles; part2: 48*3 doubles.
+hipError_t launch_factor_distance(const DevParams& p, const float* X1, const float* Y1, int rp1,
+                                  const float* X2, const float* Y2, int rp2, double* part,
+                                  double* part2, double* out2, hipStream_t st);
+
+}  // namespace rpca

@@ -1,0 +1,53 @@
+"""Shared helpers for the GPU parity tests: run the HIP path and the FP64
+oracle on the same seeded instance and compare what is unique (L and S)."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+import oracle.reference as O
+from rpca_inputs import Instance, gaussian_init
+
+
+def announce(msg: str):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(inst: Instance, U0: np.ndarray, r: int, rho: float, lam: float, T: int, **kw):
+    import torch
+
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    M_cols = colmajor(inst.M)
+    U0_cols = colmajor(U0)
+    s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, **kw)
+    s.step(T)
+    L, S = s.get_LS(-1)
+    torch.cuda.synchronize()
+    m = inst.m
+    Lg = L[:, :m].T.double().cpu().numpy()
+    Sg = S[:, :m].T.double().cpu().numpy()
+    hist = [s.stats(t) for t in range(max(0, T - min(T, 4096)), T)]
+    return s, Lg, Sg, hist
+
+
+def run_oracle(inst: Instance, U0: np.ndarray, r: int, rho: float, lam: float, T: int,
+               K: int = 1, inner: int = 1, u_mode: str = "closed", eta0: float = 0.0,
+               eta_sched: str = "const"):
+    return O.dcfpca(inst.blocks(), r, rho, lam, T, U0, K=K, inner=inner, u_mode=u_mode,
+                    eta0=eta0, eta_sched=eta_sched)
+
+
+def rel(a: np.ndarray, b: np.ndarray) -> float:
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+
+
+def default_lam(inst: Instance) -> float:
+    return 1.0 / math.sqrt(inst.n)
+
+
+def init_for(inst: Instance, r: int, seed: int) -> np.ndarray:
+    return gaussian_init(inst.m, r, seed)

@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/rpca.h declares, validates parameters, and sizes its
+workspace; the product path never touches the oracle."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2207_11669_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2207_11669_amd import build
+        build.build()
+    return binding.load_library()
+
+
+def test_exports_every_declared_function(lib):
+    from paper_2207_11669_amd import declared_functions
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_parameter_validation_messages(lib):
+    from paper_2207_11669_amd import make_params, params_error
+    ok, _k = make_params(100, [30, 70], 5, 0.1, 0.1)
+    assert params_error(ok) is None
+    cases = [
+        (dict(m=0, widths=[3], r=1, rho=0.1, lam=0.1), "m must"),
+        (dict(m=10, widths=[3, 0], r=1, rho=0.1, lam=0.1), "n_i"),
+        (dict(m=10, widths=[3], r=0, rho=0.1, lam=0.1), "r must"),
+        (dict(m=10, widths=[3], r=65, rho=0.1, lam=0.1), "r must"),
+        (dict(m=10, widths=[3], r=2, rho=0.0, lam=0.1), "rho"),
+        (dict(m=10, widths=[3], r=2, rho=0.1, lam=-1.0), "lambda"),
+        (dict(m=10, widths=[3], r=2, rho=0.1, lam=0.1, K=0), "K must"),
+        (dict(m=10, widths=[3], r=2, rho=0.1, lam=0.1, inner=0), "inner"),
+        (dict(m=10, widths=[3], r=2, rho=0.1, lam=0.1, u_mode="grad", eta0=0.0), "eta0"),
+    ]
+    for kw, frag in cases:
+        p, _k = make_params(**kw)
+        msg = params_error(p)
+        assert msg is not None and frag in msg, (kw, msg)
+
+
+def test_workspace_bytes_grow_with_problem(lib):
+    from paper_2207_11669_amd import make_params, workspace_bytes
+    p1, _a = make_params(4000, [500] * 16, 20, 0.1, 0.01)
+    p2, _b = make_params(4000, [500] * 16, 20, 0.1, 0.01, K=2)
+    p3, _c = make_params(8000, [500] * 16, 20, 0.1, 0.01)
+    b1, b2, b3 = workspace_bytes(p1), workspace_bytes(p2), workspace_bytes(p3)
+    # S alone is m * n * 4 bytes.
+    assert b1 >= 4000 * 8000 * 4
+    assert b2 > b1 and b3 > b1
+    assert b1 % 256 == 0
+
+
+def test_product_path_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2207_11669_amd")
+    for dirpath, _dirs, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
+                assert "oracle/" not in text, f
