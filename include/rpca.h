@@ -68,8 +68,15 @@ typedef struct {
   int32_t u_mode;          /* rpca_u_mode */
   double eta0;             /* step size for RPCA_U_GRAD (> 0 there) */
   int32_t eta_sched;       /* rpca_eta_sched */
-  uint32_t flags;          /* reserved, must be 0 */
+  uint32_t flags;          /* RPCA_FLAG_* bits */
 } rpca_params;
+
+/* With K = 1 and one alternation the library does not store S between rounds:
+ * the V-pass rebuilds S_i^(t) = soft(M_i - U^(t-1) V_i^(t)T) (eq. "optS") from
+ * the previous round's factors, which halves the HBM traffic of a round. This
+ * flag keeps S in the workspace instead (the layout used for K > 1 or more
+ * than one alternation); the results agree to FP32 rounding. */
+#define RPCA_FLAG_STORE_S 1u
 
 /* Per-round statistics, FP64, recorded at the last local step of round t:
  * objective = sum_i L_i(U_i, V_i, S_i) with U_i the client factor that the

@@ -104,14 +104,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     return lib
 
 
+RPCA_FLAG_STORE_S = 1
+
+
 def make_params(m: int, widths: Sequence[int], r: int, rho: float, lam: float, K: int = 1,
                 inner: int = 1, u_mode: str = "closed", eta0: float = 0.0,
-                eta_sched: str = "const"):
+                eta_sched: str = "const", store_s: bool = False):
     """Build an rpca_params struct; returns (params, n_cols array to keep alive)."""
     ncols = (c_int64 * len(widths))(*[int(w) for w in widths])
     p = RpcaParams(m=int(m), E=len(widths), n_cols=ncols, r=int(r), rho=float(rho),
                    lam=float(lam), K=int(K), inner=int(inner), u_mode=U_MODES[u_mode],
-                   eta0=float(eta0), eta_sched=ETA_SCHEDS[eta_sched], flags=0)
+                   eta0=float(eta0), eta_sched=ETA_SCHEDS[eta_sched],
+                   flags=RPCA_FLAG_STORE_S if store_s else 0)
     return p, ncols
 
 
@@ -154,7 +158,8 @@ class DCFPCA:
 
     def __init__(self, M_cols, widths: Sequence[int], m: int, r: int, rho: float, lam: float,
                  U0_cols, K: int = 1, inner: int = 1, u_mode: str = "closed",
-                 eta0: float = 0.0, eta_sched: str = "const", stream=None):
+                 eta0: float = 0.0, eta_sched: str = "const", store_s: bool = False,
+                 stream=None):
         import torch
         self._lib = load_library()
         if not (M_cols.is_cuda and M_cols.dtype == torch.float32 and M_cols.is_contiguous()):
@@ -168,7 +173,7 @@ class DCFPCA:
             raise ValueError("M_cols must have one row per column of M")
         self.ldm = int(M_cols.shape[1])
         self.params, self._ncols = make_params(m, self.widths, r, rho, lam, K, inner, u_mode,
-                                               eta0, eta_sched)
+                                               eta0, eta_sched, store_s)
         err = params_error(self.params)
         if err:
             raise ValueError(err)

@@ -18,8 +18,13 @@ struct rpca_ctx {
   std::vector<int64_t> col_off;  // first global column of each client, [E + 1]
   hipStream_t stream = nullptr;
   int64_t rounds = 0;
-  int cur = 0;  // consensus U buffer holding U^(t)
+  int cur = 0;   // consensus U buffer holding U^(t)
+  int vcur = 0;  // V buffer holding the latest V
   int inner = 1;
+  bool recompute = false;  // S rebuilt from (U_prev, V) instead of stored
+  float* Vrow[2] = {nullptr, nullptr};
+  float* Vcol[2] = {nullptr, nullptr};
+  std::vector<VGroup> vg64;
   bool poisoned = false;
   std::string err;
   float* U[2] = {nullptr, nullptr};
@@ -45,9 +50,11 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t S, U0, U1, Uc0, Uc1, Vrow, Vcol, P, gv, Af, Bf, gram, spart, upart, ucl, Ginv, dstate,
-      hist, clients, vgroups, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout, total;
-  int32_t MP, RP, NS, NVP, nrb, nub, ngroups;
+  size_t S, U0, U1, Uc0, Uc1, Vrow0, Vrow1, Vcol0, Vcol1, Wpart, P, gv, Af, Bf, gram, spart, upart,
+      ucl, Ginv, dstate, hist, clients, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
+      total;
+  int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows;
+  bool recompute;
   int64_t lds, n, Sfloats;
 };
 
@@ -71,7 +78,7 @@ const char* check_params(const rpca_params* p) {
   if (p->u_mode == RPCA_U_GRAD && (!(p->eta0 > 0.0) || !std::isfinite(p->eta0)))
     return "eta0 must be finite and > 0 for RPCA_U_GRAD";
   if (p->eta_sched != RPCA_ETA_CONST && p->eta_sched != RPCA_ETA_SQRT) return "unknown eta_sched";
-  if (p->flags != 0) return "flags must be 0";
+  if (p->flags & ~(uint32_t)RPCA_FLAG_STORE_S) return "unknown flags";
   return nullptr;
 }
 
@@ -83,16 +90,30 @@ Layout make_layout(const rpca_params* p) {
   L.lds = round_up(p->m, 4);
   L.nrb = L.MP / kSRows;
   L.nub = L.MP / kURows;
-  int64_t nvp = 0, ng = 0, n = 0;
+  int64_t nvp = 0, ng = 0, ng64 = 0, n = 0;
   for (int i = 0; i < p->E; ++i) {
-    nvp += round_up(p->n_cols[i], kVCols);
+    nvp += round_up(p->n_cols[i], kVPad);
     ng += (p->n_cols[i] + kVCols - 1) / kVCols;
+    ng64 += (p->n_cols[i] + kVStreamCols - 1) / kVStreamCols;
     n += p->n_cols[i];
   }
   L.NVP = (int32_t)nvp;
   L.ngroups = (int32_t)ng;
+  L.ng64 = (int32_t)ng64;
   L.n = n;
-  L.Sfloats = L.lds * n;
+  // Row splits of the V-pass: enough work-groups to fill the chip (>= 1024),
+  // each covering at least 64 rows.
+  {
+    const int64_t want = (1024 + ng64 - 1) / ng64;
+    const int64_t maxs = (p->m + 63) / 64;
+    int64_t vs = want < maxs ? want : maxs;
+    if (vs < 1) vs = 1;
+    const int64_t rows = round_up((p->m + vs - 1) / vs, 16);
+    L.vsplit_rows = (int32_t)rows;
+    L.vsplit = (int32_t)((p->m + rows - 1) / rows);
+  }
+  L.recompute = p->K == 1 && p->inner == 1 && !(p->flags & RPCA_FLAG_STORE_S);
+  L.Sfloats = L.recompute ? 0 : L.lds * n;
   const int E = p->E;
   const bool multi = p->K > 1;
   const size_t f = sizeof(float), d = sizeof(double);
@@ -108,8 +129,11 @@ Layout make_layout(const rpca_params* p) {
   L.U1 = take((size_t)L.RP * L.MP * f);
   L.Uc0 = take(multi ? (size_t)E * L.RP * L.MP * f : 0);
   L.Uc1 = take(multi ? (size_t)E * L.RP * L.MP * f : 0);
-  L.Vrow = take((size_t)L.NVP * L.RP * f);
-  L.Vcol = take((size_t)L.NVP * L.RP * f);
+  L.Vrow0 = take((size_t)L.NVP * L.RP * f);
+  L.Vrow1 = take((size_t)L.NVP * L.RP * f);
+  L.Vcol0 = take((size_t)L.NVP * L.RP * f);
+  L.Vcol1 = take((size_t)L.NVP * L.RP * f);
+  L.Wpart = take((size_t)L.vsplit * L.NVP * L.RP * f);
   L.P = take((size_t)E * L.RP * L.MP * f);
   L.gv = take((size_t)L.ngroups * RR * d);
   L.Af = take((size_t)E * RR * d);
@@ -123,6 +147,7 @@ Layout make_layout(const rpca_params* p) {
   L.hist = take((size_t)kHist * sizeof(StatsRec));
   L.clients = take((size_t)E * sizeof(ClientDev));
   L.vgroups = take((size_t)L.ngroups * sizeof(VGroup));
+  L.vg64 = take((size_t)L.ng64 * sizeof(VGroup));
   L.Uprev = take((size_t)L.RP * L.MP * f);
   L.Vprev = take((size_t)L.NVP * L.RP * f);
   L.Ut = take((size_t)kMaxRank * L.MP * f);
@@ -151,12 +176,6 @@ rpca_status dev_fail(rpca_ctx* c, hipError_t e, const char* where) {
     hipError_t e_ = (call);                      \
     if (e_ != hipSuccess) return dev_fail((c), e_, (where)); \
   } while (0)
-
-double eta_at(const rpca_ctx* c) {
-  if (c->p.u_mode != RPCA_U_GRAD) return 0.0;
-  if (c->p.eta_sched == RPCA_ETA_SQRT) return c->p.eta0 / std::sqrt((double)c->rounds + 1.0);
-  return c->p.eta0;
-}
 
 // Optional per-kernel event timing (rpca_profile): a pair of events around
 // every launch, grouped by phase.
@@ -190,33 +209,64 @@ struct Profiler {
     if (prof) RPCA_HIP(c, (prof)->end((c)->stream), "event");         \
   } while (0)
 
+// Device parameters of a launch that reads or writes V buffer `v`.
+DevParams with_v(const rpca_ctx* c, int v) {
+  DevParams q = c->p;
+  q.Vrow = c->Vrow[v];
+  q.Vcol = c->Vcol[v];
+  return q;
+}
+
 // One round of Algorithm 1: K local steps (each: `inner` V/S alternations,
 // then the U step) and the consensus mean at the last one.
 rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
   const DevParams& p = c->p;
   hipStream_t st = c->stream;
-  const double eta = eta_at(c);
   const int64_t ustride = (int64_t)p.RP * p.MP;
   const int64_t gstride = (int64_t)p.RP * p.RP;
   const float* Ucons = c->U[c->cur];
+  if (c->recompute) {
+    // K = 1, one alternation: S of the previous round is rebuilt inside the
+    // V-pass from (U^(t-1), V^(t)) and never stored.
+    const int mode = c->rounds == 0 ? kSZero : kSRecompute;
+    const int vn = c->vcur ^ 1;
+    const DevParams q = with_v(c, vn);
+    RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
+                launch_vpass(q, mode, Ucons, 0, c->U[c->cur ^ 1], c->Vrow[c->vcur], c->Ginv, 0, st),
+                "V-pass launch");
+    if (p.u_mode == RPCA_U_CLOSED)
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(q, st), "client factor launch");
+    RPCA_LAUNCH(c, prof, RPCA_PHASE_SPASS, launch_spass(q, Ucons, 0, nullptr, 0, 0, 0, p.E, st), "S-pass launch");
+    RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE, launch_uupdate(q, c->U[c->cur ^ 1], 0, Ucons, 1, st),
+                "U update launch");
+    RPCA_LAUNCH(c, prof, RPCA_PHASE_FINALIZE, launch_finalize(q, c->Ginv, 0, 0, 1, st), "finalize launch");
+    c->vcur = vn;
+    c->cur ^= 1;
+    c->rounds += 1;
+    return RPCA_OK;
+  }
   for (int k = 0; k < p.K; ++k) {
     const float* Uin = k == 0 ? Ucons : c->Uc[(k - 1) & 1];
     const int64_t us = k == 0 ? 0 : ustride;
     const double* Gin = k == 0 ? c->Ginv : c->Ginv + gstride;
     const int64_t gs = k == 0 ? 0 : gstride;
-    for (int q = 0; q < c->inner; ++q) {
-      RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS, launch_vpass(p, Uin, us, Gin, gs, st), "V-pass launch");
-      RPCA_LAUNCH(c, prof, RPCA_PHASE_SPASS, launch_spass(p, Uin, us, st), "S-pass launch");
+    for (int qi = 0; qi < c->inner; ++qi) {
+      const int vn = c->vcur ^ 1;
+      const DevParams q = with_v(c, vn);
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
+                  launch_vpass(q, kSStored, Uin, us, nullptr, nullptr, Gin, gs, st), "V-pass launch");
+      c->vcur = vn;
+      if (p.u_mode == RPCA_U_CLOSED && qi == c->inner - 1)
+        RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(q, st), "client factor launch");
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_SPASS, launch_spass(q, Uin, us, p.S, p.lds, 0, 0, p.E, st), "S-pass launch");
     }
-    if (p.u_mode == RPCA_U_CLOSED)
-      RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(p, st), "client factor launch");
     if (k == p.K - 1) {
-      RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE,
-                  launch_uupdate(p, Uin, us, c->U[c->cur ^ 1], 0, Ucons, 1, eta, st), "U update launch");
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE, launch_uupdate(p, c->U[c->cur ^ 1], 0, Ucons, 1, st),
+                  "U update launch");
       RPCA_LAUNCH(c, prof, RPCA_PHASE_FINALIZE, launch_finalize(p, c->Ginv, 0, 0, 1, st), "finalize launch");
     } else {
-      RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE,
-                  launch_uupdate(p, Uin, us, c->Uc[k & 1], ustride, nullptr, 0, eta, st), "U update launch");
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE, launch_uupdate(p, c->Uc[k & 1], ustride, nullptr, 0, st),
+                  "U update launch");
       RPCA_LAUNCH(c, prof, RPCA_PHASE_FINALIZE, launch_finalize(p, c->Ginv + gstride, gstride, 1, 0, st),
                   "finalize launch");
     }
@@ -239,7 +289,7 @@ rpca_status guard(rpca_ctx* c) {
 // ||U V^T - X2 Y2^T||_F^2 and ||X2 Y2^T||_F^2 into c->dout (device).
 rpca_status enqueue_distance(rpca_ctx* c, const float* X2, const float* Y2, int rp2) {
   RPCA_HIP(c,
-           launch_factor_distance(c->p, c->U[c->cur], c->p.Vcol, c->p.RP, X2, Y2, rp2, c->dpart,
+           launch_factor_distance(c->p, c->U[c->cur], c->Vcol[c->vcur], c->p.RP, X2, Y2, rp2, c->dpart,
                                   c->dpart2, c->dout, c->stream),
            "factor distance launch");
   return RPCA_OK;
@@ -291,6 +341,9 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.nrb = L.nrb;
   p.nub = L.nub;
   p.ngroups = L.ngroups;
+  p.ng64 = L.ng64;
+  p.vsplit = L.vsplit;
+  p.vsplit_rows = L.vsplit_rows;
   p.u_mode = prm->u_mode;
   p.eta_sched = prm->eta_sched;
   p.lam = (float)prm->lambda;
@@ -298,9 +351,16 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.eta0 = prm->eta0;
   p.clients = reinterpret_cast<const ClientDev*>(ws + L.clients);
   p.vgroups = reinterpret_cast<const VGroup*>(ws + L.vgroups);
-  p.S = reinterpret_cast<float*>(ws + L.S);
-  p.Vrow = reinterpret_cast<float*>(ws + L.Vrow);
-  p.Vcol = reinterpret_cast<float*>(ws + L.Vcol);
+  p.vg64 = reinterpret_cast<const VGroup*>(ws + L.vg64);
+  p.S = L.recompute ? nullptr : reinterpret_cast<float*>(ws + L.S);
+  c->recompute = L.recompute;
+  c->Vrow[0] = reinterpret_cast<float*>(ws + L.Vrow0);
+  c->Vrow[1] = reinterpret_cast<float*>(ws + L.Vrow1);
+  c->Vcol[0] = reinterpret_cast<float*>(ws + L.Vcol0);
+  c->Vcol[1] = reinterpret_cast<float*>(ws + L.Vcol1);
+  p.Vrow = c->Vrow[0];
+  p.Vcol = c->Vcol[0];
+  p.Wpart = reinterpret_cast<float*>(ws + L.Wpart);
   p.P = reinterpret_cast<float*>(ws + L.P);
   p.gv_part = reinterpret_cast<double*>(ws + L.gv);
   p.Afac = reinterpret_cast<double*>(ws + L.Af);
@@ -335,6 +395,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
     cd.M = M_blocks[i];
     cd.ldm = ldm[i];
     cd.s_off = L.lds * col;
+    cd.col0 = col;
     cd.n = ni;
     cd.vrow0 = (int32_t)vrow;
     cd.g0 = g;
@@ -343,10 +404,12 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
       ++g;
     }
     cd.g1 = g;
+    for (int32_t j0 = 0; j0 < ni; j0 += kVStreamCols)
+      c->vg64.push_back(VGroup{i, j0, ni - j0 < kVStreamCols ? ni - j0 : kVStreamCols, 0});
     cd.c = prm->rho * (double)ni / (double)L.n;
     c->col_off[i] = col;
     col += ni;
-    vrow += round_up(ni, kVCols);
+    vrow += round_up(ni, kVPad);
   }
   c->col_off[prm->E] = col;
 
@@ -357,6 +420,9 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + L.vgroups, c->vgroups.data(), c->vgroups.size() * sizeof(VGroup),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.vg64, c->vg64.data(), c->vg64.size() * sizeof(VGroup),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = launch_copy_in_U(p, U0, ldu, c->U[0], st);
   if (e == hipSuccess) e = launch_gram_init(p, c->U[0], st);
@@ -437,7 +503,7 @@ rpca_status rpca_solve(rpca_ctx* c, int32_t max_rounds, double tol, int32_t chec
     if (!c->have_target) {
       RPCA_HIP(c, hipMemcpyAsync(c->Uprev, c->U[c->cur], ubytes, hipMemcpyDeviceToDevice, c->stream),
                "copy U");
-      RPCA_HIP(c, hipMemcpyAsync(c->Vprev, c->p.Vcol, vbytes, hipMemcpyDeviceToDevice, c->stream),
+      RPCA_HIP(c, hipMemcpyAsync(c->Vprev, c->Vcol[c->vcur], vbytes, hipMemcpyDeviceToDevice, c->stream),
                "copy V");
       c->have_prev = true;
     }
@@ -470,10 +536,31 @@ rpca_status rpca_get_LS(rpca_ctx* c, int32_t client, float* L, int64_t ldl, floa
   if (client < -1 || client >= c->p.E) return fail(c, RPCA_EINVAL, "client out of range");
   if ((L && ldl < c->p.m) || (S && lds < c->p.m)) return fail(c, RPCA_EINVAL, "leading dimension < m");
   const int b = client < 0 ? 0 : client, e = client < 0 ? c->p.E : client + 1;
-  RPCA_HIP(c,
-           launch_materialize(c->p, c->clients.data(), c->col_off.data(), c->U[c->cur], b, e, L,
-                              ldl, S, lds, c->stream),
-           "materialize launch");
+  const DevParams q = with_v(c, c->vcur);
+  const bool emit_s = S && c->recompute;
+  if (L || (S && !c->recompute))
+    RPCA_HIP(c,
+             launch_materialize(q, c->clients.data(), c->col_off.data(), c->U[c->cur], b, e, L,
+                                ldl, c->recompute ? nullptr : S, lds, c->stream),
+             "materialize launch");
+  if (emit_s) {
+    if (c->rounds == 0) {
+      // No round has run: S^(0) = 0.
+      for (int i = b; i < e; ++i)
+        RPCA_HIP(c,
+                 hipMemset2DAsync(S + (c->col_off[i] - c->col_off[b]) * lds, lds * sizeof(float), 0,
+                                  c->p.m * sizeof(float), c->clients[i].n, c->stream),
+                 "zero S");
+    } else {
+      // S of the last round, soft(M_i - U^(T-1) V_i^T), rebuilt by the S-pass
+      // tile code itself so that it is bitwise the S the round used.
+      // The kernel indexes S by global column; shift the base so that client
+      // b's first column lands at S. Only clients [b, e) are launched.
+      float* base = S - c->col_off[b] * lds;
+      RPCA_HIP(c, launch_spass(q, c->U[c->cur ^ 1], 0, base, lds, 1, b, e - b, c->stream),
+               "S emit launch");
+    }
+  }
   return RPCA_OK;
 }
 
@@ -481,7 +568,7 @@ rpca_status rpca_get_factors(rpca_ctx* c, float* U, int64_t ldu, float* V, int64
   if (rpca_status s = guard(c)) return s;
   if ((U && ldu < c->p.m) || (V && ldv < c->p.n)) return fail(c, RPCA_EINVAL, "leading dimension too small");
   RPCA_HIP(c,
-           launch_get_factors(c->p, c->clients.data(), c->col_off.data(), c->U[c->cur], U, ldu, V,
+           launch_get_factors(with_v(c, c->vcur), c->clients.data(), c->col_off.data(), c->U[c->cur], U, ldu, V,
                               ldv, c->stream),
            "factor copy launch");
   return RPCA_OK;

@@ -8,10 +8,11 @@ namespace rpca {
 
 constexpr int kMaxRank = 64;     // largest supported factor rank r
 constexpr int kHist = 4096;      // per-round statistics kept in a ring
-constexpr int kVCols = 32;       // columns per V-pass work-group
-constexpr int kVWaves = 8;       // waves per V-pass work-group (split over rows)
+constexpr int kVCols = 32;       // columns per V-finalize work-group
+constexpr int kVPad = 64;        // client V blocks are padded to multiples of 64 rows
+constexpr int kVStreamCols = 64; // columns per V-pass streaming work-group (4 waves x 16)
 constexpr int kSRows = 128;      // rows per S-pass work-group (4 waves x 32 rows)
-constexpr int kURows = 32;       // rows per U-update work-group
+constexpr int kURows = 64;       // rows per U-update work-group
 
 // One client (Section 2.1): its borrowed block M_i and where its private
 // state lives in the workspace.
@@ -19,13 +20,15 @@ struct ClientDev {
   const float* M;   // column-major m x n_i, leading dimension ldm
   int64_t ldm;
   int64_t s_off;    // first float of S_i in the S buffer (leading dimension lds)
+  int64_t col0;     // first global column of the client
   int32_t n;        // n_i
-  int32_t vrow0;    // first row of V_i in the padded V buffers (multiple of 32)
+  int32_t vrow0;    // first row of V_i in the padded V buffers (multiple of 64)
   int32_t g0, g1;   // V-pass work-groups [g0, g1) that cover this client
   double c;         // rho * n_i / n
 };
 
-// A V-pass work unit: up to 32 consecutive columns of one client.
+// A V-pass work unit: up to 32 (finalize) or 64 (streaming) consecutive
+// columns of one client.
 struct VGroup {
   int32_t client, j0, ncols, pad;
 };
@@ -48,16 +51,21 @@ struct DevParams {
   int64_t lds;           // leading dimension of S (= m rounded up to 4)
   int32_t nrb;           // S-pass row blocks (MP / kSRows)
   int32_t nub;           // U-update row blocks (MP / kURows)
-  int32_t ngroups;       // V-pass work-groups
+  int32_t ngroups;       // V-finalize work-groups (32 columns each)
+  int32_t ng64;          // V-pass streaming column groups (64 columns each)
+  int32_t vsplit;        // V-pass row splits
+  int32_t vsplit_rows;   // rows per V-pass row split (multiple of 16)
   int32_t u_mode, eta_sched;
   float lam;
   double rho, eta0;
   const ClientDev* clients;
   const VGroup* vgroups;
+  const VGroup* vg64;
   float* S;              // all clients' S_i
-  float* Vrow;           // V, row-major NVP x RP
-  float* Vcol;           // V, column-major NVP x RP (leading dimension NVP)
-  float* P;              // per-client Lambda_i V_i, column-major MP x RP each
+  float* Vrow;           // V written/read by this launch, row-major NVP x RP
+  float* Vcol;           // the same V, column-major NVP x RP (leading dimension NVP)
+  float* Wpart;          // V-pass partial W per row split, [vsplit][NVP][RP]
+  float* P;              // per-client U-step term T_i (from Lambda_i V_i), column-major MP x RP
   double* gv_part;       // per V-group partial V^T V, RP x RP
   double* Afac;          // per-client (V_i^T V_i + c_i I)^{-1}, RP x RP
   double* Bfac;          // per-client V_i^T V_i (V_i^T V_i + c_i I)^{-1}
@@ -71,13 +79,21 @@ struct DevParams {
 
 // Launch helpers (kernels live in rpca_kernels.hip).
 constexpr int kDistBlocks = 64;  // work-groups per side of the factor-distance kernel
-hipError_t launch_vpass(const DevParams& p, const float* U, int64_t u_stride, const double* Ginv,
+// S source for the V-pass: zero, the stored S buffer, or recomputed from the
+// previous round's factors.
+enum VMode { kSZero = 0, kSStored = 1, kSRecompute = 2 };
+hipError_t launch_vpass(const DevParams& p, int mode, const float* U, int64_t u_stride,
+                        const float* Uold, const float* Vrow_old, const double* Ginv,
                         int64_t g_stride, hipStream_t st);
 hipError_t launch_client_factor(const DevParams& p, hipStream_t st);
-hipError_t launch_spass(const DevParams& p, const float* U, int64_t u_stride, hipStream_t st);
-hipError_t launch_uupdate(const DevParams& p, const float* Uin, int64_t uin_stride, float* Uout,
-                          int64_t uout_stride, const float* Uprev_cons, int final_step,
-                          double eta, hipStream_t st);
+// S-pass over clients [client_base, client_base + client_count). Sout/lds_out:
+// column-major buffer S is written to, indexed by global column (NULL: S is
+// not stored); emit_only: write S only (no U-step term, no statistics).
+hipError_t launch_spass(const DevParams& p, const float* U, int64_t u_stride, float* Sout,
+                        int64_t lds_out, int emit_only, int client_base, int client_count,
+                        hipStream_t st);
+hipError_t launch_uupdate(const DevParams& p, float* Uout, int64_t uout_stride,
+                          const float* Uprev_cons, int final_step, hipStream_t st);
 hipError_t launch_finalize(const DevParams& p, double* Ginv, int64_t g_stride, int per_client,
                            int record, hipStream_t st);
 hipError_t launch_gram_init(const DevParams& p, const float* U, hipStream_t st);

@@ -36,133 +36,187 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// In-place inverse of an r x r SPD matrix A (row stride ld, in LDS) through
-// its Cholesky factor: A = L L^T, A^{-1} = L^{-T} L^{-1}. X is r x ld scratch.
-// A non-positive pivot yields NaN, which the round statistics then expose.
-__device__ void spd_inverse(double* A, double* X, int r, int ld) {
+// In-place inverse of an r x r SPD matrix A (row stride ld, in LDS) by a
+// Gauss-Jordan sweep without pivoting: the k-th pivot is a diagonal entry of a
+// Schur complement of an SPD matrix, hence positive, and every step updates all
+// r^2 entries in parallel (no serial triangular solves). A pivot that is not
+// positive (non-SPD or NaN input) turns the result into NaN, which the round
+// statistics then expose.
+__device__ void spd_inverse(double* A, int r, int ld) {
+  __shared__ double colk[kMaxRank], rowk[kMaxRank];
+  __shared__ double pinv_sh;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int k = 0; k < r; ++k) {
+    for (int i = tid; i < r; i += nt) {
+      colk[i] = A[i * ld + k];
+      rowk[i] = A[k * ld + i];
+    }
     if (tid == 0) {
-      const double d = A[k * ld + k];
-      A[k * ld + k] = d > 0.0 ? sqrt(d) : NAN;
+      const double pv = A[k * ld + k];
+      pinv_sh = pv > 0.0 ? 1.0 / pv : NAN;
     }
     __syncthreads();
-    const double dk = A[k * ld + k];
-    for (int i = k + 1 + tid; i < r; i += nt) A[i * ld + k] /= dk;
-    __syncthreads();
-    const int rem = r - k - 1;
-    for (int e = tid; e < rem * rem; e += nt) {
-      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      if (j <= i) A[i * ld + j] -= A[i * ld + k] * A[j * ld + k];
+    const double pinv = pinv_sh;
+    for (int e = tid; e < r * r; e += nt) {
+      const int i = e / r, j = e % r;
+      double v;
+      if (i == k)
+        v = (j == k) ? pinv : rowk[j] * pinv;
+      else if (j == k)
+        v = -colk[i] * pinv;
+      else
+        v = A[i * ld + j] - colk[i] * rowk[j] * pinv;
+      A[i * ld + j] = v;
     }
     __syncthreads();
   }
-  for (int c = tid; c < r; c += nt) {  // column c of L^{-1}
-    for (int i = 0; i < r; ++i) {
-      if (i < c) {
-        X[i * ld + c] = 0.0;
-        continue;
-      }
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= A[i * ld + k] * X[k * ld + c];
-      X[i * ld + c] = s / A[i * ld + i];
-    }
+}
+
+__device__ __forceinline__ double eta_of_round(const DevParams& p, int64_t t) {
+  if (p.u_mode != 0) return 0.0;
+  return p.eta_sched == 1 ? p.eta0 / sqrt((double)t + 1.0) : p.eta0;
+}
+
+// Sum of count strided FP64 values, four independent chains so that the loads
+// of a long partial list are in flight together.
+__device__ __forceinline__ double sum_strided(const double* __restrict__ x, int count,
+                                              int64_t stride) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int k = 0;
+#pragma unroll 2
+  for (; k + 4 <= count; k += 4) {
+    s0 += x[(int64_t)k * stride];
+    s1 += x[(int64_t)(k + 1) * stride];
+    s2 += x[(int64_t)(k + 2) * stride];
+    s3 += x[(int64_t)(k + 3) * stride];
   }
-  __syncthreads();
-  for (int e = tid; e < r * r; e += nt) {
-    const int pq = e / r, qq = e % r;
-    const int k0 = pq > qq ? pq : qq;
-    double s = 0.0;
-    for (int k = k0; k < r; ++k) s += X[k * ld + pq] * X[k * ld + qq];
-    A[pq * ld + qq] = s;
-  }
-  __syncthreads();
+  for (; k < count; ++k) s0 += x[(int64_t)k * stride];
+  return (s0 + s1) + (s2 + s3);
 }
 
 // ---------------------------------------------------------------------------
-// V-pass: one work-group per (client, 32 columns); 8 waves split the rows.
-// Wave tile: 16 rows x 16 columns of D = M - S per MFMA step. Lane l holds
-// rows 4*(l/16)..+3 of column l%16 (one float4 along the contiguous rows), so
-// element s of that float4 is the A operand of step s; U^T supplies the B
-// operand as a float4 of U's column-major layout. Output W[col][c].
+// V-pass, streaming part: W = (M_i - S_i)^T U_i partial sums over row splits.
+// grid = (64-column groups, row splits); 4 waves, wave w owns the 16 columns
+// 16w..16w+15 of the group and all four waves walk the same rows, so the U
+// operands they load are shared through L1.
+// Lane l holds rows 4*(l/16)..+3 of column l%16 (one float4 along the
+// contiguous rows of the column-major block): element s of that float4 is the
+// A operand of MFMA step s, and U supplies the B operand as a float4 of its
+// column-major layout. Accumulator: W[col 4*(l/16)+v][rank 16*ct + l%16].
+// MODE kSRecompute rebuilds S = soft(M - Uo Vo^T) of the previous round on the
+// fly: its MFMA puts Uo rows on the A side and Vo^T on the B side, so the
+// 16x16 residual tile comes out in exactly the float4 layout of M.
 // ---------------------------------------------------------------------------
-template <int RT>
-__global__ __launch_bounds__(512) void k_vpass(DevParams p, const float* __restrict__ Ubase,
-                                               int64_t u_stride, const double* __restrict__ Gbase,
-                                               int64_t g_stride) {
-  constexpr int RP = 16 * RT;
-  __shared__ float red[kVWaves][kVCols][RP];
-  __shared__ double wd[kVCols][RP + 1];
-  const VGroup vg = p.vgroups[blockIdx.x];
+template <int RT, int MODE>
+__global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restrict__ Ubase,
+                                               int64_t u_stride, const float* __restrict__ Uold,
+                                               const float* __restrict__ Vrow_old) {
+  constexpr int RP = 16 * RT, NSMAX = 4 * RT;
+  const VGroup vg = p.vg64[blockIdx.x];
   const ClientDev cl = p.clients[vg.client];
   const float* __restrict__ U = Ubase + (int64_t)vg.client * u_stride;
-  const double* __restrict__ Gi = Gbase + (int64_t)vg.client * g_stride;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lg = lane >> 4;
-  const float* __restrict__ Sblk = p.S + cl.s_off;
+  const int j0 = vg.j0 + 16 * w;  // client-local first column of this wave's tile
+  const int col = j0 + li;
+  const bool colok = col < cl.n;
+  const int ns = p.NS;
+  const float lam = p.lam;
 
-  f4 acc[2][RT];
+  float vb[NSMAX];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int ct = 0; ct < RT; ++ct) acc[t][ct] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int s = 0; s < NSMAX; ++s)
+    vb[s] = (MODE == kSRecompute && s < ns)
+                ? Vrow_old[(int64_t)(cl.vrow0 + col) * RP + lg * ns + s]
+                : 0.f;
 
-  const int nchunks = (p.m + 15) >> 4;
-  for (int ch = w; ch < nchunks; ch += kVWaves) {
-    const int row = (ch << 4) + 4 * lg;
-    f4 d[2];
+  const int rbeg = blockIdx.y * p.vsplit_rows;
+  const int rend = min(p.m, rbeg + p.vsplit_rows);
+  f4 acc[RT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int col = vg.j0 + 16 * t + li;
-      f4 dv = {0.f, 0.f, 0.f, 0.f};
-      if (col < cl.n && row < p.m) {
-        const f4 mv = *reinterpret_cast<const f4*>(cl.M + (int64_t)col * cl.ldm + row);
-        const f4 sv = *reinterpret_cast<const f4*>(Sblk + (int64_t)col * p.lds + row);
-        dv = mv - sv;
-        if (row + 4 > p.m) {
+  for (int ct = 0; ct < RT; ++ct) acc[ct] = f4{0.f, 0.f, 0.f, 0.f};
+  const float* __restrict__ Mc = cl.M + (int64_t)(colok ? col : 0) * cl.ldm;
+  const float* __restrict__ Sc = p.S + cl.s_off + (int64_t)(colok ? col : 0) * p.lds;
+
+  for (int row0 = rbeg; row0 < rend; row0 += 16) {
+    const int row = row0 + 4 * lg;
+    f4 mv = {0.f, 0.f, 0.f, 0.f}, sv = {0.f, 0.f, 0.f, 0.f};
+    if (colok && row < p.m) {
+      mv = *reinterpret_cast<const f4*>(Mc + row);
+      if (MODE == kSStored) sv = *reinterpret_cast<const f4*>(Sc + row);
+      if (row + 4 > p.m) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (row + e >= p.m) dv[e] = 0.f;
-        }
+        for (int e = 0; e < 4; ++e)
+          if (row + e >= p.m) mv[e] = sv[e] = 0.f;
       }
-      d[t] = dv;
     }
     f4 u[RT];
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct)
       u[ct] = *reinterpret_cast<const f4*>(U + (int64_t)(16 * ct + li) * p.MP + row);
+    f4 d;
+    if (MODE == kSRecompute) {
+      f4 a1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < NSMAX; ++s)
+        if (s < ns) a1 = mfma4(Uold[(int64_t)(lg * ns + s) * p.MP + row0 + li], vb[s], a1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float R = mv[e] - a1[e];
+        const float Sv = R - fminf(fmaxf(R, -lam), lam);
+        d[e] = mv[e] - Sv;
+      }
+    } else {
+      d = mv - sv;
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int ct = 0; ct < RT; ++ct) acc[t][ct] = mfma4(d[t][s], u[ct][s], acc[t][ct]);
+      for (int ct = 0; ct < RT; ++ct) acc[ct] = mfma4(d[s], u[ct][s], acc[ct]);
   }
+  float* __restrict__ wp = p.Wpart + ((int64_t)blockIdx.y * p.NVP + cl.vrow0 + j0) * RP;
+#pragma unroll
+  for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) wp[(4 * lg + v) * RP + 16 * ct + li] = acc[ct][v];
+}
 
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int ct = 0; ct < RT; ++ct)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) red[w][16 * t + 4 * lg + v][16 * ct + li] = acc[t][ct][v];
-  __syncthreads();
+// ---------------------------------------------------------------------------
+// V-pass, finalize: one work-group per 32 columns. W = sum of the row-split
+// partials (fixed order, FP64), V = W (U^T U + rho I)^{-1} (eq. "condition1"),
+// rounded to FP32 once and written in both layouts, plus the partial V^T V of
+// these columns.
+// ---------------------------------------------------------------------------
+template <int RT>
+__global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __restrict__ Gbase,
+                                                int64_t g_stride) {
+  constexpr int RP = 16 * RT;
+  __shared__ double wd[kVCols][RP + 1];
+  __shared__ double gl[RP * RP];
+  const VGroup vg = p.vgroups[blockIdx.x];
+  const ClientDev cl = p.clients[vg.client];
+  const double* __restrict__ Gi = Gbase + (int64_t)vg.client * g_stride;
+  const int tid = threadIdx.x;
+  const int vrow = cl.vrow0 + vg.j0;
+  const int64_t split_stride = (int64_t)p.NVP * RP;
   for (int e = tid; e < kVCols * RP; e += blockDim.x) {
     const int j = e / RP, c = e % RP;
-    double s = 0.0;
-#pragma unroll
-    for (int w2 = 0; w2 < kVWaves; ++w2) s += (double)red[w2][j][c];
-    wd[j][c] = s;
+    double s0 = 0.0, s1 = 0.0;
+    const float* src = p.Wpart + (int64_t)(vrow + j) * RP + c;
+    int q = 0;
+    for (; q + 2 <= p.vsplit; q += 2) {
+      s0 += (double)src[(int64_t)q * split_stride];
+      s1 += (double)src[(int64_t)(q + 1) * split_stride];
+    }
+    if (q < p.vsplit) s0 += (double)src[(int64_t)q * split_stride];
+    wd[j][c] = s0 + s1;
   }
-  __syncthreads();
-  double* gl = reinterpret_cast<double*>(&red[0][0][0]);  // RP*RP doubles fit
   for (int e = tid; e < RP * RP; e += blockDim.x) gl[e] = Gi[e];
   __syncthreads();
-
-  // V[j][c] = sum_k W[j][k] Ginv[k][c], rounded to FP32 once.
-  constexpr int kPer = (kVCols * RP + 511) / 512;
+  constexpr int kPer = (kVCols * RP + 255) / 256;
   float vres[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int e = tid + q * 512;
+    const int e = tid + q * 256;
     float vf = 0.f;
     if (e < kVCols * RP) {
       const int j = e / RP, c = e % RP;
@@ -175,10 +229,9 @@ __global__ __launch_bounds__(512) void k_vpass(DevParams p, const float* __restr
     vres[q] = vf;
   }
   __syncthreads();
-  const int vrow = cl.vrow0 + vg.j0;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int e = tid + q * 512;
+    const int e = tid + q * 256;
     if (e < kVCols * RP) {
       const int j = e / RP, c = e % RP;
       wd[j][c] = (double)vres[q];
@@ -202,23 +255,22 @@ __global__ __launch_bounds__(512) void k_vpass(DevParams p, const float* __restr
 // One work-group per client; FP64 throughout.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_client_factor(DevParams p) {
-  // Static LDS (96 KiB at r = 64): gfx950 work-groups may hold up to 160 KiB.
-  __shared__ double A[kMaxRank * kMaxRank], X[kMaxRank * kMaxRank], G[kMaxRank * kMaxRank];
+  __shared__ double A[kMaxRank * kMaxRank], G[kMaxRank * kMaxRank];
   const int r = p.r, RP = p.RP;
+  const int64_t RR = (int64_t)RP * RP;
   const ClientDev cl = p.clients[blockIdx.x];
   const int tid = threadIdx.x;
   for (int e = tid; e < r * r; e += blockDim.x) {
     const int a = e / r, b = e % r;
-    double s = 0.0;
-    for (int g = cl.g0; g < cl.g1; ++g) s += p.gv_part[(int64_t)g * RP * RP + a * RP + b];
+    const double s = sum_strided(p.gv_part + (int64_t)cl.g0 * RR + a * RP + b, cl.g1 - cl.g0, RR);
     G[e] = s;
     A[e] = s + (a == b ? cl.c : 0.0);
   }
   __syncthreads();
-  spd_inverse(A, X, r, r);
-  double* Af = p.Afac + (int64_t)blockIdx.x * RP * RP;
-  double* Bf = p.Bfac + (int64_t)blockIdx.x * RP * RP;
-  for (int e = tid; e < RP * RP; e += blockDim.x) {
+  spd_inverse(A, r, r);
+  double* Af = p.Afac + (int64_t)blockIdx.x * RR;
+  double* Bf = p.Bfac + (int64_t)blockIdx.x * RR;
+  for (int e = tid; e < RR; e += blockDim.x) {
     const int a = e / RP, b = e % RP;
     double av = 0.0, bv = 0.0;
     if (a < r && b < r) {
@@ -244,9 +296,10 @@ __global__ __launch_bounds__(256) void k_client_factor(DevParams p) {
 // ---------------------------------------------------------------------------
 template <int RT>
 __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restrict__ Ubase,
-                                               int64_t u_stride) {
+                                               int64_t u_stride, float* __restrict__ Sout,
+                                               int64_t lds_out, int emit_only, int client_base) {
   constexpr int RP = 16 * RT, NSMAX = 4 * RT;
-  const int b = blockIdx.x, ci = blockIdx.y;
+  const int b = blockIdx.x, ci = client_base + (int)blockIdx.y;
   const ClientDev cl = p.clients[ci];
   const float* __restrict__ U = Ubase + (int64_t)ci * u_stride;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lg = lane >> 4;
@@ -269,7 +322,7 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
 
   double sl2 = 0.0, sl1 = 0.0, snz = 0.0;
   const float lam = p.lam;
-  float* __restrict__ Sblk = p.S + cl.s_off;
+  float* __restrict__ Sblk = Sout ? Sout + cl.col0 * lds_out : nullptr;
   const float* __restrict__ Mb = cl.M;
 
   for (int j0 = 0; j0 < cl.n; j0 += 16) {
@@ -304,7 +357,7 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
         const float R = mv[v] - a1[v];
         const float L = fminf(fmaxf(R, -lam), lam);
         const float Sv = R - L;
-        if (rok && col < cl.n) Sblk[(int64_t)col * p.lds + row] = Sv;
+        if (Sblk && rok && col < cl.n) Sblk[(int64_t)col * lds_out + row] = Sv;
         lamv[v] = L;
         l2 += L * L;
         l1 += fabsf(Sv);
@@ -320,13 +373,55 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
     }
   }
 
-  float* Pi = p.P + (int64_t)ci * RP * p.MP;
+  if (emit_only) return;
+  // Epilogue: the client's U-step term for these 128 rows (Lemma 2 proof for
+  // the gradient, argmin_U L_i for the closed form), from P = Lambda V_i:
+  //   GRAD   T = U_i - eta (c_i U_i - P)
+  //   CLOSED T = P A_i + U_i B_i,  A_i = (V_i^T V_i + c_i I)^{-1}, B_i = V_i^T V_i A_i
+  // in FP64, stored FP32 into the client's slot of p.P.
+  __shared__ float ptile[kSRows][RP + 1];
+  __shared__ float utile[kSRows][RP + 1];
+  __shared__ double fab[2][RP * RP];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct)
-      *reinterpret_cast<f4*>(Pi + (int64_t)(16 * ct + li) * p.MP + arow0 + 16 * rt + 4 * lg) =
-          accp[rt][ct];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ptile[w * 32 + 16 * rt + 4 * lg + v][16 * ct + li] = accp[rt][ct][v];
+  const int row0 = b * kSRows;
+  for (int e = tid; e < kSRows * RP; e += blockDim.x) {
+    const int rl = e % kSRows, c = e / kSRows;
+    utile[rl][c] = U[(int64_t)c * p.MP + row0 + rl];
+  }
+  const bool closed = p.u_mode != 0;
+  if (closed) {
+    const double* __restrict__ Af = p.Afac + (int64_t)ci * RP * RP;
+    const double* __restrict__ Bf = p.Bfac + (int64_t)ci * RP * RP;
+    for (int e = tid; e < RP * RP; e += blockDim.x) {
+      fab[0][e] = Af[e];
+      fab[1][e] = Bf[e];
+    }
+  }
+  __syncthreads();
+  float* Ti = p.P + (int64_t)ci * RP * p.MP;
+  const double eta = eta_of_round(p, p.dstate->t);
+  const double cc = cl.c;
+  for (int e = tid; e < kSRows * RP; e += blockDim.x) {
+    const int rl = e % kSRows, c = e / kSRows;
+    double t;
+    if (closed) {
+      t = 0.0;
+      if (c < p.r) {
+#pragma unroll 4
+        for (int k = 0; k < p.r; ++k)
+          t += (double)ptile[rl][k] * fab[0][k * RP + c] + (double)utile[rl][k] * fab[1][k * RP + c];
+      }
+    } else {
+      const double u = utile[rl][c];
+      t = u - eta * (cc * u - (double)ptile[rl][c]);
+    }
+    Ti[(int64_t)c * p.MP + row0 + rl] = (float)t;
+  }
 
   __shared__ double sred[4][3];
   sl2 = wave_sum(sl2);
@@ -347,85 +442,63 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
   }
 }
 
-// Partial Gram of 32 rows of a column-major U block (values in LDS as FP64).
-__device__ void gram_rows_partial(const double (*ul)[kMaxRank + 1], int RP, double* out) {
+// Partial Gram of kURows rows held in LDS (FP64, row stride kMaxRank).
+__device__ void gram_rows_partial(const double* ul, int RP, double* out) {
   for (int e = threadIdx.x; e < RP * RP; e += blockDim.x) {
     const int a = e / RP, b = e % RP;
-    double s = 0.0;
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll 8
-    for (int j = 0; j < kURows; ++j) s += ul[j][a] * ul[j][b];
-    out[e] = s;
+    for (int j = 0; j < kURows; j += 2) {
+      s0 += ul[j * kMaxRank + a] * ul[j * kMaxRank + b];
+      s1 += ul[(j + 1) * kMaxRank + a] * ul[(j + 1) * kMaxRank + b];
+    }
+    out[e] = s0 + s1;
   }
 }
 
 // ---------------------------------------------------------------------------
-// U update. grid = (row blocks of 32, final ? 1 : E). Thread (a = tid % 32,
-// cq = tid / 32) owns row a and rank columns cq, cq + 8, ...
-// final = 1: U^(t+1) = mean_i U_i^new (eq. "U_agg") into the consensus buffer,
-//            plus ||U^(t+1) - U^(t)||^2 partials; Gram slot 0.
-// final = 0: per-client U_i^new (K > 1 intermediate local steps); Gram slot i.
+// U update. grid = (MP / 64, final ? 1 : E), 256 threads; thread (a = tid % 64,
+// cq = tid / 64) owns row a and rank columns cq, cq + 4, ... The S-pass left
+// each client's U-step term T_i in p.P.
+// final = 1: U^(t+1) = mean_i T_i (eq. "U_agg") into the consensus buffer,
+//            ||U^(t+1) - U^(t)||^2 partials and Gram slot 0;
+// final = 0: U_i = T_i (intermediate local steps), Gram slot i.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_uupdate(DevParams p, const float* __restrict__ Uin,
-                                                 int64_t uin_stride, float* __restrict__ Uout,
+template <int RT>
+__global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict__ Uout,
                                                  int64_t uout_stride,
-                                                 const float* __restrict__ Uprev, int final_step,
-                                                 double eta) {
-  __shared__ double ul[kURows][kMaxRank + 1];
+                                                 const float* __restrict__ Uprev, int final_step) {
+  constexpr int RP = 16 * RT, NQ = RP / 4;
+  __shared__ double ul[kURows * kMaxRank];
   __shared__ double dred[4];
-  const int RP = p.RP, r = p.r, MP = p.MP;
-  const int tid = threadIdx.x, al = tid & 31, cq = tid >> 5;
+  const int MP = p.MP, r = p.r;
+  const int tid = threadIdx.x, al = tid & 63, cq = tid >> 6;
   const int a = blockIdx.x * kURows + al;
-  const int nq = RP / 8;
   const int i_first = final_step ? 0 : (int)blockIdx.y;
   const int i_last = final_step ? p.E : (int)blockIdx.y + 1;
-  double acc[8];
+  double acc[NQ];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
   for (int i = i_first; i < i_last; ++i) {
-    const float* __restrict__ Ui = Uin + (int64_t)i * uin_stride;
-    const float* __restrict__ Pi = p.P + (int64_t)i * RP * MP;
-    const double ci = p.clients[i].c;
-    if (p.u_mode == 0) {  // gradient step
+    const float* __restrict__ Ti = p.P + (int64_t)i * RP * MP + a;
+    float tv[NQ];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (q < nq) {
-          const int c = cq + 8 * q;
-          const double u = Ui[(int64_t)c * MP + a];
-          const double pv = Pi[(int64_t)c * MP + a];
-          acc[q] += u - eta * (ci * u - pv);
-        }
-      }
-    } else {  // closed form: P_i A_i + U_i B_i
-      const double* __restrict__ Af = p.Afac + (int64_t)i * RP * RP;
-      const double* __restrict__ Bf = p.Bfac + (int64_t)i * RP * RP;
-      for (int k = 0; k < r; ++k) {
-        const double pk = Pi[(int64_t)k * MP + a];
-        const double uk = Ui[(int64_t)k * MP + a];
+    for (int q = 0; q < NQ; ++q) tv[q] = Ti[(int64_t)(cq + 4 * q) * MP];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          if (q < nq) {
-            const int c = cq + 8 * q;
-            acc[q] += pk * Af[k * RP + c] + uk * Bf[k * RP + c];
-          }
-        }
-      }
-    }
+    for (int q = 0; q < NQ; ++q) acc[q] += (double)tv[q];
   }
   const double scale = final_step ? 1.0 / (double)p.E : 1.0;
   float* __restrict__ Uo = Uout + (final_step ? 0 : (int64_t)blockIdx.y * uout_stride);
   double dsq = 0.0;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    if (q < nq) {
-      const int c = cq + 8 * q;
-      const float v = (a < p.m && c < r) ? (float)(acc[q] * scale) : 0.f;
-      Uo[(int64_t)c * MP + a] = v;
-      ul[al][c] = (double)v;
-      if (final_step) {
-        const double d = (double)v - (double)Uprev[(int64_t)c * MP + a];
-        dsq += d * d;
-      }
+  for (int q = 0; q < NQ; ++q) {
+    const int c = cq + 4 * q;
+    const float v = (a < p.m && c < r) ? (float)(acc[q] * scale) : 0.f;
+    Uo[(int64_t)c * MP + a] = v;
+    ul[al * kMaxRank + c] = (double)v;
+    if (final_step) {
+      const double d = (double)v - (double)Uprev[(int64_t)c * MP + a];
+      dsq += d * d;
     }
   }
   dsq = wave_sum(dsq);
@@ -438,34 +511,60 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, const float* __res
 
 // Gram partials of the consensus U (start of the run).
 __global__ __launch_bounds__(256) void k_gram_init(DevParams p, const float* __restrict__ U) {
-  __shared__ double ul[kURows][kMaxRank + 1];
+  __shared__ double ul[kURows * kMaxRank];
   const int RP = p.RP;
   for (int e = threadIdx.x; e < kURows * RP; e += blockDim.x) {
     const int al = e % kURows, c = e / kURows;
-    ul[al][c] = (double)U[(int64_t)c * p.MP + blockIdx.x * kURows + al];
+    ul[al * kMaxRank + c] = (double)U[(int64_t)c * p.MP + blockIdx.x * kURows + al];
   }
   __syncthreads();
   gram_rows_partial(ul, RP, p.gram_part + (int64_t)blockIdx.x * RP * RP);
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: G = U^T U + rho I from the Gram partials, G^{-1} via FP64
-// Cholesky, and (record = 1) the round statistics. grid = per_client ? E : 1.
+// Finalize (1024 threads): G = U^T U + rho I from the Gram partials, G^{-1} by
+// the FP64 sweep, and (record = 1) the round statistics. grid = per_client ? E : 1.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(DevParams p, double* Ginv, int64_t g_stride,
-                                                  int per_client, int record) {
-  __shared__ double A[kMaxRank * kMaxRank], X[kMaxRank * kMaxRank];
-  const int r = p.r, RP = p.RP;
+__global__ __launch_bounds__(1024) void k_finalize(DevParams p, double* Ginv, int64_t g_stride,
+                                                   int per_client, int record) {
+  __shared__ double A[kMaxRank * kMaxRank];
+  __shared__ double red[16][5];
   __shared__ double tr_sh;
-  __shared__ double red[8][4];
+  const int r = p.r, RP = p.RP;
+  const int64_t RR = (int64_t)RP * RP;
   const int tid = threadIdx.x;
   const int gi = blockIdx.x;
-  const double* gp = p.gram_part + (int64_t)gi * p.nub * RP * RP;
+  const double* gp = p.gram_part + (int64_t)gi * p.nub * RR;
   for (int e = tid; e < r * r; e += blockDim.x) {
     const int a = e / r, b = e % r;
-    double s = 0.0;
-    for (int k = 0; k < p.nub; ++k) s += gp[(int64_t)k * RP * RP + a * RP + b];
-    A[e] = s;
+    A[e] = sum_strided(gp + a * RP + b, p.nub, RR);
+  }
+  // Round statistics (FP64, fixed order) while the Gram sums land.
+  double l2 = 0.0, l1 = 0.0, nz = 0.0, vsq = 0.0, du = 0.0;
+  if (record && !per_client) {
+    const int nsp = p.E * p.nrb;
+    for (int k = tid; k < nsp; k += blockDim.x) {
+      l2 += p.spart[(int64_t)k * 4 + 0];
+      l1 += p.spart[(int64_t)k * 4 + 1];
+      nz += p.spart[(int64_t)k * 4 + 2];
+    }
+    for (int k = tid; k < p.ngroups * r; k += blockDim.x) {
+      const int g = k / r, d = k % r;
+      vsq += p.gv_part[(int64_t)g * RR + d * RP + d];
+    }
+    for (int k = tid; k < p.nub; k += blockDim.x) du += p.upart[k];
+    l2 = wave_sum(l2);
+    l1 = wave_sum(l1);
+    nz = wave_sum(nz);
+    vsq = wave_sum(vsq);
+    du = wave_sum(du);
+    if ((tid & 63) == 0) {
+      red[tid >> 6][0] = l2;
+      red[tid >> 6][1] = l1;
+      red[tid >> 6][2] = nz;
+      red[tid >> 6][3] = vsq;
+      red[tid >> 6][4] = du;
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -476,9 +575,9 @@ __global__ __launch_bounds__(256) void k_finalize(DevParams p, double* Ginv, int
   __syncthreads();
   for (int k = tid; k < r; k += blockDim.x) A[k * r + k] += p.rho;
   __syncthreads();
-  spd_inverse(A, X, r, r);
+  spd_inverse(A, r, r);
   double* Gout = Ginv + (int64_t)gi * g_stride;
-  for (int e = tid; e < RP * RP; e += blockDim.x) {
+  for (int e = tid; e < RR; e += blockDim.x) {
     const int a = e / RP, b = e % RP;
     Gout[e] = (a < r && b < r) ? A[a * r + b] : 0.0;
   }
@@ -490,43 +589,11 @@ __global__ __launch_bounds__(256) void k_finalize(DevParams p, double* Ginv, int
     if (tid == 0) p.dstate->u_sq = tr_sh;
     return;
   }
-  // Round statistics (FP64, fixed summation order).
-  double l2 = 0.0, l1 = 0.0, nz = 0.0, vsq = 0.0, du = 0.0;
-  const int nsp = p.E * p.nrb;
-  for (int k = tid; k < nsp; k += blockDim.x) {
-    l2 += p.spart[(int64_t)k * 4 + 0];
-    l1 += p.spart[(int64_t)k * 4 + 1];
-    nz += p.spart[(int64_t)k * 4 + 2];
-  }
-  for (int k = tid; k < p.ngroups * r; k += blockDim.x) {
-    const int g = k / r, d = k % r;
-    vsq += p.gv_part[(int64_t)g * RP * RP + d * RP + d];
-  }
-  for (int k = tid; k < p.nub; k += blockDim.x) du += p.upart[k];
-  l2 = wave_sum(l2);
-  l1 = wave_sum(l1);
-  nz = wave_sum(nz);
-  vsq = wave_sum(vsq);
-  du = wave_sum(du);
-  const int w = tid >> 6;
-  if ((tid & 63) == 0) {
-    red[w][0] = l2;
-    red[w][1] = l1;
-    red[w][2] = nz;
-    red[w][3] = vsq;
-    red[w + 4][0] = du;
-  }
-  __syncthreads();
   if (tid == 0) {
     const int nw = blockDim.x >> 6;
     double s[5] = {0, 0, 0, 0, 0};
-    for (int k = 0; k < nw; ++k) {
-      s[0] += red[k][0];
-      s[1] += red[k][1];
-      s[2] += red[k][2];
-      s[3] += red[k][3];
-      s[4] += red[k + 4][0];
-    }
+    for (int k = 0; k < nw; ++k)
+      for (int q = 0; q < 5; ++q) s[q] += red[k][q];
     double ureg;
     if (p.K == 1) {
       ureg = 0.5 * p.rho * p.dstate->u_sq;
@@ -609,7 +676,7 @@ __global__ void k_pack_target_U(DevParams p, const float* __restrict__ Us, int64
 __global__ void k_pack_target_V(DevParams p, const float* __restrict__ Vs, int64_t ldvs, int rs,
                                 float* __restrict__ Vt, int RPT, int client, int64_t col0) {
   const ClientDev cl = p.clients[client];
-  const int span = (cl.n + kVCols - 1) / kVCols * kVCols;
+  const int span = (cl.n + kVPad - 1) / kVPad * kVPad;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)span * RPT) return;
   const int j = (int)(e % span), c = (int)(e / span);
@@ -695,17 +762,34 @@ __global__ void k_dist_final(const double* __restrict__ part2, double* __restric
 // ---------------------------------------------------------------------------
 // Launch helpers.
 // ---------------------------------------------------------------------------
-hipError_t launch_vpass(const DevParams& p, const float* U, int64_t u_stride, const double* Ginv,
+template <int RT>
+static hipError_t launch_vpass_rt(const DevParams& p, int mode, const float* U, int64_t u_stride,
+                                  const float* Uold, const float* Vrow_old, const double* Ginv,
+                                  int64_t g_stride, hipStream_t st) {
+  dim3 grid(p.ng64, p.vsplit), block(256);
+  if (mode == kSZero)
+    hipLaunchKernelGGL((k_vpass<RT, kSZero>), grid, block, 0, st, p, U, u_stride, Uold, Vrow_old);
+  else if (mode == kSStored)
+    hipLaunchKernelGGL((k_vpass<RT, kSStored>), grid, block, 0, st, p, U, u_stride, Uold, Vrow_old);
+  else
+    hipLaunchKernelGGL((k_vpass<RT, kSRecompute>), grid, block, 0, st, p, U, u_stride, Uold,
+                       Vrow_old);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vfinal<RT>, dim3(p.ngroups), dim3(256), 0, st, p, Ginv, g_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_vpass(const DevParams& p, int mode, const float* U, int64_t u_stride,
+                        const float* Uold, const float* Vrow_old, const double* Ginv,
                         int64_t g_stride, hipStream_t st) {
-  dim3 grid(p.ngroups), block(512);
   switch (p.RP / 16) {
-    case 1: hipLaunchKernelGGL(k_vpass<1>, grid, block, 0, st, p, U, u_stride, Ginv, g_stride); break;
-    case 2: hipLaunchKernelGGL(k_vpass<2>, grid, block, 0, st, p, U, u_stride, Ginv, g_stride); break;
-    case 3: hipLaunchKernelGGL(k_vpass<3>, grid, block, 0, st, p, U, u_stride, Ginv, g_stride); break;
-    case 4: hipLaunchKernelGGL(k_vpass<4>, grid, block, 0, st, p, U, u_stride, Ginv, g_stride); break;
+    case 1: return launch_vpass_rt<1>(p, mode, U, u_stride, Uold, Vrow_old, Ginv, g_stride, st);
+    case 2: return launch_vpass_rt<2>(p, mode, U, u_stride, Uold, Vrow_old, Ginv, g_stride, st);
+    case 3: return launch_vpass_rt<3>(p, mode, U, u_stride, Uold, Vrow_old, Ginv, g_stride, st);
+    case 4: return launch_vpass_rt<4>(p, mode, U, u_stride, Uold, Vrow_old, Ginv, g_stride, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_client_factor(const DevParams& p, hipStream_t st) {
@@ -713,30 +797,36 @@ hipError_t launch_client_factor(const DevParams& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_spass(const DevParams& p, const float* U, int64_t u_stride, hipStream_t st) {
-  dim3 grid(p.nrb, p.E), block(256);
+hipError_t launch_spass(const DevParams& p, const float* U, int64_t u_stride, float* Sout,
+                        int64_t lds_out, int emit_only, int client_base, int client_count,
+                        hipStream_t st) {
+  dim3 grid(p.nrb, client_count), block(256);
   switch (p.RP / 16) {
-    case 1: hipLaunchKernelGGL(k_spass<1>, grid, block, 0, st, p, U, u_stride); break;
-    case 2: hipLaunchKernelGGL(k_spass<2>, grid, block, 0, st, p, U, u_stride); break;
-    case 3: hipLaunchKernelGGL(k_spass<3>, grid, block, 0, st, p, U, u_stride); break;
-    case 4: hipLaunchKernelGGL(k_spass<4>, grid, block, 0, st, p, U, u_stride); break;
+    case 1: hipLaunchKernelGGL(k_spass<1>, grid, block, 0, st, p, U, u_stride, Sout, lds_out, emit_only, client_base); break;
+    case 2: hipLaunchKernelGGL(k_spass<2>, grid, block, 0, st, p, U, u_stride, Sout, lds_out, emit_only, client_base); break;
+    case 3: hipLaunchKernelGGL(k_spass<3>, grid, block, 0, st, p, U, u_stride, Sout, lds_out, emit_only, client_base); break;
+    case 4: hipLaunchKernelGGL(k_spass<4>, grid, block, 0, st, p, U, u_stride, Sout, lds_out, emit_only, client_base); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_uupdate(const DevParams& p, const float* Uin, int64_t uin_stride, float* Uout,
-                          int64_t uout_stride, const float* Uprev_cons, int final_step,
-                          double eta, hipStream_t st) {
+hipError_t launch_uupdate(const DevParams& p, float* Uout, int64_t uout_stride,
+                          const float* Uprev_cons, int final_step, hipStream_t st) {
   dim3 grid(p.nub, final_step ? 1 : p.E), block(256);
-  hipLaunchKernelGGL(k_uupdate, grid, block, 0, st, p, Uin, uin_stride, Uout, uout_stride,
-                     Uprev_cons, final_step, eta);
+  switch (p.RP / 16) {
+    case 1: hipLaunchKernelGGL(k_uupdate<1>, grid, block, 0, st, p, Uout, uout_stride, Uprev_cons, final_step); break;
+    case 2: hipLaunchKernelGGL(k_uupdate<2>, grid, block, 0, st, p, Uout, uout_stride, Uprev_cons, final_step); break;
+    case 3: hipLaunchKernelGGL(k_uupdate<3>, grid, block, 0, st, p, Uout, uout_stride, Uprev_cons, final_step); break;
+    case 4: hipLaunchKernelGGL(k_uupdate<4>, grid, block, 0, st, p, Uout, uout_stride, Uprev_cons, final_step); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const DevParams& p, double* Ginv, int64_t g_stride, int per_client,
                            int record, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(per_client ? p.E : 1), dim3(256), 0, st, p, Ginv,
+  hipLaunchKernelGGL(k_finalize, dim3(per_client ? p.E : 1), dim3(1024), 0, st, p, Ginv,
                      g_stride, per_client, record);
   return hipGetLastError();
 }
@@ -794,7 +884,7 @@ hipError_t launch_pack_target(const DevParams& p, const ClientDev* host_clients,
   hipLaunchKernelGGL(k_pack_target_U, dim3((unsigned)((totu + 255) / 256)), dim3(256), 0, st, p,
                      Us, ldus, rs, Ut, RPT);
   for (int i = 0; i < p.E; ++i) {
-    const int span = (host_clients[i].n + kVCols - 1) / kVCols * kVCols;
+    const int span = (host_clients[i].n + kVPad - 1) / kVPad * kVPad;
     const int64_t tot = (int64_t)span * RPT;
     hipLaunchKernelGGL(k_pack_target_V, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
                        p, Vs, ldvs, rs, Vt, RPT, i, col_off[i]);

@@ -49,14 +49,17 @@ def test_parameter_validation_messages(lib):
 
 def test_workspace_bytes_grow_with_problem(lib):
     from paper_2207_11669_amd import make_params, workspace_bytes
-    p1, _a = make_params(4000, [500] * 16, 20, 0.1, 0.01)
+    p1, _a = make_params(4000, [500] * 16, 20, 0.1, 0.01, store_s=True)
     p2, _b = make_params(4000, [500] * 16, 20, 0.1, 0.01, K=2)
-    p3, _c = make_params(8000, [500] * 16, 20, 0.1, 0.01)
-    b1, b2, b3 = workspace_bytes(p1), workspace_bytes(p2), workspace_bytes(p3)
-    # S alone is m * n * 4 bytes.
+    p3, _c = make_params(8000, [500] * 16, 20, 0.1, 0.01, store_s=True)
+    p4, _d = make_params(4000, [500] * 16, 20, 0.1, 0.01)
+    b1, b2, b3, b4 = (workspace_bytes(p) for p in (p1, p2, p3, p4))
+    # A stored S alone is m * n * 4 bytes; K > 1 stores S and per-client factors.
     assert b1 >= 4000 * 8000 * 4
     assert b2 > b1 and b3 > b1
-    assert b1 % 256 == 0
+    # With S rebuilt each round (K = 1, one alternation) no m x n buffer exists.
+    assert b4 < 4000 * 8000 * 4 // 2
+    assert b1 % 256 == 0 and b4 % 256 == 0
 
 
 def test_product_path_never_imports_the_oracle():
