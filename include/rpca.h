@@ -57,7 +57,7 @@ typedef enum {
 } rpca_eta_sched;
 
 typedef struct {
-  int64_t m;               /* rows of M (all clients share them), m >= 1 */
+  int64_t m;               /* rows of M (all clients share them), 1 <= m < 2^26 */
   int32_t E;               /* number of clients, 1 <= E <= 4096 */
   const int64_t* n_cols;   /* host array [E]: n_i >= 1 columns of client i */
   int32_t r;               /* factor rank, 1 <= r <= 64 */
@@ -101,8 +101,8 @@ rpca_status rpca_workspace_bytes(const rpca_params* p, size_t* bytes);
  *  M_blocks: host array [E] of device pointers; M_blocks[i] is client i's
  *            m x n_i block, column-major with leading dimension ldm[i].
  *            Borrowed, read-only, and must stay valid while the context
- *            lives. Each pointer must be 16-byte aligned, ldm[i] >= m and
- *            ldm[i] % 4 == 0.
+ *            lives. Each pointer must be 16-byte aligned, m <= ldm[i] < 2^26
+ *            and ldm[i] % 4 == 0.
  *  U0:       device m x r column-major start U^(0) with leading dimension
  *            ldu >= m (copied; not retained).
  *  workspace/ws_bytes: caller-owned device memory of at least

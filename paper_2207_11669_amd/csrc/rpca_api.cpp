@@ -22,8 +22,7 @@ struct rpca_ctx {
   int vcur = 0;  // V buffer holding the latest V
   int inner = 1;
   bool recompute = false;  // S rebuilt from (U_prev, V) instead of stored
-  float* Vrow[2] = {nullptr, nullptr};
-  float* Vcol[2] = {nullptr, nullptr};
+  float* V[2] = {nullptr, nullptr};  // V buffers (row-major copy + factor block)
   std::vector<VGroup> vg64;
   bool poisoned = false;
   std::string err;
@@ -50,7 +49,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t S, U0, U1, Uc0, Uc1, Vrow0, Vrow1, Vcol0, Vcol1, Wpart, P, gv, Af, Bf, gram, spart, upart,
+  size_t S, U0, U1, Uc0, Uc1, V0, V1, Wpart, P, gv, Af, Bf, gram, spart, upart,
       ucl, Ginv, dstate, hist, clients, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
       total;
   int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows;
@@ -60,7 +59,7 @@ struct Layout {
 
 const char* check_params(const rpca_params* p) {
   if (!p) return "params is NULL";
-  if (p->m < 1 || p->m > (int64_t)1 << 30) return "m must be in [1, 2^30]";
+  if (p->m < 1 || p->m >= (int64_t)1 << 26) return "m must be in [1, 2^26)";
   if (p->E < 1 || p->E > 4096) return "E must be in [1, 4096]";
   if (!p->n_cols) return "n_cols is NULL";
   int64_t n = 0;
@@ -125,14 +124,13 @@ Layout make_layout(const rpca_params* p) {
     return at;
   };
   L.S = take((size_t)L.Sfloats * f);
-  L.U0 = take((size_t)L.RP * L.MP * f);
-  L.U1 = take((size_t)L.RP * L.MP * f);
-  L.Uc0 = take(multi ? (size_t)E * L.RP * L.MP * f : 0);
-  L.Uc1 = take(multi ? (size_t)E * L.RP * L.MP * f : 0);
-  L.Vrow0 = take((size_t)L.NVP * L.RP * f);
-  L.Vrow1 = take((size_t)L.NVP * L.RP * f);
-  L.Vcol0 = take((size_t)L.NVP * L.RP * f);
-  L.Vcol1 = take((size_t)L.NVP * L.RP * f);
+  const size_t ub = (size_t)fb_floats(L.MP, L.RP, L.NS);
+  L.U0 = take(ub * f);
+  L.U1 = take(ub * f);
+  L.Uc0 = take(multi ? (size_t)E * ub * f : 0);
+  L.Uc1 = take(multi ? (size_t)E * ub * f : 0);
+  L.V0 = take((size_t)vbuf_floats(L.NVP, L.RP, L.NS) * f);
+  L.V1 = take((size_t)vbuf_floats(L.NVP, L.RP, L.NS) * f);
   L.Wpart = take((size_t)L.vsplit * L.NVP * L.RP * f);
   L.P = take((size_t)E * L.RP * L.MP * f);
   L.gv = take((size_t)L.ngroups * RR * d);
@@ -212,8 +210,7 @@ struct Profiler {
 // Device parameters of a launch that reads or writes V buffer `v`.
 DevParams with_v(const rpca_ctx* c, int v) {
   DevParams q = c->p;
-  q.Vrow = c->Vrow[v];
-  q.Vcol = c->Vcol[v];
+  q.V = c->V[v];
   return q;
 }
 
@@ -222,7 +219,7 @@ DevParams with_v(const rpca_ctx* c, int v) {
 rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
   const DevParams& p = c->p;
   hipStream_t st = c->stream;
-  const int64_t ustride = (int64_t)p.RP * p.MP;
+  const int64_t ustride = p.ublock;
   const int64_t gstride = (int64_t)p.RP * p.RP;
   const float* Ucons = c->U[c->cur];
   if (c->recompute) {
@@ -232,7 +229,7 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     const int vn = c->vcur ^ 1;
     const DevParams q = with_v(c, vn);
     RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
-                launch_vpass(q, mode, Ucons, 0, c->U[c->cur ^ 1], c->Vrow[c->vcur], c->Ginv, 0, st),
+                launch_vpass(q, mode, Ucons, 0, c->U[c->cur ^ 1], c->V[c->vcur], c->Ginv, 0, st),
                 "V-pass launch");
     if (p.u_mode == RPCA_U_CLOSED)
       RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(q, st), "client factor launch");
@@ -289,7 +286,7 @@ rpca_status guard(rpca_ctx* c) {
 // ||U V^T - X2 Y2^T||_F^2 and ||X2 Y2^T||_F^2 into c->dout (device).
 rpca_status enqueue_distance(rpca_ctx* c, const float* X2, const float* Y2, int rp2) {
   RPCA_HIP(c,
-           launch_factor_distance(c->p, c->U[c->cur], c->Vcol[c->vcur], c->p.RP, X2, Y2, rp2, c->dpart,
+           launch_factor_distance(c->p, c->U[c->cur], v_fb(c->V[c->vcur], c->p.NVP, c->p.RP), c->p.RP, X2, Y2, rp2, c->dpart,
                                   c->dpart2, c->dout, c->stream),
            "factor distance launch");
   return RPCA_OK;
@@ -315,7 +312,8 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   if (check_params(prm)) return RPCA_EINVAL;
   if (!M_blocks || !ldm || !U0 || ldu < prm->m) return RPCA_EINVAL;
   for (int i = 0; i < prm->E; ++i) {
-    if (!M_blocks[i] || ldm[i] < prm->m || ldm[i] % 4 != 0 ||
+    // Kernels address 16 columns of a block with 32-bit byte offsets.
+    if (!M_blocks[i] || ldm[i] < prm->m || ldm[i] % 4 != 0 || ldm[i] >= ((int64_t)1 << 26) ||
         reinterpret_cast<uintptr_t>(M_blocks[i]) % 16 != 0)
       return RPCA_EINVAL;
   }
@@ -354,12 +352,10 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.vg64 = reinterpret_cast<const VGroup*>(ws + L.vg64);
   p.S = L.recompute ? nullptr : reinterpret_cast<float*>(ws + L.S);
   c->recompute = L.recompute;
-  c->Vrow[0] = reinterpret_cast<float*>(ws + L.Vrow0);
-  c->Vrow[1] = reinterpret_cast<float*>(ws + L.Vrow1);
-  c->Vcol[0] = reinterpret_cast<float*>(ws + L.Vcol0);
-  c->Vcol[1] = reinterpret_cast<float*>(ws + L.Vcol1);
-  p.Vrow = c->Vrow[0];
-  p.Vcol = c->Vcol[0];
+  c->V[0] = reinterpret_cast<float*>(ws + L.V0);
+  c->V[1] = reinterpret_cast<float*>(ws + L.V1);
+  p.V = c->V[0];
+  p.ublock = fb_floats(L.MP, L.RP, L.NS);
   p.Wpart = reinterpret_cast<float*>(ws + L.Wpart);
   p.P = reinterpret_cast<float*>(ws + L.P);
   p.gv_part = reinterpret_cast<double*>(ws + L.gv);
@@ -503,7 +499,7 @@ rpca_status rpca_solve(rpca_ctx* c, int32_t max_rounds, double tol, int32_t chec
     if (!c->have_target) {
       RPCA_HIP(c, hipMemcpyAsync(c->Uprev, c->U[c->cur], ubytes, hipMemcpyDeviceToDevice, c->stream),
                "copy U");
-      RPCA_HIP(c, hipMemcpyAsync(c->Vprev, c->Vcol[c->vcur], vbytes, hipMemcpyDeviceToDevice, c->stream),
+      RPCA_HIP(c, hipMemcpyAsync(c->Vprev, v_fb(c->V[c->vcur], c->p.NVP, c->p.RP), vbytes, hipMemcpyDeviceToDevice, c->stream),
                "copy V");
       c->have_prev = true;
     }

@@ -14,6 +14,32 @@ constexpr int kVStreamCols = 64; // columns per V-pass streaming work-group (4 w
 constexpr int kSRows = 128;      // rows per S-pass work-group (4 waves x 32 rows)
 constexpr int kURows = 64;       // rows per U-update work-group
 
+// Factor storage. A factor X (U: MP rows, V: NVP rows; RP = r rounded up to 16
+// ranks, zero padded) is kept in three layouts in one block of floats:
+//   col : column-major, leading dimension = rows            (RP * rows)
+//   pa  : MFMA A-operand packing, for 16-row chunk ch, step s < NS, lane l:
+//         X[16 ch + l % 16][(l / 16) * NS + s]                (4 * NS * rows)
+//   pb  : MFMA B-operand packing, for chunk ch, rank tile ct, lane l, e < 4:
+//         X[16 ch + 4 (l / 16) + e][16 ct + l % 16]           (RP * rows)
+// so that every operand a wave needs for one 16x16x4 MFMA step is a single
+// contiguous 256 B (pa) or 1 KiB (pb) read. V additionally keeps a row-major
+// copy (rows x RP) in front of its factor block.
+__host__ __device__ inline int64_t fb_floats(int64_t rows, int RP, int NS) {
+  return 2 * (int64_t)RP * rows + 4 * (int64_t)NS * rows;
+}
+__host__ __device__ inline int64_t fb_pa_off(int64_t rows, int RP) { return (int64_t)RP * rows; }
+__host__ __device__ inline int64_t fb_pb_off(int64_t rows, int RP, int NS) {
+  return (int64_t)RP * rows + 4 * (int64_t)NS * rows;
+}
+// V buffer: row-major NVP x RP copy, then the factor block.
+__host__ __device__ inline int64_t vbuf_floats(int64_t NVP, int RP, int NS) {
+  return (int64_t)NVP * RP + fb_floats(NVP, RP, NS);
+}
+__host__ __device__ inline float* v_fb(float* V, int64_t NVP, int RP) { return V + NVP * RP; }
+__host__ __device__ inline const float* v_fb(const float* V, int64_t NVP, int RP) {
+  return V + NVP * RP;
+}
+
 // One client (Section 2.1): its borrowed block M_i and where its private
 // state lives in the workspace.
 struct ClientDev {
@@ -23,7 +49,7 @@ struct ClientDev {
   int64_t col0;     // first global column of the client
   int32_t n;        // n_i
   int32_t vrow0;    // first row of V_i in the padded V buffers (multiple of 64)
-  int32_t g0, g1;   // V-pass work-groups [g0, g1) that cover this client
+  int32_t g0, g1;   // V-finalize work-groups [g0, g1) that cover this client
   double c;         // rho * n_i / n
 };
 
@@ -49,6 +75,7 @@ struct DevParams {
   int32_t NVP;           // padded rows of the V buffers
   int64_t n;             // total columns
   int64_t lds;           // leading dimension of S (= m rounded up to 4)
+  int64_t ublock;        // floats of one U factor block, fb_floats(MP, RP, NS)
   int32_t nrb;           // S-pass row blocks (MP / kSRows)
   int32_t nub;           // U-update row blocks (MP / kURows)
   int32_t ngroups;       // V-finalize work-groups (32 columns each)
@@ -61,16 +88,15 @@ struct DevParams {
   const ClientDev* clients;
   const VGroup* vgroups;
   const VGroup* vg64;
-  float* S;              // all clients' S_i
-  float* Vrow;           // V written/read by this launch, row-major NVP x RP
-  float* Vcol;           // the same V, column-major NVP x RP (leading dimension NVP)
+  float* S;              // all clients' S_i (stored-S layout only)
+  float* V;              // V buffer this launch writes or reads (see vbuf_floats)
   float* Wpart;          // V-pass partial W per row split, [vsplit][NVP][RP]
-  float* P;              // per-client U-step term T_i (from Lambda_i V_i), column-major MP x RP
-  double* gv_part;       // per V-group partial V^T V, RP x RP
+  float* P;              // per-client U-step term T_i, column-major MP x RP
+  double* gv_part;       // per V-finalize group partial V^T V, RP x RP
   double* Afac;          // per-client (V_i^T V_i + c_i I)^{-1}, RP x RP
   double* Bfac;          // per-client V_i^T V_i (V_i^T V_i + c_i I)^{-1}
   double* gram_part;     // per (client,) U row block partial U^T U, RP x RP
-  double* spart;         // per S-pass work-group: 1/2-free sums (l2, l1, nnz, 0)
+  double* spart;         // per S-pass work-group: sums of Lambda^2, |S|, nnz(S)
   double* upart;         // per U row block: ||dU||^2
   double* ucl_sq;        // per-client ||U_i||^2 of the current local factors
   DevState* dstate;
@@ -82,22 +108,26 @@ constexpr int kDistBlocks = 64;  // work-groups per side of the factor-distance 
 // S source for the V-pass: zero, the stored S buffer, or recomputed from the
 // previous round's factors.
 enum VMode { kSZero = 0, kSStored = 1, kSRecompute = 2 };
+// V-pass into p.V. U: factor block of the input U (client stride u_stride);
+// Uold / Vold: previous U factor block and previous V buffer (kSRecompute).
 hipError_t launch_vpass(const DevParams& p, int mode, const float* U, int64_t u_stride,
-                        const float* Uold, const float* Vrow_old, const double* Ginv,
+                        const float* Uold, const float* Vold, const double* Ginv,
                         int64_t g_stride, hipStream_t st);
 hipError_t launch_client_factor(const DevParams& p, hipStream_t st);
-// S-pass over clients [client_base, client_base + client_count). Sout/lds_out:
-// column-major buffer S is written to, indexed by global column (NULL: S is
-// not stored); emit_only: write S only (no U-step term, no statistics).
+// S-pass over clients [client_base, client_base + client_count) with V = p.V.
+// Sout/lds_out: column-major buffer S is written to, indexed by global column
+// (NULL: S is not stored); emit_only: write S only (no U-step term, no
+// statistics).
 hipError_t launch_spass(const DevParams& p, const float* U, int64_t u_stride, float* Sout,
                         int64_t lds_out, int emit_only, int client_base, int client_count,
                         hipStream_t st);
+// U update into factor block(s) Uout; Uprev_col: column-major previous U.
 hipError_t launch_uupdate(const DevParams& p, float* Uout, int64_t uout_stride,
-                          const float* Uprev_cons, int final_step, hipStream_t st);
+                          const float* Uprev_col, int final_step, hipStream_t st);
 hipError_t launch_finalize(const DevParams& p, double* Ginv, int64_t g_stride, int per_client,
                            int record, hipStream_t st);
-hipError_t launch_gram_init(const DevParams& p, const float* U, hipStream_t st);
-hipError_t launch_copy_in_U(const DevParams& p, const float* U0, int64_t ldu, float* Ucol,
+hipError_t launch_gram_init(const DevParams& p, const float* Ucol, hipStream_t st);
+hipError_t launch_copy_in_U(const DevParams& p, const float* U0, int64_t ldu, float* Ufb,
                             hipStream_t st);
 hipError_t launch_materialize(const DevParams& p, const ClientDev* host_clients,
                               const int64_t* col_off, const float* Ucol, int client_begin,
@@ -113,7 +143,7 @@ hipError_t launch_pack_target(const DevParams& p, const ClientDev* host_clients,
 // ||X1 Y1^T - X2 Y2^T||_F^2 -> out2[0] and ||X2 Y2^T||_F^2 -> out2[1], from
 // Gram matrices (FP64). X*: column-major, MP rows (ld MP); Y*: column-major,
 // NVP rows (ld NVP); widths rp1, rp2 <= 64. part: 2*kDistBlocks*3*64*64
-// doubles; part2: 48*3 doubles.
+// doubles; part2: 48 doubles.
 hipError_t launch_factor_distance(const DevParams& p, const float* X1, const float* Y1, int rp1,
                                   const float* X2, const float* Y2, int rp2, double* part,
                                   double* part2, double* out2, hipStream_t st);

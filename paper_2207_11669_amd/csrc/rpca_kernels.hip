@@ -19,10 +19,49 @@
 #include "rpca_internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace rpca {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Global-address-space views. Pointers read from device tables (the client
+// table) are not known to be global to the compiler, which then emits flat
+// memory instructions; those count against both wait counters and serialise
+// the prefetch rings below.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const GLOBAL T* gptr(const T* p) {
+  return (const GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ GLOBAL T* gptr_w(T* p) {
+  return (GLOBAL T*)p;
+}
+
+// Raw buffer loads. A buffer resource holds a base address and a byte range;
+// lanes whose offset falls outside the range read 0 instead of memory, and the
+// per-lane offset is 32-bit, so addresses need no 64-bit arithmetic per load.
+// Only the per-lane voffset takes part in the range check; the scalar soffset
+// is used only where every access is in range by construction.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kBufferDword3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kBufferDword3);
+}
+__device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ f4 bload4(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+// Bytes of a client block from column j0 on (0 past the end), capped to the
+// 32-bit range of a buffer resource.
+__device__ __forceinline__ uint32_t block_bytes_from(int n, int j0, int64_t ldm) {
+  if (j0 >= n) return 0u;
+  const int64_t b = (int64_t)(n - j0) * ldm * 4;
+  return b > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)b;
+}
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   // D[i][j] += sum_k A[i][k] B[k][j] over a 16x16x4 tile. Lane l supplies
@@ -94,6 +133,20 @@ __device__ __forceinline__ double sum_strided(const double* __restrict__ x, int 
   return (s0 + s1) + (s2 + s3);
 }
 
+// Store element (a, c) of a factor with `rows` rows into its factor block
+// (column-major, A-operand packing, B-operand packing; see rpca_internal.h).
+__device__ __forceinline__ void fb_store(float* fb, int64_t rows, int RP, int NS, int a, int c,
+                                         float v) {
+  fb[(int64_t)c * rows + a] = v;
+  const int ch = a >> 4, li = a & 15;
+  if (c < 4 * NS) {
+    const int g = c / NS, s = c - g * NS;
+    fb[fb_pa_off(rows, RP) + ((int64_t)ch * NS + s) * 64 + g * 16 + li] = v;
+  }
+  const int ct = c >> 4, lane = ((li >> 2) << 4) + (c & 15);
+  fb[fb_pb_off(rows, RP, NS) + (((int64_t)ch * (RP >> 4) + ct) * 64 + lane) * 4 + (li & 3)] = v;
+}
+
 // ---------------------------------------------------------------------------
 // V-pass, streaming part: W = (M_i - S_i)^T U_i partial sums over row splits.
 // grid = (64-column groups, row splits); 4 waves, wave w owns the 16 columns
@@ -101,17 +154,18 @@ __device__ __forceinline__ double sum_strided(const double* __restrict__ x, int 
 // operands they load are shared through L1.
 // Lane l holds rows 4*(l/16)..+3 of column l%16 (one float4 along the
 // contiguous rows of the column-major block): element s of that float4 is the
-// A operand of MFMA step s, and U supplies the B operand as a float4 of its
-// column-major layout. Accumulator: W[col 4*(l/16)+v][rank 16*ct + l%16].
+// A operand of MFMA step s, and U supplies the B operand as one float4 of its
+// B-operand packing. Accumulator: W[col 4*(l/16)+v][rank 16*ct + l%16].
 // MODE kSRecompute rebuilds S = soft(M - Uo Vo^T) of the previous round on the
 // fly: its MFMA puts Uo rows on the A side and Vo^T on the B side, so the
 // 16x16 residual tile comes out in exactly the float4 layout of M.
 // ---------------------------------------------------------------------------
-template <int RT, int MODE>
+template <int RT, int NS, int MODE>
 __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restrict__ Ubase,
                                                int64_t u_stride, const float* __restrict__ Uold,
-                                               const float* __restrict__ Vrow_old) {
-  constexpr int RP = 16 * RT, NSMAX = 4 * RT;
+                                               const float* __restrict__ Vold) {
+  constexpr int RP = 16 * RT;
+  static_assert(NS >= 1 && NS <= 4 * RT, "NS = ceil(r / 4) must fit the rank tiles");
   const VGroup vg = p.vg64[blockIdx.x];
   const ClientDev cl = p.clients[vg.client];
   const float* __restrict__ U = Ubase + (int64_t)vg.client * u_stride;
@@ -119,61 +173,112 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
   const int j0 = vg.j0 + 16 * w;  // client-local first column of this wave's tile
   const int col = j0 + li;
   const bool colok = col < cl.n;
-  const int ns = p.NS;
   const float lam = p.lam;
 
-  float vb[NSMAX];
+  const float* gUpb_raw = U + fb_pb_off(p.MP, RP, NS);
+  const float* gUopa_raw = (MODE == kSRecompute) ? Uold + fb_pa_off(p.MP, RP) : gUpb_raw;
+  float vb[NS];  // B operand of the S rebuild: Vo[col j0 + l%16][rank (l/16)*NS + s]
+  if (MODE == kSRecompute) {
+    const GLOBAL float* Vopa = gptr(v_fb(Vold, p.NVP, RP)) + fb_pa_off(p.NVP, RP);
+    const int vch = (cl.vrow0 + j0) >> 4;
 #pragma unroll
-  for (int s = 0; s < NSMAX; ++s)
-    vb[s] = (MODE == kSRecompute && s < ns)
-                ? Vrow_old[(int64_t)(cl.vrow0 + col) * RP + lg * ns + s]
-                : 0.f;
+    for (int s = 0; s < NS; ++s) vb[s] = Vopa[((int64_t)vch * NS + s) * 64 + lane];
+  }
 
   const int rbeg = blockIdx.y * p.vsplit_rows;
   const int rend = min(p.m, rbeg + p.vsplit_rows);
   f4 acc[RT];
 #pragma unroll
   for (int ct = 0; ct < RT; ++ct) acc[ct] = f4{0.f, 0.f, 0.f, 0.f};
-  const float* __restrict__ Mc = cl.M + (int64_t)(colok ? col : 0) * cl.ldm;
-  const float* __restrict__ Sc = p.S + cl.s_off + (int64_t)(colok ? col : 0) * p.lds;
+  // M (and stored S) through a buffer resource over this wave's 16 columns:
+  // columns past n_i lie beyond its range and read 0; rows are clamped to the
+  // last float4 of the column and masked when used. U operands are packed and
+  // always in range: lane offset plus a scalar chunk offset.
+  const int mlast4 = (p.m - 1) & ~3;
+  const rsrc_t rM = make_rsrc(cl.M + (int64_t)min(j0, cl.n) * cl.ldm, block_bytes_from(cl.n, j0, cl.ldm));
+  rsrc_t rS = rM;
+  if (MODE == kSStored)
+    rS = make_rsrc(p.S + cl.s_off + (int64_t)min(j0, cl.n) * p.lds, block_bytes_from(cl.n, j0, p.lds));
+  const uint32_t vM = (uint32_t)(li * cl.ldm) * 4u, vS = (uint32_t)(li * p.lds) * 4u;
+  const rsrc_t rUb = make_rsrc(gUpb_raw, (uint32_t)(p.MP * RP * 4));
+  const rsrc_t rUa = make_rsrc(gUopa_raw, (uint32_t)(p.MP * 4 * NS * 4));
 
-  for (int row0 = rbeg; row0 < rend; row0 += 16) {
-    const int row = row0 + 4 * lg;
-    f4 mv = {0.f, 0.f, 0.f, 0.f}, sv = {0.f, 0.f, 0.f, 0.f};
-    if (colok && row < p.m) {
-      mv = *reinterpret_cast<const f4*>(Mc + row);
-      if (MODE == kSStored) sv = *reinterpret_cast<const f4*>(Sc + row);
-      if (row + 4 > p.m) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (row + e >= p.m) mv[e] = sv[e] = 0.f;
-      }
-    }
-    f4 u[RT];
+  // Operands of one 16-row chunk; kVDepth chunks are kept in flight (vector
+  // loads complete in order, so everything a chunk needs is issued together).
+  struct Chunk {
+    f4 m, s;          // M (and stored S) rows 4*(l/16)..+3 of column l%16
+    f4 u[RT];         // U^T operand: U[row][rank 16*ct + l%16] for the 4 rows
+    float uo[NS];     // previous U, A operand of the S rebuild: Uo[row l%16][rank g*NS + s]
+  };
+  constexpr int kVDepth = 4;
+  Chunk ring[kVDepth];
+  const int nch = (rend - rbeg + 15) >> 4;
+  auto load_chunk = [&](Chunk& c, int ch) {
+    const int row0 = rbeg + (ch << 4);
+    const uint32_t rowb = (uint32_t)min(row0 + 4 * lg, mlast4) * 4u;
+    c.m = bload4(rM, vM + rowb, 0);
+    if (MODE == kSStored) c.s = bload4(rS, vS + rowb, 0);
+    const uint32_t chg = (uint32_t)(row0 >> 4);
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct)
-      u[ct] = *reinterpret_cast<const f4*>(U + (int64_t)(16 * ct + li) * p.MP + row);
+      c.u[ct] = bload4(rUb, (uint32_t)lane * 16u, ((chg * RT + ct) * 64u) * 16u);
+    if (MODE == kSRecompute) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) c.uo[s] = bload(rUa, (uint32_t)lane * 4u, ((chg * NS + s) * 64u) * 4u);
+    }
+  };
+  auto compute_chunk = [&](const Chunk& c, int ch) {
+    // Rows outside [rbeg, rend) (tail chunk, or a padding chunk that reuses
+    // the last chunk's registers) and columns past n_i contribute nothing.
+    const int row = rbeg + (ch << 4) + 4 * lg;
+    bool ok[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ok[e] = colok && row + e < rend;
     f4 d;
     if (MODE == kSRecompute) {
       f4 a1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < NSMAX; ++s)
-        if (s < ns) a1 = mfma4(Uold[(int64_t)(lg * ns + s) * p.MP + row0 + li], vb[s], a1);
+      for (int s = 0; s < NS; ++s) a1 = mfma4(c.uo[s], vb[s], a1);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const float R = mv[e] - a1[e];
+        const float R = c.m[e] - a1[e];
         const float Sv = R - fminf(fmaxf(R, -lam), lam);
-        d[e] = mv[e] - Sv;
+        d[e] = ok[e] ? c.m[e] - Sv : 0.f;
       }
     } else {
-      d = mv - sv;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) d[e] = ok[e] ? c.m[e] - (MODE == kSStored ? c.s[e] : 0.f) : 0.f;
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int ct = 0; ct < RT; ++ct) acc[ct] = mfma4(d[s], u[ct][s], acc[ct]);
+      for (int ct = 0; ct < RT; ++ct) acc[ct] = mfma4(d[s], c.u[ct][s], acc[ct]);
+  };
+  // Uniform loop: every iteration loads (the chunk index is clamped to the
+  // last chunk, whose addresses are then cache hits), so the wait counts stay
+  // exact and kVDepth - 1 chunks remain in flight at every wait.
+  const int nchp = (nch + kVDepth - 1) / kVDepth * kVDepth;
+  // The prologue issues the ring in slot order (fenced like the loop body),
+  // so that at the loop head slot 0 holds the oldest loads on every path.
+#pragma unroll
+  for (int d = 0; d < kVDepth; ++d) {
+    load_chunk(ring[d], min(d, nch - 1));
+    __builtin_amdgcn_sched_barrier(0);
   }
-  float* __restrict__ wp = p.Wpart + ((int64_t)blockIdx.y * p.NVP + cl.vrow0 + j0) * RP;
+  for (int c0 = 0; c0 < nchp; c0 += kVDepth) {
+#pragma unroll
+    for (int d = 0; d < kVDepth; ++d) {
+      const int ch = c0 + d;
+      compute_chunk(ring[d], ch);
+      // Keep the refill at this point of the program: left alone, the
+      // scheduler sinks loads towards their first use and the ring collapses
+      // to a single chunk in flight.
+      __builtin_amdgcn_sched_barrier(0);
+      load_chunk(ring[d], min(ch + kVDepth, nch - 1));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  GLOBAL float* wp = gptr_w(p.Wpart) + ((int64_t)blockIdx.y * p.NVP + cl.vrow0 + j0) * RP;
 #pragma unroll
   for (int ct = 0; ct < RT; ++ct)
 #pragma unroll
@@ -235,8 +340,8 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
     if (e < kVCols * RP) {
       const int j = e / RP, c = e % RP;
       wd[j][c] = (double)vres[q];
-      p.Vrow[(int64_t)(vrow + j) * RP + c] = vres[q];
-      p.Vcol[(int64_t)c * p.NVP + vrow + j] = vres[q];
+      p.V[(int64_t)(vrow + j) * RP + c] = vres[q];
+      fb_store(v_fb(p.V, p.NVP, RP), p.NVP, RP, p.NS, vrow + j, c, vres[q]);
     }
   }
   __syncthreads();
@@ -294,25 +399,27 @@ __global__ __launch_bounds__(256) void k_client_factor(DevParams p) {
 // The contraction index of MFMA 1 is split as k-group g = l/16 taking rank
 // indices g*NS + s, s < NS = ceil(r/4), so no padding steps run for r % 16.
 // ---------------------------------------------------------------------------
-template <int RT>
+template <int RT, int NS>
 __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restrict__ Ubase,
                                                int64_t u_stride, float* __restrict__ Sout,
                                                int64_t lds_out, int emit_only, int client_base) {
-  constexpr int RP = 16 * RT, NSMAX = 4 * RT;
+  constexpr int RP = 16 * RT;
+  static_assert(NS >= 1 && NS <= 4 * RT, "NS = ceil(r / 4) must fit the rank tiles");
   const int b = blockIdx.x, ci = client_base + (int)blockIdx.y;
   const ClientDev cl = p.clients[ci];
   const float* __restrict__ U = Ubase + (int64_t)ci * u_stride;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lg = lane >> 4;
   const int arow0 = b * kSRows + w * 32;
-  const int ns = p.NS;
 
-  float ub[2][NSMAX];
+  float ub[2][NS];  // MFMA 1 B operand: U[row arow0 + 16 rt + l%16][rank (l/16)*NS + s]
+  {
+    const GLOBAL float* Upa = gptr(U) + fb_pa_off(p.MP, RP);
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-    const int row = arow0 + 16 * rt + li;
+    for (int rt = 0; rt < 2; ++rt) {
+      const int64_t ch = (arow0 + 16 * rt) >> 4;
 #pragma unroll
-    for (int s = 0; s < NSMAX; ++s)
-      ub[rt][s] = (s < ns) ? U[(int64_t)(lg * ns + s) * p.MP + row] : 0.f;
+      for (int s = 0; s < NS; ++s) ub[rt][s] = Upa[(ch * NS + s) * 64 + lane];
+    }
   }
   f4 accp[2][RT];
 #pragma unroll
@@ -322,42 +429,64 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
 
   double sl2 = 0.0, sl1 = 0.0, snz = 0.0;
   const float lam = p.lam;
-  float* __restrict__ Sblk = Sout ? Sout + cl.col0 * lds_out : nullptr;
-  const float* __restrict__ Mb = cl.M;
+  GLOBAL float* Sblk = Sout ? gptr_w(Sout) + cl.col0 * lds_out : nullptr;
+  // V operands: packed, always in range (lane offset + scalar chunk offset).
+  const rsrc_t rVa = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pa_off(p.NVP, RP), (uint32_t)(p.NVP * 4 * NS * 4));
+  const rsrc_t rVb = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pb_off(p.NVP, RP, NS), (uint32_t)(p.NVP * RP * 4));
+  // M: one buffer resource per 16-column chunk (base at the chunk's first
+  // column, range = the rest of the block), fixed per-lane offsets; columns
+  // past n_i read 0. Rows past m are clamped here and masked when used.
+  uint32_t vm[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      vm[rt][v] = ((uint32_t)((4 * lg + v) * cl.ldm) + (uint32_t)min(arow0 + 16 * rt + li, p.m - 1)) * 4u;
 
-  for (int j0 = 0; j0 < cl.n; j0 += 16) {
-    const int vr = cl.vrow0 + j0;
-    float va[NSMAX];
+  // Operands of one 16-column chunk; a ring of kSDepth chunks is kept in
+  // flight so that each wave has several chunks of M loads outstanding (vector
+  // loads complete in order, so everything a chunk needs is issued together).
+  struct Chunk {
+    float m[2][4];   // M[row][col] for this lane's rows (two 16-row tiles) and 4 columns
+    float va[NS];    // MFMA 1 A operand (V A-packing): V[col j0 + l%16][rank (l/16)*NS + s]
+    f4 vb[RT];       // MFMA 2 B operand (V B-packing): V[col j0 + 4*(l/16) + e][rank 16*ct + l%16]
+  };
+  constexpr int kSDepth = 3;
+  Chunk ring[kSDepth];
+  const int nch = (cl.n + 15) >> 4;
+  auto load_chunk = [&](Chunk& c, int ch) {
+    const int j0 = ch << 4;
+    const uint32_t vch = (uint32_t)((cl.vrow0 + j0) >> 4);
 #pragma unroll
-    for (int s = 0; s < NSMAX; ++s)
-      va[s] = (s < ns) ? p.Vrow[(int64_t)(vr + li) * RP + lg * ns + s] : 0.f;
-    f4 vb[RT];
+    for (int s = 0; s < NS; ++s) c.va[s] = bload(rVa, (uint32_t)lane * 4u, ((vch * NS + s) * 64u) * 4u);
 #pragma unroll
-    for (int ct = 0; ct < RT; ++ct)
-      vb[ct] = *reinterpret_cast<const f4*>(p.Vcol + (int64_t)(16 * ct + li) * p.NVP + vr + 4 * lg);
+    for (int ct = 0; ct < RT; ++ct) c.vb[ct] = bload4(rVb, (uint32_t)lane * 16u, ((vch * RT + ct) * 64u) * 16u);
+    const rsrc_t rM = make_rsrc(cl.M + (int64_t)j0 * cl.ldm, block_bytes_from(cl.n, j0, cl.ldm));
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c.m[rt][v] = bload(rM, vm[rt][v], 0);
+  };
+  auto compute_chunk = [&](const Chunk& c, int ch) {
+    const int j0 = ch << 4;
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
       const int row = arow0 + 16 * rt + li;
       const bool rok = row < p.m;
-      float mv[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = j0 + 4 * lg + v;
-        mv[v] = (rok && col < cl.n) ? Mb[(int64_t)col * cl.ldm + row] : 0.f;
-      }
       f4 a1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < NSMAX; ++s)
-        if (s < ns) a1 = mfma4(va[s], ub[rt][s], a1);
+      for (int s = 0; s < NS; ++s) a1 = mfma4(c.va[s], ub[rt][s], a1);
       f4 lamv;
       float l2 = 0.f, l1 = 0.f, nz = 0.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int col = j0 + 4 * lg + v;
-        const float R = mv[v] - a1[v];
+        const bool ok = rok && col < cl.n;
+        // Columns past n_i (tail or padding chunk) contribute nothing.
+        const float R = ok ? c.m[rt][v] - a1[v] : 0.f;
         const float L = fminf(fmaxf(R, -lam), lam);
         const float Sv = R - L;
-        if (Sblk && rok && col < cl.n) Sblk[(int64_t)col * lds_out + row] = Sv;
+        if (Sblk && ok) Sblk[(int64_t)col * lds_out + row] = Sv;
         lamv[v] = L;
         l2 += L * L;
         l1 += fabsf(Sv);
@@ -369,7 +498,30 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
 #pragma unroll
       for (int ct = 0; ct < RT; ++ct)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) accp[rt][ct] = mfma4(lamv[s], vb[ct][s], accp[rt][ct]);
+        for (int s = 0; s < 4; ++s) accp[rt][ct] = mfma4(lamv[s], c.vb[ct][s], accp[rt][ct]);
+    }
+  };
+  // Uniform loop: every iteration loads (chunk index clamped to the last
+  // chunk), so the wait counts stay exact; padding chunks are fully masked.
+  const int nchp = (nch + kSDepth - 1) / kSDepth * kSDepth;
+  // The prologue issues the ring in slot order (fenced like the loop body),
+  // so that at the loop head slot 0 holds the oldest loads on every path.
+#pragma unroll
+  for (int d = 0; d < kSDepth; ++d) {
+    load_chunk(ring[d], min(d, nch - 1));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  for (int c0 = 0; c0 < nchp; c0 += kSDepth) {
+#pragma unroll
+    for (int d = 0; d < kSDepth; ++d) {
+      const int ch = c0 + d;
+      compute_chunk(ring[d], ch);
+      // Keep the refill at this point of the program: left alone, the
+      // scheduler sinks loads towards their first use and the ring collapses
+      // to a single chunk in flight.
+      __builtin_amdgcn_sched_barrier(0);
+      load_chunk(ring[d], min(ch + kSDepth, nch - 1));
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 
@@ -494,7 +646,7 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
   for (int q = 0; q < NQ; ++q) {
     const int c = cq + 4 * q;
     const float v = (a < p.m && c < r) ? (float)(acc[q] * scale) : 0.f;
-    Uo[(int64_t)c * MP + a] = v;
+    fb_store(Uo, MP, RP, p.NS, a, c, v);
     ul[al * kMaxRank + c] = (double)v;
     if (final_step) {
       const double d = (double)v - (double)Uprev[(int64_t)c * MP + a];
@@ -617,13 +769,13 @@ __global__ __launch_bounds__(1024) void k_finalize(DevParams p, double* Ginv, in
   }
 }
 
-// U^(0) into the padded column-major layout (zeros outside m x r).
+// U^(0) into a factor block (zeros outside m x r).
 __global__ void k_copy_in_U(DevParams p, const float* __restrict__ U0, int64_t ldu,
-                            float* __restrict__ Ucol) {
+                            float* __restrict__ Ufb) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)p.RP * p.MP) return;
   const int a = (int)(e % p.MP), c = (int)(e / p.MP);
-  Ucol[e] = (a < p.m && c < p.r) ? U0[(int64_t)c * ldu + a] : 0.f;
+  fb_store(Ufb, p.MP, p.RP, p.NS, a, c, (a < p.m && c < p.r) ? U0[(int64_t)c * ldu + a] : 0.f);
 }
 
 // L_i = U V_i^T (FP64 accumulation) and S_i, for one client, column-major out.
@@ -639,7 +791,7 @@ __global__ void k_materialize(DevParams p, const float* __restrict__ Ucol, int c
       double s = 0.0;
       for (int c = 0; c < p.r; ++c)
         s += (double)Ucol[(int64_t)c * p.MP + a] *
-             (double)p.Vrow[(int64_t)(cl.vrow0 + j) * p.RP + c];
+             (double)p.V[(int64_t)(cl.vrow0 + j) * p.RP + c];
       L[(int64_t)j * ldl + a] = (float)s;
     }
     if (S) S[(int64_t)j * lds_out + a] = p.S[cl.s_off + (int64_t)j * p.lds + a];
@@ -660,7 +812,7 @@ __global__ void k_get_V(DevParams p, int client, int64_t col0, float* __restrict
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)cl.n * p.r) return;
   const int j = (int)(e % cl.n), c = (int)(e / cl.n);
-  V[(int64_t)c * ldv + col0 + j] = p.Vrow[(int64_t)(cl.vrow0 + j) * p.RP + c];
+  V[(int64_t)c * ldv + col0 + j] = p.V[(int64_t)(cl.vrow0 + j) * p.RP + c];
 }
 
 // Target factors into padded layouts: Ut column-major MP x RPT, Vt column-major
@@ -762,34 +914,58 @@ __global__ void k_dist_final(const double* __restrict__ part2, double* __restric
 // ---------------------------------------------------------------------------
 // Launch helpers.
 // ---------------------------------------------------------------------------
-template <int RT>
-static hipError_t launch_vpass_rt(const DevParams& p, int mode, const float* U, int64_t u_stride,
-                                  const float* Uold, const float* Vrow_old, const double* Ginv,
-                                  int64_t g_stride, hipStream_t st) {
+template <int RT, int NS>
+static hipError_t launch_vpass_t(const DevParams& p, int mode, const float* U, int64_t u_stride,
+                                 const float* Uold, const float* Vold, const double* Ginv,
+                                 int64_t g_stride, hipStream_t st) {
   dim3 grid(p.ng64, p.vsplit), block(256);
   if (mode == kSZero)
-    hipLaunchKernelGGL((k_vpass<RT, kSZero>), grid, block, 0, st, p, U, u_stride, Uold, Vrow_old);
+    hipLaunchKernelGGL((k_vpass<RT, NS, kSZero>), grid, block, 0, st, p, U, u_stride, Uold, Vold);
   else if (mode == kSStored)
-    hipLaunchKernelGGL((k_vpass<RT, kSStored>), grid, block, 0, st, p, U, u_stride, Uold, Vrow_old);
+    hipLaunchKernelGGL((k_vpass<RT, NS, kSStored>), grid, block, 0, st, p, U, u_stride, Uold, Vold);
   else
-    hipLaunchKernelGGL((k_vpass<RT, kSRecompute>), grid, block, 0, st, p, U, u_stride, Uold,
-                       Vrow_old);
+    hipLaunchKernelGGL((k_vpass<RT, NS, kSRecompute>), grid, block, 0, st, p, U, u_stride, Uold,
+                       Vold);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_vfinal<RT>, dim3(p.ngroups), dim3(256), 0, st, p, Ginv, g_stride);
   return hipGetLastError();
 }
 
-hipError_t launch_vpass(const DevParams& p, int mode, const float* U, int64_t u_stride,
-                        const float* Uold, const float* Vrow_old, const double* Ginv,
-                        int64_t g_stride, hipStream_t st) {
+template <int RT, int NS>
+static hipError_t launch_spass_t(const DevParams& p, const float* U, int64_t u_stride, float* Sout,
+                                 int64_t lds_out, int emit_only, int client_base,
+                                 int client_count, hipStream_t st) {
+  hipLaunchKernelGGL((k_spass<RT, NS>), dim3(p.nrb, client_count), dim3(256), 0, st, p, U,
+                     u_stride, Sout, lds_out, emit_only, client_base);
+  return hipGetLastError();
+}
+
+// Compile-time (RT, NS) dispatch: NS = ceil(r/4) lies in [4 RT - 3, 4 RT].
+template <int RT, int NS, class F>
+static hipError_t with_ns(int ns, F&& f) {
+  if (ns == NS) return f(std::integral_constant<int, RT>{}, std::integral_constant<int, NS>{});
+  if constexpr (NS < 4 * RT) return with_ns<RT, NS + 1>(ns, f);
+  return hipErrorInvalidValue;
+}
+template <class F>
+static hipError_t with_rank(const DevParams& p, F&& f) {
   switch (p.RP / 16) {
-    case 1: return launch_vpass_rt<1>(p, mode, U, u_stride, Uold, Vrow_old, Ginv, g_stride, st);
-    case 2: return launch_vpass_rt<2>(p, mode, U, u_stride, Uold, Vrow_old, Ginv, g_stride, st);
-    case 3: return launch_vpass_rt<3>(p, mode, U, u_stride, Uold, Vrow_old, Ginv, g_stride, st);
-    case 4: return launch_vpass_rt<4>(p, mode, U, u_stride, Uold, Vrow_old, Ginv, g_stride, st);
+    case 1: return with_ns<1, 1>(p.NS, f);
+    case 2: return with_ns<2, 5>(p.NS, f);
+    case 3: return with_ns<3, 9>(p.NS, f);
+    case 4: return with_ns<4, 13>(p.NS, f);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_vpass(const DevParams& p, int mode, const float* U, int64_t u_stride,
+                        const float* Uold, const float* Vold, const double* Ginv,
+                        int64_t g_stride, hipStream_t st) {
+  return with_rank(p, [&](auto rt, auto ns) {
+    return launch_vpass_t<decltype(rt)::value, decltype(ns)::value>(p, mode, U, u_stride, Uold,
+                                                                   Vold, Ginv, g_stride, st);
+  });
 }
 
 hipError_t launch_client_factor(const DevParams& p, hipStream_t st) {
@@ -800,15 +976,10 @@ hipError_t launch_client_factor(const DevParams& p, hipStream_t st) {
 hipError_t launch_spass(const DevParams& p, const float* U, int64_t u_stride, float* Sout,
                         int64_t lds_out, int emit_only, int client_base, int client_count,
                         hipStream_t st) {
-  dim3 grid(p.nrb, client_count), block(256);
-  switch (p.RP / 16) {
-    case 1: hipLaunchKernelGGL(k_spass<1>, grid, block, 0, st, p, U, u_stride, Sout, lds_out, emit_only, client_base); break;
-    case 2: hipLaunchKernelGGL(k_spass<2>, grid, block, 0, st, p, U, u_stride, Sout, lds_out, emit_only, client_base); break;
-    case 3: hipLaunchKernelGGL(k_spass<3>, grid, block, 0, st, p, U, u_stride, Sout, lds_out, emit_only, client_base); break;
-    case 4: hipLaunchKernelGGL(k_spass<4>, grid, block, 0, st, p, U, u_stride, Sout, lds_out, emit_only, client_base); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return with_rank(p, [&](auto rt, auto ns) {
+    return launch_spass_t<decltype(rt)::value, decltype(ns)::value>(
+        p, U, u_stride, Sout, lds_out, emit_only, client_base, client_count, st);
+  });
 }
 
 hipError_t launch_uupdate(const DevParams& p, float* Uout, int64_t uout_stride,
@@ -836,11 +1007,11 @@ hipError_t launch_gram_init(const DevParams& p, const float* U, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t launch_copy_in_U(const DevParams& p, const float* U0, int64_t ldu, float* Ucol,
+hipError_t launch_copy_in_U(const DevParams& p, const float* U0, int64_t ldu, float* Ufb,
                             hipStream_t st) {
   const int64_t tot = (int64_t)p.RP * p.MP;
   hipLaunchKernelGGL(k_copy_in_U, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, p, U0,
-                     ldu, Ucol);
+                     ldu, Ufb);
   return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ def test_parameter_validation_messages(lib):
     assert params_error(ok) is None
     cases = [
         (dict(m=0, widths=[3], r=1, rho=0.1, lam=0.1), "m must"),
+        (dict(m=1 << 26, widths=[3], r=1, rho=0.1, lam=0.1), "m must"),
         (dict(m=10, widths=[3, 0], r=1, rho=0.1, lam=0.1), "n_i"),
         (dict(m=10, widths=[3], r=0, rho=0.1, lam=0.1), "r must"),
         (dict(m=10, widths=[3], r=65, rho=0.1, lam=0.1), "r must"),
