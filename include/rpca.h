@@ -157,12 +157,13 @@ rpca_status rpca_get_stats(rpca_ctx* c, int64_t round, rpca_stats* out);
 
 /* Kernel phases of one local step, for rpca_profile. */
 typedef enum {
-  RPCA_PHASE_VPASS = 0,          /* V_i ridge solve: W = (M_i - S_i)^T U, V = W G^{-1} */
+  RPCA_PHASE_VPASS = 0,          /* V_i ridge solve, streaming part: W = (M_i - S_i)^T U */
   RPCA_PHASE_SPASS = 1,          /* fused U V_i^T, soft-threshold into S_i, Lambda V_i */
   RPCA_PHASE_CLIENT_FACTOR = 2,  /* per-client r x r factors of the closed U step */
   RPCA_PHASE_UUPDATE = 3,        /* U step and consensus mean, Gram partials */
-  RPCA_PHASE_FINALIZE = 4,       /* r x r Gram, FP64 Cholesky inverse, statistics */
-  RPCA_NUM_PHASES = 5
+  RPCA_PHASE_FINALIZE = 4,       /* r x r Gram, its FP64 inverse, round statistics */
+  RPCA_PHASE_VFINAL = 5,         /* V_i ridge solve, finishing part: V = W G^{-1}, V_i^T V_i */
+  RPCA_NUM_PHASES = 6
 } rpca_phase;
 
 /* Measurement hook: run `rounds` rounds like rpca_step, with a HIP event pair

@@ -250,12 +250,12 @@ class DCFPCA:
         self._check(self._lib.rpca_get_stats(self.ctx, int(round_index), ctypes.byref(out)))
         return out.as_dict()
 
-    PHASES = ("vpass", "spass", "client_factor", "uupdate", "finalize")
+    PHASES = ("vpass", "spass", "client_factor", "uupdate", "finalize", "vfinal")
 
     def profile(self, rounds: int) -> dict:
         """Average launch duration (ms) and launch count per kernel phase."""
-        avg = (c_double * 5)()
-        cnt = (c_int64 * 5)()
+        avg = (c_double * len(self.PHASES))()
+        cnt = (c_int64 * len(self.PHASES))()
         self._check(self._lib.rpca_profile(self.ctx, int(rounds), avg, cnt))
         return {ph: (float(avg[k]), int(cnt[k])) for k, ph in enumerate(self.PHASES)}
 

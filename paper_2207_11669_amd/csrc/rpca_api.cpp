@@ -229,8 +229,9 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     const int vn = c->vcur ^ 1;
     const DevParams q = with_v(c, vn);
     RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
-                launch_vpass(q, mode, Ucons, 0, c->U[c->cur ^ 1], c->V[c->vcur], c->Ginv, 0, st),
+                launch_vpass(q, mode, Ucons, 0, c->U[c->cur ^ 1], c->V[c->vcur], st),
                 "V-pass launch");
+    RPCA_LAUNCH(c, prof, RPCA_PHASE_VFINAL, launch_vfinal(q, c->Ginv, 0, st), "V finish launch");
     if (p.u_mode == RPCA_U_CLOSED)
       RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(q, st), "client factor launch");
     RPCA_LAUNCH(c, prof, RPCA_PHASE_SPASS, launch_spass(q, Ucons, 0, nullptr, 0, 0, 0, p.E, st), "S-pass launch");
@@ -251,7 +252,8 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
       const int vn = c->vcur ^ 1;
       const DevParams q = with_v(c, vn);
       RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
-                  launch_vpass(q, kSStored, Uin, us, nullptr, nullptr, Gin, gs, st), "V-pass launch");
+                  launch_vpass(q, kSStored, Uin, us, nullptr, nullptr, st), "V-pass launch");
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_VFINAL, launch_vfinal(q, Gin, gs, st), "V finish launch");
       c->vcur = vn;
       if (p.u_mode == RPCA_U_CLOSED && qi == c->inner - 1)
         RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(q, st), "client factor launch");

@@ -108,11 +108,14 @@ constexpr int kDistBlocks = 64;  // work-groups per side of the factor-distance 
 // S source for the V-pass: zero, the stored S buffer, or recomputed from the
 // previous round's factors.
 enum VMode { kSZero = 0, kSStored = 1, kSRecompute = 2 };
-// V-pass into p.V. U: factor block of the input U (client stride u_stride);
-// Uold / Vold: previous U factor block and previous V buffer (kSRecompute).
+// V-pass, streaming part: partial W = (M_i - S_i)^T U_i per row split into
+// p.Wpart. U: factor block of the input U (client stride u_stride); Uold /
+// Vold: previous U factor block and previous V buffer (kSRecompute).
 hipError_t launch_vpass(const DevParams& p, int mode, const float* U, int64_t u_stride,
-                        const float* Uold, const float* Vold, const double* Ginv,
-                        int64_t g_stride, hipStream_t st);
+                        const float* Uold, const float* Vold, hipStream_t st);
+// V-pass, finishing part: V = W G^{-1} into p.V, and the V_i^T V_i partials.
+hipError_t launch_vfinal(const DevParams& p, const double* Ginv, int64_t g_stride,
+                         hipStream_t st);
 hipError_t launch_client_factor(const DevParams& p, hipStream_t st);
 // S-pass over clients [client_base, client_base + client_count) with V = p.V.
 // Sout/lds_out: column-major buffer S is written to, indexed by global column

@@ -12,8 +12,13 @@
 //              CLOSED (P_i + U_i V_i^T V_i)(V_i^T V_i + rho n_i/n I)^{-1}
 //              and, at the last local step, the mean over clients (eq. "U_agg")
 //              together with partial Gram matrices of the new U;
-//   finalize : U^T U + rho I, its FP64 Cholesky factor and inverse, and the
-//              round's FP64 statistics.
+//   finalize : U^T U + rho I and its FP64 inverse (a Gauss-Jordan sweep, which
+//              needs no pivoting on an SPD matrix), and the round's FP64
+//              statistics.
+// With K = 1 and one V/S alternation, S_i is not stored: the next V-pass
+// rebuilds it as soft(M_i - U^(t-1) V_i^T) from the previous factors, which
+// gives bitwise the S the S-pass computed, so each round streams M twice and
+// nothing else of size m x n.
 // The rank-r contractions run on the fp32 MFMA (v_mfma_f32_16x16x4f32); the
 // r x r algebra and all reductions that feed a convergence test are FP64.
 #include "rpca_internal.h"
@@ -76,19 +81,27 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // In-place inverse of an r x r SPD matrix A (row stride ld, in LDS) by a
-// Gauss-Jordan sweep without pivoting: the k-th pivot is a diagonal entry of a
-// Schur complement of an SPD matrix, hence positive, and every step updates all
-// r^2 entries in parallel (no serial triangular solves). A pivot that is not
-// positive (non-SPD or NaN input) turns the result into NaN, which the round
-// statistics then expose.
+// Gauss-Jordan sweep without pivoting, run by the whole work-group (at least
+// r*r/4 threads): the k-th pivot is a diagonal entry of a Schur complement of
+// an SPD matrix, hence positive, and every step updates all r^2 entries in
+// parallel (no serial triangular solves). Each thread owns up to four entries,
+// indexed once. A pivot that is not positive (non-SPD or NaN input) turns the
+// result into NaN, which the round statistics then expose.
 __device__ void spd_inverse(double* A, int r, int ld) {
   __shared__ double colk[kMaxRank], rowk[kMaxRank];
   __shared__ double pinv_sh;
   const int tid = threadIdx.x, nt = blockDim.x;
+  int ei[4], ej[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + q * nt;
+    ei[q] = e < r * r ? e / r : -1;
+    ej[q] = e < r * r ? e % r : -1;
+  }
   for (int k = 0; k < r; ++k) {
-    for (int i = tid; i < r; i += nt) {
-      colk[i] = A[i * ld + k];
-      rowk[i] = A[k * ld + i];
+    if (tid < r) {
+      colk[tid] = A[tid * ld + k];
+      rowk[tid] = A[k * ld + tid];
     }
     if (tid == 0) {
       const double pv = A[k * ld + k];
@@ -96,16 +109,19 @@ __device__ void spd_inverse(double* A, int r, int ld) {
     }
     __syncthreads();
     const double pinv = pinv_sh;
-    for (int e = tid; e < r * r; e += nt) {
-      const int i = e / r, j = e % r;
-      double v;
-      if (i == k)
-        v = (j == k) ? pinv : rowk[j] * pinv;
-      else if (j == k)
-        v = -colk[i] * pinv;
-      else
-        v = A[i * ld + j] - colk[i] * rowk[j] * pinv;
-      A[i * ld + j] = v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ei[q], j = ej[q];
+      if (i >= 0) {
+        double v;
+        if (i == k)
+          v = (j == k) ? pinv : rowk[j] * pinv;
+        else if (j == k)
+          v = -colk[i] * pinv;
+        else
+          v = A[i * ld + j] - colk[i] * rowk[j] * pinv;
+        A[i * ld + j] = v;
+      }
     }
     __syncthreads();
   }
@@ -116,21 +132,22 @@ __device__ __forceinline__ double eta_of_round(const DevParams& p, int64_t t) {
   return p.eta_sched == 1 ? p.eta0 / sqrt((double)t + 1.0) : p.eta0;
 }
 
-// Sum of count strided FP64 values, four independent chains so that the loads
-// of a long partial list are in flight together.
-__device__ __forceinline__ double sum_strided(const double* __restrict__ x, int count,
+// Sum of count strided values in FP64, in a fixed order; loads are issued in
+// batches of 16 so that a long list of partials costs a few memory latencies.
+template <class T>
+__device__ __forceinline__ double sum_strided(const T* __restrict__ x, int count,
                                               int64_t stride) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int k = 0;
-#pragma unroll 2
-  for (; k + 4 <= count; k += 4) {
-    s0 += x[(int64_t)k * stride];
-    s1 += x[(int64_t)(k + 1) * stride];
-    s2 += x[(int64_t)(k + 2) * stride];
-    s3 += x[(int64_t)(k + 3) * stride];
+  double s = 0.0;
+  for (int k = 0; k < count; k += 16) {
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = (k + u < count) ? x[(int64_t)(k + u) * stride] : T(0);
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t += (double)v[u];
+    s += t;
   }
-  for (; k < count; ++k) s0 += x[(int64_t)k * stride];
-  return (s0 + s1) + (s2 + s3);
+  return s;
 }
 
 // Store element (a, c) of a factor with `rows` rows into its factor block
@@ -305,15 +322,7 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
   const int64_t split_stride = (int64_t)p.NVP * RP;
   for (int e = tid; e < kVCols * RP; e += blockDim.x) {
     const int j = e / RP, c = e % RP;
-    double s0 = 0.0, s1 = 0.0;
-    const float* src = p.Wpart + (int64_t)(vrow + j) * RP + c;
-    int q = 0;
-    for (; q + 2 <= p.vsplit; q += 2) {
-      s0 += (double)src[(int64_t)q * split_stride];
-      s1 += (double)src[(int64_t)(q + 1) * split_stride];
-    }
-    if (q < p.vsplit) s0 += (double)src[(int64_t)q * split_stride];
-    wd[j][c] = s0 + s1;
+    wd[j][c] = sum_strided(p.Wpart + (int64_t)(vrow + j) * RP + c, p.vsplit, split_stride);
   }
   for (int e = tid; e < RP * RP; e += blockDim.x) gl[e] = Gi[e];
   __syncthreads();
@@ -359,7 +368,7 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
 //   A_i = (V_i^T V_i + c_i I)^{-1},  B_i = V_i^T V_i A_i,  c_i = rho n_i / n.
 // One work-group per client; FP64 throughout.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_client_factor(DevParams p) {
+__global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
   __shared__ double A[kMaxRank * kMaxRank], G[kMaxRank * kMaxRank];
   const int r = p.r, RP = p.RP;
   const int64_t RR = (int64_t)RP * RP;
@@ -631,7 +640,23 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (int i = i_first; i < i_last; ++i) {
+  // Clients are summed in order, four at a time so that their loads are in
+  // flight together.
+  int i = i_first;
+  for (; i + 4 <= i_last; i += 4) {
+    float tv[4][NQ];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float* __restrict__ Ti = p.P + (int64_t)(i + u) * RP * MP + a;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) tv[u][q] = Ti[(int64_t)(cq + 4 * q) * MP];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[q] += (double)tv[u][q];
+  }
+  for (; i < i_last; ++i) {
     const float* __restrict__ Ti = p.P + (int64_t)i * RP * MP + a;
     float tv[NQ];
 #pragma unroll
@@ -916,8 +941,7 @@ __global__ void k_dist_final(const double* __restrict__ part2, double* __restric
 // ---------------------------------------------------------------------------
 template <int RT, int NS>
 static hipError_t launch_vpass_t(const DevParams& p, int mode, const float* U, int64_t u_stride,
-                                 const float* Uold, const float* Vold, const double* Ginv,
-                                 int64_t g_stride, hipStream_t st) {
+                                 const float* Uold, const float* Vold, hipStream_t st) {
   dim3 grid(p.ng64, p.vsplit), block(256);
   if (mode == kSZero)
     hipLaunchKernelGGL((k_vpass<RT, NS, kSZero>), grid, block, 0, st, p, U, u_stride, Uold, Vold);
@@ -926,8 +950,11 @@ static hipError_t launch_vpass_t(const DevParams& p, int mode, const float* U, i
   else
     hipLaunchKernelGGL((k_vpass<RT, NS, kSRecompute>), grid, block, 0, st, p, U, u_stride, Uold,
                        Vold);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+template <int RT>
+static hipError_t launch_vfinal_t(const DevParams& p, const double* Ginv, int64_t g_stride,
+                                  hipStream_t st) {
   hipLaunchKernelGGL(k_vfinal<RT>, dim3(p.ngroups), dim3(256), 0, st, p, Ginv, g_stride);
   return hipGetLastError();
 }
@@ -960,16 +987,22 @@ static hipError_t with_rank(const DevParams& p, F&& f) {
 }
 
 hipError_t launch_vpass(const DevParams& p, int mode, const float* U, int64_t u_stride,
-                        const float* Uold, const float* Vold, const double* Ginv,
-                        int64_t g_stride, hipStream_t st) {
+                        const float* Uold, const float* Vold, hipStream_t st) {
   return with_rank(p, [&](auto rt, auto ns) {
     return launch_vpass_t<decltype(rt)::value, decltype(ns)::value>(p, mode, U, u_stride, Uold,
-                                                                   Vold, Ginv, g_stride, st);
+                                                                   Vold, st);
+  });
+}
+
+hipError_t launch_vfinal(const DevParams& p, const double* Ginv, int64_t g_stride,
+                         hipStream_t st) {
+  return with_rank(p, [&](auto rt, auto) {
+    return launch_vfinal_t<decltype(rt)::value>(p, Ginv, g_stride, st);
   });
 }
 
 hipError_t launch_client_factor(const DevParams& p, hipStream_t st) {
-  hipLaunchKernelGGL(k_client_factor, dim3(p.E), dim3(256), 0, st, p);
+  hipLaunchKernelGGL(k_client_factor, dim3(p.E), dim3(1024), 0, st, p);
   return hipGetLastError();
 }
 
