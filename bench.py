@@ -112,6 +112,18 @@ def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_r
             "final_relerr": err, "max_rounds": max_rounds, "check_every": 10}
 
 
+def copy_calibration() -> int:
+    import torch
+    n = (256 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.zeros(n, dtype=torch.float32, device="cuda:0")
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,7 +135,12 @@ def main() -> int:
     ap.add_argument("--fixed-point-rounds", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-relerr", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device to device three times (a kernel of known "
+                         "traffic, to scale hardware byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the DCF-PCA path here runs every client on a "

@@ -67,6 +67,15 @@ __device__ __forceinline__ uint32_t block_bytes_from(int n, int j0, int64_t ldm)
   const int64_t b = (int64_t)(n - j0) * ldm * 4;
   return b > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)b;
 }
+// Range of a resource over one 16-column chunk: every offset a chunk uses is
+// below 64 ldm <= 0xFFFFFF00 bytes (ldm < 2^26), so kOffNone always falls
+// outside it and loads at kOffNone return 0.
+constexpr uint32_t kChunkRange = 0xFFFFFF00u;
+constexpr uint32_t kOffNone = 0xFFFFFF80u;
+__device__ __forceinline__ uint32_t chunk_bytes_from(int n, int j0, int64_t ldm) {
+  const uint32_t b = block_bytes_from(n, j0, ldm);
+  return b > kChunkRange ? kChunkRange : b;
+}
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   // D[i][j] += sum_k A[i][k] B[k][j] over a 16x16x4 tile. Lane l supplies
@@ -408,8 +417,8 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
 // The contraction index of MFMA 1 is split as k-group g = l/16 taking rank
 // indices g*NS + s, s < NS = ceil(r/4), so no padding steps run for r % 16.
 // ---------------------------------------------------------------------------
-template <int RT, int NS>
-__global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restrict__ Ubase,
+template <int RT, int NS, bool STORE>
+__global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restrict__ Ubase,
                                                int64_t u_stride, float* __restrict__ Sout,
                                                int64_t lds_out, int emit_only, int client_base) {
   constexpr int RP = 16 * RT;
@@ -417,7 +426,11 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
   const int b = blockIdx.x, ci = client_base + (int)blockIdx.y;
   const ClientDev cl = p.clients[ci];
   const float* __restrict__ U = Ubase + (int64_t)ci * u_stride;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lg = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) & 3;
+  // Wave-uniform (waves 0-3: phase 0, waves 4-7: phase 1); readfirstlane tells
+  // the compiler so, which keeps the chunk addressing in scalar registers.
+  const int phase = __builtin_amdgcn_readfirstlane(tid >> 8);
+  const int li = lane & 15, lg = lane >> 4;
   const int arow0 = b * kSRows + w * 32;
 
   float ub[2][NS];  // MFMA 1 B operand: U[row arow0 + 16 rt + l%16][rank (l/16)*NS + s]
@@ -436,25 +449,33 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
 
-  double sl2 = 0.0, sl1 = 0.0, snz = 0.0;
+  double sl2 = 0.0, sl1 = 0.0;
+  uint32_t nnz = 0;  // wave-uniform count of nonzero S entries
   const float lam = p.lam;
-  GLOBAL float* Sblk = Sout ? gptr_w(Sout) + cl.col0 * lds_out : nullptr;
+  GLOBAL float* Sblk = STORE ? gptr_w(Sout) + cl.col0 * lds_out : nullptr;
   // V operands: packed, always in range (lane offset + scalar chunk offset).
   const rsrc_t rVa = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pa_off(p.NVP, RP), (uint32_t)(p.NVP * 4 * NS * 4));
   const rsrc_t rVb = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pb_off(p.NVP, RP, NS), (uint32_t)(p.NVP * RP * 4));
   // M: one buffer resource per 16-column chunk (base at the chunk's first
-  // column, range = the rest of the block), fixed per-lane offsets; columns
-  // past n_i read 0. Rows past m are clamped here and masked when used.
+  // column, range = the rest of the block, at most kChunkRange), fixed per-lane
+  // offsets. Columns past n_i fall outside the range and rows past m get an
+  // offset beyond any range, so both read 0. The padding rows of U and of the
+  // client's V block are 0 as well, hence R = 0 there and such entries add
+  // nothing to S, Lambda or the statistics: no per-entry masks are needed.
   uint32_t vm[2][4];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      vm[rt][v] = ((uint32_t)((4 * lg + v) * cl.ldm) + (uint32_t)min(arow0 + 16 * rt + li, p.m - 1)) * 4u;
+    for (int v = 0; v < 4; ++v) {
+      const int row = arow0 + 16 * rt + li;
+      vm[rt][v] = row < p.m ? ((uint32_t)((4 * lg + v) * cl.ldm) + (uint32_t)row) * 4u : kOffNone;
+    }
 
   // Operands of one 16-column chunk; a ring of kSDepth chunks is kept in
   // flight so that each wave has several chunks of M loads outstanding (vector
   // loads complete in order, so everything a chunk needs is issued together).
+  // The two halves of the work-group (phase 0, 1) take alternate chunks; their
+  // partial P are summed in LDS at the end.
   struct Chunk {
     float m[2][4];   // M[row][col] for this lane's rows (two 16-row tiles) and 4 columns
     float va[NS];    // MFMA 1 A operand (V A-packing): V[col j0 + l%16][rank (l/16)*NS + s]
@@ -463,74 +484,75 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
   constexpr int kSDepth = 3;
   Chunk ring[kSDepth];
   const int nch = (cl.n + 15) >> 4;
-  auto load_chunk = [&](Chunk& c, int ch) {
-    const int j0 = ch << 4;
+  const int nk = (nch - phase + 1) >> 1;  // chunks phase, phase + 2, ... below nch
+  auto load_chunk = [&](Chunk& c, int k) {
+    const int j0 = (phase + 2 * k) << 4;
     const uint32_t vch = (uint32_t)((cl.vrow0 + j0) >> 4);
 #pragma unroll
     for (int s = 0; s < NS; ++s) c.va[s] = bload(rVa, (uint32_t)lane * 4u, ((vch * NS + s) * 64u) * 4u);
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct) c.vb[ct] = bload4(rVb, (uint32_t)lane * 16u, ((vch * RT + ct) * 64u) * 16u);
-    const rsrc_t rM = make_rsrc(cl.M + (int64_t)j0 * cl.ldm, block_bytes_from(cl.n, j0, cl.ldm));
+    const rsrc_t rM = make_rsrc(cl.M + (int64_t)j0 * cl.ldm, chunk_bytes_from(cl.n, j0, cl.ldm));
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) c.m[rt][v] = bload(rM, vm[rt][v], 0);
   };
-  auto compute_chunk = [&](const Chunk& c, int ch) {
-    const int j0 = ch << 4;
+  auto compute_chunk = [&](const Chunk& c, int k) {
+    const int j0 = (phase + 2 * k) << 4;
+    float l2 = 0.f, l1 = 0.f;
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
-      const int row = arow0 + 16 * rt + li;
-      const bool rok = row < p.m;
       f4 a1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < NS; ++s) a1 = mfma4(c.va[s], ub[rt][s], a1);
       f4 lamv;
-      float l2 = 0.f, l1 = 0.f, nz = 0.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int col = j0 + 4 * lg + v;
-        const bool ok = rok && col < cl.n;
-        // Columns past n_i (tail or padding chunk) contribute nothing.
-        const float R = ok ? c.m[rt][v] - a1[v] : 0.f;
-        const float L = fminf(fmaxf(R, -lam), lam);
+        const float R = c.m[rt][v] - a1[v];
+        const float L = __builtin_amdgcn_fmed3f(R, -lam, lam);  // clip(R, -lam, lam)
         const float Sv = R - L;
-        if (Sblk && ok) Sblk[(int64_t)col * lds_out + row] = Sv;
+        if (STORE) {
+          const int row = arow0 + 16 * rt + li, col = j0 + 4 * lg + v;
+          if (row < p.m && col < cl.n) Sblk[(int64_t)col * lds_out + row] = Sv;
+        }
         lamv[v] = L;
-        l2 += L * L;
+        l2 = fmaf(L, L, l2);
         l1 += fabsf(Sv);
-        nz += (Sv != 0.f) ? 1.f : 0.f;
+        nnz += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(Sv != 0.f));
       }
-      sl2 += (double)l2;
-      sl1 += (double)l1;
-      snz += (double)nz;
 #pragma unroll
       for (int ct = 0; ct < RT; ++ct)
 #pragma unroll
         for (int s = 0; s < 4; ++s) accp[rt][ct] = mfma4(lamv[s], c.vb[ct][s], accp[rt][ct]);
     }
+    sl2 += (double)l2;
+    sl1 += (double)l1;
   };
-  // Uniform loop: every iteration loads (chunk index clamped to the last
-  // chunk), so the wait counts stay exact; padding chunks are fully masked.
-  const int nchp = (nch + kSDepth - 1) / kSDepth * kSDepth;
-  // The prologue issues the ring in slot order (fenced like the loop body),
-  // so that at the loop head slot 0 holds the oldest loads on every path.
-#pragma unroll
-  for (int d = 0; d < kSDepth; ++d) {
-    load_chunk(ring[d], min(d, nch - 1));
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  for (int c0 = 0; c0 < nchp; c0 += kSDepth) {
+  // Uniform loop: every iteration loads (chunk index clamped to the wave's
+  // last chunk), so the wait counts stay exact; iterations past the wave's
+  // chunks compute nothing (a wave-uniform branch).
+  if (nk > 0) {
+    const int nkp = (nk + kSDepth - 1) / kSDepth * kSDepth;
+    // The prologue issues the ring in slot order (fenced like the loop body),
+    // so that at the loop head slot 0 holds the oldest loads on every path.
 #pragma unroll
     for (int d = 0; d < kSDepth; ++d) {
-      const int ch = c0 + d;
-      compute_chunk(ring[d], ch);
-      // Keep the refill at this point of the program: left alone, the
-      // scheduler sinks loads towards their first use and the ring collapses
-      // to a single chunk in flight.
+      load_chunk(ring[d], min(d, nk - 1));
       __builtin_amdgcn_sched_barrier(0);
-      load_chunk(ring[d], min(ch + kSDepth, nch - 1));
-      __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int k0 = 0; k0 < nkp; k0 += kSDepth) {
+#pragma unroll
+      for (int d = 0; d < kSDepth; ++d) {
+        const int k = k0 + d;
+        if (k < nk) compute_chunk(ring[d], k);
+        // Keep the refill at this point of the program: left alone, the
+        // scheduler sinks loads towards their first use and the ring
+        // collapses to a single chunk in flight.
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk(ring[d], min(k + kSDepth, nk - 1));
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
 
@@ -543,12 +565,23 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
   __shared__ float ptile[kSRows][RP + 1];
   __shared__ float utile[kSRows][RP + 1];
   __shared__ double fab[2][RP * RP];
+  if (phase == 0) {
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < RT; ++ct)
+      for (int ct = 0; ct < RT; ++ct)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) ptile[w * 32 + 16 * rt + 4 * lg + v][16 * ct + li] = accp[rt][ct][v];
+        for (int v = 0; v < 4; ++v) ptile[w * 32 + 16 * rt + 4 * lg + v][16 * ct + li] = accp[rt][ct][v];
+  }
+  __syncthreads();
+  if (phase == 1) {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ptile[w * 32 + 16 * rt + 4 * lg + v][16 * ct + li] += accp[rt][ct][v];
+  }
   const int row0 = b * kSRows;
   for (int e = tid; e < kSRows * RP; e += blockDim.x) {
     const int rl = e % kSRows, c = e / kSRows;
@@ -584,21 +617,25 @@ __global__ __launch_bounds__(256) void k_spass(DevParams p, const float* __restr
     Ti[(int64_t)c * p.MP + row0 + rl] = (float)t;
   }
 
-  __shared__ double sred[4][3];
+  __shared__ double sred[8][3];
   sl2 = wave_sum(sl2);
   sl1 = wave_sum(sl1);
-  snz = wave_sum(snz);
+  const int wv = tid >> 6;
   if (lane == 0) {
-    sred[w][0] = sl2;
-    sred[w][1] = sl1;
-    sred[w][2] = snz;
+    sred[wv][0] = sl2;
+    sred[wv][1] = sl1;
+    sred[wv][2] = (double)nnz;
   }
   __syncthreads();
   if (tid == 0) {
     double* o = p.spart + ((int64_t)ci * p.nrb + b) * 4;
-    o[0] = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
-    o[1] = sred[0][1] + sred[1][1] + sred[2][1] + sred[3][1];
-    o[2] = sred[0][2] + sred[1][2] + sred[2][2] + sred[3][2];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t += sred[k][q];
+      o[q] = t;
+    }
     o[3] = 0.0;
   }
 }
@@ -963,8 +1000,12 @@ template <int RT, int NS>
 static hipError_t launch_spass_t(const DevParams& p, const float* U, int64_t u_stride, float* Sout,
                                  int64_t lds_out, int emit_only, int client_base,
                                  int client_count, hipStream_t st) {
-  hipLaunchKernelGGL((k_spass<RT, NS>), dim3(p.nrb, client_count), dim3(256), 0, st, p, U,
-                     u_stride, Sout, lds_out, emit_only, client_base);
+  if (Sout)
+    hipLaunchKernelGGL((k_spass<RT, NS, true>), dim3(p.nrb, client_count), dim3(512), 0, st, p, U,
+                       u_stride, Sout, lds_out, emit_only, client_base);
+  else
+    hipLaunchKernelGGL((k_spass<RT, NS, false>), dim3(p.nrb, client_count), dim3(512), 0, st, p, U,
+                       u_stride, Sout, lds_out, emit_only, client_base);
   return hipGetLastError();
 }
 
