@@ -195,10 +195,11 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
   const VGroup vg = p.vg64[blockIdx.x];
   const ClientDev cl = p.clients[vg.client];
   const float* __restrict__ U = Ubase + (int64_t)vg.client * u_stride;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lg = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  // Wave-uniform; readfirstlane lets the compiler keep the buffer resources
+  // built from it in scalar registers (no per-load uniformity loops).
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int j0 = vg.j0 + 16 * w;  // client-local first column of this wave's tile
-  const int col = j0 + li;
-  const bool colok = col < cl.n;
   const float lam = p.lam;
 
   const float* gUpb_raw = U + fb_pb_off(p.MP, RP, NS);
@@ -254,12 +255,11 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
     }
   };
   auto compute_chunk = [&](const Chunk& c, int ch) {
-    // Rows outside [rbeg, rend) (tail chunk, or a padding chunk that reuses
-    // the last chunk's registers) and columns past n_i contribute nothing.
+    // Columns past n_i read 0 from M (and S) and have zero rows in the old V,
+    // so they give d = 0 without a mask; only the chunk that crosses row m
+    // (whose last float4 may hold the caller's padding rows) is masked.
     const int row = rbeg + (ch << 4) + 4 * lg;
-    bool ok[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) ok[e] = colok && row + e < rend;
+    const bool tail = rbeg + (ch << 4) + 16 > p.m;  // wave-uniform
     f4 d;
     if (MODE == kSRecompute) {
       f4 a1 = {0.f, 0.f, 0.f, 0.f};
@@ -268,12 +268,16 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const float R = c.m[e] - a1[e];
-        const float Sv = R - fminf(fmaxf(R, -lam), lam);
-        d[e] = ok[e] ? c.m[e] - Sv : 0.f;
+        const float Sv = R - __builtin_amdgcn_fmed3f(R, -lam, lam);
+        d[e] = c.m[e] - Sv;
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) d[e] = ok[e] ? c.m[e] - (MODE == kSStored ? c.s[e] : 0.f) : 0.f;
+      for (int e = 0; e < 4; ++e) d[e] = c.m[e] - (MODE == kSStored ? c.s[e] : 0.f);
+    }
+    if (tail) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) d[e] = row + e < p.m ? d[e] : 0.f;
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -295,7 +299,7 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
 #pragma unroll
     for (int d = 0; d < kVDepth; ++d) {
       const int ch = c0 + d;
-      compute_chunk(ring[d], ch);
+      if (ch < nch) compute_chunk(ring[d], ch);  // wave-uniform
       // Keep the refill at this point of the program: left alone, the
       // scheduler sinks loads towards their first use and the ring collapses
       // to a single chunk in flight.
