@@ -73,6 +73,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch wheels carry their own HIP runtime; loading torch first makes the
+    # library bind to that same runtime, so that torch's streams and device
+    # pointers are valid in it.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build the HIP library first "
                            "(python -c 'import __graft_entry__ as g; g.build()')")

@@ -18,6 +18,11 @@ struct rpca_ctx {
   std::vector<int64_t> col_off;  // first global column of each client, [E + 1]
   hipStream_t stream = nullptr;
   int64_t rounds = 0;
+  // The last local step's finalize (Gram inverse of the new U and the round
+  // statistics) is deferred into the next round's V-pass launch, which runs it
+  // in one extra work-group next to the streaming ones. Calls that read its
+  // outputs flush it first with a standalone launch.
+  bool fin_pending = false;
   int cur = 0;   // consensus U buffer holding U^(t)
   int vcur = 0;  // V buffer holding the latest V
   int inner = 1;
@@ -50,7 +55,7 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t S, U0, U1, Uc0, Uc1, V0, V1, Wpart, P, gv, Af, Bf, gram, spart, upart,
-      ucl, Ginv, dstate, hist, clients, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
+      ucl, Ginv, dstate, hist, stat_part, clients, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
       total;
   int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows;
   bool recompute;
@@ -143,6 +148,7 @@ Layout make_layout(const rpca_params* p) {
   L.Ginv = take((size_t)(1 + (multi ? E : 0)) * RR * d);
   L.dstate = take(sizeof(DevState));
   L.hist = take((size_t)kHist * sizeof(StatsRec));
+  L.stat_part = take((size_t)8 * d);
   L.clients = take((size_t)E * sizeof(ClientDev));
   L.vgroups = take((size_t)L.ngroups * sizeof(VGroup));
   L.vg64 = take((size_t)L.ng64 * sizeof(VGroup));
@@ -228,16 +234,19 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     const int mode = c->rounds == 0 ? kSZero : kSRecompute;
     const int vn = c->vcur ^ 1;
     const DevParams q = with_v(c, vn);
+    double* fin = c->fin_pending ? c->Ginv : nullptr;
+    c->fin_pending = false;
     RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
-                launch_vpass(q, mode, Ucons, 0, c->U[c->cur ^ 1], c->V[c->vcur], st),
+                launch_vpass(q, mode, Ucons, 0, c->U[c->cur ^ 1], c->V[c->vcur], fin, st),
                 "V-pass launch");
-    RPCA_LAUNCH(c, prof, RPCA_PHASE_VFINAL, launch_vfinal(q, c->Ginv, 0, st), "V finish launch");
+    RPCA_LAUNCH(c, prof, RPCA_PHASE_VFINAL, launch_vfinal(q, c->Ginv, 0, fin ? 1 : 0, st),
+                "V finish launch");
     if (p.u_mode == RPCA_U_CLOSED)
       RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(q, st), "client factor launch");
     RPCA_LAUNCH(c, prof, RPCA_PHASE_SPASS, launch_spass(q, Ucons, 0, nullptr, 0, 0, 0, p.E, st), "S-pass launch");
     RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE, launch_uupdate(q, c->U[c->cur ^ 1], 0, Ucons, 1, st),
                 "U update launch");
-    RPCA_LAUNCH(c, prof, RPCA_PHASE_FINALIZE, launch_finalize(q, c->Ginv, 0, 0, 1, st), "finalize launch");
+    c->fin_pending = true;
     c->vcur = vn;
     c->cur ^= 1;
     c->rounds += 1;
@@ -251,9 +260,12 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     for (int qi = 0; qi < c->inner; ++qi) {
       const int vn = c->vcur ^ 1;
       const DevParams q = with_v(c, vn);
+      double* fin = c->fin_pending ? c->Ginv : nullptr;
+      c->fin_pending = false;
       RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
-                  launch_vpass(q, kSStored, Uin, us, nullptr, nullptr, st), "V-pass launch");
-      RPCA_LAUNCH(c, prof, RPCA_PHASE_VFINAL, launch_vfinal(q, Gin, gs, st), "V finish launch");
+                  launch_vpass(q, kSStored, Uin, us, nullptr, nullptr, fin, st), "V-pass launch");
+      RPCA_LAUNCH(c, prof, RPCA_PHASE_VFINAL, launch_vfinal(q, Gin, gs, fin ? 1 : 0, st),
+                  "V finish launch");
       c->vcur = vn;
       if (p.u_mode == RPCA_U_CLOSED && qi == c->inner - 1)
         RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(q, st), "client factor launch");
@@ -262,7 +274,7 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     if (k == p.K - 1) {
       RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE, launch_uupdate(p, c->U[c->cur ^ 1], 0, Ucons, 1, st),
                   "U update launch");
-      RPCA_LAUNCH(c, prof, RPCA_PHASE_FINALIZE, launch_finalize(p, c->Ginv, 0, 0, 1, st), "finalize launch");
+      c->fin_pending = true;
     } else {
       RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE, launch_uupdate(p, c->Uc[k & 1], ustride, nullptr, 0, st),
                   "U update launch");
@@ -282,6 +294,15 @@ namespace {
 rpca_status guard(rpca_ctx* c) {
   if (!c) return RPCA_EINVAL;
   if (c->poisoned) return RPCA_ESTATE;
+  return RPCA_OK;
+}
+
+// Run a deferred finalize now (before reading statistics or the Gram inverse).
+rpca_status flush_finalize(rpca_ctx* c) {
+  if (c->fin_pending) {
+    RPCA_HIP(c, launch_finalize(c->p, c->Ginv, 0, 0, 1, c->stream), "finalize launch");
+    c->fin_pending = false;
+  }
   return RPCA_OK;
 }
 
@@ -369,6 +390,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.ucl_sq = reinterpret_cast<double*>(ws + L.ucl);
   p.dstate = reinterpret_cast<DevState*>(ws + L.dstate);
   p.hist = reinterpret_cast<StatsRec*>(ws + L.hist);
+  p.stat_part = reinterpret_cast<double*>(ws + L.stat_part);
   c->U[0] = reinterpret_cast<float*>(ws + L.U0);
   c->U[1] = reinterpret_cast<float*>(ws + L.U1);
   c->Uc[0] = reinterpret_cast<float*>(ws + L.Uc0);
@@ -505,6 +527,7 @@ rpca_status rpca_solve(rpca_ctx* c, int32_t max_rounds, double tol, int32_t chec
                "copy V");
       c->have_prev = true;
     }
+    if (rpca_status s = flush_finalize(c)) return s;
     double h[2] = {0.0, 1.0};
     StatsRec rec;
     if (have_metric)
@@ -575,6 +598,7 @@ rpca_status rpca_get_factors(rpca_ctx* c, float* U, int64_t ldu, float* V, int64
 rpca_status rpca_get_stats(rpca_ctx* c, int64_t round, rpca_stats* out) {
   if (rpca_status s = guard(c)) return s;
   if (!out) return fail(c, RPCA_EINVAL, "out is NULL");
+  if (rpca_status s = flush_finalize(c)) return s;
   if (round < 0) round = c->rounds - 1;
   if (round < 0 || round >= c->rounds || round < c->rounds - kHist)
     return fail(c, RPCA_EINVAL, "round not available");

@@ -63,7 +63,8 @@ struct VGroup {
 struct DevState {
   int64_t t;                 // rounds finished
   double u_sq;               // ||U^(t)||_F^2 (trace of the current Gram)
-  double pad[6];
+  double u_sq_next;          // trace of the new Gram until the round is recorded
+  double pad[5];
 };
 
 struct StatsRec {  // mirrors rpca_stats
@@ -101,6 +102,7 @@ struct DevParams {
   double* ucl_sq;        // per-client ||U_i||^2 of the current local factors
   DevState* dstate;
   StatsRec* hist;
+  double* stat_part;     // six round statistics (finalize folded into the V-pass)
 };
 
 // Launch helpers (kernels live in rpca_kernels.hip).
@@ -111,10 +113,13 @@ enum VMode { kSZero = 0, kSStored = 1, kSRecompute = 2 };
 // V-pass, streaming part: partial W = (M_i - S_i)^T U_i per row split into
 // p.Wpart. U: factor block of the input U (client stride u_stride); Uold /
 // Vold: previous U factor block and previous V buffer (kSRecompute).
+// fin_Ginv != NULL: two extra work-groups run the previous round's finalize
+// (Gram inverse into fin_Ginv; statistics) alongside the streaming ones.
 hipError_t launch_vpass(const DevParams& p, int mode, const float* U, int64_t u_stride,
-                        const float* Uold, const float* Vold, hipStream_t st);
-// V-pass, finishing part: V = W G^{-1} into p.V, and the V_i^T V_i partials.
-hipError_t launch_vfinal(const DevParams& p, const double* Ginv, int64_t g_stride,
+                        const float* Uold, const float* Vold, double* fin_Ginv, hipStream_t st);
+// V-pass, finishing part: V = W G^{-1} into p.V, and the V_i^T V_i partials;
+// rec = 1 also records the previous round (its finalize ran in the V-pass).
+hipError_t launch_vfinal(const DevParams& p, const double* Ginv, int64_t g_stride, int rec,
                          hipStream_t st);
 hipError_t launch_client_factor(const DevParams& p, hipStream_t st);
 // S-pass over clients [client_base, client_base + client_count) with V = p.V.

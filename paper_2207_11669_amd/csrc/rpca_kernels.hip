@@ -89,20 +89,35 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+constexpr int kFinThreads = 256;                             // finalize work-groups
+constexpr int kFinEPT = kMaxRank * kMaxRank / kFinThreads;   // sweep entries per thread
+
+// 1/x for x > 0 without the correctly rounded division sequence: the
+// hardware reciprocal estimate refined by two Newton steps (each squares the
+// relative error), which lands within an ulp or two of 1/x.
+__device__ __forceinline__ double recip_pos(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
 // In-place inverse of an r x r SPD matrix A (row stride ld, in LDS) by a
-// Gauss-Jordan sweep without pivoting, run by the whole work-group (at least
-// r*r/4 threads): the k-th pivot is a diagonal entry of a Schur complement of
-// an SPD matrix, hence positive, and every step updates all r^2 entries in
-// parallel (no serial triangular solves). Each thread owns up to four entries,
-// indexed once. A pivot that is not positive (non-SPD or NaN input) turns the
-// result into NaN, which the round statistics then expose.
+// Gauss-Jordan sweep without pivoting, run by the whole work-group (EPT *
+// blockDim.x >= r * r): the k-th pivot is a diagonal entry of a Schur
+// complement of an SPD matrix, hence positive, and every step updates all r^2
+// entries in parallel (no serial triangular solves). Each thread owns up to
+// EPT entries, indexed once. A pivot that is not positive (non-SPD or NaN
+// input) turns the result into NaN, which the round statistics then expose.
+template <int EPT>
 __device__ void spd_inverse(double* A, int r, int ld) {
   __shared__ double colk[kMaxRank], rowk[kMaxRank];
   __shared__ double pinv_sh;
   const int tid = threadIdx.x, nt = blockDim.x;
-  int ei[4], ej[4];
+  int ei[EPT], ej[EPT];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < EPT; ++q) {
     const int e = tid + q * nt;
     ei[q] = e < r * r ? e / r : -1;
     ej[q] = e < r * r ? e % r : -1;
@@ -114,12 +129,12 @@ __device__ void spd_inverse(double* A, int r, int ld) {
     }
     if (tid == 0) {
       const double pv = A[k * ld + k];
-      pinv_sh = pv > 0.0 ? 1.0 / pv : NAN;
+      pinv_sh = pv > 0.0 ? recip_pos(pv) : NAN;
     }
     __syncthreads();
     const double pinv = pinv_sh;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < EPT; ++q) {
       const int i = ei[q], j = ej[q];
       if (i >= 0) {
         double v;
@@ -159,6 +174,27 @@ __device__ __forceinline__ double sum_strided(const T* __restrict__ x, int count
   return s;
 }
 
+// Per-thread part of sum_{k < count} load(k) over nt threads, thread t
+// taking k = t, t + nt, ...; each batch of 16 loads is issued before
+// any of them is used, so a long list costs a few memory latencies rather
+// than one per element. Fixed order for a fixed block size.
+template <class F>
+__device__ __forceinline__ double block_strided_sum(int count, F load, int nt) {
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int k0 = tid; k0 < count; k0 += 16 * nt) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = k0 + u * nt;
+      v[u] = k < count ? load(k) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += v[u];
+  }
+  return s;
+}
+
 // Store element (a, c) of a factor with `rows` rows into its factor block
 // (column-major, A-operand packing, B-operand packing; see rpca_internal.h).
 __device__ __forceinline__ void fb_store(float* fb, int64_t rows, int RP, int NS, int a, int c,
@@ -186,13 +222,29 @@ __device__ __forceinline__ void fb_store(float* fb, int64_t rows, int RP, int NS
 // fly: its MFMA puts Uo rows on the A side and Vo^T on the B side, so the
 // 16x16 residual tile comes out in exactly the float4 layout of M.
 // ---------------------------------------------------------------------------
+__device__ void finalize_role(const DevParams& p, double* Ginv, int role);
+__device__ void fin_record(const DevParams& p, const double* stats, double tr);
+
 template <int RT, int NS, int MODE>
 __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restrict__ Ubase,
                                                int64_t u_stride, const float* __restrict__ Uold,
-                                               const float* __restrict__ Vold) {
+                                               const float* __restrict__ Vold,
+                                               double* __restrict__ fin_Ginv, int fin) {
   constexpr int RP = 16 * RT;
   static_assert(NS >= 1 && NS <= 4 * RT, "NS = ceil(r / 4) must fit the rank tiles");
-  const VGroup vg = p.vg64[blockIdx.x];
+  // fin = 1: the first two work-groups run the previous round's finalize
+  // (Gram inverse into fin_Ginv slot 0; round statistics) while the others
+  // stream; nothing in this kernel reads what they write.
+  int bid = (int)blockIdx.x;
+  if (fin) {
+    if (bid < 2) {
+      finalize_role(p, fin_Ginv, bid);
+      return;
+    }
+    bid -= 2;
+  }
+  const int gx = bid % p.ng64, gy = bid / p.ng64;
+  const VGroup vg = p.vg64[gx];
   const ClientDev cl = p.clients[vg.client];
   const float* __restrict__ U = Ubase + (int64_t)vg.client * u_stride;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
@@ -212,7 +264,7 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
     for (int s = 0; s < NS; ++s) vb[s] = Vopa[((int64_t)vch * NS + s) * 64 + lane];
   }
 
-  const int rbeg = blockIdx.y * p.vsplit_rows;
+  const int rbeg = gy * p.vsplit_rows;
   const int rend = min(p.m, rbeg + p.vsplit_rows);
   f4 acc[RT];
 #pragma unroll
@@ -308,7 +360,7 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  GLOBAL float* wp = gptr_w(p.Wpart) + ((int64_t)blockIdx.y * p.NVP + cl.vrow0 + j0) * RP;
+  GLOBAL float* wp = gptr_w(p.Wpart) + ((int64_t)gy * p.NVP + cl.vrow0 + j0) * RP;
 #pragma unroll
   for (int ct = 0; ct < RT; ++ct)
 #pragma unroll
@@ -323,8 +375,14 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
 // ---------------------------------------------------------------------------
 template <int RT>
 __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __restrict__ Gbase,
-                                                int64_t g_stride) {
+                                                int64_t g_stride, int rec) {
   constexpr int RP = 16 * RT;
+  // rec = 1: record the previous round, whose finalize ran in the V-pass.
+  if (rec && blockIdx.x == 0 && threadIdx.x == 0) {
+    double st[6];
+    for (int q = 0; q < 6; ++q) st[q] = p.stat_part[q];
+    fin_record(p, st, p.dstate->u_sq_next);
+  }
   __shared__ double wd[kVCols][RP + 1];
   __shared__ double gl[RP * RP];
   const VGroup vg = p.vgroups[blockIdx.x];
@@ -394,7 +452,7 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
     A[e] = s + (a == b ? cl.c : 0.0);
   }
   __syncthreads();
-  spd_inverse(A, r, r);
+  spd_inverse<4>(A, r, r);  // 1024 threads x 4 >= 64^2
   double* Af = p.Afac + (int64_t)blockIdx.x * RR;
   double* Bf = p.Bfac + (int64_t)blockIdx.x * RR;
   for (int e = tid; e < RR; e += blockDim.x) {
@@ -740,37 +798,42 @@ __global__ __launch_bounds__(256) void k_gram_init(DevParams p, const float* __r
 }
 
 // ---------------------------------------------------------------------------
-// Finalize (1024 threads): G = U^T U + rho I from the Gram partials, G^{-1} by
-// the FP64 sweep, and (record = 1) the round statistics. grid = per_client ? E : 1.
+// Finalize: G = U^T U + rho I from the Gram partials, G^{-1} by the FP64
+// sweep, and (record = 1) the round statistics. It runs either as one
+// standalone work-group (k_finalize) or folded into the next round's V-pass
+// launch as two extra work-groups (Gram and inverse; statistics) whose record
+// the V finish then assembles. Both forms run the same functions on
+// kFinThreads threads, so they give bitwise the same results.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_finalize(DevParams p, double* Ginv, int64_t g_stride,
-                                                   int per_client, int record) {
-  __shared__ double A[kMaxRank * kMaxRank];
-  __shared__ double red[16][5];
-  __shared__ double tr_sh;
+
+// Gram of the new U (slot gi) from its row-block partials into LDS A (r x r).
+__device__ void fin_gram(const DevParams& p, int gi, double* A) {
   const int r = p.r, RP = p.RP;
   const int64_t RR = (int64_t)RP * RP;
-  const int tid = threadIdx.x;
-  const int gi = blockIdx.x;
   const double* gp = p.gram_part + (int64_t)gi * p.nub * RR;
-  for (int e = tid; e < r * r; e += blockDim.x) {
-    const int a = e / r, b = e % r;
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+    const int a = e / r, b = e - (e / r) * r;
     A[e] = sum_strided(gp + a * RP + b, p.nub, RR);
   }
-  // Round statistics (FP64, fixed order) while the Gram sums land.
-  double l2 = 0.0, l1 = 0.0, nz = 0.0, vsq = 0.0, du = 0.0;
-  if (record && !per_client) {
+}
+
+// Round statistics from the partials of the round's kernels; result in
+// out[0..5] of thread 0: ||Lambda||^2, ||S||_1, nnz(S), ||V||^2, ||dU||^2 and
+// the U penalty of the objective at the round's start.
+__device__ void fin_stats(const DevParams& p, double* out) {
+  __shared__ double red[kFinThreads / 64][5];
+  const int tid = threadIdx.x, r = p.r, RP = p.RP;
+  const int64_t RR = (int64_t)RP * RP;
+  if (tid < kFinThreads) {
     const int nsp = p.E * p.nrb;
-    for (int k = tid; k < nsp; k += blockDim.x) {
-      l2 += p.spart[(int64_t)k * 4 + 0];
-      l1 += p.spart[(int64_t)k * 4 + 1];
-      nz += p.spart[(int64_t)k * 4 + 2];
-    }
-    for (int k = tid; k < p.ngroups * r; k += blockDim.x) {
-      const int g = k / r, d = k % r;
-      vsq += p.gv_part[(int64_t)g * RR + d * RP + d];
-    }
-    for (int k = tid; k < p.nub; k += blockDim.x) du += p.upart[k];
+    double l2 = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 0]; }, kFinThreads);
+    double l1 = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 1]; }, kFinThreads);
+    double nz = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 2]; }, kFinThreads);
+    double vsq = block_strided_sum(p.ngroups * r, [&](int k) {
+      const int g = k / r, d = k - g * r;
+      return p.gv_part[(int64_t)g * RR + d * RP + d];
+    }, kFinThreads);
+    double du = block_strided_sum(p.nub, [&](int k) { return p.upart[k]; }, kFinThreads);
     l2 = wave_sum(l2);
     l1 = wave_sum(l1);
     nz = wave_sum(nz);
@@ -786,32 +849,11 @@ __global__ __launch_bounds__(1024) void k_finalize(DevParams p, double* Ginv, in
   }
   __syncthreads();
   if (tid == 0) {
-    double t = 0.0;
-    for (int k = 0; k < r; ++k) t += A[k * r + k];
-    tr_sh = t;
-  }
-  __syncthreads();
-  for (int k = tid; k < r; k += blockDim.x) A[k * r + k] += p.rho;
-  __syncthreads();
-  spd_inverse(A, r, r);
-  double* Gout = Ginv + (int64_t)gi * g_stride;
-  for (int e = tid; e < RR; e += blockDim.x) {
-    const int a = e / RP, b = e % RP;
-    Gout[e] = (a < r && b < r) ? A[a * r + b] : 0.0;
-  }
-  if (per_client) {
-    if (tid == 0) p.ucl_sq[gi] = tr_sh;
-    return;
-  }
-  if (!record) {
-    if (tid == 0) p.dstate->u_sq = tr_sh;
-    return;
-  }
-  if (tid == 0) {
-    const int nw = blockDim.x >> 6;
-    double s[5] = {0, 0, 0, 0, 0};
-    for (int k = 0; k < nw; ++k)
-      for (int q = 0; q < 5; ++q) s[q] += red[k][q];
+    for (int q = 0; q < 5; ++q) {
+      double t = 0.0;
+      for (int k = 0; k < kFinThreads / 64; ++k) t += red[k][q];
+      out[q] = t;
+    }
     double ureg;
     if (p.K == 1) {
       ureg = 0.5 * p.rho * p.dstate->u_sq;
@@ -819,19 +861,86 @@ __global__ __launch_bounds__(1024) void k_finalize(DevParams p, double* Ginv, in
       ureg = 0.0;
       for (int i = 0; i < p.E; ++i) ureg += 0.5 * p.clients[i].c * p.ucl_sq[i];
     }
-    const int64_t t = p.dstate->t;
-    StatsRec rec;
-    rec.t = (double)t;
-    rec.objective = 0.5 * s[0] + 0.5 * p.rho * s[3] + (double)p.lam * s[1] + ureg;
-    rec.lambda_fro_sq = s[0];
-    rec.nnz = s[2];
-    rec.du_sq = s[4];
-    rec.u_sq = tr_sh;
-    rec.v_sq = s[3];
-    rec.l1 = s[1];
-    p.hist[t % kHist] = rec;
-    p.dstate->t = t + 1;
-    p.dstate->u_sq = tr_sh;
+    out[5] = ureg;
+  }
+}
+
+// G^{-1} of the Gram in LDS A (adds rho I) into Ginv slot gi; returns
+// tr(U^T U) (valid in every thread).
+__device__ double fin_inverse(const DevParams& p, double* A, double* Ginv, int64_t g_stride, int gi) {
+  __shared__ double tr_sh;
+  const int tid = threadIdx.x, r = p.r, RP = p.RP;
+  const int64_t RR = (int64_t)RP * RP;
+  if (tid == 0) {
+    double t = 0.0;
+    for (int k = 0; k < r; ++k) t += A[k * r + k];
+    tr_sh = t;
+  }
+  __syncthreads();
+  for (int k = tid; k < r; k += blockDim.x) A[k * r + k] += p.rho;
+  __syncthreads();
+  spd_inverse<kFinEPT>(A, r, r);
+  double* Gout = Ginv + (int64_t)gi * g_stride;
+  for (int e = tid; e < RR; e += blockDim.x) {
+    const int a = e / RP, b = e % RP;
+    Gout[e] = (a < r && b < r) ? A[a * r + b] : 0.0;
+  }
+  return tr_sh;
+}
+
+// Round record from the statistics and tr(U^(t+1)T U^(t+1)) (one thread).
+__device__ void fin_record(const DevParams& p, const double* stats, double tr) {
+  const int64_t t = p.dstate->t;
+  StatsRec rec;
+  rec.t = (double)t;
+  rec.objective = 0.5 * stats[0] + 0.5 * p.rho * stats[3] + (double)p.lam * stats[1] + stats[5];
+  rec.lambda_fro_sq = stats[0];
+  rec.nnz = stats[2];
+  rec.du_sq = stats[4];
+  rec.u_sq = tr;
+  rec.v_sq = stats[3];
+  rec.l1 = stats[1];
+  p.hist[t % kHist] = rec;
+  p.dstate->t = t + 1;
+  p.dstate->u_sq = tr;
+}
+
+// Standalone finalize: one work-group per Gram slot (grid = per_client ? E : 1).
+__global__ __launch_bounds__(kFinThreads) void k_finalize(DevParams p, double* Ginv,
+                                                          int64_t g_stride, int per_client,
+                                                          int record) {
+  __shared__ double A[kMaxRank * kMaxRank];
+  __shared__ double st[6];
+  const int gi = (int)blockIdx.x;
+  fin_gram(p, gi, A);
+  if (record && !per_client) fin_stats(p, st);
+  __syncthreads();
+  const double tr = fin_inverse(p, A, Ginv, g_stride, gi);
+  if (threadIdx.x != 0) return;
+  if (per_client)
+    p.ucl_sq[gi] = tr;
+  else if (!record)
+    p.dstate->u_sq = tr;
+  else
+    fin_record(p, st, tr);
+}
+
+// The same work folded into a V-pass launch, by work-group role: role 0 forms
+// the Gram and its inverse (into Ginv slot 0, trace into dstate->u_sq_next),
+// role 1 the statistics (into p.stat_part). Neither reads what the other or
+// the streaming work-groups write; the V finish records the round.
+__device__ void finalize_role(const DevParams& p, double* Ginv, int role) {
+  if (role == 0) {
+    __shared__ double A[kMaxRank * kMaxRank];
+    fin_gram(p, 0, A);
+    __syncthreads();
+    const double tr = fin_inverse(p, A, Ginv, 0, 0);
+    if (threadIdx.x == 0) p.dstate->u_sq_next = tr;
+  } else {
+    __shared__ double st[6];
+    fin_stats(p, st);
+    if (threadIdx.x == 0)
+      for (int q = 0; q < 6; ++q) p.stat_part[q] = st[q];
   }
 }
 
@@ -982,21 +1091,25 @@ __global__ void k_dist_final(const double* __restrict__ part2, double* __restric
 // ---------------------------------------------------------------------------
 template <int RT, int NS>
 static hipError_t launch_vpass_t(const DevParams& p, int mode, const float* U, int64_t u_stride,
-                                 const float* Uold, const float* Vold, hipStream_t st) {
-  dim3 grid(p.ng64, p.vsplit), block(256);
+                                 const float* Uold, const float* Vold, double* fin_Ginv,
+                                 hipStream_t st) {
+  const int fin = fin_Ginv ? 1 : 0;
+  dim3 grid(p.ng64 * p.vsplit + (fin ? 2 : 0)), block(256);
   if (mode == kSZero)
-    hipLaunchKernelGGL((k_vpass<RT, NS, kSZero>), grid, block, 0, st, p, U, u_stride, Uold, Vold);
+    hipLaunchKernelGGL((k_vpass<RT, NS, kSZero>), grid, block, 0, st, p, U, u_stride, Uold, Vold,
+                       fin_Ginv, fin);
   else if (mode == kSStored)
-    hipLaunchKernelGGL((k_vpass<RT, NS, kSStored>), grid, block, 0, st, p, U, u_stride, Uold, Vold);
+    hipLaunchKernelGGL((k_vpass<RT, NS, kSStored>), grid, block, 0, st, p, U, u_stride, Uold, Vold,
+                       fin_Ginv, fin);
   else
     hipLaunchKernelGGL((k_vpass<RT, NS, kSRecompute>), grid, block, 0, st, p, U, u_stride, Uold,
-                       Vold);
+                       Vold, fin_Ginv, fin);
   return hipGetLastError();
 }
 template <int RT>
 static hipError_t launch_vfinal_t(const DevParams& p, const double* Ginv, int64_t g_stride,
-                                  hipStream_t st) {
-  hipLaunchKernelGGL(k_vfinal<RT>, dim3(p.ngroups), dim3(256), 0, st, p, Ginv, g_stride);
+                                  int rec, hipStream_t st) {
+  hipLaunchKernelGGL(k_vfinal<RT>, dim3(p.ngroups), dim3(256), 0, st, p, Ginv, g_stride, rec);
   return hipGetLastError();
 }
 
@@ -1032,17 +1145,17 @@ static hipError_t with_rank(const DevParams& p, F&& f) {
 }
 
 hipError_t launch_vpass(const DevParams& p, int mode, const float* U, int64_t u_stride,
-                        const float* Uold, const float* Vold, hipStream_t st) {
+                        const float* Uold, const float* Vold, double* fin_Ginv, hipStream_t st) {
   return with_rank(p, [&](auto rt, auto ns) {
     return launch_vpass_t<decltype(rt)::value, decltype(ns)::value>(p, mode, U, u_stride, Uold,
-                                                                   Vold, st);
+                                                                   Vold, fin_Ginv, st);
   });
 }
 
-hipError_t launch_vfinal(const DevParams& p, const double* Ginv, int64_t g_stride,
+hipError_t launch_vfinal(const DevParams& p, const double* Ginv, int64_t g_stride, int rec,
                          hipStream_t st) {
   return with_rank(p, [&](auto rt, auto) {
-    return launch_vfinal_t<decltype(rt)::value>(p, Ginv, g_stride, st);
+    return launch_vfinal_t<decltype(rt)::value>(p, Ginv, g_stride, rec, st);
   });
 }
 
@@ -1075,7 +1188,7 @@ hipError_t launch_uupdate(const DevParams& p, float* Uout, int64_t uout_stride,
 
 hipError_t launch_finalize(const DevParams& p, double* Ginv, int64_t g_stride, int per_client,
                            int record, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(per_client ? p.E : 1), dim3(1024), 0, st, p, Ginv,
+  hipLaunchKernelGGL(k_finalize, dim3(per_client ? p.E : 1), dim3(kFinThreads), 0, st, p, Ginv,
                      g_stride, per_client, record);
   return hipGetLastError();
 }
