@@ -511,6 +511,26 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
 
+  // Epilogue operands that do not depend on the sweep: the closed-form
+  // factors A_i and B_i are fetched now (into registers, stored to LDS once
+  // the ring's first loads are in flight), so the epilogue waits on no memory.
+  __shared__ float ptile[kSRows][RP + 1];
+  __shared__ float utile[kSRows][RP + 1];
+  __shared__ double fab[2][RP * RP];
+  const bool closed = p.u_mode != 0;
+  constexpr int kFabPer = (RP * RP + 511) / 512;
+  double fa[kFabPer], fbv[kFabPer];
+  if (!emit_only && closed) {
+    const double* __restrict__ Af = p.Afac + (int64_t)ci * RP * RP;
+    const double* __restrict__ Bf = p.Bfac + (int64_t)ci * RP * RP;
+#pragma unroll
+    for (int q = 0; q < kFabPer; ++q) {
+      const int e = tid + q * 512;
+      fa[q] = e < RP * RP ? Af[e] : 0.0;
+      fbv[q] = e < RP * RP ? Bf[e] : 0.0;
+    }
+  }
+
   double sl2 = 0.0, sl1 = 0.0;
   uint32_t nnz = 0;  // wave-uniform count of nonzero S entries
   const float lam = p.lam;
@@ -603,6 +623,17 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
       load_chunk(ring[d], min(d, nk - 1));
       __builtin_amdgcn_sched_barrier(0);
     }
+    if (!emit_only && closed) {
+#pragma unroll
+      for (int q = 0; q < kFabPer; ++q) {
+        const int e = tid + q * 512;
+        if (e < RP * RP) {
+          fab[0][e] = fa[q];
+          fab[1][e] = fbv[q];
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
     for (int k0 = 0; k0 < nkp; k0 += kSDepth) {
 #pragma unroll
       for (int d = 0; d < kSDepth; ++d) {
@@ -623,17 +654,24 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
   // the gradient, argmin_U L_i for the closed form), from P = Lambda V_i:
   //   GRAD   T = U_i - eta (c_i U_i - P)
   //   CLOSED T = P A_i + U_i B_i,  A_i = (V_i^T V_i + c_i I)^{-1}, B_i = V_i^T V_i A_i
-  // in FP64, stored FP32 into the client's slot of p.P.
-  __shared__ float ptile[kSRows][RP + 1];
-  __shared__ float utile[kSRows][RP + 1];
-  __shared__ double fab[2][RP * RP];
+  // in FP64, stored FP32 into the client's slot of p.P. U_i comes from the
+  // MFMA operand registers (rank (l/16) NS + s of row l%16; ranks from 4 NS
+  // on are zero), P from the two phases' accumulators summed in LDS.
   if (phase == 0) {
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < 2; ++rt) {
 #pragma unroll
       for (int ct = 0; ct < RT; ++ct)
 #pragma unroll
         for (int v = 0; v < 4; ++v) ptile[w * 32 + 16 * rt + 4 * lg + v][16 * ct + li] = accp[rt][ct][v];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) utile[w * 32 + 16 * rt + li][lg * NS + s] = ub[rt][s];
+    }
+  } else {
+    for (int c = 4 * NS + lg; c < RP; c += 4) {
+      utile[w * 32 + li][c] = 0.f;
+      utile[w * 32 + 16 + li][c] = 0.f;
+    }
   }
   __syncthreads();
   if (phase == 1) {
@@ -644,39 +682,35 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
 #pragma unroll
         for (int v = 0; v < 4; ++v) ptile[w * 32 + 16 * rt + 4 * lg + v][16 * ct + li] += accp[rt][ct][v];
   }
-  const int row0 = b * kSRows;
-  for (int e = tid; e < kSRows * RP; e += blockDim.x) {
-    const int rl = e % kSRows, c = e / kSRows;
-    utile[rl][c] = U[(int64_t)c * p.MP + row0 + rl];
-  }
-  const bool closed = p.u_mode != 0;
-  if (closed) {
-    const double* __restrict__ Af = p.Afac + (int64_t)ci * RP * RP;
-    const double* __restrict__ Bf = p.Bfac + (int64_t)ci * RP * RP;
-    for (int e = tid; e < RP * RP; e += blockDim.x) {
-      fab[0][e] = Af[e];
-      fab[1][e] = Bf[e];
-    }
-  }
   __syncthreads();
+  const int row0 = b * kSRows;
   float* Ti = p.P + (int64_t)ci * RP * p.MP;
   const double eta = eta_of_round(p, p.dstate->t);
   const double cc = cl.c;
-  for (int e = tid; e < kSRows * RP; e += blockDim.x) {
-    const int rl = e % kSRows, c = e / kSRows;
-    double t;
+  // Thread: one row, eight rank columns (register blocking: each LDS read of
+  // P or U feeds eight FMAs).
+  for (int e = tid; e < kSRows * (RP / 8); e += blockDim.x) {
+    const int rl = e % kSRows, c0 = (e / kSRows) * 8;
+    double t[8];
     if (closed) {
-      t = 0.0;
-      if (c < p.r) {
-#pragma unroll 4
-        for (int k = 0; k < p.r; ++k)
-          t += (double)ptile[rl][k] * fab[0][k * RP + c] + (double)utile[rl][k] * fab[1][k * RP + c];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) t[j] = 0.0;
+      for (int k = 0; k < p.r; ++k) {
+        const double pk = (double)ptile[rl][k], uk = (double)utile[rl][k];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          t[j] = fma(pk, fab[0][k * RP + c0 + j], fma(uk, fab[1][k * RP + c0 + j], t[j]));
       }
     } else {
-      const double u = utile[rl][c];
-      t = u - eta * (cc * u - (double)ptile[rl][c]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double u = utile[rl][c0 + j];
+        t[j] = u - eta * (cc * u - (double)ptile[rl][c0 + j]);
+      }
     }
-    Ti[(int64_t)c * p.MP + row0 + rl] = (float)t;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      Ti[(int64_t)(c0 + j) * p.MP + row0 + rl] = c0 + j < p.r ? (float)t[j] : 0.f;
   }
 
   __shared__ double sred[8][3];
