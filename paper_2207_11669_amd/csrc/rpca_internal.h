@@ -24,12 +24,25 @@ constexpr int kURows = 64;       // rows per U-update work-group
 // so that every operand a wave needs for one 16x16x4 MFMA step is a single
 // contiguous 256 B (pa) or 1 KiB (pb) read. V additionally keeps a row-major
 // copy (rows x RP) in front of its factor block.
+// When the last rank tile holds at most 12 ranks, products whose output
+// dimension is the rank use 4x4 MFMA blocks for it, one per group of four
+// ranks ("quads"), instead of a zero-padded 16x16 tile:
+//   nquads = ceil(r/4) - 4 (RP/16 - 1) if that is <= 3, else 0,
+// and the factor keeps a fourth layout for them:
+//   pq  : for chunk ch, quad q, g < 4, j < 4, e < 4 (16 floats per (ch, q, g)):
+//         X[16 ch + 4 g + e][RP - 16 + 4 q + j]               (4 * nquads * rows)
+__host__ __device__ constexpr int nquads(int RP, int NS) {
+  return NS - 4 * (RP / 16 - 1) <= 3 ? NS - 4 * (RP / 16 - 1) : 0;
+}
 __host__ __device__ inline int64_t fb_floats(int64_t rows, int RP, int NS) {
-  return 2 * (int64_t)RP * rows + 4 * (int64_t)NS * rows;
+  return 2 * (int64_t)RP * rows + 4 * (int64_t)NS * rows + 4 * (int64_t)nquads(RP, NS) * rows;
 }
 __host__ __device__ inline int64_t fb_pa_off(int64_t rows, int RP) { return (int64_t)RP * rows; }
 __host__ __device__ inline int64_t fb_pb_off(int64_t rows, int RP, int NS) {
   return (int64_t)RP * rows + 4 * (int64_t)NS * rows;
+}
+__host__ __device__ inline int64_t fb_pq_off(int64_t rows, int RP, int NS) {
+  return 2 * (int64_t)RP * rows + 4 * (int64_t)NS * rows;
 }
 // V buffer: row-major NVP x RP copy, then the factor block.
 __host__ __device__ inline int64_t vbuf_floats(int64_t NVP, int RP, int NS) {

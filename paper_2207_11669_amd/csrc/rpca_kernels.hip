@@ -207,6 +207,17 @@ __device__ __forceinline__ void fb_store(float* fb, int64_t rows, int RP, int NS
   }
   const int ct = c >> 4, lane = ((li >> 2) << 4) + (c & 15);
   fb[fb_pb_off(rows, RP, NS) + (((int64_t)ch * (RP >> 4) + ct) * 64 + lane) * 4 + (li & 3)] = v;
+  const int NQ = nquads(RP, NS), cq = c - (RP - 16);
+  if (cq >= 0 && cq < 4 * NQ)
+    fb[fb_pq_off(rows, RP, NS) +
+       ((((int64_t)ch * NQ + (cq >> 2)) * 4 + (li >> 2)) * 4 + (cq & 3)) * 4 + (li & 3)] = v;
+}
+
+// v_mfma_f32_4x4x1f32: 16 independent 4x4x1 products; block b = l/4 takes
+// A_b[i] from lane 4b + i and B_b[j] from lane 4b + j, and D_b[i][j] lands in
+// lane 4b + j, element i.
+__device__ __forceinline__ f4 mfma4x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -232,6 +243,8 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
                                                double* __restrict__ fin_Ginv, int fin) {
   constexpr int RP = 16 * RT;
   static_assert(NS >= 1 && NS <= 4 * RT, "NS = ceil(r / 4) must fit the rank tiles");
+  // W's last rank tile in 4x4 blocks when it holds at most 12 ranks.
+  constexpr int NQ = nquads(RP, NS), RTF = NQ ? RT - 1 : RT;
   // fin = 1: the first two work-groups run the previous round's finalize
   // (Gram inverse into fin_Ginv slot 0; round statistics) while the others
   // stream; nothing in this kernel reads what they write.
@@ -266,9 +279,11 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
 
   const int rbeg = gy * p.vsplit_rows;
   const int rend = min(p.m, rbeg + p.vsplit_rows);
-  f4 acc[RT];
+  f4 acc[RTF > 0 ? RTF : 1], accq[NQ > 0 ? NQ : 1];
 #pragma unroll
-  for (int ct = 0; ct < RT; ++ct) acc[ct] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int ct = 0; ct < RTF; ++ct) acc[ct] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) accq[q] = f4{0.f, 0.f, 0.f, 0.f};
   // M (and stored S) through a buffer resource over this wave's 16 columns:
   // columns past n_i lie beyond its range and read 0; rows are clamped to the
   // last float4 of the column and masked when used. U operands are packed and
@@ -280,13 +295,16 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
     rS = make_rsrc(p.S + cl.s_off + (int64_t)min(j0, cl.n) * p.lds, block_bytes_from(cl.n, j0, p.lds));
   const uint32_t vM = (uint32_t)(li * cl.ldm) * 4u, vS = (uint32_t)(li * p.lds) * 4u;
   const rsrc_t rUb = make_rsrc(gUpb_raw, (uint32_t)(p.MP * RP * 4));
+  const rsrc_t rUq = make_rsrc(U + fb_pq_off(p.MP, RP, NS), (uint32_t)(p.MP * 4 * NQ * 4));
+  const uint32_t vq_off = (uint32_t)(((lane >> 4) * 4 + (lane & 3)) * 16);
   const rsrc_t rUa = make_rsrc(gUopa_raw, (uint32_t)(p.MP * 4 * NS * 4));
 
   // Operands of one 16-row chunk; kVDepth chunks are kept in flight (vector
   // loads complete in order, so everything a chunk needs is issued together).
   struct Chunk {
     f4 m, s;          // M (and stored S) rows 4*(l/16)..+3 of column l%16
-    f4 u[RT];         // U^T operand: U[row][rank 16*ct + l%16] for the 4 rows
+    f4 u[RTF > 0 ? RTF : 1];  // U^T operand: U[row][rank 16*ct + l%16] for the 4 rows
+    f4 uq[NQ > 0 ? NQ : 1];   // quads: U[row][rank RP - 16 + 4 q + l%4] for the 4 rows
     float uo[NS];     // previous U, A operand of the S rebuild: Uo[row l%16][rank g*NS + s]
   };
   constexpr int kVDepth = 4;
@@ -299,8 +317,10 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
     if (MODE == kSStored) c.s = bload4(rS, vS + rowb, 0);
     const uint32_t chg = (uint32_t)(row0 >> 4);
 #pragma unroll
-    for (int ct = 0; ct < RT; ++ct)
+    for (int ct = 0; ct < RTF; ++ct)
       c.u[ct] = bload4(rUb, (uint32_t)lane * 16u, ((chg * RT + ct) * 64u) * 16u);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) c.uq[q] = bload4(rUq, vq_off, (chg * NQ + q) * 256u);
     if (MODE == kSRecompute) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) c.uo[s] = bload(rUa, (uint32_t)lane * 4u, ((chg * NS + s) * 64u) * 4u);
@@ -332,9 +352,12 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
       for (int e = 0; e < 4; ++e) d[e] = row + e < p.m ? d[e] : 0.f;
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s) {
 #pragma unroll
-      for (int ct = 0; ct < RT; ++ct) acc[ct] = mfma4(d[s], c.u[ct][s], acc[ct]);
+      for (int ct = 0; ct < RTF; ++ct) acc[ct] = mfma4(d[s], c.u[ct][s], acc[ct]);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) accq[q] = mfma4x4(d[s], c.uq[q][s], accq[q]);
+    }
   };
   // Uniform loop: every iteration loads (the chunk index is clamped to the
   // last chunk, whose addresses are then cache hits), so the wait counts stay
@@ -362,9 +385,21 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
   }
   GLOBAL float* wp = gptr_w(p.Wpart) + ((int64_t)gy * p.NVP + cl.vrow0 + j0) * RP;
 #pragma unroll
-  for (int ct = 0; ct < RT; ++ct)
+  for (int ct = 0; ct < RTF; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v) wp[(4 * lg + v) * RP + 16 * ct + li] = acc[ct][v];
+  // Quads: block b = l/4 summed rows 4 (b/4) + s of columns 4 (b%4) + i; the
+  // four row groups (lanes l, l ^ 16, l ^ 32, l ^ 48) are added here.
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float x = accq[q][i];
+      x += __shfl_xor(x, 16, 64);
+      x += __shfl_xor(x, 32, 64);
+      if (lane < 16) wp[(4 * (lane >> 2) + i) * RP + 16 * RTF + 4 * q + (lane & 3)] = x;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -485,6 +520,8 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
                                                int64_t lds_out, int emit_only, int client_base) {
   constexpr int RP = 16 * RT;
   static_assert(NS >= 1 && NS <= 4 * RT, "NS = ceil(r / 4) must fit the rank tiles");
+  // P's last rank tile in 4x4 blocks when it holds at most 12 ranks.
+  constexpr int NQ = nquads(RP, NS), RTF = NQ ? RT - 1 : RT;
   const int b = blockIdx.x, ci = client_base + (int)blockIdx.y;
   const ClientDev cl = p.clients[ci];
   const float* __restrict__ U = Ubase + (int64_t)ci * u_stride;
@@ -505,11 +542,14 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
       for (int s = 0; s < NS; ++s) ub[rt][s] = Upa[(ch * NS + s) * 64 + lane];
     }
   }
-  f4 accp[2][RT];
+  f4 accp[2][RTF > 0 ? RTF : 1], accq[2][NQ > 0 ? NQ : 1];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+  for (int rt = 0; rt < 2; ++rt) {
 #pragma unroll
-    for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int ct = 0; ct < RTF; ++ct) accp[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) accq[rt][q] = f4{0.f, 0.f, 0.f, 0.f};
+  }
 
   // Epilogue operands that do not depend on the sweep: the closed-form
   // factors A_i and B_i are fetched now (into registers, stored to LDS once
@@ -538,6 +578,8 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
   // V operands: packed, always in range (lane offset + scalar chunk offset).
   const rsrc_t rVa = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pa_off(p.NVP, RP), (uint32_t)(p.NVP * 4 * NS * 4));
   const rsrc_t rVb = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pb_off(p.NVP, RP, NS), (uint32_t)(p.NVP * RP * 4));
+  const rsrc_t rVq = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pq_off(p.NVP, RP, NS), (uint32_t)(p.NVP * 4 * NQ * 4));
+  const uint32_t vq_off = (uint32_t)(((lane >> 4) * 4 + (lane & 3)) * 16);
   // M: one buffer resource per 16-column chunk (base at the chunk's first
   // column, range = the rest of the block, at most kChunkRange), fixed per-lane
   // offsets. Columns past n_i fall outside the range and rows past m get an
@@ -561,7 +603,8 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
   struct Chunk {
     float m[2][4];   // M[row][col] for this lane's rows (two 16-row tiles) and 4 columns
     float va[NS];    // MFMA 1 A operand (V A-packing): V[col j0 + l%16][rank (l/16)*NS + s]
-    f4 vb[RT];       // MFMA 2 B operand (V B-packing): V[col j0 + 4*(l/16) + e][rank 16*ct + l%16]
+    f4 vb[RTF > 0 ? RTF : 1];  // MFMA 2 B operand (V B-packing): V[col j0 + 4*(l/16) + e][rank 16*ct + l%16]
+    f4 vq[NQ > 0 ? NQ : 1];    // quads: V[col j0 + 4*(l/16) + e][rank RP - 16 + 4 q + l%4]
   };
   constexpr int kSDepth = 3;
   Chunk ring[kSDepth];
@@ -573,7 +616,9 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
 #pragma unroll
     for (int s = 0; s < NS; ++s) c.va[s] = bload(rVa, (uint32_t)lane * 4u, ((vch * NS + s) * 64u) * 4u);
 #pragma unroll
-    for (int ct = 0; ct < RT; ++ct) c.vb[ct] = bload4(rVb, (uint32_t)lane * 16u, ((vch * RT + ct) * 64u) * 16u);
+    for (int ct = 0; ct < RTF; ++ct) c.vb[ct] = bload4(rVb, (uint32_t)lane * 16u, ((vch * RT + ct) * 64u) * 16u);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) c.vq[q] = bload4(rVq, vq_off, (vch * NQ + q) * 256u);
     const rsrc_t rM = make_rsrc(cl.M + (int64_t)j0 * cl.ldm, chunk_bytes_from(cl.n, j0, cl.ldm));
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -604,9 +649,12 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
         nnz += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(Sv != 0.f));
       }
 #pragma unroll
-      for (int ct = 0; ct < RT; ++ct)
+      for (int s = 0; s < 4; ++s) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) accp[rt][ct] = mfma4(lamv[s], c.vb[ct][s], accp[rt][ct]);
+        for (int ct = 0; ct < RTF; ++ct) accp[rt][ct] = mfma4(lamv[s], c.vb[ct][s], accp[rt][ct]);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) accq[rt][q] = mfma4x4(lamv[s], c.vq[q][s], accq[rt][q]);
+      }
     }
     sl2 += (double)l2;
     sl1 += (double)l1;
@@ -657,13 +705,31 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
   // in FP64, stored FP32 into the client's slot of p.P. U_i comes from the
   // MFMA operand registers (rank (l/16) NS + s of row l%16; ranks from 4 NS
   // on are zero), P from the two phases' accumulators summed in LDS.
+  // Quads: block b = l/4 summed columns 4 (b/4) + s for rows 4 (b%4) + i; the
+  // four column groups (lanes l, l ^ 16, l ^ 32, l ^ 48) are added first.
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float x = accq[rt][q][i];
+        x += __shfl_xor(x, 16, 64);
+        x += __shfl_xor(x, 32, 64);
+        accq[rt][q][i] = x;
+      }
   if (phase == 0) {
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
 #pragma unroll
-      for (int ct = 0; ct < RT; ++ct)
+      for (int ct = 0; ct < RTF; ++ct)
 #pragma unroll
         for (int v = 0; v < 4; ++v) ptile[w * 32 + 16 * rt + 4 * lg + v][16 * ct + li] = accp[rt][ct][v];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (lane < 16) ptile[w * 32 + 16 * rt + 4 * (lane >> 2) + i][16 * RTF + 4 * q + (lane & 3)] = accq[rt][q][i];
 #pragma unroll
       for (int s = 0; s < NS; ++s) utile[w * 32 + 16 * rt + li][lg * NS + s] = ub[rt][s];
     }
@@ -676,11 +742,17 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
   __syncthreads();
   if (phase == 1) {
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < 2; ++rt) {
 #pragma unroll
-      for (int ct = 0; ct < RT; ++ct)
+      for (int ct = 0; ct < RTF; ++ct)
 #pragma unroll
         for (int v = 0; v < 4; ++v) ptile[w * 32 + 16 * rt + 4 * lg + v][16 * ct + li] += accp[rt][ct][v];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (lane < 16) ptile[w * 32 + 16 * rt + 4 * (lane >> 2) + i][16 * RTF + 4 * q + (lane & 3)] += accq[rt][q][i];
+    }
   }
   __syncthreads();
   const int row0 = b * kSRows;
