@@ -28,7 +28,7 @@ struct rpca_ctx {
   int inner = 1;
   bool recompute = false;  // S rebuilt from (U_prev, V) instead of stored
   float* V[2] = {nullptr, nullptr};  // V buffers (row-major copy + factor block)
-  std::vector<VGroup> vg64;
+  std::vector<VTile> vg64;
   bool poisoned = false;
   std::string err;
   float* U[2] = {nullptr, nullptr};
@@ -151,7 +151,7 @@ Layout make_layout(const rpca_params* p) {
   L.stat_part = take((size_t)8 * d);
   L.clients = take((size_t)E * sizeof(ClientDev));
   L.vgroups = take((size_t)L.ngroups * sizeof(VGroup));
-  L.vg64 = take((size_t)L.ng64 * sizeof(VGroup));
+  L.vg64 = take((size_t)L.ng64 * sizeof(VTile));
   L.Uprev = take((size_t)L.RP * L.MP * f);
   L.Vprev = take((size_t)L.NVP * L.RP * f);
   L.Ut = take((size_t)kMaxRank * L.MP * f);
@@ -372,7 +372,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.eta0 = prm->eta0;
   p.clients = reinterpret_cast<const ClientDev*>(ws + L.clients);
   p.vgroups = reinterpret_cast<const VGroup*>(ws + L.vgroups);
-  p.vg64 = reinterpret_cast<const VGroup*>(ws + L.vg64);
+  p.vg64 = reinterpret_cast<const VTile*>(ws + L.vg64);
   p.S = L.recompute ? nullptr : reinterpret_cast<float*>(ws + L.S);
   c->recompute = L.recompute;
   c->V[0] = reinterpret_cast<float*>(ws + L.V0);
@@ -420,13 +420,13 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
     cd.vrow0 = (int32_t)vrow;
     cd.g0 = g;
     for (int32_t j0 = 0; j0 < ni; j0 += kVCols) {
-      c->vgroups.push_back(VGroup{i, j0, ni - j0 < kVCols ? ni - j0 : kVCols, 0});
+      c->vgroups.push_back(VGroup{i, j0, ni - j0 < kVCols ? ni - j0 : kVCols, (int32_t)vrow + j0});
       ++g;
     }
     cd.g1 = g;
-    for (int32_t j0 = 0; j0 < ni; j0 += kVStreamCols)
-      c->vg64.push_back(VGroup{i, j0, ni - j0 < kVStreamCols ? ni - j0 : kVStreamCols, 0});
     cd.c = prm->rho * (double)ni / (double)L.n;
+    for (int32_t j0 = 0; j0 < ni; j0 += kVStreamCols)
+      c->vg64.push_back(VTile{cd, i, j0, ni - j0 < kVStreamCols ? ni - j0 : kVStreamCols, 0});
     c->col_off[i] = col;
     col += ni;
     vrow += round_up(ni, kVPad);
@@ -442,7 +442,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
     e = hipMemcpyAsync(ws + L.vgroups, c->vgroups.data(), c->vgroups.size() * sizeof(VGroup),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(ws + L.vg64, c->vg64.data(), c->vg64.size() * sizeof(VGroup),
+    e = hipMemcpyAsync(ws + L.vg64, c->vg64.data(), c->vg64.size() * sizeof(VTile),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = launch_copy_in_U(p, U0, ldu, c->U[0], st);
   if (e == hipSuccess) e = launch_gram_init(p, c->U[0], st);

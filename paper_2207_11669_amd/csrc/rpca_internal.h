@@ -69,6 +69,13 @@ struct ClientDev {
 // A V-pass work unit: up to 32 (finalize) or 64 (streaming) consecutive
 // columns of one client.
 struct VGroup {
+  int32_t client, j0, ncols, vrow;  // vrow: first row in the padded V buffers
+};
+
+// A V-pass streaming work unit (up to 64 columns of one client) with its
+// client's record inline, so that a work-group needs one table read.
+struct VTile {
+  ClientDev cl;
   int32_t client, j0, ncols, pad;
 };
 
@@ -101,7 +108,7 @@ struct DevParams {
   double rho, eta0;
   const ClientDev* clients;
   const VGroup* vgroups;
-  const VGroup* vg64;
+  const VTile* vg64;
   float* S;              // all clients' S_i (stored-S layout only)
   float* V;              // V buffer this launch writes or reads (see vbuf_floats)
   float* Wpart;          // V-pass partial W per row split, [vsplit][NVP][RP]

@@ -257,14 +257,14 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
     bid -= 2;
   }
   const int gx = bid % p.ng64, gy = bid / p.ng64;
-  const VGroup vg = p.vg64[gx];
-  const ClientDev cl = p.clients[vg.client];
-  const float* __restrict__ U = Ubase + (int64_t)vg.client * u_stride;
+  const VTile vt = p.vg64[gx];
+  const ClientDev& cl = vt.cl;
+  const float* __restrict__ U = Ubase + (int64_t)vt.client * u_stride;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   // Wave-uniform; readfirstlane lets the compiler keep the buffer resources
   // built from it in scalar registers (no per-load uniformity loops).
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int j0 = vg.j0 + 16 * w;  // client-local first column of this wave's tile
+  const int j0 = vt.j0 + 16 * w;  // client-local first column of this wave's tile
   const float lam = p.lam;
 
   const float* gUpb_raw = U + fb_pb_off(p.MP, RP, NS);
@@ -421,18 +421,53 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
   __shared__ double wd[kVCols][RP + 1];
   __shared__ double gl[RP * RP];
   const VGroup vg = p.vgroups[blockIdx.x];
-  const ClientDev cl = p.clients[vg.client];
   const double* __restrict__ Gi = Gbase + (int64_t)vg.client * g_stride;
   const int tid = threadIdx.x;
-  const int vrow = cl.vrow0 + vg.j0;
+  const int vrow = vg.vrow;
   const int64_t split_stride = (int64_t)p.NVP * RP;
-  for (int e = tid; e < kVCols * RP; e += blockDim.x) {
-    const int j = e / RP, c = e % RP;
-    wd[j][c] = sum_strided(p.Wpart + (int64_t)(vrow + j) * RP + c, p.vsplit, split_stride);
-  }
-  for (int e = tid; e < RP * RP; e += blockDim.x) gl[e] = Gi[e];
-  __syncthreads();
   constexpr int kPer = (kVCols * RP + 255) / 256;
+  constexpr int kGPer = (RP * RP + 255) / 256;
+  {
+    // All of a thread's loads (eight row splits of each of its W entries, and
+    // its share of G^{-1}) are issued before any is used; splits are summed
+    // in increasing order.
+    double gv_[kGPer];
+#pragma unroll
+    for (int q = 0; q < kGPer; ++q) {
+      const int e = tid + q * 256;
+      gv_[q] = e < RP * RP ? Gi[e] : 0.0;
+    }
+    double acc[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
+    for (int s0 = 0; s0 < p.vsplit; s0 += 8) {
+      float wv[kPer][8];
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int e = tid + q * 256;
+        const int j = e / RP, c = e % RP;
+        const float* src = p.Wpart + (int64_t)(vrow + j) * RP + c;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          wv[q][u] = (e < kVCols * RP && s0 + u < p.vsplit) ? src[(int64_t)(s0 + u) * split_stride] : 0.f;
+      }
+#pragma unroll
+      for (int q = 0; q < kPer; ++q)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[q] += (double)wv[q][u];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * 256;
+      if (e < kVCols * RP) wd[e / RP][e % RP] = acc[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kGPer; ++q) {
+      const int e = tid + q * 256;
+      if (e < RP * RP) gl[e] = gv_[q];
+    }
+  }
+  __syncthreads();
   float vres[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
@@ -460,12 +495,16 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
     }
   }
   __syncthreads();
+  // Partial V^T V of these columns (symmetric: each pair a <= b once).
   double* gv = p.gv_part + (int64_t)blockIdx.x * RP * RP;
   for (int e = tid; e < RP * RP; e += blockDim.x) {
     const int a = e / RP, b = e % RP;
+    if (a > b) continue;
     double s = 0.0;
+#pragma unroll 8
     for (int j = 0; j < kVCols; ++j) s += wd[j][a] * wd[j][b];
     gv[e] = s;
+    if (a != b) gv[b * RP + a] = s;
   }
 }
 
@@ -845,19 +884,20 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  // Clients are summed in order, four at a time so that their loads are in
+  // Clients are summed in order, kUB at a time so that their loads are in
   // flight together.
+  constexpr int kUB = RT <= 2 ? 8 : 4;
   int i = i_first;
-  for (; i + 4 <= i_last; i += 4) {
-    float tv[4][NQ];
+  for (; i + kUB <= i_last; i += kUB) {
+    float tv[kUB][NQ];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kUB; ++u) {
       const float* __restrict__ Ti = p.P + (int64_t)(i + u) * RP * MP + a;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) tv[u][q] = Ti[(int64_t)(cq + 4 * q) * MP];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kUB; ++u)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) acc[q] += (double)tv[u][q];
   }
