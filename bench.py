@@ -26,9 +26,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DCF-PCA iters/sec + time-to-relerr 1e-4 (BF16/learned vs plain FP32), 1 GPU"
 WORKLOAD = "plain_4000x8000_r20"
+WORKLOADS = ("plain_4000x8000_r20", "uneven_10000_r32")
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFS = 157.3
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_4000x8000_r20.json")
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_11669_amd", "csrc", "rpca_kernels.hip")
 
 
@@ -72,6 +74,10 @@ def src_hash() -> str:
 
 
 def cpu_baseline(inst, U0, r, rho, lam, budget_s: float = 12.0, max_rounds: int = 10) -> dict:
+    """The FP64 oracle timed on this host's cores. Small workloads run whole
+    rounds of the same instance; for an instance too large for it, one round
+    over a prefix of the clients (about 1/16 of the columns) is timed and
+    scaled to the full column count (the work of a round is linear in n)."""
     import numpy as np
     import oracle.reference as O
     try:
@@ -79,14 +85,28 @@ def cpu_baseline(inst, U0, r, rho, lam, budget_s: float = 12.0, max_rounds: int 
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         cores = os.cpu_count() or 1
+    blocks = inst.blocks()
+    if inst.M.dtype != np.float64:
+        ncols, k = 0, 0
+        while k < len(blocks) and ncols < inst.n / 16:
+            ncols += blocks[k].shape[1]
+            k += 1
+        sub = [np.asarray(b, dtype=np.float64) for b in blocks[:k]]
+        O.dcfpca([b[:, :8] for b in sub[:1]], r, rho, lam, 1, U0, record=False)
+        t0 = time.perf_counter()
+        O.dcfpca(sub, r, rho, lam, 1, U0, record=False)
+        dt = (time.perf_counter() - t0) * inst.n / ncols
+        return {"value": 1.0 / dt, "unit": "iters/s", "cores": int(cores), "kind": "oracle",
+                "sample": f"one round of the FP64 numpy oracle over the first {k} clients "
+                          f"({ncols} of {inst.n} columns, m={inst.m}, r={r}), time scaled by "
+                          f"{inst.n / ncols:.2f} to the full instance"}
     t0 = time.perf_counter()
-    O.dcfpca(inst.blocks(), r, rho, lam, 1, U0, record=False)
+    O.dcfpca(blocks, r, rho, lam, 1, U0, record=False)
     one = time.perf_counter() - t0
     rounds = int(max(1, min(max_rounds, budget_s // max(one, 1e-3))))
     t0 = time.perf_counter()
-    O.dcfpca(inst.blocks(), r, rho, lam, rounds, U0, record=False)
+    O.dcfpca(blocks, r, rho, lam, rounds, U0, record=False)
     dt = time.perf_counter() - t0
-    del np
     return {"value": rounds / dt, "unit": "iters/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{rounds} rounds of the FP64 numpy oracle on the same {inst.m}x{inst.n} "
                       f"instance (E={inst.E}, r={r}), after one untimed round"}
@@ -127,6 +147,9 @@ def copy_calibration() -> int:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default=WORKLOAD, choices=WORKLOADS,
+                    help="plain_4000x8000_r20 (default): m=4000, n=8000, E=16 x 500, r=20; "
+                         "uneven_10000_r32: m=10000, E=64 log-uniform widths in [64, 4096], r=32")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--u-mode", default="closed", choices=["closed", "grad"])
@@ -153,10 +176,11 @@ def main() -> int:
     from paper_2207_11669_amd import DCFPCA, colmajor
     from rpca_inputs import RECIPES, gaussian_init, recipe
 
-    cfg = RECIPES[WORKLOAD]
+    workload = args.workload
+    cfg = RECIPES[workload]
     r, rho = cfg["r"], cfg["rho"]
-    print(f"[bench] generating {WORKLOAD}", file=sys.stderr, flush=True)
-    inst = recipe(WORKLOAD, seed=0)
+    print(f"[bench] generating {workload}", file=sys.stderr, flush=True)
+    inst = recipe(workload, seed=0)
     lam = 1.0 / math.sqrt(inst.n)
     U0 = gaussian_init(inst.m, r, 7)
     dev = torch.device("cuda:0")
@@ -197,8 +221,8 @@ def main() -> int:
     avg_s = prof[dom][0] / 1e3
     roofline = roofline_of(costs[dom], avg_s)
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
+    if os.path.exists(traffic_file(workload)):
+        with open(traffic_file(workload)) as f:
             tr = json.load(f)
         if tr.get("kernel_source_sha256_16") == src_hash() and dom in tr.get("bytes_per_launch", {}):
             traffic = tr["bytes_per_launch"][dom]
@@ -238,7 +262,7 @@ def main() -> int:
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
+        "config": {"workload": workload, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
                    "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam,
                    "rho": rho, "K": 1, "inner": 1, "u_mode": args.u_mode},
         "roofline": roofline,

@@ -21,7 +21,9 @@ Recipes (all seeded; independent streams for factors, support, values and U^(0))
 * corruption values: uniform on [-a, a] ("uniform") or a uniform magnitude on
   [lo, hi] with a fair random sign ("signed");
 * client widths: equal blocks, or log-uniform widths in [lo, hi] rounded to
-  integers (the uneven-client workload).
+  integers (the uneven-client workload);
+* instances too large for dense FP64 work arrays are built one client block at
+  a time (Bernoulli support, per-block streams) and kept as FP32.
 """
 from __future__ import annotations
 
@@ -196,6 +198,50 @@ def planted_instance(
                     seed=int(seed), name=name)
 
 
+def planted_instance_large(
+    m: int,
+    widths: Sequence[int],
+    rstar: int,
+    s: float,
+    values: str = "signed",
+    lo: float = 1.0,
+    hi: float = 50.0,
+    seed: int = 0,
+    name: str = "",
+) -> Instance:
+    """The laws of planted_instance (Gaussian factors, Bernoulli(s) support)
+    for instances too large for dense FP64 work arrays: M is built one client
+    block at a time, each block drawing its support and values from streams of
+    its own, and is kept as FP32, column-major (M.T is C-contiguous). S* is
+    not kept (Sstar is None)."""
+    widths = [int(w) for w in widths]
+    n = int(sum(widths))
+    frng = _rng(seed, _STREAM_FACTORS)
+    Ustar = frng.standard_normal((m, rstar))
+    Vstar = frng.standard_normal((n, rstar))
+    Mt = np.empty((n, m), dtype=np.float32)
+    off = 0
+    for i, w in enumerate(widths):
+        Lt = Vstar[off:off + w] @ Ustar.T                     # (w, m): client block, transposed
+        srng = np.random.default_rng(np.random.SeedSequence([int(seed), _STREAM_SUPPORT, i]))
+        mask = srng.random((w, m)) < s
+        count = int(mask.sum())
+        vrng = np.random.default_rng(np.random.SeedSequence([int(seed), _STREAM_VALUES, i]))
+        if values == "uniform":
+            vals = vrng.uniform(-hi, hi, size=count)
+        elif values == "signed":
+            mag = vrng.uniform(lo, hi, size=count)
+            sg = np.random.default_rng(np.random.SeedSequence([int(seed), _STREAM_SIGNS, i]))
+            vals = np.where(sg.random(count) < 0.5, -1.0, 1.0) * mag
+        else:
+            raise ValueError(f"unknown values {values!r}")
+        Lt[mask] += vals
+        Mt[off:off + w] = Lt
+        off += w
+    return Instance(M=Mt.T, widths=widths, Ustar=Ustar, Vstar=Vstar, Sstar=None,
+                    seed=int(seed), name=name)
+
+
 # Named workloads. Each entry gives the instance recipe and the solver
 # parameters the workload is quoted with (lambda = 1/sqrt(n), rho = 0.1).
 RECIPES = {
@@ -212,6 +258,12 @@ RECIPES = {
     "geom_2000x2000_r64": dict(m=2000, n=2000, E=1, rstar=64, s=0.05, values="signed",
                                lo=1.0, hi=100.0, r=64, rho=0.1, T=100,
                                spectrum="geometric"),
+    # m = 10000, 64 clients with widths log-uniform in [64, 4096] (seeded),
+    # rank 32, 5% of entries corrupted (Bernoulli) with magnitude U[1, 50],
+    # r = 32. About 62,000 columns: M is 2.5 GB in FP32, built blockwise.
+    "uneven_10000_r32": dict(m=10000, E=64, widths=("loguniform", 64, 4096), rstar=32,
+                             s=0.05, values="signed", lo=1.0, hi=50.0, r=32, rho=0.1,
+                             T=200, large=True),
 }
 
 
@@ -219,6 +271,12 @@ def recipe(name: str, seed: int = 0, E: Optional[int] = None) -> Instance:
     """Instantiate a named workload (see RECIPES)."""
     cfg = dict(RECIPES[name])
     E = int(E if E is not None else cfg["E"])
+    if cfg.get("large"):
+        kind, wlo, whi = cfg["widths"]
+        widths = loguniform_widths(E, wlo, whi, seed)
+        return planted_instance_large(cfg["m"], widths, cfg["rstar"], cfg["s"],
+                                      values=cfg["values"], lo=cfg["lo"], hi=cfg["hi"],
+                                      seed=seed, name=name)
     widths = equal_widths(cfg["n"], E)
     return planted_instance(cfg["m"], widths, cfg["rstar"], cfg["s"], values=cfg["values"],
                             lo=cfg["lo"], hi=cfg["hi"], seed=seed,
