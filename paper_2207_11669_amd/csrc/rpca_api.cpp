@@ -3,6 +3,7 @@
 #include "../../include/rpca.h"
 #include "rpca_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -14,6 +15,7 @@ using namespace rpca;
 struct rpca_ctx {
   DevParams p{};
   std::vector<ClientDev> clients;
+  std::vector<ClientDev> clients_lpt;  // widest first
   std::vector<VGroup> vgroups;
   std::vector<int64_t> col_off;  // first global column of each client, [E + 1]
   hipStream_t stream = nullptr;
@@ -55,7 +57,7 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t S, U0, U1, Uc0, Uc1, V0, V1, Wpart, P, gv, Af, Bf, gram, spart, upart,
-      ucl, Ginv, dstate, hist, stat_part, clients, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
+      ucl, Ginv, dstate, hist, stat_part, clients, clients_lpt, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
       total;
   int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows;
   bool recompute;
@@ -150,6 +152,7 @@ Layout make_layout(const rpca_params* p) {
   L.hist = take((size_t)kHist * sizeof(StatsRec));
   L.stat_part = take((size_t)8 * d);
   L.clients = take((size_t)E * sizeof(ClientDev));
+  L.clients_lpt = take((size_t)E * sizeof(ClientDev));
   L.vgroups = take((size_t)L.ngroups * sizeof(VGroup));
   L.vg64 = take((size_t)L.ng64 * sizeof(VTile));
   L.Uprev = take((size_t)L.RP * L.MP * f);
@@ -371,6 +374,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.rho = prm->rho;
   p.eta0 = prm->eta0;
   p.clients = reinterpret_cast<const ClientDev*>(ws + L.clients);
+  p.clients_lpt = reinterpret_cast<const ClientDev*>(ws + L.clients_lpt);
   p.vgroups = reinterpret_cast<const VGroup*>(ws + L.vgroups);
   p.vg64 = reinterpret_cast<const VTile*>(ws + L.vg64);
   p.S = L.recompute ? nullptr : reinterpret_cast<float*>(ws + L.S);
@@ -425,6 +429,8 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
     }
     cd.g1 = g;
     cd.c = prm->rho * (double)ni / (double)L.n;
+    cd.idx = i;
+    cd.pad = 0;
     for (int32_t j0 = 0; j0 < ni; j0 += kVStreamCols)
       c->vg64.push_back(VTile{cd, i, j0, ni - j0 < kVStreamCols ? ni - j0 : kVStreamCols, 0});
     c->col_off[i] = col;
@@ -432,12 +438,18 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
     vrow += round_up(ni, kVPad);
   }
   c->col_off[prm->E] = col;
+  c->clients_lpt = c->clients;
+  std::stable_sort(c->clients_lpt.begin(), c->clients_lpt.end(),
+                   [](const ClientDev& x, const ClientDev& y) { return x.n > y.n; });
 
   hipStream_t st = c->stream;
   hipError_t e = hipMemsetAsync(workspace, 0, L.total, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + L.clients, c->clients.data(), c->clients.size() * sizeof(ClientDev),
                        hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.clients_lpt, c->clients_lpt.data(),
+                       c->clients_lpt.size() * sizeof(ClientDev), hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + L.vgroups, c->vgroups.data(), c->vgroups.size() * sizeof(VGroup),
                        hipMemcpyHostToDevice, st);

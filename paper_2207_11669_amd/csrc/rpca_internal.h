@@ -64,6 +64,8 @@ struct ClientDev {
   int32_t vrow0;    // first row of V_i in the padded V buffers (multiple of 64)
   int32_t g0, g1;   // V-finalize work-groups [g0, g1) that cover this client
   double c;         // rho * n_i / n
+  int32_t idx;      // client index i
+  int32_t pad;
 };
 
 // A V-pass work unit: up to 32 (finalize) or 64 (streaming) consecutive
@@ -107,6 +109,7 @@ struct DevParams {
   float lam;
   double rho, eta0;
   const ClientDev* clients;
+  const ClientDev* clients_lpt;  // the same records, widest client first (S-pass order)
   const VGroup* vgroups;
   const VTile* vg64;
   float* S;              // all clients' S_i (stored-S layout only)

@@ -561,8 +561,12 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
   static_assert(NS >= 1 && NS <= 4 * RT, "NS = ceil(r / 4) must fit the rank tiles");
   // P's last rank tile in 4x4 blocks when it holds at most 12 ranks.
   constexpr int NQ = nquads(RP, NS), RTF = NQ ? RT - 1 : RT;
-  const int b = blockIdx.x, ci = client_base + (int)blockIdx.y;
-  const ClientDev cl = p.clients[ci];
+  // Clients run widest first (longest work-groups dispatched earliest), except
+  // for the S emission of a client range.
+  const int b = blockIdx.x;
+  const ClientDev cl = emit_only ? p.clients[client_base + (int)blockIdx.y]
+                                 : p.clients_lpt[blockIdx.y];
+  const int ci = cl.idx;
   const float* __restrict__ U = Ubase + (int64_t)ci * u_stride;
   const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) & 3;
   // Wave-uniform (waves 0-3: phase 0, waves 4-7: phase 1); readfirstlane tells

@@ -51,3 +51,23 @@ def default_lam(inst: Instance) -> float:
 
 def init_for(inst: Instance, r: int, seed: int) -> np.ndarray:
     return gaussian_init(inst.m, r, seed)
+
+
+TOL = 1e-5
+
+
+def parity(inst: Instance, r: int, T: int, seed: int = 7, rho: float = 0.1, lam=None,
+           tol: float = TOL, **kw):
+    """Run both paths for T rounds and require relative Frobenius differences
+    <= tol on L and on S."""
+    lam = default_lam(inst) if lam is None else lam
+    U0 = init_for(inst, r, seed)
+    announce(f"m={inst.m} widths={inst.widths[:8]}{'...' if inst.E > 8 else ''} r={r} T={T} {kw}")
+    s, Lg, Sg, hist = run_gpu(inst, U0, r, rho, lam, T, **kw)
+    res = run_oracle(inst, U0, r, rho, lam, T, **kw)
+    eL = rel(Lg, res.L_full())
+    eS = rel(Sg, res.S_full())
+    announce(f"relL={eL:.3e} relS={eS:.3e}")
+    assert eL <= tol, eL
+    assert eS <= tol, eS
+    return s, Lg, Sg, hist, res

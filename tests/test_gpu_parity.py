@@ -7,26 +7,13 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import announce, default_lam, init_for, rel, run_gpu, run_oracle
+from gpu_helpers import TOL, announce, default_lam, init_for, parity, rel, run_gpu, run_oracle
 from rpca_inputs import equal_widths, planted_instance, recipe
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-5
-
-
-def _parity(inst, r, T, seed=7, rho=0.1, lam=None, tol=TOL, **kw):
-    lam = default_lam(inst) if lam is None else lam
-    U0 = init_for(inst, r, seed)
-    announce(f"m={inst.m} widths={inst.widths[:8]}{'...' if inst.E > 8 else ''} r={r} T={T} {kw}")
-    s, Lg, Sg, hist = run_gpu(inst, U0, r, rho, lam, T, **kw)
-    res = run_oracle(inst, U0, r, rho, lam, T, **kw)
-    eL = rel(Lg, res.L_full())
-    eS = rel(Sg, res.S_full())
-    announce(f"relL={eL:.3e} relS={eS:.3e}")
-    assert eL <= tol, eL
-    assert eS <= tol, eS
-    return s, Lg, Sg, hist, res
+def _parity(inst, r, T, **kw):
+    return parity(inst, r, T, **kw)
 
 
 @pytest.mark.parametrize("store_s", [False, True])
