@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DCF-PCA iters/sec + time-to-relerr 1e-4 (BF16/learned vs plain FP32), 1 GPU"
 WORKLOAD = "plain_4000x8000_r20"
-WORKLOADS = ("plain_4000x8000_r20", "uneven_10000_r32")
+WORKLOADS = ("plain_4000x8000_r20", "uneven_10000_r32", "plain_500x500_r5")
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFS = 157.3
 def traffic_file(workload: str) -> str:
@@ -153,6 +153,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--u-mode", default="closed", choices=["closed", "grad"])
+    ap.add_argument("--graph", action="store_true",
+                    help="replay steady-state rounds from HIP graphs (RPCA_FLAG_GRAPH)")
     ap.add_argument("--profile-rounds", type=int, default=50)
     ap.add_argument("--relerr-rounds", type=int, default=3000)
     ap.add_argument("--fixed-point-rounds", type=int, default=8000)
@@ -189,13 +191,13 @@ def main() -> int:
     U0_cols = colmajor(U0, device=dev)
     eta0 = 0.0 if args.u_mode == "closed" else 1e-4
     s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-               eta0=eta0)
+               eta0=eta0, graph=args.graph)
     torch.cuda.synchronize()
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     s.step(args.warmup)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream(dev)
+    stream = s.stream
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     print(f"[bench] timing {args.steps} rounds", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -264,7 +266,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": workload, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
                    "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam,
-                   "rho": rho, "K": 1, "inner": 1, "u_mode": args.u_mode},
+                   "rho": rho, "K": 1, "inner": 1, "u_mode": args.u_mode,
+                   "graph": bool(args.graph)},
         "roofline": roofline,
         "time_to_relerr": ttr,
         "time_to_fixed_point": ttf,

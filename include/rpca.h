@@ -77,6 +77,14 @@ typedef struct {
  * flag keeps S in the workspace instead (the layout used for K > 1 or more
  * than one alternation); the results agree to FP32 rounding. */
 #define RPCA_FLAG_STORE_S 1u
+/* Replay steady-state rounds from HIP graphs: rpca_step captures two
+ * consecutive rounds (K = 1, one alternation, S rebuilt) once per buffer
+ * parity and launches the graph for every later pair of rounds, which removes
+ * the host cost of the per-round launches. Results are bitwise those of the
+ * eager launches. Needs a stream other than the null stream (rpca_init
+ * returns RPCA_EINVAL otherwise); ignored with RPCA_FLAG_STORE_S, K > 1 or
+ * inner > 1. */
+#define RPCA_FLAG_GRAPH 2u
 
 /* Per-round statistics, FP64, recorded at the last local step of round t:
  * objective = sum_i L_i(U_i, V_i, S_i) with U_i the client factor that the

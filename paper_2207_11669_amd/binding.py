@@ -109,17 +109,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
 
 
 RPCA_FLAG_STORE_S = 1
+RPCA_FLAG_GRAPH = 2
 
 
 def make_params(m: int, widths: Sequence[int], r: int, rho: float, lam: float, K: int = 1,
                 inner: int = 1, u_mode: str = "closed", eta0: float = 0.0,
-                eta_sched: str = "const", store_s: bool = False):
+                eta_sched: str = "const", store_s: bool = False, graph: bool = False):
     """Build an rpca_params struct; returns (params, n_cols array to keep alive)."""
     ncols = (c_int64 * len(widths))(*[int(w) for w in widths])
+    flags = (RPCA_FLAG_STORE_S if store_s else 0) | (RPCA_FLAG_GRAPH if graph else 0)
     p = RpcaParams(m=int(m), E=len(widths), n_cols=ncols, r=int(r), rho=float(rho),
                    lam=float(lam), K=int(K), inner=int(inner), u_mode=U_MODES[u_mode],
-                   eta0=float(eta0), eta_sched=ETA_SCHEDS[eta_sched],
-                   flags=RPCA_FLAG_STORE_S if store_s else 0)
+                   eta0=float(eta0), eta_sched=ETA_SCHEDS[eta_sched], flags=flags)
     return p, ncols
 
 
@@ -163,7 +164,7 @@ class DCFPCA:
     def __init__(self, M_cols, widths: Sequence[int], m: int, r: int, rho: float, lam: float,
                  U0_cols, K: int = 1, inner: int = 1, u_mode: str = "closed",
                  eta0: float = 0.0, eta_sched: str = "const", store_s: bool = False,
-                 stream=None):
+                 graph: bool = False, stream=None):
         import torch
         self._lib = load_library()
         if not (M_cols.is_cuda and M_cols.dtype == torch.float32 and M_cols.is_contiguous()):
@@ -177,14 +178,22 @@ class DCFPCA:
             raise ValueError("M_cols must have one row per column of M")
         self.ldm = int(M_cols.shape[1])
         self.params, self._ncols = make_params(m, self.widths, r, rho, lam, K, inner, u_mode,
-                                               eta0, eta_sched, store_s)
+                                               eta0, eta_sched, store_s, graph)
         err = params_error(self.params)
         if err:
             raise ValueError(err)
         self.device = M_cols.device
         self.M_cols = M_cols  # borrowed by the library: keep it alive
         self.ws = torch.empty(workspace_bytes(self.params), dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+            if graph and stream.cuda_stream == 0:
+                # Graph capture needs a stream other than the null stream.
+                stream = torch.cuda.Stream(self.device)
+        self.stream = stream
+        # Inputs were written on the caller's stream; order the library's work
+        # after them. Outputs are handed back the same way (see _hand_back).
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         base = M_cols.data_ptr()
         ptrs, lds, off = [], [], 0
         for w in self.widths:
@@ -206,6 +215,13 @@ class DCFPCA:
     def _check(self, st: int):
         if st != RPCA_OK:
             raise RpcaError(st, self._lib.rpca_last_error(self.ctx).decode())
+
+    def _hand_back(self):
+        """Order the caller's current stream after the library's work."""
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.wait_stream(self.stream)
 
     def step(self, rounds: int = 1):
         self._check(self._lib.rpca_step(self.ctx, int(rounds)))
@@ -237,6 +253,7 @@ class DCFPCA:
         S = torch.empty((ncols, ld), dtype=torch.float32, device=self.device)
         self._check(self._lib.rpca_get_LS(self.ctx, int(client), c_void_p(L.data_ptr()), ld,
                                           c_void_p(S.data_ptr()), ld))
+        self._hand_back()
         return L, S
 
     def get_factors(self):
@@ -247,6 +264,7 @@ class DCFPCA:
         V = torch.empty((self.r, ldv), dtype=torch.float32, device=self.device)
         self._check(self._lib.rpca_get_factors(self.ctx, c_void_p(U.data_ptr()), ldu,
                                                c_void_p(V.data_ptr()), ldv))
+        self._hand_back()
         return U, V
 
     def stats(self, round_index: int = -1) -> dict:

@@ -25,6 +25,9 @@ struct rpca_ctx {
   // in one extra work-group next to the streaming ones. Calls that read its
   // outputs flush it first with a standalone launch.
   bool fin_pending = false;
+  // RPCA_FLAG_GRAPH: two-round graphs, one per starting buffer parity.
+  bool use_graph = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int cur = 0;   // consensus U buffer holding U^(t)
   int vcur = 0;  // V buffer holding the latest V
   int inner = 1;
@@ -84,7 +87,7 @@ const char* check_params(const rpca_params* p) {
   if (p->u_mode == RPCA_U_GRAD && (!(p->eta0 > 0.0) || !std::isfinite(p->eta0)))
     return "eta0 must be finite and > 0 for RPCA_U_GRAD";
   if (p->eta_sched != RPCA_ETA_CONST && p->eta_sched != RPCA_ETA_SQRT) return "unknown eta_sched";
-  if (p->flags & ~(uint32_t)RPCA_FLAG_STORE_S) return "unknown flags";
+  if (p->flags & ~(uint32_t)(RPCA_FLAG_STORE_S | RPCA_FLAG_GRAPH)) return "unknown flags";
   return nullptr;
 }
 
@@ -347,6 +350,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   if (!workspace || ws_bytes < L.total || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
     return RPCA_EWORKSPACE;
 
+  if ((prm->flags & RPCA_FLAG_GRAPH) && !stream) return RPCA_EINVAL;
   rpca_ctx* c = new rpca_ctx();
   c->stream = reinterpret_cast<hipStream_t>(stream);
   c->inner = prm->inner;
@@ -379,6 +383,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.vg64 = reinterpret_cast<const VTile*>(ws + L.vg64);
   p.S = L.recompute ? nullptr : reinterpret_cast<float*>(ws + L.S);
   c->recompute = L.recompute;
+  c->use_graph = L.recompute && (prm->flags & RPCA_FLAG_GRAPH);
   c->V[0] = reinterpret_cast<float*>(ws + L.V0);
   c->V[1] = reinterpret_cast<float*>(ws + L.V1);
   p.V = c->V[0];
@@ -474,11 +479,51 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   return RPCA_OK;
 }
 
+// Two rounds from a steady state (rebuilt S, finalize deferred) as one graph
+// launch; the graph for this buffer parity is captured on first use. The host
+// state after two rounds equals the state before them except for the count.
+rpca_status enqueue_round_pair_graph(rpca_ctx* c) {
+  const int key = c->cur;
+  if (!c->gexec[key]) {
+    const int cur = c->cur, vcur = c->vcur;
+    const int64_t rounds = c->rounds;
+    const bool fin = c->fin_pending;
+    RPCA_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    rpca_status s1 = enqueue_round(c);
+    rpca_status s2 = s1 == RPCA_OK ? enqueue_round(c) : s1;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->cur = cur;
+    c->vcur = vcur;
+    c->rounds = rounds;
+    c->fin_pending = fin;
+    if (s2 != RPCA_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s2;
+    }
+    RPCA_HIP(c, e, "end capture");
+    const hipError_t ei = hipGraphInstantiate(&c->gexec[key], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    RPCA_HIP(c, ei, "graph instantiate");
+  }
+  RPCA_HIP(c, hipGraphLaunch(c->gexec[key], c->stream), "graph launch");
+  c->rounds += 2;
+  return RPCA_OK;
+}
+
 rpca_status rpca_step(rpca_ctx* c, int32_t rounds) {
   if (rpca_status s = guard(c)) return s;
   if (rounds < 0) return fail(c, RPCA_EINVAL, "rounds must be >= 0");
-  for (int32_t t = 0; t < rounds; ++t)
-    if (rpca_status s = enqueue_round(c)) return s;
+  int32_t t = 0;
+  while (t < rounds) {
+    if (c->use_graph && rounds - t >= 2 && c->rounds >= 1 && c->fin_pending) {
+      if (rpca_status s = enqueue_round_pair_graph(c)) return s;
+      t += 2;
+    } else {
+      if (rpca_status s = enqueue_round(c)) return s;
+      t += 1;
+    }
+  }
   return RPCA_OK;
 }
 
@@ -653,6 +698,11 @@ const char* rpca_last_error(const rpca_ctx* c) {
   return c->err.c_str();
 }
 
-void rpca_destroy(rpca_ctx* c) { delete c; }
+void rpca_destroy(rpca_ctx* c) {
+  if (!c) return;
+  for (hipGraphExec_t& g : c->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  delete c;
+}
 
 }  // extern "C"
