@@ -180,6 +180,16 @@ typedef enum {
  * launches (launches[RPCA_NUM_PHASES]). The rounds count as real rounds. */
 rpca_status rpca_profile(rpca_ctx* c, int32_t rounds, double* avg_ms, int64_t* launches);
 
+/* Autotuner for the V-pass split of the row dimension (the split-K of
+ * W = (M_i - S_i)^T U over m): runs `rounds` timed rounds (plus one untimed)
+ * at each candidate split count -- the default, half of it and twice it,
+ * within what the workspace holds -- keeps the fastest, and returns it in
+ * *vsplit_out (optional). Synchronises. The rounds are real rounds of the
+ * method. The split count changes only the summation order of W, so results
+ * stay within FP32 rounding of the default and are deterministic for a given
+ * choice; the choice itself depends on timing. */
+rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out);
+
 /* Rounds enqueued so far. */
 int64_t rpca_rounds(const rpca_ctx* c);
 

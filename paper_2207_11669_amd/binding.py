@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rpca_init": (c_int32, [POINTER(vp), POINTER(RpcaParams), POINTER(vp), POINTER(c_int64),
                                 vp, c_int64, vp, c_size_t, vp]),
         "rpca_step": (c_int32, [vp, c_int32]),
+        "rpca_autotune": (c_int32, [vp, c_int32, POINTER(c_int32)]),
         "rpca_solve": (c_int32, [vp, c_int32, c_double, c_int32, POINTER(c_int32),
                                  POINTER(c_double)]),
         "rpca_set_target": (c_int32, [vp, vp, c_int64, vp, c_int64, c_int32]),
@@ -225,6 +226,12 @@ class DCFPCA:
 
     def step(self, rounds: int = 1):
         self._check(self._lib.rpca_step(self.ctx, int(rounds)))
+
+    def autotune(self, rounds: int = 10) -> int:
+        """Pick the V-pass row-split count by timing; returns it."""
+        out = c_int32(0)
+        self._check(self._lib.rpca_autotune(self.ctx, int(rounds), ctypes.byref(out)))
+        return int(out.value)
 
     def solve(self, max_rounds: int, tol: float, check_every: int = 1):
         done, metric = c_int32(0), c_double(0.0)

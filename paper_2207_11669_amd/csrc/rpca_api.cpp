@@ -27,6 +27,7 @@ struct rpca_ctx {
   bool fin_pending = false;
   // RPCA_FLAG_GRAPH: two-round graphs, one per starting buffer parity.
   bool use_graph = false;
+  int32_t vsplit_max = 1;  // largest V-pass row-split count the workspace holds
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int cur = 0;   // consensus U buffer holding U^(t)
   int vcur = 0;  // V buffer holding the latest V
@@ -62,7 +63,7 @@ struct Layout {
   size_t S, U0, U1, Uc0, Uc1, V0, V1, Wpart, P, gv, Af, Bf, gram, spart, upart,
       ucl, Ginv, dstate, hist, stat_part, clients, clients_lpt, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
       total;
-  int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows;
+  int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows, vsplit_max;
   bool recompute;
   int64_t lds, n, Sfloats;
 };
@@ -120,6 +121,9 @@ Layout make_layout(const rpca_params* p) {
     const int64_t rows = round_up((p->m + vs - 1) / vs, 16);
     L.vsplit_rows = (int32_t)rows;
     L.vsplit = (int32_t)((p->m + rows - 1) / rows);
+    // rpca_autotune may try up to twice as many splits.
+    const int64_t vmax = 2 * L.vsplit < maxs ? 2 * L.vsplit : maxs;
+    L.vsplit_max = (int32_t)(vmax > L.vsplit ? vmax : L.vsplit);
   }
   L.recompute = p->K == 1 && p->inner == 1 && !(p->flags & RPCA_FLAG_STORE_S);
   L.Sfloats = L.recompute ? 0 : L.lds * n;
@@ -141,7 +145,7 @@ Layout make_layout(const rpca_params* p) {
   L.Uc1 = take(multi ? (size_t)E * ub * f : 0);
   L.V0 = take((size_t)vbuf_floats(L.NVP, L.RP, L.NS) * f);
   L.V1 = take((size_t)vbuf_floats(L.NVP, L.RP, L.NS) * f);
-  L.Wpart = take((size_t)L.vsplit * L.NVP * L.RP * f);
+  L.Wpart = take((size_t)(L.vsplit_max + 1) * L.NVP * L.RP * f);
   L.P = take((size_t)E * L.RP * L.MP * f);
   L.gv = take((size_t)L.ngroups * RR * d);
   L.Af = take((size_t)E * RR * d);
@@ -372,6 +376,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.ng64 = L.ng64;
   p.vsplit = L.vsplit;
   p.vsplit_rows = L.vsplit_rows;
+  c->vsplit_max = L.vsplit_max;
   p.u_mode = prm->u_mode;
   p.eta_sched = prm->eta_sched;
   p.lam = (float)prm->lambda;
@@ -525,6 +530,68 @@ rpca_status rpca_step(rpca_ctx* c, int32_t rounds) {
     }
   }
   return RPCA_OK;
+}
+
+// Row splits for a given count: rows per split a multiple of 16.
+static void set_vsplit(rpca_ctx* c, int64_t vs) {
+  const int64_t m = c->p.m;
+  const int64_t rows = round_up((m + vs - 1) / vs, 16);
+  c->p.vsplit_rows = (int32_t)rows;
+  c->p.vsplit = (int32_t)((m + rows - 1) / rows);
+}
+
+rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out) {
+  if (rpca_status s = guard(c)) return s;
+  if (rounds < 1) return fail(c, RPCA_EINVAL, "rounds must be >= 1");
+  const int32_t v0 = c->p.vsplit;
+  std::vector<int32_t> cand;
+  for (int64_t v : {(int64_t)(v0 + 1) / 2, (int64_t)v0, (int64_t)c->vsplit_max}) {
+    if (v < 1 || v > c->vsplit_max) continue;
+    set_vsplit(c, v);
+    if (std::find(cand.begin(), cand.end(), c->p.vsplit) == cand.end()) cand.push_back(c->p.vsplit);
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  RPCA_HIP(c, hipEventCreate(&a), "event");
+  const hipError_t eb = hipEventCreate(&b);
+  if (eb != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return dev_fail(c, eb, "event");
+  }
+  int32_t best = v0;
+  float best_ms = 0.f;
+  rpca_status result = RPCA_OK;
+  for (int32_t v : cand) {
+    set_vsplit(c, v);
+    // One untimed round in the new configuration, then the timed ones.
+    if ((result = enqueue_round(c)) != RPCA_OK) break;
+    hipError_t e = hipEventRecord(a, c->stream);
+    for (int32_t t = 0; t < rounds && e == hipSuccess && result == RPCA_OK; ++t)
+      result = enqueue_round(c);
+    if (result != RPCA_OK) break;
+    if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e != hipSuccess) {
+      result = dev_fail(c, e, "autotune timing");
+      break;
+    }
+    if (best_ms == 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  set_vsplit(c, result == RPCA_OK ? best : v0);
+  // Graphs captured before bake the old launch shapes.
+  for (hipGraphExec_t& g : c->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  if (vsplit_out) *vsplit_out = c->p.vsplit;
+  return result;
 }
 
 rpca_status rpca_set_target(rpca_ctx* c, const float* Ustar, int64_t ldus, const float* Vstar,

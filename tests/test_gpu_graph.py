@@ -38,3 +38,32 @@ def test_graph_replay_matches_eager():
         same = np.array_equal(Le, Lg) and np.array_equal(Se, Sg) and ste == stg
         announce(f"checkpoint {k}: round {ste['t']:.0f} bitwise={same}")
         assert same
+
+
+def test_autotune_keeps_parity():
+    """The V-pass row-split autotuner runs real rounds under several split
+    counts; the trajectory still matches the oracle's for the same number of
+    rounds, and the pick is one of the candidates."""
+    import torch
+
+    import oracle.reference as O
+    from gpu_helpers import rel
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    inst = planted_instance(2000, [500, 500, 500, 500], 6, 0.05, values="uniform", hi=10.0,
+                            seed=23)
+    U0 = init_for(inst, 8, 4)
+    lam = default_lam(inst)
+    s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 8, 0.1, lam, colmajor(U0), u_mode="closed")
+    s.step(3)
+    v = s.autotune(3)
+    s.step(4)
+    T = s.rounds
+    L, S = s.get_LS(-1)
+    torch.cuda.synchronize()
+    Lg = L[:, :inst.m].T.double().cpu().numpy()
+    Sg = S[:, :inst.m].T.double().cpu().numpy()
+    res = O.dcfpca(inst.blocks(), 8, 0.1, lam, T, U0)
+    eL, eS = rel(Lg, res.L_full()), rel(Sg, res.S_full())
+    announce(f"autotune picked {v} row splits; {T} rounds; relL={eL:.3e} relS={eS:.3e}")
+    assert 1 <= v <= 64 and eL <= 1e-5 and eS <= 1e-5
+    s.close()
