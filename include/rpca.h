@@ -85,6 +85,25 @@ typedef struct {
  * returns RPCA_EINVAL otherwise); ignored with RPCA_FLAG_STORE_S, K > 1 or
  * inner > 1. */
 #define RPCA_FLAG_GRAPH 2u
+/* Mixed precision. rpca_init makes two BF16 copies of M (2 B per entry each,
+ * in the operand layouts of the two streaming passes) and the factor kernels
+ * keep BF16 copies of U and V next to the FP32 ones. While the context's
+ * precision is RPCA_PREC_BF16 (the initial precision with this flag), the
+ * rank-r contractions of a round take M, U and V in BF16 with FP32
+ * accumulation, so each streaming pass reads 2 B per entry of M instead of 4.
+ * The residual, soft-threshold, Lambda, the U step and all statistics stay
+ * FP32/FP64, and the factors are FP32 throughout. rpca_set_precision switches
+ * to FP32 rounds (which read the caller's FP32 M) at any round boundary: the
+ * FP32 closing rounds refine the BF16 iterate to the FP32 fixed point.
+ * Needs K = 1, inner = 1 and no RPCA_FLAG_STORE_S. rpca_get_LS evaluates S in
+ * FP32 from the current factors in either precision. */
+#define RPCA_FLAG_BF16 4u
+
+/* Arithmetic of a round's streaming passes (rpca_set_precision). */
+typedef enum {
+  RPCA_PREC_FP32 = 0,
+  RPCA_PREC_BF16 = 1  /* needs a context created with RPCA_FLAG_BF16 */
+} rpca_precision;
 
 /* Per-round statistics, FP64, recorded at the last local step of round t:
  * objective = sum_i L_i(U_i, V_i, S_i) with U_i the client factor that the
@@ -189,6 +208,12 @@ rpca_status rpca_profile(rpca_ctx* c, int32_t rounds, double* avg_ms, int64_t* l
  * stay within FP32 rounding of the default and are deterministic for a given
  * choice; the choice itself depends on timing. */
 rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out);
+
+/* Precision of the rounds enqueued from now on (rpca_precision). BF16 needs
+ * a context created with RPCA_FLAG_BF16 (RPCA_EINVAL otherwise). Switching
+ * drops captured graphs. The next round's V-pass rebuilds S^(t) from the
+ * previous factors in the new precision. */
+rpca_status rpca_set_precision(rpca_ctx* c, int32_t precision);
 
 /* Rounds enqueued so far. */
 int64_t rpca_rounds(const rpca_ctx* c);

@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                 vp, c_int64, vp, c_size_t, vp]),
         "rpca_step": (c_int32, [vp, c_int32]),
         "rpca_autotune": (c_int32, [vp, c_int32, POINTER(c_int32)]),
+        "rpca_set_precision": (c_int32, [vp, c_int32]),
         "rpca_solve": (c_int32, [vp, c_int32, c_double, c_int32, POINTER(c_int32),
                                  POINTER(c_double)]),
         "rpca_set_target": (c_int32, [vp, vp, c_int64, vp, c_int64, c_int32]),
@@ -111,14 +112,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
 
 RPCA_FLAG_STORE_S = 1
 RPCA_FLAG_GRAPH = 2
+RPCA_FLAG_BF16 = 4
+PRECISIONS = {"fp32": 0, "bf16": 1}
 
 
 def make_params(m: int, widths: Sequence[int], r: int, rho: float, lam: float, K: int = 1,
                 inner: int = 1, u_mode: str = "closed", eta0: float = 0.0,
-                eta_sched: str = "const", store_s: bool = False, graph: bool = False):
+                eta_sched: str = "const", store_s: bool = False, graph: bool = False,
+                bf16: bool = False):
     """Build an rpca_params struct; returns (params, n_cols array to keep alive)."""
     ncols = (c_int64 * len(widths))(*[int(w) for w in widths])
-    flags = (RPCA_FLAG_STORE_S if store_s else 0) | (RPCA_FLAG_GRAPH if graph else 0)
+    flags = ((RPCA_FLAG_STORE_S if store_s else 0) | (RPCA_FLAG_GRAPH if graph else 0)
+             | (RPCA_FLAG_BF16 if bf16 else 0))
     p = RpcaParams(m=int(m), E=len(widths), n_cols=ncols, r=int(r), rho=float(rho),
                    lam=float(lam), K=int(K), inner=int(inner), u_mode=U_MODES[u_mode],
                    eta0=float(eta0), eta_sched=ETA_SCHEDS[eta_sched], flags=flags)
@@ -159,13 +164,14 @@ class DCFPCA:
 
     M_cols: (n, ldm) FP32 CUDA tensor, M column-major (see `colmajor`); client i
     owns columns offsets[i]:offsets[i+1] in order. U0_cols: (r, ldu) tensor
-    with U^(0) column-major.
+    with U^(0) column-major. bf16=True creates the context with
+    RPCA_FLAG_BF16: rounds run in BF16 until set_precision("fp32").
     """
 
     def __init__(self, M_cols, widths: Sequence[int], m: int, r: int, rho: float, lam: float,
                  U0_cols, K: int = 1, inner: int = 1, u_mode: str = "closed",
                  eta0: float = 0.0, eta_sched: str = "const", store_s: bool = False,
-                 graph: bool = False, stream=None):
+                 graph: bool = False, stream=None, bf16: bool = False):
         import torch
         self._lib = load_library()
         if not (M_cols.is_cuda and M_cols.dtype == torch.float32 and M_cols.is_contiguous()):
@@ -179,7 +185,7 @@ class DCFPCA:
             raise ValueError("M_cols must have one row per column of M")
         self.ldm = int(M_cols.shape[1])
         self.params, self._ncols = make_params(m, self.widths, r, rho, lam, K, inner, u_mode,
-                                               eta0, eta_sched, store_s, graph)
+                                               eta0, eta_sched, store_s, graph, bf16)
         err = params_error(self.params)
         if err:
             raise ValueError(err)
@@ -232,6 +238,10 @@ class DCFPCA:
         out = c_int32(0)
         self._check(self._lib.rpca_autotune(self.ctx, int(rounds), ctypes.byref(out)))
         return int(out.value)
+
+    def set_precision(self, precision: str):
+        """Precision of the following rounds' streaming passes: "fp32" or "bf16"."""
+        self._check(self._lib.rpca_set_precision(self.ctx, PRECISIONS[precision]))
 
     def solve(self, max_rounds: int, tol: float, check_every: int = 1):
         done, metric = c_int32(0), c_double(0.0)

@@ -28,6 +28,7 @@ struct rpca_ctx {
   // RPCA_FLAG_GRAPH: two-round graphs, one per starting buffer parity.
   bool use_graph = false;
   int32_t vsplit_max = 1;  // largest V-pass row-split count the workspace holds
+  int32_t prec = RPCA_PREC_FP32;  // precision of the streaming passes
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int cur = 0;   // consensus U buffer holding U^(t)
   int vcur = 0;  // V buffer holding the latest V
@@ -60,11 +61,11 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t S, U0, U1, Uc0, Uc1, V0, V1, Wpart, P, gv, Af, Bf, gram, spart, upart,
+  size_t S, U0, U1, Uc0, Uc1, V0, V1, Mbv, Mbs, Wpart, P, gv, Af, Bf, gram, spart, upart,
       ucl, Ginv, dstate, hist, stat_part, clients, clients_lpt, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
       total;
-  int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows, vsplit_max;
-  bool recompute;
+  int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows, vsplit_max, RK;
+  bool recompute, bf16;
   int64_t lds, n, Sfloats;
 };
 
@@ -88,7 +89,11 @@ const char* check_params(const rpca_params* p) {
   if (p->u_mode == RPCA_U_GRAD && (!(p->eta0 > 0.0) || !std::isfinite(p->eta0)))
     return "eta0 must be finite and > 0 for RPCA_U_GRAD";
   if (p->eta_sched != RPCA_ETA_CONST && p->eta_sched != RPCA_ETA_SQRT) return "unknown eta_sched";
-  if (p->flags & ~(uint32_t)(RPCA_FLAG_STORE_S | RPCA_FLAG_GRAPH)) return "unknown flags";
+  if (p->flags & ~(uint32_t)(RPCA_FLAG_STORE_S | RPCA_FLAG_GRAPH | RPCA_FLAG_BF16))
+    return "unknown flags";
+  if ((p->flags & RPCA_FLAG_BF16) &&
+      (p->K != 1 || p->inner != 1 || (p->flags & RPCA_FLAG_STORE_S)))
+    return "RPCA_FLAG_BF16 needs K = 1, inner = 1 and no RPCA_FLAG_STORE_S";
   return nullptr;
 }
 
@@ -98,6 +103,8 @@ Layout make_layout(const rpca_params* p) {
   L.RP = (int32_t)round_up(p->r, 16);
   L.NS = (p->r + 3) / 4;
   L.lds = round_up(p->m, 4);
+  L.RK = (int32_t)round_up(p->r, 32);
+  L.bf16 = (p->flags & RPCA_FLAG_BF16) != 0;
   L.nrb = L.MP / kSRows;
   L.nub = L.MP / kURows;
   int64_t nvp = 0, ng = 0, ng64 = 0, n = 0;
@@ -118,7 +125,8 @@ Layout make_layout(const rpca_params* p) {
     const int64_t maxs = (p->m + 63) / 64;
     int64_t vs = want < maxs ? want : maxs;
     if (vs < 1) vs = 1;
-    const int64_t rows = round_up((p->m + vs - 1) / vs, 16);
+    // BF16 rounds walk 32-row chunks.
+    const int64_t rows = round_up((p->m + vs - 1) / vs, L.bf16 ? 32 : 16);
     L.vsplit_rows = (int32_t)rows;
     L.vsplit = (int32_t)((p->m + rows - 1) / rows);
     // rpca_autotune may try up to twice as many splits.
@@ -139,12 +147,18 @@ Layout make_layout(const rpca_params* p) {
   };
   L.S = take((size_t)L.Sfloats * f);
   const size_t ub = (size_t)fb_floats(L.MP, L.RP, L.NS);
-  L.U0 = take(ub * f);
-  L.U1 = take(ub * f);
+  // BF16 packings follow the FP32 layouts of each U block and V buffer.
+  const size_t uh = L.bf16 ? (size_t)hb_elems(L.MP, L.RK, L.RP) / 2 : 0;
+  const size_t vh = L.bf16 ? (size_t)hb_elems(L.NVP, L.RK, L.RP) / 2 : 0;
+  L.U0 = take((ub + uh) * f);
+  L.U1 = take((ub + uh) * f);
   L.Uc0 = take(multi ? (size_t)E * ub * f : 0);
   L.Uc1 = take(multi ? (size_t)E * ub * f : 0);
-  L.V0 = take((size_t)vbuf_floats(L.NVP, L.RP, L.NS) * f);
-  L.V1 = take((size_t)vbuf_floats(L.NVP, L.RP, L.NS) * f);
+  L.V0 = take(((size_t)vbuf_floats(L.NVP, L.RP, L.NS) + vh) * f);
+  L.V1 = take(((size_t)vbuf_floats(L.NVP, L.RP, L.NS) + vh) * f);
+  const size_t mh = L.bf16 ? (size_t)L.NVP * L.MP * sizeof(uint16_t) : 0;
+  L.Mbv = take(mh);
+  L.Mbs = take(mh);
   L.Wpart = take((size_t)(L.vsplit_max + 1) * L.NVP * L.RP * f);
   L.P = take((size_t)E * L.RP * L.MP * f);
   L.gv = take((size_t)L.ngroups * RR * d);
@@ -246,14 +260,18 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     const DevParams q = with_v(c, vn);
     double* fin = c->fin_pending ? c->Ginv : nullptr;
     c->fin_pending = false;
+    const bool h = c->prec == RPCA_PREC_BF16;
     RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
-                launch_vpass(q, mode, Ucons, 0, c->U[c->cur ^ 1], c->V[c->vcur], fin, st),
+                h ? launch_vpass_h(q, mode, Ucons, c->U[c->cur ^ 1], c->V[c->vcur], fin, st)
+                  : launch_vpass(q, mode, Ucons, 0, c->U[c->cur ^ 1], c->V[c->vcur], fin, st),
                 "V-pass launch");
     RPCA_LAUNCH(c, prof, RPCA_PHASE_VFINAL, launch_vfinal(q, c->Ginv, 0, fin ? 1 : 0, st),
                 "V finish launch");
     if (p.u_mode == RPCA_U_CLOSED)
       RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(q, st), "client factor launch");
-    RPCA_LAUNCH(c, prof, RPCA_PHASE_SPASS, launch_spass(q, Ucons, 0, nullptr, 0, 0, 0, p.E, st), "S-pass launch");
+    RPCA_LAUNCH(c, prof, RPCA_PHASE_SPASS,
+                h ? launch_spass_h(q, Ucons, st) : launch_spass(q, Ucons, 0, nullptr, 0, 0, 0, p.E, st),
+                "S-pass launch");
     RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE, launch_uupdate(q, c->U[c->cur ^ 1], 0, Ucons, 1, st),
                 "U update launch");
     c->fin_pending = true;
@@ -382,6 +400,12 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.lam = (float)prm->lambda;
   p.rho = prm->rho;
   p.eta0 = prm->eta0;
+  p.bf16 = L.bf16 ? 1 : 0;
+  p.RK = L.RK;
+  p.NK = L.RK / 32;
+  p.Mbv = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.Mbv) : nullptr;
+  p.Mbs = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.Mbs) : nullptr;
+  c->prec = L.bf16 ? RPCA_PREC_BF16 : RPCA_PREC_FP32;
   p.clients = reinterpret_cast<const ClientDev*>(ws + L.clients);
   p.clients_lpt = reinterpret_cast<const ClientDev*>(ws + L.clients_lpt);
   p.vgroups = reinterpret_cast<const VGroup*>(ws + L.vgroups);
@@ -467,6 +491,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
     e = hipMemcpyAsync(ws + L.vg64, c->vg64.data(), c->vg64.size() * sizeof(VTile),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = launch_copy_in_U(p, U0, ldu, c->U[0], st);
+  if (e == hipSuccess && L.bf16) e = launch_m_to_bf16(p, st);
   if (e == hipSuccess) e = launch_gram_init(p, c->U[0], st);
   if (e == hipSuccess) e = launch_finalize(p, c->Ginv, 0, 0, 0, st);
   // The host tables must outlive the asynchronous copies above.
@@ -532,10 +557,20 @@ rpca_status rpca_step(rpca_ctx* c, int32_t rounds) {
   return RPCA_OK;
 }
 
-// Row splits for a given count: rows per split a multiple of 16.
+// Graphs captured before bake the old launch shapes and kernels.
+static void drop_graphs(rpca_ctx* c) {
+  for (hipGraphExec_t& g : c->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Row splits for a given count: rows per split a multiple of 16 (32 when BF16
+// rounds, which walk 32-row chunks, may run).
 static void set_vsplit(rpca_ctx* c, int64_t vs) {
   const int64_t m = c->p.m;
-  const int64_t rows = round_up((m + vs - 1) / vs, 16);
+  const int64_t rows = round_up((m + vs - 1) / vs, c->p.bf16 ? 32 : 16);
   c->p.vsplit_rows = (int32_t)rows;
   c->p.vsplit = (int32_t)((m + rows - 1) / rows);
 }
@@ -584,14 +619,20 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out) {
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   set_vsplit(c, result == RPCA_OK ? best : v0);
-  // Graphs captured before bake the old launch shapes.
-  for (hipGraphExec_t& g : c->gexec)
-    if (g) {
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  drop_graphs(c);
   if (vsplit_out) *vsplit_out = c->p.vsplit;
   return result;
+}
+
+rpca_status rpca_set_precision(rpca_ctx* c, int32_t precision) {
+  if (rpca_status s = guard(c)) return s;
+  if (precision != RPCA_PREC_FP32 && precision != RPCA_PREC_BF16)
+    return fail(c, RPCA_EINVAL, "unknown precision");
+  if (precision == RPCA_PREC_BF16 && !c->p.bf16)
+    return fail(c, RPCA_EINVAL, "BF16 rounds need a context created with RPCA_FLAG_BF16");
+  if (precision != c->prec) drop_graphs(c);
+  c->prec = precision;
+  return RPCA_OK;
 }
 
 rpca_status rpca_set_target(rpca_ctx* c, const float* Ustar, int64_t ldus, const float* Vstar,

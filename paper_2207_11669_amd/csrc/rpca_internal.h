@@ -53,6 +53,42 @@ __host__ __device__ inline const float* v_fb(const float* V, int64_t NVP, int RP
   return V + NVP * RP;
 }
 
+// BF16 operand packings (mixed-precision rounds, v_mfma_f32_16x16x32_bf16,
+// whose lane l supplies A[l%16][8 (l/16) + e] and B[8 (l/16) + e][l%16],
+// e < 8, and receives D[4 (l/16) + v][l%16]). RK = 32 ceil(r/32) ranks on the
+// contraction side (NK = RK / 32 blocks), RP ranks on the output side; rows is
+// a multiple of 32 and every entry past the factor's rows or rank is 0.
+// Element (a, c) of a factor X lives in
+//   hA : 16-row chunk ch, block kb: X[16 ch + l%16][32 kb + 8 (l/16) + e]
+//   hP : 32-row chunk ch, half t, block kb:
+//        X[32 ch + 8 ((l%16)/4) + 4 t + l%4][32 kb + 8 (l/16) + e]
+//        (rows permuted so that a product with this operand on the A side
+//        leaves lane l the rows 8 (l/16) + 4 t + v, i.e. with both halves the
+//        eight consecutive rows 8 (l/16) + e)
+//   hB : 32-row chunk ch, rank tile ct: X[32 ch + 8 (l/16) + e][16 ct + l%16]
+// each as 64 lanes x 8 bf16 = 1 KiB per operand. Sizes in bf16 elements:
+// hA and hP rows * RK, hB rows * RP, in that order.
+__host__ __device__ inline int64_t hb_elems(int64_t rows, int RK, int RP) {
+  return rows * (2 * (int64_t)RK + RP);
+}
+__host__ __device__ inline int64_t hb_hA(int a, int c, int NK) {
+  return ((((int64_t)(a >> 4) * NK + (c >> 5)) * 64 + 16 * ((c & 31) >> 3) + (a & 15)) << 3) + (c & 7);
+}
+__host__ __device__ inline int64_t hb_hP(int a, int c, int NK) {
+  const int w = a & 31, t = (w >> 2) & 1, i = 4 * (w >> 3) + (w & 3);
+  return (((((int64_t)(a >> 5) * 2 + t) * NK + (c >> 5)) * 64 + 16 * ((c & 31) >> 3) + i) << 3) + (c & 7);
+}
+__host__ __device__ inline int64_t hb_hB(int a, int c, int RT) {
+  return ((((int64_t)(a >> 5) * RT + (c >> 4)) * 64 + 16 * ((a & 31) >> 3) + (c & 15)) << 3) + (a & 7);
+}
+// BF16 copies of M, two layouts (client i's block starts at vrow0_i * MP
+// elements and spans MP rows by NVc_i = n_i rounded up to 64 columns, zero
+// padded):
+//   V-pass layout, 16-column group cg, 32-row chunk ch:
+//        M[32 ch + 8 (l/16) + e][16 cg + l%16]   at ((cg (MP/32) + ch) 64 + l) 8 + e
+//   S-pass layout, 16-row tile rt, 32-column chunk cc:
+//        M[16 rt + l%16][32 cc + 8 (l/16) + e]   at ((rt (NVc/32) + cc) 64 + l) 8 + e
+
 // One client (Section 2.1): its borrowed block M_i and where its private
 // state lives in the workspace.
 struct ClientDev {
@@ -126,7 +162,28 @@ struct DevParams {
   DevState* dstate;
   StatsRec* hist;
   double* stat_part;     // six round statistics (finalize folded into the V-pass)
+  // Mixed precision (RPCA_FLAG_BF16): factor blocks carry the BF16 packings
+  // after their FP32 layouts (U: at ublock floats; V: at vbuf_floats), and M
+  // has two BF16 copies.
+  int32_t bf16;          // 1: keep the BF16 packings up to date
+  int32_t RK, NK;        // contraction-side ranks (32 NK) and blocks
+  uint16_t* Mbv;         // BF16 M, V-pass layout
+  uint16_t* Mbs;         // BF16 M, S-pass layout
 };
+
+// BF16 packings of a U factor block / a V buffer.
+__host__ __device__ inline uint16_t* u_hb(float* U, const DevParams& p) {
+  return reinterpret_cast<uint16_t*>(U + p.ublock);
+}
+__host__ __device__ inline const uint16_t* u_hb(const float* U, const DevParams& p) {
+  return reinterpret_cast<const uint16_t*>(U + p.ublock);
+}
+__host__ __device__ inline uint16_t* v_hb(float* V, const DevParams& p) {
+  return reinterpret_cast<uint16_t*>(V + vbuf_floats(p.NVP, p.RP, p.NS));
+}
+__host__ __device__ inline const uint16_t* v_hb(const float* V, const DevParams& p) {
+  return reinterpret_cast<const uint16_t*>(V + vbuf_floats(p.NVP, p.RP, p.NS));
+}
 
 // Launch helpers (kernels live in rpca_kernels.hip).
 constexpr int kDistBlocks = 64;  // work-groups per side of the factor-distance kernel
@@ -175,6 +232,16 @@ hipError_t launch_pack_target(const DevParams& p, const ClientDev* host_clients,
 // Gram matrices (FP64). X*: column-major, MP rows (ld MP); Y*: column-major,
 // NVP rows (ld NVP); widths rp1, rp2 <= 64. part: 2*kDistBlocks*3*64*64
 // doubles; part2: 48 doubles.
+// Mixed precision (rpca_bf16.hip). The BF16 copies of M from the borrowed
+// FP32 blocks (zero padded).
+hipError_t launch_m_to_bf16(const DevParams& p, hipStream_t st);
+// BF16 V-pass (streaming part) and S-pass; same outputs and work-group roles
+// as launch_vpass (mode kSZero or kSRecompute) and launch_spass (all clients,
+// no S output).
+hipError_t launch_vpass_h(const DevParams& p, int mode, const float* U, const float* Uold,
+                          const float* Vold, double* fin_Ginv, hipStream_t st);
+hipError_t launch_spass_h(const DevParams& p, const float* U, hipStream_t st);
+
 hipError_t launch_factor_distance(const DevParams& p, const float* X1, const float* Y1, int rp1,
                                   const float* X2, const float* Y2, int rp2, double* part,
                                   double* part2, double* out2, hipStream_t st);

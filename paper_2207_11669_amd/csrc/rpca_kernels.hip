@@ -213,6 +213,17 @@ __device__ __forceinline__ void fb_store(float* fb, int64_t rows, int RP, int NS
        ((((int64_t)ch * NQ + (cq >> 2)) * 4 + (li >> 2)) * 4 + (cq & 3)) * 4 + (li & 3)] = v;
 }
 
+// Store element (a, c), c < RP, of a factor with `rows` rows into its BF16
+// packings (hA, hP, hB; see rpca_internal.h), rounded to nearest even once.
+__device__ __forceinline__ void hb_store(uint16_t* hb, int64_t rows, const DevParams& p, int a,
+                                         int c, float v) {
+  __bf16* h = reinterpret_cast<__bf16*>(hb);
+  const __bf16 b = (__bf16)v;
+  h[hb_hA(a, c, p.NK)] = b;
+  h[rows * p.RK + hb_hP(a, c, p.NK)] = b;
+  h[2 * rows * p.RK + hb_hB(a, c, p.RP >> 4)] = b;
+}
+
 // v_mfma_f32_4x4x1f32: 16 independent 4x4x1 products; block b = l/4 takes
 // A_b[i] from lane 4b + i and B_b[j] from lane 4b + j, and D_b[i][j] lands in
 // lane 4b + j, element i.
@@ -492,6 +503,7 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
       wd[j][c] = (double)vres[q];
       p.V[(int64_t)(vrow + j) * RP + c] = vres[q];
       fb_store(v_fb(p.V, p.NVP, RP), p.NVP, RP, p.NS, vrow + j, c, vres[q]);
+      if (p.bf16) hb_store(v_hb(p.V, p), p.NVP, p, vrow + j, c, vres[q]);
     }
   }
   __syncthreads();
@@ -538,6 +550,75 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
     }
     Af[e] = av;
     Bf[e] = bv;
+  }
+}
+
+// S-pass epilogue, shared by the FP32 and BF16 forms (512 threads): the
+// client's U-step term for the work-group's 128 rows from P = Lambda V_i and
+// U_i staged in LDS (Lemma 2 proof for the gradient, argmin_U L_i for the
+// closed form):
+//   GRAD   T = U_i - eta (c_i U_i - P)
+//   CLOSED T = P A_i + U_i B_i,  A_i = (V_i^T V_i + c_i I)^{-1}, B_i = V_i^T V_i A_i
+// in FP64, stored FP32 into the client's slot of p.P; then the work-group's
+// sums of Lambda^2, |S| and nnz(S) into p.spart.
+template <int RP>
+__device__ __forceinline__ void spass_terms_and_stats(const DevParams& p, const ClientDev& cl, int b,
+                                                      const float (*ptile)[RP + 1],
+                                                      const float (*utile)[RP + 1],
+                                                      const double (*fab)[RP * RP], bool closed,
+                                                      double sl2, double sl1, uint32_t nnz) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int ci = cl.idx;
+  const int row0 = b * kSRows;
+  float* Ti = p.P + (int64_t)ci * RP * p.MP;
+  const double eta = eta_of_round(p, p.dstate->t);
+  const double cc = cl.c;
+  // Thread: one row, eight rank columns (register blocking: each LDS read of
+  // P or U feeds eight FMAs).
+  for (int e = tid; e < kSRows * (RP / 8); e += blockDim.x) {
+    const int rl = e % kSRows, c0 = (e / kSRows) * 8;
+    double t[8];
+    if (closed) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) t[j] = 0.0;
+      for (int k = 0; k < p.r; ++k) {
+        const double pk = (double)ptile[rl][k], uk = (double)utile[rl][k];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          t[j] = fma(pk, fab[0][k * RP + c0 + j], fma(uk, fab[1][k * RP + c0 + j], t[j]));
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double u = utile[rl][c0 + j];
+        t[j] = u - eta * (cc * u - (double)ptile[rl][c0 + j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      Ti[(int64_t)(c0 + j) * p.MP + row0 + rl] = c0 + j < p.r ? (float)t[j] : 0.f;
+  }
+
+  __shared__ double sred[8][3];
+  sl2 = wave_sum(sl2);
+  sl1 = wave_sum(sl1);
+  const int wv = tid >> 6;
+  if (lane == 0) {
+    sred[wv][0] = sl2;
+    sred[wv][1] = sl1;
+    sred[wv][2] = (double)nnz;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double* o = p.spart + ((int64_t)ci * p.nrb + b) * 4;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t += sred[k][q];
+      o[q] = t;
+    }
+    o[3] = 0.0;
   }
 }
 
@@ -738,16 +819,23 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
         __builtin_amdgcn_sched_barrier(0);
       }
     }
+  } else if (!emit_only && closed) {
+    // A phase with no chunk (a client of at most 16 columns) still stages its
+    // share of A_i and B_i.
+#pragma unroll
+    for (int q = 0; q < kFabPer; ++q) {
+      const int e = tid + q * 512;
+      if (e < RP * RP) {
+        fab[0][e] = fa[q];
+        fab[1][e] = fbv[q];
+      }
+    }
   }
 
   if (emit_only) return;
-  // Epilogue: the client's U-step term for these 128 rows (Lemma 2 proof for
-  // the gradient, argmin_U L_i for the closed form), from P = Lambda V_i:
-  //   GRAD   T = U_i - eta (c_i U_i - P)
-  //   CLOSED T = P A_i + U_i B_i,  A_i = (V_i^T V_i + c_i I)^{-1}, B_i = V_i^T V_i A_i
-  // in FP64, stored FP32 into the client's slot of p.P. U_i comes from the
-  // MFMA operand registers (rank (l/16) NS + s of row l%16; ranks from 4 NS
-  // on are zero), P from the two phases' accumulators summed in LDS.
+  // Epilogue: the client's U-step term for these 128 rows. U_i comes from
+  // the MFMA operand registers (rank (l/16) NS + s of row l%16; ranks from
+  // 4 NS on are zero), P from the two phases' accumulators summed in LDS.
   // Quads: block b = l/4 summed columns 4 (b/4) + s for rows 4 (b%4) + i; the
   // four column groups (lanes l, l ^ 16, l ^ 32, l ^ 48) are added first.
 #pragma unroll
@@ -798,57 +886,7 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
     }
   }
   __syncthreads();
-  const int row0 = b * kSRows;
-  float* Ti = p.P + (int64_t)ci * RP * p.MP;
-  const double eta = eta_of_round(p, p.dstate->t);
-  const double cc = cl.c;
-  // Thread: one row, eight rank columns (register blocking: each LDS read of
-  // P or U feeds eight FMAs).
-  for (int e = tid; e < kSRows * (RP / 8); e += blockDim.x) {
-    const int rl = e % kSRows, c0 = (e / kSRows) * 8;
-    double t[8];
-    if (closed) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) t[j] = 0.0;
-      for (int k = 0; k < p.r; ++k) {
-        const double pk = (double)ptile[rl][k], uk = (double)utile[rl][k];
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          t[j] = fma(pk, fab[0][k * RP + c0 + j], fma(uk, fab[1][k * RP + c0 + j], t[j]));
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const double u = utile[rl][c0 + j];
-        t[j] = u - eta * (cc * u - (double)ptile[rl][c0 + j]);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      Ti[(int64_t)(c0 + j) * p.MP + row0 + rl] = c0 + j < p.r ? (float)t[j] : 0.f;
-  }
-
-  __shared__ double sred[8][3];
-  sl2 = wave_sum(sl2);
-  sl1 = wave_sum(sl1);
-  const int wv = tid >> 6;
-  if (lane == 0) {
-    sred[wv][0] = sl2;
-    sred[wv][1] = sl1;
-    sred[wv][2] = (double)nnz;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double* o = p.spart + ((int64_t)ci * p.nrb + b) * 4;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      double t = 0.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) t += sred[k][q];
-      o[q] = t;
-    }
-    o[3] = 0.0;
-  }
+  spass_terms_and_stats<RP>(p, cl, b, ptile, utile, fab, closed, sl2, sl1, nnz);
 }
 
 // Partial Gram of kURows rows held in LDS (FP64, row stride kMaxRank).
@@ -921,6 +959,7 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
     const int c = cq + 4 * q;
     const float v = (a < p.m && c < r) ? (float)(acc[q] * scale) : 0.f;
     fb_store(Uo, MP, RP, p.NS, a, c, v);
+    if (p.bf16) hb_store(u_hb(Uo, p), MP, p, a, c, v);
     ul[al * kMaxRank + c] = (double)v;
     if (final_step) {
       const double d = (double)v - (double)Uprev[(int64_t)c * MP + a];
@@ -1100,7 +1139,9 @@ __global__ void k_copy_in_U(DevParams p, const float* __restrict__ U0, int64_t l
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)p.RP * p.MP) return;
   const int a = (int)(e % p.MP), c = (int)(e / p.MP);
-  fb_store(Ufb, p.MP, p.RP, p.NS, a, c, (a < p.m && c < p.r) ? U0[(int64_t)c * ldu + a] : 0.f);
+  const float v = (a < p.m && c < p.r) ? U0[(int64_t)c * ldu + a] : 0.f;
+  fb_store(Ufb, p.MP, p.RP, p.NS, a, c, v);
+  if (p.bf16) hb_store(u_hb(Ufb, p), p.MP, p, a, c, v);
 }
 
 // L_i = U V_i^T (FP64 accumulation) and S_i, for one client, column-major out.
@@ -1411,6 +1452,460 @@ hipError_t launch_factor_distance(const DevParams& p, const float* X1, const flo
                      Y2, rp2, part);
   hipLaunchKernelGGL(k_dist_reduce, dim3(kDistEntries / 256), dim3(256), 0, st, part, part2);
   hipLaunchKernelGGL(k_dist_final, dim3(1), dim3(64), 0, st, part2, out2);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Mixed precision (RPCA_FLAG_BF16). M, U and V enter the rank-r contractions
+// as BF16 on v_mfma_f32_16x16x32_bf16 with FP32 accumulation; the residual,
+// the soft-threshold, Lambda, the U-step terms and every statistic stay
+// FP32/FP64 as in the FP32 passes, and the factors themselves stay FP32 (the
+// BF16 operands are rounded copies written by the kernels that produce the
+// factors). Each pass streams its own BF16 copy of M, laid out so that one
+// 16-byte load per lane is exactly its MFMA operand: 2 B per entry and pass.
+// ===========================================================================
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// Eight BF16 values of one 16-byte load as FP32 (a BF16 is the upper half of
+// the FP32 of the same value; element 2k is the low half of word k).
+__device__ __forceinline__ void unpack8(u4 u, float* x) {
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    x[2 * k] = __uint_as_float(w[k] << 16);
+    x[2 * k + 1] = __uint_as_float(w[k] & 0xFFFF0000u);
+  }
+}
+// Eight FP32 values rounded to nearest even into one BF16 operand.
+__device__ __forceinline__ bf8 pack8(const float* x) {
+  const f8 v = {x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7]};
+  return __builtin_convertvector(v, bf8);
+}
+
+// The two BF16 copies of M (layouts in rpca_internal.h); grid = (blocks,
+// clients), each thread forms 16-byte units of both layouts, zero outside
+// the client's m x n_i block.
+__global__ __launch_bounds__(256) void k_m_to_bf16(DevParams p) {
+  const ClientDev cl = p.clients[blockIdx.y];
+  const int MP = p.MP, m = p.m;
+  const int nvc = (cl.n + kVPad - 1) / kVPad * kVPad;
+  const int64_t units = (int64_t)nvc * MP / 8;
+  const int64_t base = (int64_t)cl.vrow0 * MP;
+  const GLOBAL float* M = gptr(cl.M);
+  bf8* Mv = reinterpret_cast<bf8*>(p.Mbv + base);
+  bf8* Ms = reinterpret_cast<bf8*>(p.Mbs + base);
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(u & 63), g = l >> 4, li = l & 15;
+    const int64_t tile = u >> 6;
+    float x[8];
+    {
+      const int ch = (int)(tile % (MP >> 5)), cg = (int)(tile / (MP >> 5));
+      const int j = 16 * cg + li, a0 = 32 * ch + 8 * g;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        x[e] = (a0 + e < m && j < cl.n) ? M[(int64_t)j * cl.ldm + a0 + e] : 0.f;
+      Mv[u] = pack8(x);
+    }
+    {
+      const int cc = (int)(tile % (nvc >> 5)), rt = (int)(tile / (nvc >> 5));
+      const int a = 16 * rt + li, j0 = 32 * cc + 8 * g;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        x[e] = (a < m && j0 + e < cl.n) ? M[(int64_t)(j0 + e) * cl.ldm + a] : 0.f;
+      Ms[u] = pack8(x);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 V-pass, streaming part: same grid, work-group roles and output
+// (W = (M_i - S_i)^T U partials per row split) as k_vpass. Every BF16
+// operand of a 32-row chunk is a 1 KiB wave load, and the U operands of a
+// chunk (hP halves for the S rebuild, hB for W) cost as many loads as M
+// itself, so each wave takes all 64 columns of the tile (four 16-column
+// groups sharing the chunk's U operands in registers) and the four waves
+// split the rows: wave w takes chunks w, w + 4, ... of the row split; their
+// partial W are added in LDS in wave order at the end.
+// Lane l holds rows 8 (l/16) + e of column 16 cg + l%16 (one 16-byte load
+// of the V-pass copy of M): the A operand of W's MFMA, with U's hB packing
+// as B; accumulator W[col 16 cg + 4 (l/16) + v][rank 16 ct + l%16].
+// kSRecompute rebuilds S = soft(M - Uo Vo^T): two 16x16 products per chunk
+// and column group with the previous U's hP packing on the A side and the
+// previous V's hA packing on the B side leave lane l the same eight rows of
+// its column.
+// ---------------------------------------------------------------------------
+template <int RT, int NK, int MODE>
+__global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __restrict__ Ubase,
+                                                 const float* __restrict__ Uold,
+                                                 const float* __restrict__ Vold,
+                                                 double* __restrict__ fin_Ginv, int fin) {
+  constexpr int RP = 16 * RT;
+  constexpr int kG = kVStreamCols / 16;  // column groups per wave
+  int bid = (int)blockIdx.x;
+  if (fin) {
+    if (bid < 2) {
+      finalize_role(p, fin_Ginv, bid);
+      return;
+    }
+    bid -= 2;
+  }
+  const int gx = bid % p.ng64, gy = bid / p.ng64;
+  const VTile vt = p.vg64[gx];
+  const ClientDev& cl = vt.cl;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const float lam = p.lam;
+  const int MP = p.MP;
+
+  const GLOBAL bf8* UhB = reinterpret_cast<const GLOBAL bf8*>(gptr(u_hb(Ubase, p))) +
+                          2 * (int64_t)MP * p.RK / 8;
+  const GLOBAL bf8* UohP = reinterpret_cast<const GLOBAL bf8*>(gptr(u_hb(Uold, p))) +
+                           (int64_t)MP * p.RK / 8;
+  bf8 vb[kG][NK];  // S rebuild B operand: Vo[col j0 + 16 g + l%16][rank 32 kb + 8 (l/16) + e]
+  if (MODE == kSRecompute) {
+    const GLOBAL bf8* VohA = reinterpret_cast<const GLOBAL bf8*>(gptr(v_hb(Vold, p)));
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int vch = (cl.vrow0 + vt.j0 + 16 * g) >> 4;
+#pragma unroll
+      for (int kb = 0; kb < NK; ++kb) vb[g][kb] = VohA[((int64_t)vch * NK + kb) * 64 + lane];
+    }
+  }
+  const int rbeg = gy * p.vsplit_rows;
+  const int rend = min(p.m, rbeg + p.vsplit_rows);
+  const int ch0 = rbeg >> 5;
+  const int nch = (rend - rbeg + 31) >> 5;
+  const int nk = (nch - w + 3) >> 2;  // this wave's chunks w, w + 4, ... below nch
+  // Column group g of the tile: cg = (j0 + 16 g) / 16 in the client's copy.
+  const GLOBAL u4* Mv = reinterpret_cast<const GLOBAL u4*>(gptr(p.Mbv)) +
+                        (int64_t)cl.vrow0 * MP / 8 + (int64_t)(vt.j0 >> 4) * (MP >> 5) * 64 + lane;
+  const int64_t gstride = (int64_t)(MP >> 5) * 64;  // u4 units between column groups
+  f4 acc[kG][RT];
+#pragma unroll
+  for (int g = 0; g < kG; ++g)
+#pragma unroll
+    for (int ct = 0; ct < RT; ++ct) acc[g][ct] = f4{0.f, 0.f, 0.f, 0.f};
+
+  struct Chunk {
+    u4 m[kG];         // M rows 32 ch + 8 (l/16) + e of column 16 g + l%16
+    bf8 uo[2][NK];    // previous U, hP halves (S rebuild, A operand)
+    bf8 u[RT];        // U, hB (W, B operand)
+  };
+  constexpr int kDepth = 2;
+  Chunk ring[kDepth];
+  auto load_chunk = [&](Chunk& c, int k) {
+    const int ch = ch0 + w + 4 * k;
+#pragma unroll
+    for (int g = 0; g < kG; ++g) c.m[g] = Mv[g * gstride + (int64_t)ch * 64];
+    if (MODE == kSRecompute) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int kb = 0; kb < NK; ++kb) c.uo[t][kb] = UohP[(((int64_t)ch * 2 + t) * NK + kb) * 64 + lane];
+    }
+#pragma unroll
+    for (int ct = 0; ct < RT; ++ct) c.u[ct] = UhB[((int64_t)ch * RT + ct) * 64 + lane];
+  };
+  auto compute_chunk = [&](const Chunk& c) {
+    // Rows past m and columns past n_i are zero in the copy of M and in the
+    // factors' packings, so they give d = 0 without a mask.
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      float x[8], d[8];
+      unpack8(c.m[g], x);
+      if (MODE == kSRecompute) {
+        f4 o[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int kb = 0; kb < NK; ++kb) {
+          o[0] = mfma_bf16(c.uo[0][kb], vb[g][kb], o[0]);
+          o[1] = mfma_bf16(c.uo[1][kb], vb[g][kb], o[1]);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float a1 = o[e >> 2][e & 3];
+          // M - S = Uo Vo^T + clip(M - Uo Vo^T, -lambda, lambda)
+          d[e] = a1 + __builtin_amdgcn_fmed3f(x[e] - a1, -lam, lam);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) d[e] = x[e];
+      }
+      const bf8 dh = pack8(d);
+#pragma unroll
+      for (int ct = 0; ct < RT; ++ct) acc[g][ct] = mfma_bf16(dh, c.u[ct], acc[g][ct]);
+    }
+  };
+  if (nk > 0) {
+    // Uniform ring as in k_vpass: every iteration loads (index clamped to the
+    // wave's last chunk), so the wait counts stay exact.
+    const int nkp = (nk + kDepth - 1) / kDepth * kDepth;
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      load_chunk(ring[d], min(d, nk - 1));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int k0 = 0; k0 < nkp; k0 += kDepth) {
+#pragma unroll
+      for (int d = 0; d < kDepth; ++d) {
+        const int k = k0 + d;
+        if (k < nk) compute_chunk(ring[d]);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk(ring[d], min(k + kDepth, nk - 1));
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  // Partial W of the four waves, added in wave order in LDS; the last wave
+  // writes the work-group's partial.
+  __shared__ float red[kVStreamCols][RP];
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+#pragma unroll
+        for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            float& x = red[16 * g + 4 * lg + v][16 * ct + li];
+            x = ww == 0 ? acc[g][ct][v] : x + acc[g][ct][v];
+          }
+    }
+    __syncthreads();
+  }
+  GLOBAL float* wp = gptr_w(p.Wpart) + ((int64_t)gy * p.NVP + cl.vrow0 + vt.j0) * RP;
+  for (int e = tid; e < kVStreamCols * RP; e += blockDim.x) wp[e] = red[e / RP][e % RP];
+}
+
+// ---------------------------------------------------------------------------
+// BF16 S-pass: same grid (128-row blocks x clients, widest client first),
+// outputs and epilogue as k_spass, over 32-column chunks. The eight waves are
+// two 64-row groups by four column phases (wave (g, q) takes rows 64 g ..
+// 64 g + 63 and chunks q, q + 4, ...): four 16-row tiles per wave share each
+// chunk's V operands in registers. MFMA 1 forms (U V^T)^T for two 16x16
+// tiles per row tile with V's hP halves as A and U's hA as B, leaving lane l
+// row l%16 and the eight columns 8 (l/16) + e of the chunk -- the lane's
+// 16-byte load of the S-pass copy of M, and the A operand of MFMA 2
+// (P += Lambda V with V's hB packing as B). The phases' partial P are added
+// in LDS in phase order.
+// ---------------------------------------------------------------------------
+template <int RT, int NK>
+__global__ __launch_bounds__(512) void k_spass_h(DevParams p, const float* __restrict__ U) {
+  constexpr int RP = 16 * RT;
+  constexpr int kRT = 4;  // 16-row tiles per wave
+  const int b = blockIdx.x;
+  const ClientDev cl = p.clients_lpt[blockIdx.y];
+  const int ci = cl.idx;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rg = wv & 1, phase = wv >> 1;
+  const int li = lane & 15, lg = lane >> 4;
+  const int arow0 = b * kSRows + rg * 64;
+  const int MP = p.MP;
+
+  bf8 ub[kRT][NK];  // MFMA 1 B operand: U[row arow0 + 16 rt + l%16][rank 32 kb + 8 (l/16) + e]
+  {
+    const GLOBAL bf8* UhA = reinterpret_cast<const GLOBAL bf8*>(gptr(u_hb(U, p)));
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt)
+#pragma unroll
+      for (int kb = 0; kb < NK; ++kb)
+        ub[rt][kb] = UhA[((int64_t)((arow0 >> 4) + rt) * NK + kb) * 64 + lane];
+  }
+  f4 accp[kRT][RT];
+#pragma unroll
+  for (int rt = 0; rt < kRT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+
+  __shared__ float ptile[kSRows][RP + 1];
+  __shared__ float utile[kSRows][RP + 1];
+  __shared__ double fab[2][RP * RP];
+  const bool closed = p.u_mode != 0;
+  constexpr int kFabPer = (RP * RP + 511) / 512;
+  double fa[kFabPer], fbv[kFabPer];
+  if (closed) {
+    const double* __restrict__ Af = p.Afac + (int64_t)ci * RP * RP;
+    const double* __restrict__ Bf = p.Bfac + (int64_t)ci * RP * RP;
+#pragma unroll
+    for (int q = 0; q < kFabPer; ++q) {
+      const int e = tid + q * 512;
+      fa[q] = e < RP * RP ? Af[e] : 0.0;
+      fbv[q] = e < RP * RP ? Bf[e] : 0.0;
+    }
+  }
+  auto stage_fab = [&]() {
+    if (closed) {
+#pragma unroll
+      for (int q = 0; q < kFabPer; ++q) {
+        const int e = tid + q * 512;
+        if (e < RP * RP) {
+          fab[0][e] = fa[q];
+          fab[1][e] = fbv[q];
+        }
+      }
+    }
+  };
+
+  double sl2 = 0.0, sl1 = 0.0;
+  uint32_t nnz = 0;
+  const float lam = p.lam;
+  const GLOBAL bf8* Vh = reinterpret_cast<const GLOBAL bf8*>(gptr(v_hb(p.V, p)));
+  const GLOBAL bf8* VhP = Vh + (int64_t)p.NVP * p.RK / 8;
+  const GLOBAL bf8* VhB = Vh + 2 * (int64_t)p.NVP * p.RK / 8;
+  const int nvc32 = (cl.n + kVPad - 1) / kVPad * (kVPad / 32);
+  const GLOBAL u4* Ms = reinterpret_cast<const GLOBAL u4*>(gptr(p.Mbs)) +
+                        (int64_t)cl.vrow0 * MP / 8 + (int64_t)(arow0 >> 4) * nvc32 * 64 + lane;
+  struct Chunk {
+    u4 m[kRT];        // M[row arow0 + 16 rt + l%16][col 32 cc + 8 (l/16) + e]
+    bf8 va[2][NK];    // V hP halves (MFMA 1, A operand)
+    bf8 vb[RT];       // V hB (MFMA 2, B operand)
+  };
+  constexpr int kDepth = 2;
+  Chunk ring[kDepth];
+  const int nch = (cl.n + 31) >> 5;
+  const int nk = (nch - phase + 3) >> 2;  // chunks phase, phase + 4, ... below nch
+  auto load_chunk = [&](Chunk& c, int k) {
+    const int cc = phase + 4 * k;
+    const int64_t vch = (cl.vrow0 >> 5) + cc;
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt) c.m[rt] = Ms[((int64_t)rt * nvc32 + cc) * 64];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int kb = 0; kb < NK; ++kb) c.va[t][kb] = VhP[((vch * 2 + t) * NK + kb) * 64 + lane];
+#pragma unroll
+    for (int ct = 0; ct < RT; ++ct) c.vb[ct] = VhB[(vch * RT + ct) * 64 + lane];
+  };
+  auto compute_chunk = [&](const Chunk& c) {
+    float l2 = 0.f, l1 = 0.f;
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt) {
+      f4 o[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+      for (int kb = 0; kb < NK; ++kb) {
+        o[0] = mfma_bf16(c.va[0][kb], ub[rt][kb], o[0]);
+        o[1] = mfma_bf16(c.va[1][kb], ub[rt][kb], o[1]);
+      }
+      float x[8], lamv[8];
+      unpack8(c.m[rt], x);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float R = x[e] - o[e >> 2][e & 3];
+        const float L = __builtin_amdgcn_fmed3f(R, -lam, lam);  // clip(R, -lam, lam)
+        const float Sv = R - L;
+        lamv[e] = L;
+        l2 = fmaf(L, L, l2);
+        l1 += fabsf(Sv);
+        nnz += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(Sv != 0.f));
+      }
+      const bf8 lh = pack8(lamv);
+#pragma unroll
+      for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = mfma_bf16(lh, c.vb[ct], accp[rt][ct]);
+    }
+    sl2 += (double)l2;
+    sl1 += (double)l1;
+  };
+  if (nk > 0) {
+    const int nkp = (nk + kDepth - 1) / kDepth * kDepth;
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      load_chunk(ring[d], min(d, nk - 1));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    stage_fab();
+    __builtin_amdgcn_sched_barrier(0);
+    for (int k0 = 0; k0 < nkp; k0 += kDepth) {
+#pragma unroll
+      for (int d = 0; d < kDepth; ++d) {
+        const int k = k0 + d;
+        if (k < nk) compute_chunk(ring[d]);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk(ring[d], min(k + kDepth, nk - 1));
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  } else {
+    // A phase with no chunk (a client of at most 96 columns) still stages
+    // its share of A_i and B_i.
+    stage_fab();
+  }
+
+  // Epilogue: P from the four phases' accumulators added in LDS in phase
+  // order; U_i in FP32 from the factor's column-major layout (not its BF16
+  // operand copy).
+  {
+    const GLOBAL float* Uc = gptr(U) + (int64_t)b * kSRows;
+    for (int e = tid; e < kSRows * RP; e += blockDim.x) {
+      const int rl = e % kSRows, c = e / kSRows;
+      utile[rl][c] = c < p.r ? Uc[(int64_t)c * MP + rl] : 0.f;
+    }
+  }
+  for (int q = 0; q < 4; ++q) {
+    if (phase == q) {
+#pragma unroll
+      for (int rt = 0; rt < kRT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            float& x = ptile[rg * 64 + 16 * rt + 4 * lg + v][16 * ct + li];
+            x = q == 0 ? accp[rt][ct][v] : x + accp[rt][ct][v];
+          }
+    }
+    __syncthreads();
+  }
+  spass_terms_and_stats<RP>(p, cl, b, ptile, utile, fab, closed, sl2, sl1, nnz);
+}
+
+hipError_t launch_m_to_bf16(const DevParams& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_m_to_bf16, dim3(1024, p.E), dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+// The contraction-side block count follows from the rank tiles:
+// NK = ceil(r/32) = ceil(RT/2).
+template <int RT>
+static hipError_t launch_vpass_h_t(const DevParams& p, int mode, const float* U, const float* Uold,
+                                   const float* Vold, double* fin_Ginv, hipStream_t st) {
+  constexpr int NK = (RT + 1) / 2;
+  const int fin = fin_Ginv ? 1 : 0;
+  const dim3 grid((unsigned)(p.ng64 * p.vsplit + 2 * fin));
+  if (mode == kSRecompute)
+    hipLaunchKernelGGL((k_vpass_h<RT, NK, kSRecompute>), grid, dim3(256), 0, st, p, U, Uold, Vold,
+                       fin_Ginv, fin);
+  else
+    hipLaunchKernelGGL((k_vpass_h<RT, NK, kSZero>), grid, dim3(256), 0, st, p, U, Uold, Vold,
+                       fin_Ginv, fin);
+  return hipGetLastError();
+}
+
+hipError_t launch_vpass_h(const DevParams& p, int mode, const float* U, const float* Uold,
+                          const float* Vold, double* fin_Ginv, hipStream_t st) {
+  if (mode != kSZero && mode != kSRecompute) return hipErrorInvalidValue;
+  switch (p.RP / 16) {
+    case 1: return launch_vpass_h_t<1>(p, mode, U, Uold, Vold, fin_Ginv, st);
+    case 2: return launch_vpass_h_t<2>(p, mode, U, Uold, Vold, fin_Ginv, st);
+    case 3: return launch_vpass_h_t<3>(p, mode, U, Uold, Vold, fin_Ginv, st);
+    case 4: return launch_vpass_h_t<4>(p, mode, U, Uold, Vold, fin_Ginv, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_spass_h(const DevParams& p, const float* U, hipStream_t st) {
+  const dim3 grid(p.nrb, p.E);
+  switch (p.RP / 16) {
+    case 1: hipLaunchKernelGGL((k_spass_h<1, 1>), grid, dim3(512), 0, st, p, U); break;
+    case 2: hipLaunchKernelGGL((k_spass_h<2, 1>), grid, dim3(512), 0, st, p, U); break;
+    case 3: hipLaunchKernelGGL((k_spass_h<3, 2>), grid, dim3(512), 0, st, p, U); break;
+    case 4: hipLaunchKernelGGL((k_spass_h<4, 2>), grid, dim3(512), 0, st, p, U); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

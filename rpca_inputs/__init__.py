@@ -127,6 +127,27 @@ def gaussian_init(m: int, r: int, seed: int) -> np.ndarray:
     return _f32(_rng(seed, _STREAM_INIT).standard_normal((m, r)))
 
 
+def _planted_factors(m: int, n: int, rstar: int, seed: int, spectrum: str, sigma_hi: float,
+                     sigma_lo: float):
+    """Planted factors with L* = U* V*^T: i.i.d. N(0,1) ("gaussian"), or
+    Q_U diag(sigma) Q_V^T split as (Q_U sqrt(sigma), Q_V sqrt(sigma)) with Q from
+    the QR factorisation of Gaussian matrices and sigma geometric from
+    sigma_hi down to sigma_lo ("geometric")."""
+    frng = _rng(seed, _STREAM_FACTORS)
+    if spectrum == "gaussian":
+        return frng.standard_normal((m, rstar)), frng.standard_normal((n, rstar))
+    if spectrum == "geometric":
+        qu, _ = np.linalg.qr(frng.standard_normal((m, rstar)))
+        qv, _ = np.linalg.qr(frng.standard_normal((n, rstar)))
+        if rstar > 1:
+            k = np.arange(rstar, dtype=np.float64)
+            sig = sigma_hi * (sigma_lo / sigma_hi) ** (k / (rstar - 1))
+        else:
+            sig = np.array([sigma_hi])
+        return qu * np.sqrt(sig)[None, :], qv * np.sqrt(sig)[None, :]
+    raise ValueError(f"unknown spectrum {spectrum!r}")
+
+
 def planted_instance(
     m: int,
     widths: Sequence[int],
@@ -152,22 +173,7 @@ def planted_instance(
     """
     widths = [int(w) for w in widths]
     n = int(sum(widths))
-    frng = _rng(seed, _STREAM_FACTORS)
-    if spectrum == "gaussian":
-        Ustar = frng.standard_normal((m, rstar))
-        Vstar = frng.standard_normal((n, rstar))
-    elif spectrum == "geometric":
-        qu, _ = np.linalg.qr(frng.standard_normal((m, rstar)))
-        qv, _ = np.linalg.qr(frng.standard_normal((n, rstar)))
-        if rstar > 1:
-            k = np.arange(rstar, dtype=np.float64)
-            sig = sigma_hi * (sigma_lo / sigma_hi) ** (k / (rstar - 1))
-        else:
-            sig = np.array([sigma_hi])
-        Ustar = qu * np.sqrt(sig)[None, :]
-        Vstar = qv * np.sqrt(sig)[None, :]
-    else:
-        raise ValueError(f"unknown spectrum {spectrum!r}")
+    Ustar, Vstar = _planted_factors(m, n, rstar, seed, spectrum, sigma_hi, sigma_lo)
 
     total = m * n
     srng = _rng(seed, _STREAM_SUPPORT)
@@ -208,17 +214,18 @@ def planted_instance_large(
     hi: float = 50.0,
     seed: int = 0,
     name: str = "",
+    spectrum: str = "gaussian",
+    sigma_hi: float = 100.0,
+    sigma_lo: float = 1.0,
 ) -> Instance:
-    """The laws of planted_instance (Gaussian factors, Bernoulli(s) support)
-    for instances too large for dense FP64 work arrays: M is built one client
-    block at a time, each block drawing its support and values from streams of
-    its own, and is kept as FP32, column-major (M.T is C-contiguous). S* is
-    not kept (Sstar is None)."""
+    """The laws of planted_instance (Gaussian or geometric-spectrum factors,
+    Bernoulli(s) support) for instances too large for dense FP64 work arrays:
+    M is built one client block at a time, each block drawing its support and
+    values from streams of its own, and is kept as FP32, column-major (M.T is
+    C-contiguous). S* is not kept (Sstar is None)."""
     widths = [int(w) for w in widths]
     n = int(sum(widths))
-    frng = _rng(seed, _STREAM_FACTORS)
-    Ustar = frng.standard_normal((m, rstar))
-    Vstar = frng.standard_normal((n, rstar))
+    Ustar, Vstar = _planted_factors(m, n, rstar, seed, spectrum, sigma_hi, sigma_lo)
     Mt = np.empty((n, m), dtype=np.float32)
     off = 0
     for i, w in enumerate(widths):
@@ -264,6 +271,12 @@ RECIPES = {
     "uneven_10000_r32": dict(m=10000, E=64, widths=("loguniform", 64, 4096), rstar=32,
                              s=0.05, values="signed", lo=1.0, hi=50.0, r=32, rho=0.1,
                              T=200, large=True),
+    # m = 20000, n = 100000, fifty clients of 2000 columns, rank 64 with a
+    # geometric spectrum 100 -> 1, 5% of entries corrupted (Bernoulli) with
+    # magnitude U[1, 100], r = 64. M is 8 GB in FP32, built blockwise.
+    "geom_20000x100000_r64": dict(m=20000, n=100000, E=50, rstar=64, s=0.05,
+                                  values="signed", lo=1.0, hi=100.0, r=64, rho=0.1, T=100,
+                                  spectrum="geometric", large=True),
 }
 
 
@@ -272,11 +285,15 @@ def recipe(name: str, seed: int = 0, E: Optional[int] = None) -> Instance:
     cfg = dict(RECIPES[name])
     E = int(E if E is not None else cfg["E"])
     if cfg.get("large"):
-        kind, wlo, whi = cfg["widths"]
-        widths = loguniform_widths(E, wlo, whi, seed)
+        if "widths" in cfg:
+            kind, wlo, whi = cfg["widths"]
+            widths = loguniform_widths(E, wlo, whi, seed)
+        else:
+            widths = equal_widths(cfg["n"], E)
         return planted_instance_large(cfg["m"], widths, cfg["rstar"], cfg["s"],
                                       values=cfg["values"], lo=cfg["lo"], hi=cfg["hi"],
-                                      seed=seed, name=name)
+                                      seed=seed, name=name,
+                                      spectrum=cfg.get("spectrum", "gaussian"))
     widths = equal_widths(cfg["n"], E)
     return planted_instance(cfg["m"], widths, cfg["rstar"], cfg["s"], values=cfg["values"],
                             lo=cfg["lo"], hi=cfg["hi"], seed=seed,

@@ -71,3 +71,21 @@ def test_product_path_never_imports_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
                 assert "oracle/" not in text, f
+
+
+def test_bf16_flag_rules_and_workspace(lib):
+    """RPCA_FLAG_BF16 needs the rebuilt-S form (K = 1, one alternation, no
+    stored S); its workspace holds two BF16 copies of M (2 B per entry each,
+    columns padded to 64 per client, rows to 128)."""
+    from paper_2207_11669_amd import make_params, params_error, workspace_bytes
+    for kw in (dict(K=2), dict(inner=2), dict(store_s=True)):
+        p, _k = make_params(100, [30, 70], 5, 0.1, 0.1, bf16=True, **kw)
+        msg = params_error(p)
+        assert msg is not None and "RPCA_FLAG_BF16" in msg, (kw, msg)
+    p32, _a = make_params(4000, [500] * 16, 20, 0.1, 0.01)
+    p16, _b = make_params(4000, [500] * 16, 20, 0.1, 0.01, bf16=True)
+    assert params_error(p16) is None
+    extra = workspace_bytes(p16) - workspace_bytes(p32)
+    mp, nvp = 4096, 16 * 512
+    assert extra >= 2 * 2 * mp * nvp
+    assert extra < 2 * 2 * mp * nvp + 16 * (mp + nvp) * 64 * 4
