@@ -26,40 +26,46 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DCF-PCA iters/sec + time-to-relerr 1e-4 (BF16/learned vs plain FP32), 1 GPU"
 WORKLOAD = "plain_4000x8000_r20"
-WORKLOADS = ("plain_4000x8000_r20", "uneven_10000_r32", "plain_500x500_r5")
+WORKLOADS = ("plain_4000x8000_r20", "uneven_10000_r32", "geom_20000x100000_r64",
+             "plain_500x500_r5")
 HBM_PEAK_GBS = 8000.0
-FP32_MFMA_PEAK_TFS = 157.3
+MFMA_PEAK_TFS = {"fp32": 157.3, "bf16": 2500.0}  # dense MFMA peaks of one MI355X
 def traffic_file(workload: str) -> str:
     return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_11669_amd", "csrc", "rpca_kernels.hip")
 
 
-def kernel_costs(m: int, n: int, E: int, r: int) -> dict:
+def kernel_costs(m: int, n: int, E: int, r: int, precision: str = "fp32") -> dict:
     """Algorithmic HBM bytes and flops per launch of the two streaming kernels,
     for the default round (K = 1, one V/S alternation, S rebuilt from the
     previous factors instead of stored).
 
-    V-pass: reads M once (4 B per entry), U, the previous U and V, and writes
-    W = (M - S)^T U (n x r); flops: 2r per entry to rebuild the residual
-    U_old V_old^T and 2r per entry for W.
-    S-pass: reads M once (4 B per entry), U and V, writes the per-client U-step
-    terms (E x m x r); flops: 2r per entry for U V^T and 2r for Lambda V."""
+    V-pass: reads M once (4 B per entry; 2 B in BF16 rounds, which read their
+    BF16 copy), U, the previous U and V, and writes W = (M - S)^T U (n x r);
+    flops: 2r per entry to rebuild the residual U_old V_old^T and 2r per entry
+    for W.
+    S-pass: reads M once (4 B, or 2 B in BF16), U and V, writes the
+    per-client U-step terms (E x m x r); flops: 2r per entry for U V^T and 2r
+    for Lambda V. Factor operands count at their own width (4 B, or 2 B)."""
     elem = m * n
+    w = 2 if precision == "bf16" else 4
     return {
-        "vpass": {"bytes": 4 * elem + 4 * (2 * m * r + n * r) + 4 * n * r, "flops": 4 * r * elem},
-        "spass": {"bytes": 4 * elem + 4 * (m * r + n * r) + 4 * E * m * r, "flops": 4 * r * elem},
+        "vpass": {"bytes": w * elem + w * (2 * m * r + n * r) + 4 * n * r, "flops": 4 * r * elem},
+        "spass": {"bytes": w * elem + w * (m * r + n * r) + 4 * E * m * r, "flops": 4 * r * elem},
     }
 
 
-def roofline_of(cost: dict, avg_s: float) -> dict:
+def roofline_of(cost: dict, avg_s: float, precision: str = "fp32") -> dict:
     """Bound = the resource whose peak gives the longer time for this kernel's
-    algorithmic work (HBM at 8 TB/s, FP32 MFMA at 157.3 TFLOP/s)."""
+    algorithmic work (HBM at 8 TB/s; dense MFMA at 157.3 TFLOP/s in FP32,
+    2.5 PFLOP/s in BF16)."""
+    peak = MFMA_PEAK_TFS[precision]
     t_hbm = cost["bytes"] / (HBM_PEAK_GBS * 1e9)
-    t_mfma = cost["flops"] / (FP32_MFMA_PEAK_TFS * 1e12)
+    t_mfma = cost["flops"] / (peak * 1e12)
     hbm = {"bound": "hbm", "achieved": cost["bytes"] / avg_s / 1e9, "peak": HBM_PEAK_GBS,
            "unit": "GB/s"}
     mfma = {"bound": "mfma", "achieved": cost["flops"] / avg_s / 1e12,
-            "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s"}
+            "peak": peak, "unit": "TFLOP/s"}
     main, other = (mfma, hbm) if t_mfma > t_hbm else (hbm, mfma)
     for d in (main, other):
         d["frac"] = round(d["achieved"] / d["peak"], 4)
@@ -132,6 +138,37 @@ def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_r
             "final_relerr": err, "max_rounds": max_rounds, "check_every": 10}
 
 
+def bf16_comparison(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, rounds) -> dict:
+    """The same workload with BF16 rounds (RPCA_FLAG_BF16): rounds/s, and the
+    relative error against the planted L* after `rounds` rounds next to the
+    FP32 rounds' error after as many rounds."""
+    import torch
+    from paper_2207_11669_amd import DCFPCA
+    print("[bench] BF16 rounds", file=sys.stderr, flush=True)
+    out = {"precision": "bf16"}
+    s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
+               eta0=eta0, bf16=True)
+    s.step(args.warmup)
+    if args.autotune > 0:
+        s.autotune(args.autotune)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["iters_per_s"] = round(args.steps / dt, 2)
+    out["avg_launch_us"] = {k: round(v[0] * 1e3, 2) for k, v in s.profile(20).items()}
+    s.close()
+    for name, bf in (("bf16", True), ("fp32", False)):
+        s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
+                   eta0=eta0, bf16=bf)
+        s.set_target(*target)
+        s.step(rounds)
+        out[f"relerr_after_{rounds}_rounds_{name}"] = s.target_error()
+        s.close()
+    return out
+
+
 def copy_calibration() -> int:
     import torch
     n = (256 << 20) // 4
@@ -153,6 +190,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--u-mode", default="closed", choices=["closed", "grad"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
+                    help="arithmetic of the timed rounds' streaming passes: fp32, or bf16 "
+                         "(RPCA_FLAG_BF16: BF16 copies of M, U, V on BF16 MFMA, FP32 accumulation)")
     ap.add_argument("--graph", action="store_true",
                     help="replay steady-state rounds from HIP graphs (RPCA_FLAG_GRAPH)")
     ap.add_argument("--autotune", type=int, default=10, metavar="ROUNDS",
@@ -193,8 +233,9 @@ def main() -> int:
     M_cols = colmajor(inst.M, device=dev)
     U0_cols = colmajor(U0, device=dev)
     eta0 = 0.0 if args.u_mode == "closed" else 1e-4
+    bf16 = args.precision == "bf16"
     s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-               eta0=eta0, graph=args.graph)
+               eta0=eta0, graph=args.graph, bf16=bf16)
     torch.cuda.synchronize()
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
@@ -221,13 +262,13 @@ def main() -> int:
     # the library launches on.
     print(f"[bench] per-kernel events over {args.profile_rounds} rounds", file=sys.stderr, flush=True)
     prof = s.profile(args.profile_rounds)
-    costs = kernel_costs(inst.m, inst.n, inst.E, r)
+    costs = kernel_costs(inst.m, inst.n, inst.E, r, args.precision)
     total = {k: v[0] * v[1] for k, v in prof.items()}
     dom = max(("vpass", "spass"), key=lambda k: total[k])
     avg_s = prof[dom][0] / 1e3
-    roofline = roofline_of(costs[dom], avg_s)
+    roofline = roofline_of(costs[dom], avg_s, args.precision)
     traffic = None
-    if os.path.exists(traffic_file(workload)):
+    if not bf16 and os.path.exists(traffic_file(workload)):
         with open(traffic_file(workload)) as f:
             tr = json.load(f)
         if tr.get("kernel_source_sha256_16") == src_hash() and dom in tr.get("bytes_per_launch", {}):
@@ -239,11 +280,14 @@ def main() -> int:
                      "launches_per_round": {k: v[1] / args.profile_rounds
                                             for k, v in prof.items()}})
 
-    ttr = ttf = None
-    if not args.no_relerr:
+    ttr = ttf = mixed = None
+    if not args.no_relerr and not cfg.get("large"):
         target = (colmajor(inst.Ustar, device=dev), colmajor(inst.Vstar, device=dev), cfg["rstar"])
         ttr = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target,
                              args.relerr_rounds)
+        if not bf16:
+            mixed = bf16_comparison(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target,
+                                    args.relerr_rounds)
         # The penalised objective's minimiser sits a little away from L*; also
         # time the approach to the method's own fixed point (the factors after
         # a long run) to the same relative tolerance.
@@ -266,15 +310,18 @@ def main() -> int:
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if bf16 else "f32",
         "data": "synthetic",
         "config": {"workload": workload, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
                    "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam,
                    "rho": rho, "K": 1, "inner": 1, "u_mode": args.u_mode,
-                   "graph": bool(args.graph), "autotuned_row_splits": vsplit},
+                   "graph": bool(args.graph), "autotuned_row_splits": vsplit,
+                   "precision": args.precision},
         "roofline": roofline,
         "time_to_relerr": ttr,
         "time_to_fixed_point": ttf,
+        "mixed_precision": mixed,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -96,7 +96,13 @@ typedef struct {
  * to FP32 rounds (which read the caller's FP32 M) at any round boundary: the
  * FP32 closing rounds refine the BF16 iterate to the FP32 fixed point.
  * Needs K = 1, inner = 1 and no RPCA_FLAG_STORE_S. rpca_get_LS evaluates S in
- * FP32 from the current factors in either precision. */
+ * FP32 from the current factors in either precision.
+ * Applicability: BF16 keeps 8 significand bits, so an entry x of M, U V^T or
+ * Lambda is off by up to 2^-9 |x|. The soft-threshold resolves the residual
+ * only to lambda, so BF16 rounds follow the FP32 iteration only while lambda
+ * is well above 2^-9 times the typical size of the low-rank part's entries;
+ * below that their Lambda is rounding noise and the iterates stall far from
+ * the FP32 fixed point. */
 #define RPCA_FLAG_BF16 4u
 
 /* Arithmetic of a round's streaming passes (rpca_set_precision). */

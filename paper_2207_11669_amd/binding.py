@@ -154,6 +154,9 @@ def colmajor(X, device="cuda", ld: Optional[int] = None):
     X = np.asarray(X, dtype=np.float32)
     m, n = X.shape
     ld = _ld(m) if ld is None else int(ld)
+    if ld == m and X.T.flags["C_CONTIGUOUS"]:
+        # Already column-major with no padding rows: upload as is.
+        return torch.from_numpy(X.T).to(device)
     buf = np.zeros((n, ld), dtype=np.float32)
     buf[:, :m] = X.T
     return torch.from_numpy(buf).to(device)

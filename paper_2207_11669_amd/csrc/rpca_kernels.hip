@@ -439,9 +439,10 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
   constexpr int kPer = (kVCols * RP + 255) / 256;
   constexpr int kGPer = (RP * RP + 255) / 256;
   {
-    // All of a thread's loads (eight row splits of each of its W entries, and
+    // All of a thread's loads (kWB row splits of each of its W entries, and
     // its share of G^{-1}) are issued before any is used; splits are summed
-    // in increasing order.
+    // in increasing order. Wider ranks batch fewer splits, which keeps the
+    // batch's addresses within the register file.
     double gv_[kGPer];
 #pragma unroll
     for (int q = 0; q < kGPer; ++q) {
@@ -451,21 +452,22 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
     double acc[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
-    for (int s0 = 0; s0 < p.vsplit; s0 += 8) {
-      float wv[kPer][8];
+    constexpr int kWB = RT <= 2 ? 8 : 4;
+    for (int s0 = 0; s0 < p.vsplit; s0 += kWB) {
+      float wv[kPer][kWB];
 #pragma unroll
       for (int q = 0; q < kPer; ++q) {
         const int e = tid + q * 256;
         const int j = e / RP, c = e % RP;
         const float* src = p.Wpart + (int64_t)(vrow + j) * RP + c;
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < kWB; ++u)
           wv[q][u] = (e < kVCols * RP && s0 + u < p.vsplit) ? src[(int64_t)(s0 + u) * split_stride] : 0.f;
       }
 #pragma unroll
       for (int q = 0; q < kPer; ++q)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[q] += (double)wv[q][u];
+        for (int u = 0; u < kWB; ++u) acc[q] += (double)wv[q][u];
     }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -479,23 +481,40 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
     }
   }
   __syncthreads();
+  // V = W G^{-1}: thread tid holds entries e = tid + 256 q, (j, c) =
+  // (e / RP, e % RP), as kPer sums in registers over k in increasing order.
+  // When RP divides 256 all of a thread's entries share c, so each G^{-1}
+  // entry it reads feeds kPer FMAs.
+  static_assert(kPer * 256 == kVCols * RP, "V finish thread mapping");
   float vres[kPer];
+  {
+    double sv[kPer];
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int e = tid + q * 256;
-    float vf = 0.f;
-    if (e < kVCols * RP) {
-      const int j = e / RP, c = e % RP;
-      if (j < vg.ncols && c < p.r) {
-        double s = 0.0;
-        for (int k = 0; k < p.r; ++k) s += wd[j][k] * gl[k * RP + c];
-        vf = (float)s;
+    for (int q = 0; q < kPer; ++q) sv[q] = 0.0;
+#pragma unroll 2
+    for (int k = 0; k < p.r; ++k) {
+      if constexpr (256 % RP == 0) {
+        const double g = gl[k * RP + tid % RP];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) sv[q] += wd[(tid + 256 * q) / RP][k] * g;
+      } else {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+          const int e = tid + 256 * q;
+          sv[q] += wd[e / RP][k] * gl[k * RP + e % RP];
+        }
       }
     }
-    vres[q] = vf;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + 256 * q, j = e / RP, c = e % RP;
+      vres[q] = (j < vg.ncols && c < p.r) ? (float)sv[q] : 0.f;
+    }
   }
   __syncthreads();
-#pragma unroll
+  // One entry at a time: unrolled, the eight layouts' addresses of every
+  // entry would be live together.
+#pragma unroll 1
   for (int q = 0; q < kPer; ++q) {
     const int e = tid + q * 256;
     if (e < kVCols * RP) {
@@ -507,16 +526,34 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
     }
   }
   __syncthreads();
-  // Partial V^T V of these columns (symmetric: each pair a <= b once).
+  // Partial V^T V of these columns: thread (ta, tb) = (tid / 16, tid % 16)
+  // forms the RT x RT block of entries (RT ta + x, RT tb + y), each a sum over
+  // the 32 columns in order (each LDS read feeds RT FMAs).
   double* gv = p.gv_part + (int64_t)blockIdx.x * RP * RP;
-  for (int e = tid; e < RP * RP; e += blockDim.x) {
-    const int a = e / RP, b = e % RP;
-    if (a > b) continue;
-    double s = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < kVCols; ++j) s += wd[j][a] * wd[j][b];
-    gv[e] = s;
-    if (a != b) gv[b * RP + a] = s;
+  {
+    const int a0 = RT * (tid >> 4), b0 = RT * (tid & 15);
+    double sg[RT][RT];
+#pragma unroll
+    for (int x = 0; x < RT; ++x)
+#pragma unroll
+      for (int y = 0; y < RT; ++y) sg[x][y] = 0.0;
+#pragma unroll 2
+    for (int j = 0; j < kVCols; ++j) {
+      double va[RT], vb[RT];
+#pragma unroll
+      for (int x = 0; x < RT; ++x) {
+        va[x] = wd[j][a0 + x];
+        vb[x] = wd[j][b0 + x];
+      }
+#pragma unroll
+      for (int x = 0; x < RT; ++x)
+#pragma unroll
+        for (int y = 0; y < RT; ++y) sg[x][y] += va[x] * vb[y];
+    }
+#pragma unroll
+    for (int x = 0; x < RT; ++x)
+#pragma unroll
+      for (int y = 0; y < RT; ++y) gv[(a0 + x) * RP + b0 + y] = sg[x][y];
   }
 }
 
@@ -553,21 +590,48 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
   }
 }
 
-// S-pass epilogue, shared by the FP32 and BF16 forms (512 threads): the
-// client's U-step term for the work-group's 128 rows from P = Lambda V_i and
+// S-pass statistics: the work-group's sums of Lambda^2, |S| and nnz(S) over
+// its NW waves, added in wave order, into p.spart.
+template <int NW>
+__device__ __forceinline__ void spass_stats(const DevParams& p, int ci, int b, double sl2,
+                                            double sl1, uint32_t nnz) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  __shared__ double sred[NW][3];
+  sl2 = wave_sum(sl2);
+  sl1 = wave_sum(sl1);
+  const int wv = tid >> 6;
+  if (lane == 0) {
+    sred[wv][0] = sl2;
+    sred[wv][1] = sl1;
+    sred[wv][2] = (double)nnz;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double* o = p.spart + ((int64_t)ci * p.nrb + b) * 4;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) t += sred[k][q];
+      o[q] = t;
+    }
+    o[3] = 0.0;
+  }
+}
+
+// S-pass epilogue of the FP32 form (512 threads): the client's U-step term for the work-group's 128 rows from P = Lambda V_i and
 // U_i staged in LDS (Lemma 2 proof for the gradient, argmin_U L_i for the
 // closed form):
 //   GRAD   T = U_i - eta (c_i U_i - P)
 //   CLOSED T = P A_i + U_i B_i,  A_i = (V_i^T V_i + c_i I)^{-1}, B_i = V_i^T V_i A_i
-// in FP64, stored FP32 into the client's slot of p.P; then the work-group's
-// sums of Lambda^2, |S| and nnz(S) into p.spart.
+// in FP64, stored FP32 into the client's slot of p.P; then the statistics.
 template <int RP>
 __device__ __forceinline__ void spass_terms_and_stats(const DevParams& p, const ClientDev& cl, int b,
                                                       const float (*ptile)[RP + 1],
                                                       const float (*utile)[RP + 1],
                                                       const double (*fab)[RP * RP], bool closed,
                                                       double sl2, double sl1, uint32_t nnz) {
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x;
   const int ci = cl.idx;
   const int row0 = b * kSRows;
   float* Ti = p.P + (int64_t)ci * RP * p.MP;
@@ -599,27 +663,7 @@ __device__ __forceinline__ void spass_terms_and_stats(const DevParams& p, const 
       Ti[(int64_t)(c0 + j) * p.MP + row0 + rl] = c0 + j < p.r ? (float)t[j] : 0.f;
   }
 
-  __shared__ double sred[8][3];
-  sl2 = wave_sum(sl2);
-  sl1 = wave_sum(sl1);
-  const int wv = tid >> 6;
-  if (lane == 0) {
-    sred[wv][0] = sl2;
-    sred[wv][1] = sl1;
-    sred[wv][2] = (double)nnz;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double* o = p.spart + ((int64_t)ci * p.nrb + b) * 4;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      double t = 0.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) t += sred[k][q];
-      o[q] = t;
-    }
-    o[3] = 0.0;
-  }
+  spass_stats<8>(p, ci, b, sl2, sl1, nnz);
 }
 
 // ---------------------------------------------------------------------------
@@ -1683,19 +1727,21 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
 }
 
 // ---------------------------------------------------------------------------
-// BF16 S-pass: same grid (128-row blocks x clients, widest client first),
-// outputs and epilogue as k_spass, over 32-column chunks. The eight waves are
-// two 64-row groups by four column phases (wave (g, q) takes rows 64 g ..
-// 64 g + 63 and chunks q, q + 4, ...): four 16-row tiles per wave share each
-// chunk's V operands in registers. MFMA 1 forms (U V^T)^T for two 16x16
-// tiles per row tile with V's hP halves as A and U's hA as B, leaving lane l
-// row l%16 and the eight columns 8 (l/16) + e of the chunk -- the lane's
-// 16-byte load of the S-pass copy of M, and the A operand of MFMA 2
+// BF16 S-pass: same grid (128-row blocks x clients, widest client first) and
+// outputs as k_spass, over 32-column chunks, with 256 threads. The four waves
+// are two 64-row groups by two column phases (wave (g, q) takes rows
+// 64 g .. 64 g + 63 and chunks q, q + 2, ...): four 16-row tiles per wave
+// share each chunk's V operands in registers. MFMA 1 forms (U V^T)^T for two
+// 16x16 tiles per row tile with V's hP halves as A and U's hA as B, leaving
+// lane l row l%16 and the eight columns 8 (l/16) + e of the chunk -- the
+// lane's 16-byte load of the S-pass copy of M, and the A operand of MFMA 2
 // (P += Lambda V with V's hB packing as B). The phases' partial P are added
-// in LDS in phase order.
+// in LDS in phase order. LDS holds P and FP32 copies of A_i and B_i (65 KB at
+// r = 64), so two work-groups fit on a compute unit and one's epilogue
+// overlaps the other's sweep.
 // ---------------------------------------------------------------------------
 template <int RT, int NK>
-__global__ __launch_bounds__(512) void k_spass_h(DevParams p, const float* __restrict__ U) {
+__global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __restrict__ U) {
   constexpr int RP = 16 * RT;
   constexpr int kRT = 4;  // 16-row tiles per wave
   const int b = blockIdx.x;
@@ -1723,34 +1769,18 @@ __global__ __launch_bounds__(512) void k_spass_h(DevParams p, const float* __res
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
 
-  __shared__ float ptile[kSRows][RP + 1];
-  __shared__ float utile[kSRows][RP + 1];
-  __shared__ double fab[2][RP * RP];
+  // A_i and B_i of the closed-form step, rounded to FP32, for the epilogue
+  // (made visible by the barriers that add the phases' P).
+  __shared__ float fab[2][RP * RP];
   const bool closed = p.u_mode != 0;
-  constexpr int kFabPer = (RP * RP + 511) / 512;
-  double fa[kFabPer], fbv[kFabPer];
   if (closed) {
     const double* __restrict__ Af = p.Afac + (int64_t)ci * RP * RP;
     const double* __restrict__ Bf = p.Bfac + (int64_t)ci * RP * RP;
-#pragma unroll
-    for (int q = 0; q < kFabPer; ++q) {
-      const int e = tid + q * 512;
-      fa[q] = e < RP * RP ? Af[e] : 0.0;
-      fbv[q] = e < RP * RP ? Bf[e] : 0.0;
+    for (int e = tid; e < RP * RP; e += blockDim.x) {
+      fab[0][e] = (float)Af[e];
+      fab[1][e] = (float)Bf[e];
     }
   }
-  auto stage_fab = [&]() {
-    if (closed) {
-#pragma unroll
-      for (int q = 0; q < kFabPer; ++q) {
-        const int e = tid + q * 512;
-        if (e < RP * RP) {
-          fab[0][e] = fa[q];
-          fab[1][e] = fbv[q];
-        }
-      }
-    }
-  };
 
   double sl2 = 0.0, sl1 = 0.0;
   uint32_t nnz = 0;
@@ -1769,9 +1799,9 @@ __global__ __launch_bounds__(512) void k_spass_h(DevParams p, const float* __res
   constexpr int kDepth = 2;
   Chunk ring[kDepth];
   const int nch = (cl.n + 31) >> 5;
-  const int nk = (nch - phase + 3) >> 2;  // chunks phase, phase + 4, ... below nch
+  const int nk = (nch - phase + 1) >> 1;  // chunks phase, phase + 2, ... below nch
   auto load_chunk = [&](Chunk& c, int k) {
-    const int cc = phase + 4 * k;
+    const int cc = phase + 2 * k;
     const int64_t vch = (cl.vrow0 >> 5) + cc;
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) c.m[rt] = Ms[((int64_t)rt * nvc32 + cc) * 64];
@@ -1818,8 +1848,6 @@ __global__ __launch_bounds__(512) void k_spass_h(DevParams p, const float* __res
       load_chunk(ring[d], min(d, nk - 1));
       __builtin_amdgcn_sched_barrier(0);
     }
-    stage_fab();
-    __builtin_amdgcn_sched_barrier(0);
     for (int k0 = 0; k0 < nkp; k0 += kDepth) {
 #pragma unroll
       for (int d = 0; d < kDepth; ++d) {
@@ -1830,23 +1858,11 @@ __global__ __launch_bounds__(512) void k_spass_h(DevParams p, const float* __res
         __builtin_amdgcn_sched_barrier(0);
       }
     }
-  } else {
-    // A phase with no chunk (a client of at most 96 columns) still stages
-    // its share of A_i and B_i.
-    stage_fab();
   }
 
-  // Epilogue: P from the four phases' accumulators added in LDS in phase
-  // order; U_i in FP32 from the factor's column-major layout (not its BF16
-  // operand copy).
-  {
-    const GLOBAL float* Uc = gptr(U) + (int64_t)b * kSRows;
-    for (int e = tid; e < kSRows * RP; e += blockDim.x) {
-      const int rl = e % kSRows, c = e / kSRows;
-      utile[rl][c] = c < p.r ? Uc[(int64_t)c * MP + rl] : 0.f;
-    }
-  }
-  for (int q = 0; q < 4; ++q) {
+  // P of the two phases, added in LDS in phase order.
+  __shared__ float ptile[kSRows][RP + 1];
+  for (int q = 0; q < 2; ++q) {
     if (phase == q) {
 #pragma unroll
       for (int rt = 0; rt < kRT; ++rt)
@@ -1860,7 +1876,47 @@ __global__ __launch_bounds__(512) void k_spass_h(DevParams p, const float* __res
     }
     __syncthreads();
   }
-  spass_terms_and_stats<RP>(p, cl, b, ptile, utile, fab, closed, sl2, sl1, nnz);
+  // U-step term of these 128 rows, as in the FP32 form's epilogue but in
+  // FP32 (the BF16 rounds' operands carry 8-bit significands, so FP32 here
+  // adds nothing measurable): thread tid owns row tid % 128 and the rank
+  // columns 8 (tid / 128) + 16 q .. + 7; its row of U_i (FP32, from the
+  // factor's column-major layout) sits in registers, P and A_i, B_i in LDS
+  // (the A_i, B_i reads are uniform across a wave).
+  const int row0 = b * kSRows;
+  const int rl = tid & (kSRows - 1);
+  float uk[RP];
+  {
+    const GLOBAL float* Uc = gptr(U) + row0 + rl;
+#pragma unroll
+    for (int k = 0; k < RP; ++k) uk[k] = Uc[(int64_t)k * MP];  // ranks past r are zero
+  }
+  float* Ti = p.P + (int64_t)ci * RP * p.MP;
+  const float eta = (float)eta_of_round(p, p.dstate->t);
+  const float cc = (float)cl.c;
+  for (int c0 = 8 * (tid >> 7); c0 < RP; c0 += 16) {
+    float t[8];
+    if (closed) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) t[j] = 0.f;
+#pragma unroll
+      for (int k = 0; k < RP; ++k) {
+        const float pk = ptile[rl][k];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          t[j] = fmaf(pk, fab[0][k * RP + c0 + j], fmaf(uk[k], fab[1][k * RP + c0 + j], t[j]));
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float u = gptr(U)[(int64_t)(c0 + j) * MP + row0 + rl];
+        t[j] = u - eta * (cc * u - ptile[rl][c0 + j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      Ti[(int64_t)(c0 + j) * MP + row0 + rl] = c0 + j < p.r ? t[j] : 0.f;
+  }
+  spass_stats<4>(p, ci, b, sl2, sl1, nnz);
 }
 
 hipError_t launch_m_to_bf16(const DevParams& p, hipStream_t st) {
@@ -1900,10 +1956,10 @@ hipError_t launch_vpass_h(const DevParams& p, int mode, const float* U, const fl
 hipError_t launch_spass_h(const DevParams& p, const float* U, hipStream_t st) {
   const dim3 grid(p.nrb, p.E);
   switch (p.RP / 16) {
-    case 1: hipLaunchKernelGGL((k_spass_h<1, 1>), grid, dim3(512), 0, st, p, U); break;
-    case 2: hipLaunchKernelGGL((k_spass_h<2, 1>), grid, dim3(512), 0, st, p, U); break;
-    case 3: hipLaunchKernelGGL((k_spass_h<3, 2>), grid, dim3(512), 0, st, p, U); break;
-    case 4: hipLaunchKernelGGL((k_spass_h<4, 2>), grid, dim3(512), 0, st, p, U); break;
+    case 1: hipLaunchKernelGGL((k_spass_h<1, 1>), grid, dim3(256), 0, st, p, U); break;
+    case 2: hipLaunchKernelGGL((k_spass_h<2, 1>), grid, dim3(256), 0, st, p, U); break;
+    case 3: hipLaunchKernelGGL((k_spass_h<3, 2>), grid, dim3(256), 0, st, p, U); break;
+    case 4: hipLaunchKernelGGL((k_spass_h<4, 2>), grid, dim3(256), 0, st, p, U); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
