@@ -118,24 +118,42 @@ def cpu_baseline(inst, U0, r, rho, lam, budget_s: float = 12.0, max_rounds: int 
                       f"instance (E={inst.E}, r={r}), after one untimed round"}
 
 
-def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_rounds) -> dict:
-    """Wall time of rpca_solve from U^(0) until ||U V^T - X Y^T||_F / ||X Y^T||_F
-    <= 1e-4 for the target factors (X, Y), checked every 10 rounds with r x r
-    Gram matrices (L is never formed)."""
+def continuation(lam: float, lam0: float, gamma: float = 0.8) -> list:
+    """lambda_t = max(lambda, lambda0 gamma^t) up to the first round at lambda."""
+    out = []
+    while not out or out[-1] > lam:
+        out.append(max(lam, lam0 * gamma ** len(out)))
+    return out
+
+
+def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_rounds,
+                   schedule=None) -> dict:
+    """Wall time from U^(0) until ||U V^T - X Y^T||_F / ||X Y^T||_F <= 1e-4 for
+    the target factors (X, Y), checked every 10 rounds with r x r Gram
+    matrices (L is never formed) by rpca_solve. With a lambda schedule, its
+    rounds (rpca_set_lambda before each) run first and count."""
     import torch
     from paper_2207_11669_amd import DCFPCA
-    print("[bench] time to relative error 1e-4", file=sys.stderr, flush=True)
+    print("[bench] time to relative error 1e-4" + (" (lambda continuation)" if schedule else ""),
+          file=sys.stderr, flush=True)
     s2 = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
                 eta0=eta0)
     s2.set_target(*target)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done, err = s2.solve(max_rounds, 1e-4, check_every=10)
+    pre = 0
+    for lt in schedule or []:
+        s2.set_lambda(lt)
+        s2.step(1)
+        pre += 1
+    s2.set_lambda(lam)
+    done, err = s2.solve(max_rounds - pre, 1e-4, check_every=10)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     s2.close()
-    return {"tol": 1e-4, "reached": bool(err <= 1e-4), "rounds": done, "seconds": round(secs, 4),
-            "final_relerr": err, "max_rounds": max_rounds, "check_every": 10}
+    return {"tol": 1e-4, "reached": bool(err <= 1e-4), "rounds": pre + done,
+            "seconds": round(secs, 4), "final_relerr": err, "max_rounds": max_rounds,
+            "check_every": 10}
 
 
 def bf16_comparison(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, rounds) -> dict:
@@ -280,7 +298,7 @@ def main() -> int:
                      "launches_per_round": {k: v[1] / args.profile_rounds
                                             for k, v in prof.items()}})
 
-    ttr = ttf = mixed = None
+    ttr = ttf = mixed = cont = None
     if not args.no_relerr and not cfg.get("large"):
         target = (colmajor(inst.Ustar, device=dev), colmajor(inst.Vstar, device=dev), cfg["rstar"])
         ttr = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target,
@@ -301,6 +319,17 @@ def main() -> int:
         ttf = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, (Uf, Vf, r),
                              args.fixed_point_rounds)
         ttf["fixed_point_rounds"] = args.fixed_point_rounds
+        # The lambda continuation (a schedule from max|M| down to lambda): the
+        # same two targets, same fixed point (the schedule ends at lambda).
+        lam0 = float(np.abs(inst.M).max())
+        sched = continuation(lam, lam0)
+        cont = {"kind": "lambda continuation", "lambda0": lam0, "gamma": 0.8,
+                "schedule_rounds": len(sched),
+                "time_to_relerr": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
+                                                 target, args.relerr_rounds, sched),
+                "time_to_fixed_point": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args,
+                                                      eta0, (Uf, Vf, r),
+                                                      args.fixed_point_rounds, sched)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -322,6 +351,7 @@ def main() -> int:
         "time_to_relerr": ttr,
         "time_to_fixed_point": ttf,
         "mixed_precision": mixed,
+        "controller": cont,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

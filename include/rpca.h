@@ -215,6 +215,16 @@ rpca_status rpca_profile(rpca_ctx* c, int32_t rounds, double* avg_ms, int64_t* l
  * choice; the choice itself depends on timing. */
 rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out);
 
+/* lambda of the rounds enqueued from now on (lambda >= 0, finite), for a
+ * lambda schedule such as a continuation from a large value down to the
+ * target. Every soft-threshold of round t uses its lambda_t, including the
+ * V-pass's rebuild of S^(t) from the previous factors, and so does the
+ * round's recorded objective. Needs the rebuilt-S form (K = 1, inner = 1, no
+ * RPCA_FLAG_STORE_S); RPCA_EINVAL otherwise. A change drops captured graphs.
+ * The paper fixes lambda; a schedule changes the path, and the method's
+ * fixed point is that of the last lambda. */
+rpca_status rpca_set_lambda(rpca_ctx* c, double lambda);
+
 /* Precision of the rounds enqueued from now on (rpca_precision). BF16 needs
  * a context created with RPCA_FLAG_BF16 (RPCA_EINVAL otherwise). Switching
  * drops captured graphs. The next round's V-pass rebuilds S^(t) from the

@@ -40,6 +40,13 @@ Readings taken where the paper is silent, garbled or ambiguous:
   is defined at t = 0.
 * The recorded round objective is sum_i L_i(U_i, V_i, S_i) at the last local
   (V, S) update of the round, with U_i the client's factor before its U step.
+* A lambda schedule (lambda_t per round; the paper fixes lambda, so this is
+  the caller's choice, e.g. a continuation down to the target) is read as:
+  every soft-threshold of round t uses lambda_t, and S^(t), which round t's V
+  update consumes, is re-evaluated at lambda_t from the residual that produced
+  it (M_i - U V_i^T of the previous round). With one alternation and K = 1 the
+  previous S is exactly that soft-threshold, so a constant schedule is the
+  plain method.
 
 Parity pins live in the test suite; every function here is pinned by at least
 one check that does not retype its formula (closed forms, library routines of
@@ -168,13 +175,14 @@ def dcfpca(Ms: Sequence[np.ndarray], r: int, rho: float, lam: float, T: int,
            U0: np.ndarray, K: int = 1, inner: int = 1, u_mode: str = "closed",
            eta0: float = 0.0, eta_sched: str = "const",
            S0: Optional[Sequence[np.ndarray]] = None, t0: int = 0,
-           record: bool = True) -> Result:
+           record: bool = True, lam_schedule: Optional[Sequence[float]] = None) -> Result:
     """Algorithm 1 (Section 2.2): T rounds of broadcast, K local steps per
     client, and the mean of the client factors.
 
     Ms: the client blocks M_i (m x n_i). U0: U^(0) (m x r). S0: optional
     starting S_i (default zeros). t0: index of the first round (for the eta
-    schedule when resuming).
+    schedule when resuming). lam_schedule: optional lambda_t for each of the T
+    rounds (K = 1 and inner = 1 only; see the module's readings).
     """
     Ms = [np.asarray(Mi, dtype=np.float64) for Mi in Ms]
     E = len(Ms)
@@ -186,8 +194,15 @@ def dcfpca(Ms: Sequence[np.ndarray], r: int, rho: float, lam: float, T: int,
     S = [np.zeros_like(Mi) if S0 is None else np.array(S0[i], dtype=np.float64, copy=True)
          for i, Mi in enumerate(Ms)]
     V: List[Optional[np.ndarray]] = [None] * E
+    if lam_schedule is not None:
+        if K != 1 or inner != 1:
+            raise ValueError("a lambda schedule needs K = 1 and inner = 1")
+        if len(lam_schedule) < T:
+            raise ValueError("lam_schedule needs one lambda per round")
+    R_last: List[Optional[np.ndarray]] = [None] * E
     history = []
     for t in range(int(t0), int(t0) + int(T)):
+        lam_t = lam if lam_schedule is None else float(lam_schedule[t - int(t0)])
         eta = eta_at(eta0, eta_sched, t) if u_mode == "grad" else 0.0
         client_U = []
         F = 0.0
@@ -195,10 +210,13 @@ def dcfpca(Ms: Sequence[np.ndarray], r: int, rho: float, lam: float, T: int,
         nnz = 0
         for i in range(E):  # clients one after another (Section 4.1)
             Ui = U.copy()  # broadcast of U^(t) (eq. "U_agg" of the previous round)
+            if lam_schedule is not None and R_last[i] is not None:
+                S[i] = soft_threshold(R_last[i], lam_t)  # S^(t) at lambda_t
             for _k in range(int(K)):
-                Vi, Si, Ri = inner_solve(Ui, Ms[i], S[i], rho, lam, inner)
+                Vi, Si, Ri = inner_solve(Ui, Ms[i], S[i], rho, lam_t, inner)
+                R_last[i] = Ri
                 if record and _k == K - 1:
-                    F += local_objective(Ui, Vi, Si, Ms[i], rho, lam, widths[i], n)
+                    F += local_objective(Ui, Vi, Si, Ms[i], rho, lam_t, widths[i], n)
                     Lam = Ri - Si
                     lam_sq += float(np.sum(Lam * Lam))
                     nnz += int(np.count_nonzero(Si))

@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rpca_step": (c_int32, [vp, c_int32]),
         "rpca_autotune": (c_int32, [vp, c_int32, POINTER(c_int32)]),
         "rpca_set_precision": (c_int32, [vp, c_int32]),
+        "rpca_set_lambda": (c_int32, [vp, c_double]),
         "rpca_solve": (c_int32, [vp, c_int32, c_double, c_int32, POINTER(c_int32),
                                  POINTER(c_double)]),
         "rpca_set_target": (c_int32, [vp, vp, c_int64, vp, c_int64, c_int32]),
@@ -241,6 +242,10 @@ class DCFPCA:
         out = c_int32(0)
         self._check(self._lib.rpca_autotune(self.ctx, int(rounds), ctypes.byref(out)))
         return int(out.value)
+
+    def set_lambda(self, lam: float):
+        """lambda of the following rounds (rebuilt-S form only)."""
+        self._check(self._lib.rpca_set_lambda(self.ctx, float(lam)))
 
     def set_precision(self, precision: str):
         """Precision of the following rounds' streaming passes: "fp32" or "bf16"."""

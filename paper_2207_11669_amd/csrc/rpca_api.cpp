@@ -278,6 +278,7 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     c->vcur = vn;
     c->cur ^= 1;
     c->rounds += 1;
+    c->p.lam_rec = c->p.lam;
     return RPCA_OK;
   }
   for (int k = 0; k < p.K; ++k) {
@@ -312,6 +313,7 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
   }
   c->cur ^= 1;
   c->rounds += 1;
+  c->p.lam_rec = c->p.lam;
   return RPCA_OK;
 }
 
@@ -398,6 +400,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.u_mode = prm->u_mode;
   p.eta_sched = prm->eta_sched;
   p.lam = (float)prm->lambda;
+  p.lam_rec = p.lam;
   p.rho = prm->rho;
   p.eta0 = prm->eta0;
   p.bf16 = L.bf16 ? 1 : 0;
@@ -546,7 +549,11 @@ rpca_status rpca_step(rpca_ctx* c, int32_t rounds) {
   if (rounds < 0) return fail(c, RPCA_EINVAL, "rounds must be >= 0");
   int32_t t = 0;
   while (t < rounds) {
-    if (c->use_graph && rounds - t >= 2 && c->rounds >= 1 && c->fin_pending) {
+    // A graph bakes its launches' parameters, including the lambda the first
+    // round's deferred record uses: capture only in a steady state, where
+    // that is the lambda of every round.
+    if (c->use_graph && rounds - t >= 2 && c->rounds >= 1 && c->fin_pending &&
+        c->p.lam_rec == c->p.lam) {
       if (rpca_status s = enqueue_round_pair_graph(c)) return s;
       t += 2;
     } else {
@@ -622,6 +629,17 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out) {
   drop_graphs(c);
   if (vsplit_out) *vsplit_out = c->p.vsplit;
   return result;
+}
+
+rpca_status rpca_set_lambda(rpca_ctx* c, double lambda) {
+  if (rpca_status s = guard(c)) return s;
+  if (!(lambda >= 0.0) || !std::isfinite(lambda))
+    return fail(c, RPCA_EINVAL, "lambda must be finite and >= 0");
+  if (!c->recompute)
+    return fail(c, RPCA_EINVAL, "rpca_set_lambda needs K = 1, inner = 1 and no RPCA_FLAG_STORE_S");
+  if ((float)lambda != c->p.lam) drop_graphs(c);
+  c->p.lam = (float)lambda;
+  return RPCA_OK;
 }
 
 rpca_status rpca_set_precision(rpca_ctx* c, int32_t precision) {

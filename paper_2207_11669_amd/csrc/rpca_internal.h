@@ -142,7 +142,8 @@ struct DevParams {
   int32_t vsplit;        // V-pass row splits
   int32_t vsplit_rows;   // rows per V-pass row split (multiple of 16)
   int32_t u_mode, eta_sched;
-  float lam;
+  float lam;             // lambda of the rounds being enqueued
+  float lam_rec;         // lambda of the last enqueued round (its deferred record)
   double rho, eta0;
   const ClientDev* clients;
   const ClientDev* clients_lpt;  // the same records, widest client first (S-pass order)

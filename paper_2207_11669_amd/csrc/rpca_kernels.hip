@@ -1126,7 +1126,7 @@ __device__ void fin_record(const DevParams& p, const double* stats, double tr) {
   const int64_t t = p.dstate->t;
   StatsRec rec;
   rec.t = (double)t;
-  rec.objective = 0.5 * stats[0] + 0.5 * p.rho * stats[3] + (double)p.lam * stats[1] + stats[5];
+  rec.objective = 0.5 * stats[0] + 0.5 * p.rho * stats[3] + (double)p.lam_rec * stats[1] + stats[5];
   rec.lambda_fro_sq = stats[0];
   rec.nnz = stats[2];
   rec.du_sq = stats[4];

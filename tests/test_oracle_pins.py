@@ -378,3 +378,35 @@ def test_planted_recovery_small_instance():
     s, r = 0.05, 3
     floor = math.sqrt(lam ** 2 * s * r * (inst.m + inst.n) + rho ** 2 * r) / np.linalg.norm(inst.Lstar)
     assert err <= 3.0 * floor, (err, floor)
+
+
+def test_constant_lambda_schedule_is_the_plain_method():
+    """A schedule that holds lambda re-evaluates S^(t) as the soft-threshold of
+    the residual that produced it, which is the stored S itself: the iterates
+    are exactly those of the plain method."""
+    inst = planted_instance(60, [20, 25], 3, 0.1, values="signed", lo=5.0, hi=20.0, seed=4)
+    lam = 1.0 / math.sqrt(inst.n)
+    U0 = gaussian_init(inst.m, 3, 1)
+    a = O.dcfpca(inst.blocks(), 3, 0.1, lam, 12, U0)
+    b = O.dcfpca(inst.blocks(), 3, 0.1, lam, 12, U0, lam_schedule=[lam] * 12)
+    assert np.array_equal(a.L_full(), b.L_full()) and np.array_equal(a.S_full(), b.S_full())
+    assert [h["objective"] for h in a.history] == [h["objective"] for h in b.history]
+
+
+def test_lambda_continuation_shortens_the_early_phase():
+    """lambda_t = max(lambda, max|M| 0.8^t): starting with every entry below
+    the threshold, L absorbs the bulk of M before S takes the outliers, so the
+    planted L* is approached to 1e-2 within 30 rounds, where the plain method
+    (S absorbing almost all of the residual from the start, so that L moves
+    by about lambda per round) is still far away."""
+    inst = planted_instance(300, [100, 100, 100], 5, 0.10, values="signed", lo=5.0, hi=20.0,
+                            seed=3)
+    lam = 1.0 / math.sqrt(inst.n)
+    U0 = gaussian_init(inst.m, 5, 7)
+    Ls = inst.Ustar @ inst.Vstar.T
+    mx = float(np.abs(inst.M).max())
+    sched = [max(lam, mx * 0.8 ** t) for t in range(30)]
+    cont = O.dcfpca(inst.blocks(), 5, 0.1, lam, 30, U0, lam_schedule=sched, record=False)
+    plain = O.dcfpca(inst.blocks(), 5, 0.1, lam, 30, U0, record=False)
+    assert O.relative_error(cont.L_full(), Ls) < 1e-2
+    assert O.relative_error(plain.L_full(), Ls) > 0.5
