@@ -30,8 +30,9 @@ WORKLOADS = ("plain_4000x8000_r20", "uneven_10000_r32", "geom_20000x100000_r64",
              "plain_500x500_r5")
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFS = {"fp32": 157.3, "bf16": 2500.0}  # dense MFMA peaks of one MI355X
-def traffic_file(workload: str) -> str:
-    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+def traffic_file(workload: str, precision: str = "fp32") -> str:
+    suffix = "" if precision == "fp32" else f"_{precision}"
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}{suffix}.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_11669_amd", "csrc", "rpca_kernels.hip")
 
 
@@ -286,8 +287,8 @@ def main() -> int:
     avg_s = prof[dom][0] / 1e3
     roofline = roofline_of(costs[dom], avg_s, args.precision)
     traffic = None
-    if not bf16 and os.path.exists(traffic_file(workload)):
-        with open(traffic_file(workload)) as f:
+    if os.path.exists(traffic_file(workload, args.precision)):
+        with open(traffic_file(workload, args.precision)) as f:
             tr = json.load(f)
         if tr.get("kernel_source_sha256_16") == src_hash() and dom in tr.get("bytes_per_launch", {}):
             traffic = tr["bytes_per_launch"][dom]
