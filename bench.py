@@ -215,8 +215,9 @@ def main() -> int:
     ap.add_argument("--graph", action="store_true",
                     help="replay steady-state rounds from HIP graphs (RPCA_FLAG_GRAPH)")
     ap.add_argument("--autotune", type=int, default=10, metavar="ROUNDS",
-                    help="before timing, pick the V-pass row-split count with rpca_autotune; 0 keeps the default "
-                         "(ROUNDS timed rounds per candidate)")
+                    help="before timing, pick the V-pass launch shape (row splits, column groups per "
+                         "wave) with rpca_autotune; 0 keeps the default (ROUNDS timed rounds per "
+                         "candidate)")
     ap.add_argument("--profile-rounds", type=int, default=50)
     ap.add_argument("--relerr-rounds", type=int, default=3000)
     ap.add_argument("--fixed-point-rounds", type=int, default=8000)
@@ -259,7 +260,7 @@ def main() -> int:
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     s.step(args.warmup)
-    vsplit = s.autotune(args.autotune) if args.autotune > 0 else None
+    shape = s.autotune(args.autotune) if args.autotune > 0 else None
     torch.cuda.synchronize()
     stream = s.stream
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -346,7 +347,7 @@ def main() -> int:
         "config": {"workload": workload, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
                    "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam,
                    "rho": rho, "K": 1, "inner": 1, "u_mode": args.u_mode,
-                   "graph": bool(args.graph), "autotuned_row_splits": vsplit,
+                   "graph": bool(args.graph), "autotuned_vpass_shape": shape,
                    "precision": args.precision},
         "roofline": roofline,
         "time_to_relerr": ttr,

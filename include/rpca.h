@@ -205,15 +205,19 @@ typedef enum {
  * launches (launches[RPCA_NUM_PHASES]). The rounds count as real rounds. */
 rpca_status rpca_profile(rpca_ctx* c, int32_t rounds, double* avg_ms, int64_t* launches);
 
-/* Autotuner for the V-pass split of the row dimension (the split-K of
- * W = (M_i - S_i)^T U over m): runs `rounds` timed rounds (plus one untimed)
- * at each candidate split count -- the default, half of it and twice it,
- * within what the workspace holds -- keeps the fastest, and returns it in
- * *vsplit_out (optional). Synchronises. The rounds are real rounds of the
- * method. The split count changes only the summation order of W, so results
- * stay within FP32 rounding of the default and are deterministic for a given
+/* Autotuner for the V-pass launch shape: the split of the row dimension (the
+ * split-K of W = (M_i - S_i)^T U over m) and the 16-column groups each
+ * FP32 V-pass wave takes (1: waves on distinct columns share U operands
+ * through the cache; 4: a wave takes all 64 columns of its tile and shares
+ * them in registers, the waves splitting the rows). It runs `rounds` timed
+ * rounds (plus one untimed) at each candidate -- the default split count,
+ * half of it and twice it (within what the workspace holds), each with 1 and
+ * 4 column groups -- keeps the fastest, and returns it in *vsplit_out and
+ * *vcols_out (both optional). Synchronises. The rounds are real rounds of the
+ * method. The shape changes only the summation order of W, so results stay
+ * within FP32 rounding of the default and are deterministic for a given
  * choice; the choice itself depends on timing. */
-rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out);
+rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int32_t* vcols_out);
 
 /* lambda of the rounds enqueued from now on (lambda >= 0, finite), for a
  * lambda schedule such as a continuation from a large value down to the

@@ -88,7 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rpca_init": (c_int32, [POINTER(vp), POINTER(RpcaParams), POINTER(vp), POINTER(c_int64),
                                 vp, c_int64, vp, c_size_t, vp]),
         "rpca_step": (c_int32, [vp, c_int32]),
-        "rpca_autotune": (c_int32, [vp, c_int32, POINTER(c_int32)]),
+        "rpca_autotune": (c_int32, [vp, c_int32, POINTER(c_int32), POINTER(c_int32)]),
         "rpca_set_precision": (c_int32, [vp, c_int32]),
         "rpca_set_lambda": (c_int32, [vp, c_double]),
         "rpca_solve": (c_int32, [vp, c_int32, c_double, c_int32, POINTER(c_int32),
@@ -237,11 +237,13 @@ class DCFPCA:
     def step(self, rounds: int = 1):
         self._check(self._lib.rpca_step(self.ctx, int(rounds)))
 
-    def autotune(self, rounds: int = 10) -> int:
-        """Pick the V-pass row-split count by timing; returns it."""
-        out = c_int32(0)
-        self._check(self._lib.rpca_autotune(self.ctx, int(rounds), ctypes.byref(out)))
-        return int(out.value)
+    def autotune(self, rounds: int = 10) -> dict:
+        """Pick the V-pass launch shape by timing real rounds; returns it as
+        {"row_splits": ..., "column_groups": ...}."""
+        v, g = c_int32(0), c_int32(0)
+        self._check(self._lib.rpca_autotune(self.ctx, int(rounds), ctypes.byref(v),
+                                            ctypes.byref(g)))
+        return {"row_splits": int(v.value), "column_groups": int(g.value)}
 
     def set_lambda(self, lam: float):
         """lambda of the following rounds (rebuilt-S form only)."""

@@ -396,6 +396,10 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.ng64 = L.ng64;
   p.vsplit = L.vsplit;
   p.vsplit_rows = L.vsplit_rows;
+  // Shared-operand V-pass waves pay off once a chunk's U operands cost more
+  // loads than its M (the rebuild's NS packed rank steps); the autotuner
+  // revisits this.
+  p.vcols = L.NS > 5 ? 4 : 1;
   c->vsplit_max = L.vsplit_max;
   p.u_mode = prm->u_mode;
   p.eta_sched = prm->eta_sched;
@@ -582,15 +586,19 @@ static void set_vsplit(rpca_ctx* c, int64_t vs) {
   c->p.vsplit = (int32_t)((m + rows - 1) / rows);
 }
 
-rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out) {
+rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int32_t* vcols_out) {
   if (rpca_status s = guard(c)) return s;
   if (rounds < 1) return fail(c, RPCA_EINVAL, "rounds must be >= 1");
-  const int32_t v0 = c->p.vsplit;
-  std::vector<int32_t> cand;
+  const int32_t v0 = c->p.vsplit, g0 = c->p.vcols;
+  // Candidates: (row splits, column groups per wave).
+  std::vector<std::pair<int32_t, int32_t>> cand;
   for (int64_t v : {(int64_t)(v0 + 1) / 2, (int64_t)v0, (int64_t)c->vsplit_max}) {
     if (v < 1 || v > c->vsplit_max) continue;
     set_vsplit(c, v);
-    if (std::find(cand.begin(), cand.end(), c->p.vsplit) == cand.end()) cand.push_back(c->p.vsplit);
+    for (int32_t g : {1, 4}) {
+      const std::pair<int32_t, int32_t> k{c->p.vsplit, g};
+      if (std::find(cand.begin(), cand.end(), k) == cand.end()) cand.push_back(k);
+    }
   }
   hipEvent_t a = nullptr, b = nullptr;
   RPCA_HIP(c, hipEventCreate(&a), "event");
@@ -599,11 +607,12 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out) {
     (void)hipEventDestroy(a);
     return dev_fail(c, eb, "event");
   }
-  int32_t best = v0;
+  std::pair<int32_t, int32_t> best{v0, g0};
   float best_ms = 0.f;
   rpca_status result = RPCA_OK;
-  for (int32_t v : cand) {
-    set_vsplit(c, v);
+  for (const auto& k : cand) {
+    set_vsplit(c, k.first);
+    c->p.vcols = k.second;
     // One untimed round in the new configuration, then the timed ones.
     if ((result = enqueue_round(c)) != RPCA_OK) break;
     hipError_t e = hipEventRecord(a, c->stream);
@@ -620,14 +629,17 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out) {
     }
     if (best_ms == 0.f || ms < best_ms) {
       best_ms = ms;
-      best = v;
+      best = k;
     }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  set_vsplit(c, result == RPCA_OK ? best : v0);
+  if (result != RPCA_OK) best = {v0, g0};
+  set_vsplit(c, best.first);
+  c->p.vcols = best.second;
   drop_graphs(c);
   if (vsplit_out) *vsplit_out = c->p.vsplit;
+  if (vcols_out) *vcols_out = c->p.vcols;
   return result;
 }
 

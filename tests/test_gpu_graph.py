@@ -41,9 +41,10 @@ def test_graph_replay_matches_eager():
 
 
 def test_autotune_keeps_parity():
-    """The V-pass row-split autotuner runs real rounds under several split
-    counts; the trajectory still matches the oracle's for the same number of
-    rounds, and the pick is one of the candidates."""
+    """The V-pass autotuner runs real rounds under several launch shapes (row
+    split counts, 1 or 4 column groups per wave); the trajectory still matches
+    the oracle's for the same number of rounds, and the pick is one of the
+    candidates."""
     import torch
 
     import oracle.reference as O
@@ -55,7 +56,8 @@ def test_autotune_keeps_parity():
     lam = default_lam(inst)
     s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 8, 0.1, lam, colmajor(U0), u_mode="closed")
     s.step(3)
-    v = s.autotune(3)
+    shape = s.autotune(3)
+    v, g = shape["row_splits"], shape["column_groups"]
     s.step(4)
     T = s.rounds
     L, S = s.get_LS(-1)
@@ -64,6 +66,7 @@ def test_autotune_keeps_parity():
     Sg = S[:, :inst.m].T.double().cpu().numpy()
     res = O.dcfpca(inst.blocks(), 8, 0.1, lam, T, U0)
     eL, eS = rel(Lg, res.L_full()), rel(Sg, res.S_full())
-    announce(f"autotune picked {v} row splits; {T} rounds; relL={eL:.3e} relS={eS:.3e}")
-    assert 1 <= v <= 64 and eL <= 1e-5 and eS <= 1e-5
+    announce(f"autotune picked {v} row splits, {g} column groups; {T} rounds; "
+             f"relL={eL:.3e} relS={eS:.3e}")
+    assert 1 <= v <= 64 and g in (1, 4) and eL <= 1e-5 and eS <= 1e-5
     s.close()
