@@ -219,6 +219,15 @@ rpca_status rpca_profile(rpca_ctx* c, int32_t rounds, double* avg_ms, int64_t* l
  * choice; the choice itself depends on timing. */
 rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int32_t* vcols_out);
 
+/* Copy the whole iterate of src into dst: factors, the S state, statistics,
+ * round count, precision, lambda and launch shape (not the borrowed M or the
+ * BF16 copies of it, which dst keeps). Both contexts must come from the same
+ * parameters (RPCA_EINVAL otherwise); they may borrow different M buffers
+ * of equal content. Synchronises src's stream, then enqueues the copy on
+ * dst's. For lookahead searches: branch a trajectory, try a choice, and
+ * compare. */
+rpca_status rpca_copy_state(rpca_ctx* dst, rpca_ctx* src);
+
 /* lambda of the rounds enqueued from now on (lambda >= 0, finite), for a
  * lambda schedule such as a continuation from a large value down to the
  * target. Every soft-threshold of round t uses its lambda_t, including the
@@ -234,6 +243,30 @@ rpca_status rpca_set_lambda(rpca_ctx* c, double lambda);
  * drops captured graphs. The next round's V-pass rebuilds S^(t) from the
  * previous factors in the new precision. */
 rpca_status rpca_set_precision(rpca_ctx* c, int32_t precision);
+
+/* A small MLP for round-by-round control (a learned lambda schedule):
+ * RPCA_MLP_IN = 8 inputs, two tanh layers of RPCA_MLP_HIDDEN = 64 units, and
+ * one output y = g_min + (1 - g_min) sigmoid(z) in [g_min, 1] with
+ * g_min = RPCA_MLP_GMIN (a per-round decay factor). Parameters are one FP32
+ * device array of rpca_mlp_param_count() floats, in this order: W1 (64 x 8,
+ * row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1).
+ * Not part of Algorithm 1; the library's own controller runs on it. */
+#define RPCA_MLP_IN 8
+#define RPCA_MLP_HIDDEN 64
+#define RPCA_MLP_GMIN 0.5f
+int64_t rpca_mlp_param_count(void);
+
+/* y[i] = MLP(x[i]) for n samples (x: n x 8 row-major, y: n; device
+ * pointers). Enqueued on `stream` (hipStream_t as void*, NULL = default). */
+rpca_status rpca_mlp_forward(const float* params, const float* x, int64_t n, float* y,
+                             void* stream);
+
+/* One step of gradient descent on the mean over n samples of
+ * 1/2 (MLP(x[i]) - target[i])^2: params -= lr * mean gradient, the samples'
+ * gradients summed in index order (bitwise reproducible). grad_ws: device
+ * scratch of n * rpca_mlp_param_count() floats. 1 <= n <= 65535. */
+rpca_status rpca_mlp_train_step(float* params, const float* x, const float* target, int64_t n,
+                                float lr, float* grad_ws, void* stream);
 
 /* Rounds enqueued so far. */
 int64_t rpca_rounds(const rpca_ctx* c);

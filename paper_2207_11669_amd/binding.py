@@ -91,6 +91,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rpca_autotune": (c_int32, [vp, c_int32, POINTER(c_int32), POINTER(c_int32)]),
         "rpca_set_precision": (c_int32, [vp, c_int32]),
         "rpca_set_lambda": (c_int32, [vp, c_double]),
+        "rpca_copy_state": (c_int32, [vp, vp]),
+        "rpca_mlp_param_count": (c_int64, []),
+        "rpca_mlp_forward": (c_int32, [vp, vp, c_int64, vp, vp]),
+        "rpca_mlp_train_step": (c_int32, [vp, vp, vp, c_int64, c_float, vp, vp]),
         "rpca_solve": (c_int32, [vp, c_int32, c_double, c_int32, POINTER(c_int32),
                                  POINTER(c_double)]),
         "rpca_set_target": (c_int32, [vp, vp, c_int64, vp, c_int64, c_int32]),
@@ -245,6 +249,10 @@ class DCFPCA:
                                             ctypes.byref(g)))
         return {"row_splits": int(v.value), "column_groups": int(g.value)}
 
+    def copy_state_from(self, other: "DCFPCA"):
+        """Take over other's whole iterate (same parameters; see rpca_copy_state)."""
+        self._check(self._lib.rpca_copy_state(self.ctx, other.ctx))
+
     def set_lambda(self, lam: float):
         """lambda of the following rounds (rebuilt-S form only)."""
         self._check(self._lib.rpca_set_lambda(self.ctx, float(lam)))
@@ -322,6 +330,36 @@ class DCFPCA:
             self.close()
         except Exception:
             pass
+
+
+def mlp_param_count() -> int:
+    return int(load_library().rpca_mlp_param_count())
+
+
+def mlp_forward(params, x, stream=None):
+    """MLP outputs for the rows of x ((n, 8) FP32 CUDA tensor); params: FP32
+    CUDA tensor of mlp_param_count() floats."""
+    import torch
+    n = int(x.shape[0])
+    y = torch.empty(n, dtype=torch.float32, device=x.device)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    s = load_library().rpca_mlp_forward(c_void_p(params.data_ptr()), c_void_p(x.data_ptr()), n,
+                                        c_void_p(y.data_ptr()), c_void_p(st.cuda_stream))
+    if s != RPCA_OK:
+        raise RpcaError(s, "rpca_mlp_forward failed")
+    return y
+
+
+def mlp_train_step(params, x, target, lr: float, grad_ws, stream=None):
+    """One gradient-descent step of params on the mean squared-error loss."""
+    import torch
+    n = int(x.shape[0])
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    s = load_library().rpca_mlp_train_step(c_void_p(params.data_ptr()), c_void_p(x.data_ptr()),
+                                           c_void_p(target.data_ptr()), n, float(lr),
+                                           c_void_p(grad_ws.data_ptr()), c_void_p(st.cuda_stream))
+    if s != RPCA_OK:
+        raise RpcaError(s, "rpca_mlp_train_step failed")
 
 
 def declared_functions(header: str = HEADER):

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "librpca.so")
-SOURCES = ["rpca_kernels.hip", "rpca_api.cpp"]
+SOURCES = ["rpca_kernels.hip", "rpca_api.cpp", "rpca_mlp.hip"]
 ARCH = "gfx950"
 
 

@@ -51,6 +51,13 @@ struct rpca_ctx {
   double* dpart = nullptr;
   double* dpart2 = nullptr;
   double* dout = nullptr;
+  // The workspace, and the byte ranges in it that belong to this context
+  // only (client tables holding its M pointers, the BF16 copies of its M);
+  // rpca_copy_state copies everything else.
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<std::pair<size_t, size_t>> own_ranges;
+  std::vector<int64_t> widths;
 };
 
 namespace {
@@ -379,6 +386,15 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   c->stream = reinterpret_cast<hipStream_t>(stream);
   c->inner = prm->inner;
   char* ws = static_cast<char*>(workspace);
+  c->ws = ws;
+  c->ws_bytes = L.total;
+  c->own_ranges = {{L.clients, (size_t)prm->E * sizeof(ClientDev)},
+                   {L.clients_lpt, (size_t)prm->E * sizeof(ClientDev)},
+                   {L.vg64, (size_t)L.ng64 * sizeof(VTile)},
+                   {L.Mbv, L.Mbs - L.Mbv},
+                   {L.Mbs, L.Wpart - L.Mbs}};
+  std::sort(c->own_ranges.begin(), c->own_ranges.end());
+  c->widths.assign(prm->n_cols, prm->n_cols + prm->E);
   DevParams& p = c->p;
   p.m = (int32_t)prm->m;
   p.MP = L.MP;
@@ -641,6 +657,44 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int3
   if (vsplit_out) *vsplit_out = c->p.vsplit;
   if (vcols_out) *vcols_out = c->p.vcols;
   return result;
+}
+
+rpca_status rpca_copy_state(rpca_ctx* dst, rpca_ctx* src) {
+  if (rpca_status s = guard(dst)) return s;
+  if (rpca_status s = guard(src)) return s;
+  if (dst == src) return RPCA_OK;
+  const DevParams &a = dst->p, &b = src->p;
+  if (dst->ws_bytes != src->ws_bytes || dst->widths != src->widths || a.m != b.m || a.r != b.r ||
+      a.K != b.K || a.u_mode != b.u_mode || a.bf16 != b.bf16 || a.eta_sched != b.eta_sched ||
+      a.rho != b.rho || a.eta0 != b.eta0 || dst->inner != src->inner ||
+      dst->recompute != src->recompute)
+    return fail(dst, RPCA_EINVAL, "rpca_copy_state needs contexts created with the same parameters");
+  RPCA_HIP(src, hipStreamSynchronize(src->stream), "synchronize");
+  size_t at = 0;
+  for (const auto& rg : dst->own_ranges) {
+    if (rg.first > at)
+      RPCA_HIP(dst, hipMemcpyAsync(dst->ws + at, src->ws + at, rg.first - at, hipMemcpyDeviceToDevice,
+                                   dst->stream), "copy state");
+    at = std::max(at, rg.first + rg.second);
+  }
+  if (dst->ws_bytes > at)
+    RPCA_HIP(dst, hipMemcpyAsync(dst->ws + at, src->ws + at, dst->ws_bytes - at,
+                                 hipMemcpyDeviceToDevice, dst->stream), "copy state");
+  dst->rounds = src->rounds;
+  dst->cur = src->cur;
+  dst->vcur = src->vcur;
+  dst->fin_pending = src->fin_pending;
+  dst->have_prev = src->have_prev;
+  dst->have_target = src->have_target;
+  dst->RPT = src->RPT;
+  dst->prec = src->prec;
+  dst->p.lam = src->p.lam;
+  dst->p.lam_rec = src->p.lam_rec;
+  dst->p.vsplit = src->p.vsplit;
+  dst->p.vsplit_rows = src->p.vsplit_rows;
+  dst->p.vcols = src->p.vcols;
+  drop_graphs(dst);
+  return RPCA_OK;
 }
 
 rpca_status rpca_set_lambda(rpca_ctx* c, double lambda) {

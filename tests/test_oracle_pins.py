@@ -410,3 +410,44 @@ def test_lambda_continuation_shortens_the_early_phase():
     plain = O.dcfpca(inst.blocks(), 5, 0.1, lam, 30, U0, record=False)
     assert O.relative_error(cont.L_full(), Ls) < 1e-2
     assert O.relative_error(plain.L_full(), Ls) > 0.5
+
+
+def _mlp_case(seed=0, n=12):
+    import oracle.controller as C
+    rng = np.random.default_rng(seed)
+    p = 0.3 * rng.standard_normal(C.N_PARAMS)
+    X = rng.standard_normal((n, C.N_IN))
+    T = rng.uniform(C.G_MIN, 1.0, n)
+    return C, p, X, T
+
+
+def test_mlp_gradient_matches_finite_differences():
+    """The chain-rule gradient of the controller MLP's mean loss agrees with
+    central differences of the loss in every parameter block."""
+    C, p, X, T = _mlp_case()
+    g = C.grad(p, X, T)
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([rng.choice(C.N_PARAMS - 1, 60, replace=False), [C.N_PARAMS - 1]])
+    h = 1e-6
+    for k in idx:
+        e = np.zeros_like(p)
+        e[k] = h
+        fd = (C.loss(p + e, X, T) - C.loss(p - e, X, T)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-7 + 1e-5 * abs(fd), (k, fd, g[k])
+
+
+def test_mlp_special_cases_and_descent():
+    """Zero weights give y = g_min + (1 - g_min) sigmoid(b3) for every input;
+    output stays in [g_min, 1]; small gradient steps decrease the loss."""
+    C, p, X, T = _mlp_case(seed=2)
+    z = np.zeros(C.N_PARAMS)
+    z[-1] = 0.7
+    y, _ = C.forward(z, X)
+    assert np.allclose(y, C.G_MIN + (1 - C.G_MIN) / (1 + math.exp(-0.7)), rtol=0, atol=1e-15)
+    y, _ = C.forward(p * 20, X)
+    assert np.all(y >= C.G_MIN) and np.all(y <= 1.0)
+    losses = [C.loss(p, X, T)]
+    for _ in range(20):
+        p = C.sgd_step(p, X, T, 0.5)
+        losses.append(C.loss(p, X, T))
+    assert all(b < a for a, b in zip(losses, losses[1:]))
