@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "DCF-PCA iters/sec + time-to-relerr 1e-4 (BF16/learned vs plain FP32), 1 GPU"
 WORKLOAD = "plain_4000x8000_r20"
 WORKLOADS = ("plain_4000x8000_r20", "uneven_10000_r32", "geom_20000x100000_r64",
-             "plain_500x500_r5")
+             "plain_8000x32000_r40", "plain_500x500_r5")
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFS = {"fp32": 157.3, "bf16": 2500.0}  # dense MFMA peaks of one MI355X
 def traffic_file(workload: str, precision: str = "fp32") -> str:
@@ -128,15 +128,17 @@ def continuation(lam: float, lam0: float, gamma: float = 0.8) -> list:
 
 
 def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_rounds,
-                   schedule=None) -> dict:
+                   schedule=None, ctl=None, lam0=None) -> dict:
     """Wall time from U^(0) until ||U V^T - X Y^T||_F / ||X Y^T||_F <= 1e-4 for
     the target factors (X, Y), checked every 10 rounds with r x r Gram
-    matrices (L is never formed) by rpca_solve. With a lambda schedule, its
-    rounds (rpca_set_lambda before each) run first and count."""
+    matrices (L is never formed) by rpca_solve. With a lambda schedule (a
+    list, or a controller deciding round by round from the recorded
+    statistics), its rounds run first and count."""
     import torch
     from paper_2207_11669_amd import DCFPCA
-    print("[bench] time to relative error 1e-4" + (" (lambda continuation)" if schedule else ""),
-          file=sys.stderr, flush=True)
+    from paper_2207_11669_amd import controller as C
+    print("[bench] time to relative error 1e-4" +
+          (" (lambda schedule)" if schedule or ctl else ""), file=sys.stderr, flush=True)
     s2 = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
                 eta0=eta0)
     s2.set_target(*target)
@@ -147,6 +149,8 @@ def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_r
         s2.set_lambda(lt)
         s2.step(1)
         pre += 1
+    if ctl is not None:
+        pre += C.run_controlled(s2, lam, lam0, ctl, float(inst.m) * inst.n)["control_rounds"]
     s2.set_lambda(lam)
     done, err = s2.solve(max_rounds - pre, 1e-4, check_every=10)
     torch.cuda.synchronize()
@@ -188,6 +192,40 @@ def bf16_comparison(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, roun
     return out
 
 
+def learned_controller(args, instances: int = 40, n: int = 256):
+    """Train the learned lambda controller on method-generated instances
+    (greedy per-round targets, MLP trained on the GPU); returns it with a
+    description of its training."""
+    import math as _m
+
+    import numpy as np
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    from paper_2207_11669_amd import controller as C
+    from rpca_inputs import controller_family, gaussian_init
+    print(f"[bench] training the learned controller on {instances} instances", file=sys.stderr,
+          flush=True)
+
+    def cases():
+        for k in range(instances):
+            inst, r = controller_family(10_000 + k, n)
+            lam = 1.0 / _m.sqrt(inst.n)
+
+            def make(inst=inst, r=r, lam=lam):
+                s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, r, 0.1, lam,
+                           colmajor(gaussian_init(inst.m, r, 7)))
+                s.set_target(colmajor(inst.Ustar), colmajor(inst.Vstar), r)
+                return s
+            yield make, lam, float(np.abs(inst.M).max()), float(inst.m * inst.n)
+
+    t0 = time.perf_counter()
+    params, (X, Y), losses = C.fit(cases())
+    info = {"kind": "learned (MLP 8-64-64-1, greedy per-round decay targets)",
+            "training_instances": instances, "training_size": f"{n}x{n}", "samples": int(len(Y)),
+            "train_seconds": round(time.perf_counter() - t0, 2),
+            "final_train_loss": round(losses[-1], 5)}
+    return C.LearnedContinuation(params), info
+
+
 def copy_calibration() -> int:
     import torch
     n = (256 << 20) // 4
@@ -219,7 +257,9 @@ def main() -> int:
                          "wave) with rpca_autotune; 0 keeps the default (ROUNDS timed rounds per "
                          "candidate)")
     ap.add_argument("--profile-rounds", type=int, default=50)
-    ap.add_argument("--relerr-rounds", type=int, default=3000)
+    ap.add_argument("--relerr-rounds", type=int, default=None,
+                    help="round budget of the time-to-relerr runs (default: 3000; 6000 for "
+                         "plain_8000x32000_r40)")
     ap.add_argument("--fixed-point-rounds", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-relerr", action="store_true")
@@ -301,7 +341,9 @@ def main() -> int:
                                             for k, v in prof.items()}})
 
     ttr = ttf = mixed = cont = None
-    if not args.no_relerr and not cfg.get("large"):
+    if args.relerr_rounds is None:
+        args.relerr_rounds = 6000 if workload == "plain_8000x32000_r40" else 3000
+    if not args.no_relerr and (not cfg.get("large") or cfg.get("recovery")):
         target = (colmajor(inst.Ustar, device=dev), colmajor(inst.Vstar, device=dev), cfg["rstar"])
         ttr = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target,
                              args.relerr_rounds)
@@ -325,13 +367,21 @@ def main() -> int:
         # same two targets, same fixed point (the schedule ends at lambda).
         lam0 = float(np.abs(inst.M).max())
         sched = continuation(lam, lam0)
-        cont = {"kind": "lambda continuation", "lambda0": lam0, "gamma": 0.8,
-                "schedule_rounds": len(sched),
-                "time_to_relerr": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
-                                                 target, args.relerr_rounds, sched),
-                "time_to_fixed_point": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args,
-                                                      eta0, (Uf, Vf, r),
-                                                      args.fixed_point_rounds, sched)}
+        cont = {"fixed": {"kind": "lambda continuation", "lambda0": lam0, "gamma": 0.8,
+                          "schedule_rounds": len(sched),
+                          "time_to_relerr": time_to_target(M_cols, inst, r, rho, lam, U0_cols,
+                                                           args, eta0, target, args.relerr_rounds,
+                                                           sched),
+                          "time_to_fixed_point": time_to_target(M_cols, inst, r, rho, lam,
+                                                                U0_cols, args, eta0, (Uf, Vf, r),
+                                                                args.fixed_point_rounds, sched)}}
+        ctl, info = learned_controller(args)
+        cont["learned"] = dict(info, **{
+            "time_to_relerr": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
+                                             target, args.relerr_rounds, ctl=ctl, lam0=lam0),
+            "time_to_fixed_point": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
+                                                  (Uf, Vf, r), args.fixed_point_rounds, ctl=ctl,
+                                                  lam0=lam0)})
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -179,15 +179,10 @@ def controller(args) -> dict:
 
     from paper_2207_11669_amd import DCFPCA, colmajor
     from paper_2207_11669_amd import controller as C
-    from rpca_inputs import equal_widths, gaussian_init, planted_instance, planted_instance_large
+    from rpca_inputs import controller_family, gaussian_init, recipe
 
     def family(seed):
-        rng = np.random.default_rng(seed)
-        n = args.train_n
-        r = int(rng.integers(4, 25))
-        s = float(rng.uniform(0.02, 0.2))
-        return planted_instance(n, equal_widths(n, 4), r, s, values="signed", lo=5.0, hi=20.0,
-                                seed=seed), r
+        return controller_family(seed, args.train_n)
 
     def session(inst, r, lam, target=True):
         s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, r, 0.1, lam,
@@ -217,10 +212,7 @@ def controller(args) -> dict:
         cases.append(("m=8000 n=32000 r=40 s=0.15 E=32", None))
     for name, seed in cases:
         if seed is None:
-            from rpca_inputs import equal_widths as ew
-            inst = planted_instance_large(8000, ew(32000, 32), 40, 0.15, values="signed",
-                                          lo=5.0, hi=20.0, seed=5)
-            r = 40
+            inst, r = recipe("plain_8000x32000_r40", seed=0), 40
         else:
             inst, r = family(seed)
         lam = 1.0 / math.sqrt(inst.n)

@@ -41,6 +41,7 @@ __all__ = [
     "gaussian_init",
     "recipe",
     "RECIPES",
+    "controller_family",
 ]
 
 # Stream identifiers for numpy SeedSequence spawning; fixed so that a change to
@@ -277,7 +278,26 @@ RECIPES = {
     "geom_20000x100000_r64": dict(m=20000, n=100000, E=50, rstar=64, s=0.05,
                                   values="signed", lo=1.0, hi=100.0, r=64, rho=0.1, T=100,
                                   spectrum="geometric", large=True),
+    # m = 8000, n = 32000, 32 clients of 1000 columns, rank 40, 15% of entries
+    # corrupted (Bernoulli) with magnitude U[5, 20], r = 40: the learned
+    # controller's evaluation instance. Relative error 1e-4 against L* is
+    # reachable here. M is 1 GB in FP32, built blockwise.
+    "plain_8000x32000_r40": dict(m=8000, n=32000, E=32, rstar=40, s=0.15, values="signed",
+                                 lo=5.0, hi=20.0, r=40, rho=0.1, T=200, large=True,
+                                 recovery=True),
 }
+
+
+def controller_family(seed: int, n: int = 256):
+    """A training instance for the learned lambda controller: m = n, four
+    equal clients, rank uniform in {4..24}, corruption fraction uniform in
+    [0.02, 0.2] with magnitude U[5, 20] and a random sign. Returns
+    (instance, rank)."""
+    rng = _rng(seed, _STREAM_WIDTHS + 1)
+    r = int(rng.integers(4, 25))
+    s = float(rng.uniform(0.02, 0.2))
+    return planted_instance(n, equal_widths(n, 4), r, s, values="signed", lo=5.0, hi=20.0,
+                            seed=seed), r
 
 
 def recipe(name: str, seed: int = 0, E: Optional[int] = None) -> Instance:
