@@ -29,7 +29,9 @@ WORKLOAD = "plain_4000x8000_r20"
 WORKLOADS = ("plain_4000x8000_r20", "uneven_10000_r32", "geom_20000x100000_r64",
              "plain_8000x32000_r40", "plain_500x500_r5")
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFS = {"fp32": 157.3, "bf16": 2500.0}  # dense MFMA peaks of one MI355X
+# Dense MFMA peaks of one MI355X, per algorithmic flop: three-product BF16
+# rounds run three BF16 products per product of the method.
+MFMA_PEAK_TFS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 3}
 def traffic_file(workload: str, precision: str = "fp32") -> str:
     suffix = "" if precision == "fp32" else f"_{precision}"
     return os.path.join(ROOT, "profiles", f"traffic_{workload}{suffix}.json")
@@ -128,7 +130,7 @@ def continuation(lam: float, lam0: float, gamma: float = 0.8) -> list:
 
 
 def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_rounds,
-                   schedule=None, ctl=None, lam0=None) -> dict:
+                   schedule=None, ctl=None, lam0=None, precision="fp32") -> dict:
     """Wall time from U^(0) until ||U V^T - X Y^T||_F / ||X Y^T||_F <= 1e-4 for
     the target factors (X, Y), checked every 10 rounds with r x r Gram
     matrices (L is never formed) by rpca_solve. With a lambda schedule (a
@@ -140,7 +142,7 @@ def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_r
     print("[bench] time to relative error 1e-4" +
           (" (lambda schedule)" if schedule or ctl else ""), file=sys.stderr, flush=True)
     s2 = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-                eta0=eta0)
+                eta0=eta0, bf16x3=precision == "bf16x3")
     s2.set_target(*target)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -162,33 +164,37 @@ def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_r
 
 
 def bf16_comparison(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, rounds) -> dict:
-    """The same workload with BF16 rounds (RPCA_FLAG_BF16): rounds/s, and the
-    relative error against the planted L* after `rounds` rounds next to the
-    FP32 rounds' error after as many rounds."""
+    """The same workload with BF16 rounds (RPCA_FLAG_BF16: BF16 copies of M,
+    one product each) and three-product BF16 rounds (RPCA_FLAG_BF16X3: FP32
+    M, hi/lo splits): rounds/s, and the relative error against the planted
+    L* after `rounds` rounds next to the FP32 rounds' error after as many."""
     import torch
     from paper_2207_11669_amd import DCFPCA
-    print("[bench] BF16 rounds", file=sys.stderr, flush=True)
-    out = {"precision": "bf16"}
-    s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-               eta0=eta0, bf16=True)
-    s.step(args.warmup)
-    if args.autotune > 0:
-        s.autotune(args.autotune)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["iters_per_s"] = round(args.steps / dt, 2)
-    out["avg_launch_us"] = {k: round(v[0] * 1e3, 2) for k, v in s.profile(20).items()}
-    s.close()
-    for name, bf in (("bf16", True), ("fp32", False)):
+    out = {}
+    for prec in ("bf16", "bf16x3", "fp32"):
+        print(f"[bench] {prec} rounds", file=sys.stderr, flush=True)
+        kw = {"bf16": dict(bf16=True), "bf16x3": dict(bf16x3=True), "fp32": {}}[prec]
+        d = {}
+        if prec != "fp32":
+            s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
+                       eta0=eta0, **kw)
+            s.step(args.warmup)
+            if args.autotune > 0:
+                s.autotune(args.autotune)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(args.steps)
+            torch.cuda.synchronize()
+            d["iters_per_s"] = round(args.steps / (time.perf_counter() - t0), 2)
+            d["avg_launch_us"] = {k: round(v[0] * 1e3, 2) for k, v in s.profile(20).items()}
+            s.close()
         s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-                   eta0=eta0, bf16=bf)
+                   eta0=eta0, **kw)
         s.set_target(*target)
         s.step(rounds)
-        out[f"relerr_after_{rounds}_rounds_{name}"] = s.target_error()
+        d[f"relerr_after_{rounds}_rounds"] = s.target_error()
         s.close()
+        out[prec] = d
     return out
 
 
@@ -247,9 +253,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--u-mode", default="closed", choices=["closed", "grad"])
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
-                    help="arithmetic of the timed rounds' streaming passes: fp32, or bf16 "
-                         "(RPCA_FLAG_BF16: BF16 copies of M, U, V on BF16 MFMA, FP32 accumulation)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x3"],
+                    help="arithmetic of the timed rounds' streaming passes: fp32; bf16 "
+                         "(RPCA_FLAG_BF16: BF16 copies of M, U, V on BF16 MFMA, FP32 accumulation); "
+                         "bf16x3 (RPCA_FLAG_BF16X3: FP32 M, hi/lo BF16 splits, three products)")
     ap.add_argument("--graph", action="store_true",
                     help="replay steady-state rounds from HIP graphs (RPCA_FLAG_GRAPH)")
     ap.add_argument("--autotune", type=int, default=10, metavar="ROUNDS",
@@ -293,9 +300,10 @@ def main() -> int:
     M_cols = colmajor(inst.M, device=dev)
     U0_cols = colmajor(U0, device=dev)
     eta0 = 0.0 if args.u_mode == "closed" else 1e-4
-    bf16 = args.precision == "bf16"
+    bf16 = args.precision != "fp32"
     s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-               eta0=eta0, graph=args.graph, bf16=bf16)
+               eta0=eta0, graph=args.graph, bf16=args.precision == "bf16",
+               bf16x3=args.precision == "bf16x3")
     torch.cuda.synchronize()
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
@@ -382,6 +390,14 @@ def main() -> int:
             "time_to_fixed_point": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
                                                   (Uf, Vf, r), args.fixed_point_rounds, ctl=ctl,
                                                   lam0=lam0)})
+        # The learned controller driving three-product BF16 rounds.
+        cont["learned_bf16x3"] = {
+            "time_to_relerr": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
+                                             target, args.relerr_rounds, ctl=ctl, lam0=lam0,
+                                             precision="bf16x3"),
+            "time_to_fixed_point": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
+                                                  (Uf, Vf, r), args.fixed_point_rounds, ctl=ctl,
+                                                  lam0=lam0, precision="bf16x3")}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -392,7 +408,7 @@ def main() -> int:
         "metric": METRIC, "value": round(value, 2), "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16" if bf16 else "f32",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3 (hi/lo splits, f32 M)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": workload, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
                    "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam,

@@ -104,11 +104,23 @@ typedef struct {
  * below that their Lambda is rounding noise and the iterates stall far from
  * the FP32 fixed point. */
 #define RPCA_FLAG_BF16 4u
+/* Three-product BF16 rounds (RPCA_PREC_BF16X3) without the BF16 copies of M:
+ * the factor kernels keep BF16 hi/lo splits of U and V (hi = BF16(x),
+ * lo = BF16(x - hi), 16 significand bits together), and each rank-r product
+ * runs as three BF16 MFMA products (hi.hi + hi.lo + lo.hi) with FP32
+ * accumulation, reading M in FP32 from the caller's blocks (4 B per entry,
+ * as FP32 rounds). The products are then accurate to about 2^-17 relative,
+ * far below lambda on every workload here, at a third of FP32 MFMA's work
+ * per product on the BF16 units. Needs K = 1, inner = 1, no
+ * RPCA_FLAG_STORE_S and every ldm < 2^24. RPCA_FLAG_BF16 also keeps the
+ * splits, so a context with it can run either BF16 precision. */
+#define RPCA_FLAG_BF16X3 8u
 
 /* Arithmetic of a round's streaming passes (rpca_set_precision). */
 typedef enum {
   RPCA_PREC_FP32 = 0,
-  RPCA_PREC_BF16 = 1  /* needs a context created with RPCA_FLAG_BF16 */
+  RPCA_PREC_BF16 = 1,   /* needs a context created with RPCA_FLAG_BF16 */
+  RPCA_PREC_BF16X3 = 2  /* needs RPCA_FLAG_BF16X3 or RPCA_FLAG_BF16 */
 } rpca_precision;
 
 /* Per-round statistics, FP64, recorded at the last local step of round t:
@@ -239,9 +251,11 @@ rpca_status rpca_copy_state(rpca_ctx* dst, rpca_ctx* src);
 rpca_status rpca_set_lambda(rpca_ctx* c, double lambda);
 
 /* Precision of the rounds enqueued from now on (rpca_precision). BF16 needs
- * a context created with RPCA_FLAG_BF16 (RPCA_EINVAL otherwise). Switching
- * drops captured graphs. The next round's V-pass rebuilds S^(t) from the
- * previous factors in the new precision. */
+ * a context created with RPCA_FLAG_BF16, BF16X3 one with RPCA_FLAG_BF16X3 or
+ * RPCA_FLAG_BF16 (RPCA_EINVAL otherwise). Switching drops captured graphs.
+ * The next round's V-pass rebuilds S^(t) from the previous factors in the
+ * new precision. A context created with RPCA_FLAG_BF16X3 only starts in
+ * BF16X3. */
 rpca_status rpca_set_precision(rpca_ctx* c, int32_t precision);
 
 /* A small MLP for round-by-round control (a learned lambda schedule):

@@ -29,6 +29,7 @@ struct rpca_ctx {
   bool use_graph = false;
   int32_t vsplit_max = 1;  // largest V-pass row-split count the workspace holds
   int32_t prec = RPCA_PREC_FP32;  // precision of the streaming passes
+  int64_t max_ldm = 0;            // largest leading dimension of the M blocks
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int cur = 0;   // consensus U buffer holding U^(t)
   int vcur = 0;  // V buffer holding the latest V
@@ -72,7 +73,7 @@ struct Layout {
       ucl, Ginv, dstate, hist, stat_part, clients, clients_lpt, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
       total;
   int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows, vsplit_max, RK;
-  bool recompute, bf16;
+  bool recompute, bf16, mcopy;
   int64_t lds, n, Sfloats;
 };
 
@@ -96,11 +97,11 @@ const char* check_params(const rpca_params* p) {
   if (p->u_mode == RPCA_U_GRAD && (!(p->eta0 > 0.0) || !std::isfinite(p->eta0)))
     return "eta0 must be finite and > 0 for RPCA_U_GRAD";
   if (p->eta_sched != RPCA_ETA_CONST && p->eta_sched != RPCA_ETA_SQRT) return "unknown eta_sched";
-  if (p->flags & ~(uint32_t)(RPCA_FLAG_STORE_S | RPCA_FLAG_GRAPH | RPCA_FLAG_BF16))
+  if (p->flags & ~(uint32_t)(RPCA_FLAG_STORE_S | RPCA_FLAG_GRAPH | RPCA_FLAG_BF16 | RPCA_FLAG_BF16X3))
     return "unknown flags";
-  if ((p->flags & RPCA_FLAG_BF16) &&
+  if ((p->flags & (RPCA_FLAG_BF16 | RPCA_FLAG_BF16X3)) &&
       (p->K != 1 || p->inner != 1 || (p->flags & RPCA_FLAG_STORE_S)))
-    return "RPCA_FLAG_BF16 needs K = 1, inner = 1 and no RPCA_FLAG_STORE_S";
+    return "RPCA_FLAG_BF16 and RPCA_FLAG_BF16X3 need K = 1, inner = 1 and no RPCA_FLAG_STORE_S";
   return nullptr;
 }
 
@@ -111,7 +112,8 @@ Layout make_layout(const rpca_params* p) {
   L.NS = (p->r + 3) / 4;
   L.lds = round_up(p->m, 4);
   L.RK = (int32_t)round_up(p->r, 32);
-  L.bf16 = (p->flags & RPCA_FLAG_BF16) != 0;
+  L.bf16 = (p->flags & (RPCA_FLAG_BF16 | RPCA_FLAG_BF16X3)) != 0;
+  L.mcopy = (p->flags & RPCA_FLAG_BF16) != 0;
   L.nrb = L.MP / kSRows;
   L.nub = L.MP / kURows;
   int64_t nvp = 0, ng = 0, ng64 = 0, n = 0;
@@ -154,16 +156,17 @@ Layout make_layout(const rpca_params* p) {
   };
   L.S = take((size_t)L.Sfloats * f);
   const size_t ub = (size_t)fb_floats(L.MP, L.RP, L.NS);
-  // BF16 packings follow the FP32 layouts of each U block and V buffer.
-  const size_t uh = L.bf16 ? (size_t)hb_elems(L.MP, L.RK, L.RP) / 2 : 0;
-  const size_t vh = L.bf16 ? (size_t)hb_elems(L.NVP, L.RK, L.RP) / 2 : 0;
+  // BF16 packings (hi, then lo) follow the FP32 layouts of each U block and V
+  // buffer.
+  const size_t uh = L.bf16 ? (size_t)hb_elems(L.MP, L.RK, L.RP) : 0;
+  const size_t vh = L.bf16 ? (size_t)hb_elems(L.NVP, L.RK, L.RP) : 0;
   L.U0 = take((ub + uh) * f);
   L.U1 = take((ub + uh) * f);
   L.Uc0 = take(multi ? (size_t)E * ub * f : 0);
   L.Uc1 = take(multi ? (size_t)E * ub * f : 0);
   L.V0 = take(((size_t)vbuf_floats(L.NVP, L.RP, L.NS) + vh) * f);
   L.V1 = take(((size_t)vbuf_floats(L.NVP, L.RP, L.NS) + vh) * f);
-  const size_t mh = L.bf16 ? (size_t)L.NVP * L.MP * sizeof(uint16_t) : 0;
+  const size_t mh = L.mcopy ? (size_t)L.NVP * L.MP * sizeof(uint16_t) : 0;
   L.Mbv = take(mh);
   L.Mbs = take(mh);
   L.Wpart = take((size_t)(L.vsplit_max + 1) * L.NVP * L.RP * f);
@@ -267,9 +270,10 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     const DevParams q = with_v(c, vn);
     double* fin = c->fin_pending ? c->Ginv : nullptr;
     c->fin_pending = false;
-    const bool h = c->prec == RPCA_PREC_BF16;
+    const bool h = c->prec != RPCA_PREC_FP32;
+    const int x3 = c->prec == RPCA_PREC_BF16X3 ? 1 : 0;
     RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
-                h ? launch_vpass_h(q, mode, Ucons, c->U[c->cur ^ 1], c->V[c->vcur], fin, st)
+                h ? launch_vpass_h(q, mode, Ucons, c->U[c->cur ^ 1], c->V[c->vcur], fin, x3, st)
                   : launch_vpass(q, mode, Ucons, 0, c->U[c->cur ^ 1], c->V[c->vcur], fin, st),
                 "V-pass launch");
     RPCA_LAUNCH(c, prof, RPCA_PHASE_VFINAL, launch_vfinal(q, c->Ginv, 0, fin ? 1 : 0, st),
@@ -277,7 +281,7 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     if (p.u_mode == RPCA_U_CLOSED)
       RPCA_LAUNCH(c, prof, RPCA_PHASE_CLIENT_FACTOR, launch_client_factor(q, st), "client factor launch");
     RPCA_LAUNCH(c, prof, RPCA_PHASE_SPASS,
-                h ? launch_spass_h(q, Ucons, st) : launch_spass(q, Ucons, 0, nullptr, 0, 0, 0, p.E, st),
+                h ? launch_spass_h(q, Ucons, x3, st) : launch_spass(q, Ucons, 0, nullptr, 0, 0, 0, p.E, st),
                 "S-pass launch");
     RPCA_LAUNCH(c, prof, RPCA_PHASE_UUPDATE, launch_uupdate(q, c->U[c->cur ^ 1], 0, Ucons, 1, st),
                 "U update launch");
@@ -382,6 +386,9 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
     return RPCA_EWORKSPACE;
 
   if ((prm->flags & RPCA_FLAG_GRAPH) && !stream) return RPCA_EINVAL;
+  if (prm->flags & RPCA_FLAG_BF16X3)
+    for (int i = 0; i < prm->E; ++i)
+      if (ldm[i] >= ((int64_t)1 << 24)) return RPCA_EINVAL;
   rpca_ctx* c = new rpca_ctx();
   c->stream = reinterpret_cast<hipStream_t>(stream);
   c->inner = prm->inner;
@@ -426,9 +433,10 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.bf16 = L.bf16 ? 1 : 0;
   p.RK = L.RK;
   p.NK = L.RK / 32;
-  p.Mbv = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.Mbv) : nullptr;
-  p.Mbs = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.Mbs) : nullptr;
-  c->prec = L.bf16 ? RPCA_PREC_BF16 : RPCA_PREC_FP32;
+  p.Mbv = L.mcopy ? reinterpret_cast<uint16_t*>(ws + L.Mbv) : nullptr;
+  p.Mbs = L.mcopy ? reinterpret_cast<uint16_t*>(ws + L.Mbs) : nullptr;
+  c->prec = L.mcopy ? RPCA_PREC_BF16 : L.bf16 ? RPCA_PREC_BF16X3 : RPCA_PREC_FP32;
+  for (int i = 0; i < prm->E; ++i) c->max_ldm = std::max(c->max_ldm, ldm[i]);
   p.clients = reinterpret_cast<const ClientDev*>(ws + L.clients);
   p.clients_lpt = reinterpret_cast<const ClientDev*>(ws + L.clients_lpt);
   p.vgroups = reinterpret_cast<const VGroup*>(ws + L.vgroups);
@@ -514,7 +522,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
     e = hipMemcpyAsync(ws + L.vg64, c->vg64.data(), c->vg64.size() * sizeof(VTile),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = launch_copy_in_U(p, U0, ldu, c->U[0], st);
-  if (e == hipSuccess && L.bf16) e = launch_m_to_bf16(p, st);
+  if (e == hipSuccess && L.mcopy) e = launch_m_to_bf16(p, st);
   if (e == hipSuccess) e = launch_gram_init(p, c->U[0], st);
   if (e == hipSuccess) e = launch_finalize(p, c->Ginv, 0, 0, 0, st);
   // The host tables must outlive the asynchronous copies above.
@@ -710,10 +718,15 @@ rpca_status rpca_set_lambda(rpca_ctx* c, double lambda) {
 
 rpca_status rpca_set_precision(rpca_ctx* c, int32_t precision) {
   if (rpca_status s = guard(c)) return s;
-  if (precision != RPCA_PREC_FP32 && precision != RPCA_PREC_BF16)
+  if (precision != RPCA_PREC_FP32 && precision != RPCA_PREC_BF16 && precision != RPCA_PREC_BF16X3)
     return fail(c, RPCA_EINVAL, "unknown precision");
-  if (precision == RPCA_PREC_BF16 && !c->p.bf16)
+  if (precision == RPCA_PREC_BF16 && !c->p.Mbv)
     return fail(c, RPCA_EINVAL, "BF16 rounds need a context created with RPCA_FLAG_BF16");
+  if (precision == RPCA_PREC_BF16X3 && !c->p.bf16)
+    return fail(c, RPCA_EINVAL,
+                "three-product BF16 rounds need RPCA_FLAG_BF16X3 or RPCA_FLAG_BF16");
+  if (precision == RPCA_PREC_BF16X3 && c->max_ldm >= ((int64_t)1 << 24))
+    return fail(c, RPCA_EINVAL, "three-product BF16 rounds need every ldm < 2^24");
   if (precision != c->prec) drop_graphs(c);
   c->prec = precision;
   return RPCA_OK;

@@ -67,7 +67,9 @@ __host__ __device__ inline const float* v_fb(const float* V, int64_t NVP, int RP
 //        eight consecutive rows 8 (l/16) + e)
 //   hB : 32-row chunk ch, rank tile ct: X[32 ch + 8 (l/16) + e][16 ct + l%16]
 // each as 64 lanes x 8 bf16 = 1 KiB per operand. Sizes in bf16 elements:
-// hA and hP rows * RK, hB rows * RP, in that order.
+// hA and hP rows * RK, hB rows * RP, in that order. Two such blocks follow
+// each other: hi = x rounded to BF16, then lo = (x - hi) rounded to BF16, so
+// that hi + lo carries 16 significand bits (three-product rounds, X3).
 __host__ __device__ inline int64_t hb_elems(int64_t rows, int RK, int RP) {
   return rows * (2 * (int64_t)RK + RP);
 }
@@ -167,7 +169,7 @@ struct DevParams {
   // Mixed precision (RPCA_FLAG_BF16): factor blocks carry the BF16 packings
   // after their FP32 layouts (U: at ublock floats; V: at vbuf_floats), and M
   // has two BF16 copies.
-  int32_t bf16;          // 1: keep the BF16 packings up to date
+  int32_t bf16;          // 1: keep the BF16 packings (hi and lo) up to date
   int32_t RK, NK;        // contraction-side ranks (32 NK) and blocks
   uint16_t* Mbv;         // BF16 M, V-pass layout
   uint16_t* Mbs;         // BF16 M, S-pass layout
@@ -240,9 +242,11 @@ hipError_t launch_m_to_bf16(const DevParams& p, hipStream_t st);
 // BF16 V-pass (streaming part) and S-pass; same outputs and work-group roles
 // as launch_vpass (mode kSZero or kSRecompute) and launch_spass (all clients,
 // no S output).
+// x3 = 1: M read in FP32 from the caller's blocks and every product formed
+// from hi/lo splits (three BF16 products).
 hipError_t launch_vpass_h(const DevParams& p, int mode, const float* U, const float* Uold,
-                          const float* Vold, double* fin_Ginv, hipStream_t st);
-hipError_t launch_spass_h(const DevParams& p, const float* U, hipStream_t st);
+                          const float* Vold, double* fin_Ginv, int x3, hipStream_t st);
+hipError_t launch_spass_h(const DevParams& p, const float* U, int x3, hipStream_t st);
 
 hipError_t launch_factor_distance(const DevParams& p, const float* X1, const float* Y1, int rp1,
                                   const float* X2, const float* Y2, int rp2, double* part,

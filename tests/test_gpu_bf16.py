@@ -144,3 +144,69 @@ def test_bf16_graph_replay_matches_eager():
         outs.append(_gpu_LS(s, inst.m))
         s.close()
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+# Three-product BF16 rounds (RPCA_FLAG_BF16X3): hi/lo splits carry 16
+# significand bits, and the dropped lo.lo term and the lo roundings leave a
+# relative error of about 2^-17 ~ 7.6e-6 per product; the bar is 2e-5 (the
+# FP32 bar's order, with room for the trajectory's amplification).
+X3_TOL = 2e-5
+
+
+def test_bf16x3_rounds_follow_oracle():
+    """100 three-product rounds on the 500 x 500 instance and 3 rounds of the
+    full 4000 x 8000, r = 20 workload (where plain BF16 rounds stall) stay
+    within 2e-5 of the FP64 trajectory."""
+    from gpu_helpers import run_gpu
+    for name, r, T in (("plain_500x500_r5", 5, 100), ("plain_4000x8000_r20", 20, 3)):
+        inst = recipe(name, seed=0)
+        U0 = init_for(inst, r, 7)
+        lam = default_lam(inst)
+        _, Lg, Sg, _ = run_gpu(inst, U0, r, 0.1, lam, T, bf16x3=True)
+        res = run_oracle(inst, U0, r, 0.1, lam, T)
+        eL, eS = rel(Lg, res.L_full()), rel(Sg, res.S_full())
+        announce(f"bf16x3 {name} T={T}: relL={eL:.3e} relS={eS:.3e}")
+        assert eL <= X3_TOL and eS <= X3_TOL
+
+
+@pytest.mark.parametrize("r,widths", [(20, [12, 90, 50]), (40, [30, 100, 70]), (64, [70, 90])])
+def test_bf16x3_ragged_and_rank_tiles(r, widths):
+    """Ragged m (row 300 is not a multiple of 32), narrow clients and every
+    rank-tile count; rho = 5 keeps n_i < r well conditioned."""
+    from gpu_helpers import run_gpu
+    inst = planted_instance(301, widths, 4, 0.05, values="uniform", hi=10.0, seed=23)
+    U0 = init_for(inst, r, 7)
+    res = run_oracle(inst, U0, r, 5.0, 0.1, 10)
+    _, Lh, Sh, _ = run_gpu(inst, U0, r, 5.0, 0.1, 10, bf16x3=True)
+    hL, hS = rel(Lh, res.L_full()), rel(Sh, res.S_full())
+    announce(f"bf16x3 r={r} widths={widths}: relL={hL:.3e} relS={hS:.3e}")
+    assert hL <= X3_TOL and hS <= X3_TOL
+
+
+def test_precision_rules_and_switching():
+    """A context made with RPCA_FLAG_BF16X3 alone starts in three-product
+    rounds, refuses plain BF16 (it holds no BF16 copy of M), and switches to
+    FP32 and back bitwise reproducibly; a context with RPCA_FLAG_BF16 can run
+    all three precisions."""
+    from paper_2207_11669_amd import RpcaError
+    inst = planted_instance(260, [90, 70, 110], 4, 0.05, values="uniform", hi=10.0, seed=5)
+    U0 = init_for(inst, 8, 3)
+    lam = default_lam(inst)
+    outs = []
+    for _ in range(2):
+        s = _session(inst, U0, 8, lam, bf16x3=True)
+        with pytest.raises(RpcaError):
+            s.set_precision("bf16")
+        s.step(5)
+        s.set_precision("fp32")
+        s.step(4)
+        s.set_precision("bf16x3")
+        s.step(3)
+        outs.append(_gpu_LS(s, inst.m))
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    s = _session(inst, U0, 8, lam, bf16=True)
+    for prec in ("bf16x3", "fp32", "bf16"):
+        s.set_precision(prec)
+        s.step(2)
+    s.close()
