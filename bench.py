@@ -259,10 +259,10 @@ def main() -> int:
                          "bf16x3 (RPCA_FLAG_BF16X3: FP32 M, hi/lo BF16 splits, three products)")
     ap.add_argument("--graph", action="store_true",
                     help="replay steady-state rounds from HIP graphs (RPCA_FLAG_GRAPH)")
-    ap.add_argument("--autotune", type=int, default=10, metavar="ROUNDS",
-                    help="before timing, pick the V-pass launch shape (row splits, column groups per "
-                         "wave) with rpca_autotune; 0 keeps the default (ROUNDS timed rounds per "
-                         "candidate)")
+    ap.add_argument("--autotune", type=int, default=30, metavar="ROUNDS",
+                    help="before timing, pick the launch shapes (V-pass row splits and column "
+                         "groups per wave, FP32 S-pass column phases) with rpca_autotune; 0 keeps "
+                         "the defaults (ROUNDS timed rounds per candidate)")
     ap.add_argument("--profile-rounds", type=int, default=50)
     ap.add_argument("--relerr-rounds", type=int, default=None,
                     help="round budget of the time-to-relerr runs (default: 3000; 6000 for "
@@ -413,7 +413,7 @@ def main() -> int:
         "config": {"workload": workload, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
                    "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam,
                    "rho": rho, "K": 1, "inner": 1, "u_mode": args.u_mode,
-                   "graph": bool(args.graph), "autotuned_vpass_shape": shape,
+                   "graph": bool(args.graph), "autotuned_launch_shape": shape,
                    "precision": args.precision},
         "roofline": roofline,
         "time_to_relerr": ttr,

@@ -88,7 +88,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rpca_init": (c_int32, [POINTER(vp), POINTER(RpcaParams), POINTER(vp), POINTER(c_int64),
                                 vp, c_int64, vp, c_size_t, vp]),
         "rpca_step": (c_int32, [vp, c_int32]),
-        "rpca_autotune": (c_int32, [vp, c_int32, POINTER(c_int32), POINTER(c_int32)]),
+        "rpca_autotune": (c_int32, [vp, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                    POINTER(c_int32)]),
+        "rpca_set_launch_shape": (c_int32, [vp, c_int32, c_int32, c_int32]),
         "rpca_set_precision": (c_int32, [vp, c_int32]),
         "rpca_set_lambda": (c_int32, [vp, c_double]),
         "rpca_copy_state": (c_int32, [vp, vp]),
@@ -244,12 +246,20 @@ class DCFPCA:
         self._check(self._lib.rpca_step(self.ctx, int(rounds)))
 
     def autotune(self, rounds: int = 10) -> dict:
-        """Pick the V-pass launch shape by timing real rounds; returns it as
-        {"row_splits": ..., "column_groups": ...}."""
-        v, g = c_int32(0), c_int32(0)
+        """Pick the launch shapes of the V-pass and the FP32 S-pass by timing
+        real rounds; returns them as
+        {"row_splits": ..., "column_groups": ..., "spass_phases": ...}."""
+        v, g, ph = c_int32(0), c_int32(0), c_int32(0)
         self._check(self._lib.rpca_autotune(self.ctx, int(rounds), ctypes.byref(v),
-                                            ctypes.byref(g)))
-        return {"row_splits": int(v.value), "column_groups": int(g.value)}
+                                            ctypes.byref(g), ctypes.byref(ph)))
+        return {"row_splits": int(v.value), "column_groups": int(g.value),
+                "spass_phases": int(ph.value)}
+
+    def set_launch_shape(self, row_splits: int = 0, column_groups: int = 0,
+                         spass_phases: int = 0):
+        """Fix the launch shapes (see rpca_set_launch_shape; 0 keeps a value)."""
+        self._check(self._lib.rpca_set_launch_shape(self.ctx, int(row_splits), int(column_groups),
+                                                    int(spass_phases)))
 
     def copy_state_from(self, other: "DCFPCA"):
         """Take over other's whole iterate (same parameters; see rpca_copy_state)."""

@@ -423,6 +423,9 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   // loads than its M (the rebuild's NS packed rank steps); the autotuner
   // revisits this.
   p.vcols = L.NS > 5 ? 4 : 1;
+  // S-pass work-groups of 8 waves, two per 32-row strip taking alternate
+  // column chunks; the autotuner also tries one wave per strip.
+  p.sphases = 2;
   c->vsplit_max = L.vsplit_max;
   p.u_mode = prm->u_mode;
   p.eta_sched = prm->eta_sched;
@@ -610,20 +613,22 @@ static void set_vsplit(rpca_ctx* c, int64_t vs) {
   c->p.vsplit = (int32_t)((m + rows - 1) / rows);
 }
 
-rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int32_t* vcols_out) {
+rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int32_t* vcols_out,
+                          int32_t* sphases_out) {
   if (rpca_status s = guard(c)) return s;
   if (rounds < 1) return fail(c, RPCA_EINVAL, "rounds must be >= 1");
-  const int32_t v0 = c->p.vsplit, g0 = c->p.vcols;
-  // Candidates: (row splits, column groups per wave).
-  std::vector<std::pair<int32_t, int32_t>> cand;
-  for (int64_t v : {(int64_t)(v0 + 1) / 2, (int64_t)v0, (int64_t)c->vsplit_max}) {
-    if (v < 1 || v > c->vsplit_max) continue;
-    set_vsplit(c, v);
-    for (int32_t g : {1, 4}) {
-      const std::pair<int32_t, int32_t> k{c->p.vsplit, g};
-      if (std::find(cand.begin(), cand.end(), k) == cand.end()) cand.push_back(k);
+  struct Shape {
+    int32_t vsplit, vcols, sphases;
+    bool operator==(const Shape& o) const {
+      return vsplit == o.vsplit && vcols == o.vcols && sphases == o.sphases;
     }
-  }
+  };
+  const Shape start{c->p.vsplit, c->p.vcols, c->p.sphases};
+  auto apply = [&](const Shape& k) {
+    set_vsplit(c, k.vsplit);
+    c->p.vcols = k.vcols;
+    c->p.sphases = k.sphases;
+  };
   hipEvent_t a = nullptr, b = nullptr;
   RPCA_HIP(c, hipEventCreate(&a), "event");
   const hipError_t eb = hipEventCreate(&b);
@@ -631,40 +636,84 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int3
     (void)hipEventDestroy(a);
     return dev_fail(c, eb, "event");
   }
-  std::pair<int32_t, int32_t> best{v0, g0};
-  float best_ms = 0.f;
   rpca_status result = RPCA_OK;
-  for (const auto& k : cand) {
-    set_vsplit(c, k.first);
-    c->p.vcols = k.second;
-    // One untimed round in the new configuration, then the timed ones.
-    if ((result = enqueue_round(c)) != RPCA_OK) break;
+  // Milliseconds of `rounds` rounds at shape k, after one untimed round; < 0
+  // on failure (result set).
+  auto time_shape = [&](const Shape& k) -> float {
+    apply(k);
+    if ((result = enqueue_round(c)) != RPCA_OK) return -1.f;
     hipError_t e = hipEventRecord(a, c->stream);
     for (int32_t t = 0; t < rounds && e == hipSuccess && result == RPCA_OK; ++t)
       result = enqueue_round(c);
-    if (result != RPCA_OK) break;
+    if (result != RPCA_OK) return -1.f;
     if (e == hipSuccess) e = hipEventRecord(b, c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
     if (e != hipSuccess) {
       result = dev_fail(c, e, "autotune timing");
-      break;
+      return -1.f;
     }
-    if (best_ms == 0.f || ms < best_ms) {
+    return ms;
+  };
+  // Stage 1, the V-pass: (row splits, column groups per wave) at the current
+  // S-pass phases.
+  std::vector<Shape> cand;
+  for (int64_t v : {(int64_t)(start.vsplit + 1) / 2, (int64_t)start.vsplit, (int64_t)c->vsplit_max}) {
+    if (v < 1 || v > c->vsplit_max) continue;
+    set_vsplit(c, v);
+    for (int32_t g : {1, 4}) {
+      const Shape k{c->p.vsplit, g, start.sphases};
+      if (std::find(cand.begin(), cand.end(), k) == cand.end()) cand.push_back(k);
+    }
+  }
+  Shape best = start;
+  float best_ms = -1.f;
+  for (const Shape& k : cand) {
+    const float ms = time_shape(k);
+    if (ms < 0.f) break;
+    if (best_ms < 0.f || ms < best_ms) {
       best_ms = ms;
       best = k;
     }
   }
+  // Stage 2, the FP32 S-pass: both column-phase counts at the chosen V-pass
+  // shape, timed alternately twice each (the gap is a few percent of a
+  // round; BF16 rounds run their own S-pass).
+  if (result == RPCA_OK && c->prec == RPCA_PREC_FP32) {
+    const Shape ks[2] = {best, {best.vsplit, best.vcols, best.sphases == 1 ? 2 : 1}};
+    float tot[2] = {0.f, 0.f};
+    for (int rep = 0; rep < 4 && result == RPCA_OK; ++rep) {
+      const float ms = time_shape(ks[rep & 1]);
+      if (ms >= 0.f) tot[rep & 1] += ms;
+    }
+    if (result == RPCA_OK && tot[1] < tot[0]) best = ks[1];
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  if (result != RPCA_OK) best = {v0, g0};
-  set_vsplit(c, best.first);
-  c->p.vcols = best.second;
+  if (result != RPCA_OK) best = start;
+  apply(best);
   drop_graphs(c);
   if (vsplit_out) *vsplit_out = c->p.vsplit;
   if (vcols_out) *vcols_out = c->p.vcols;
+  if (sphases_out) *sphases_out = c->p.sphases;
   return result;
+}
+
+rpca_status rpca_set_launch_shape(rpca_ctx* c, int32_t vsplit, int32_t vcols, int32_t sphases) {
+  if (rpca_status s = guard(c)) return s;
+  if (vsplit < 0 || vsplit > c->vsplit_max)
+    return fail(c, RPCA_EINVAL, "row splits must lie in [1, " + std::to_string(c->vsplit_max) +
+                                    "] (0 keeps the current count)");
+  if (vcols != 0 && vcols != 1 && vcols != 4)
+    return fail(c, RPCA_EINVAL, "column groups per V-pass wave must be 1 or 4 (0 keeps)");
+  if (sphases != 0 && sphases != 1 && sphases != 2)
+    return fail(c, RPCA_EINVAL, "S-pass column phases must be 1 or 2 (0 keeps)");
+  if (vsplit) set_vsplit(c, vsplit);
+  if (vcols) c->p.vcols = vcols;
+  if (sphases) c->p.sphases = sphases;
+  drop_graphs(c);
+  return RPCA_OK;
 }
 
 rpca_status rpca_copy_state(rpca_ctx* dst, rpca_ctx* src) {
@@ -701,6 +750,7 @@ rpca_status rpca_copy_state(rpca_ctx* dst, rpca_ctx* src) {
   dst->p.vsplit = src->p.vsplit;
   dst->p.vsplit_rows = src->p.vsplit_rows;
   dst->p.vcols = src->p.vcols;
+  dst->p.sphases = src->p.sphases;
   drop_graphs(dst);
   return RPCA_OK;
 }

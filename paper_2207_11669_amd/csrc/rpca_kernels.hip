@@ -108,12 +108,16 @@ __device__ __forceinline__ double recip_pos(double x) {
 // blockDim.x >= r * r): the k-th pivot is a diagonal entry of a Schur
 // complement of an SPD matrix, hence positive, and every step updates all r^2
 // entries in parallel (no serial triangular solves). Each thread owns up to
-// EPT entries, indexed once. A pivot that is not positive (non-SPD or NaN
-// input) turns the result into NaN, which the round statistics then expose.
+// EPT entries, indexed once, and is the only one to touch them during the
+// sweep; the only values a step needs from other threads are the pivot's row
+// and column, which the threads owning row and column k + 1 publish during
+// step k into a second pair of LDS vectors (double-buffered by step parity),
+// so each step costs one barrier. A pivot that is not positive (non-SPD or
+// NaN input) turns the result into NaN, which the round statistics then
+// expose.
 template <int EPT>
 __device__ void spd_inverse(double* A, int r, int ld) {
-  __shared__ double colk[kMaxRank], rowk[kMaxRank];
-  __shared__ double pinv_sh;
+  __shared__ double rowb[2][kMaxRank], colb[2][kMaxRank];
   const int tid = threadIdx.x, nt = blockDim.x;
   int ei[EPT], ej[EPT];
 #pragma unroll
@@ -122,29 +126,29 @@ __device__ void spd_inverse(double* A, int r, int ld) {
     ei[q] = e < r * r ? e / r : -1;
     ej[q] = e < r * r ? e % r : -1;
   }
+  if (tid < r) {
+    rowb[0][tid] = A[tid];
+    colb[0][tid] = A[tid * ld];
+  }
+  __syncthreads();
   for (int k = 0; k < r; ++k) {
-    if (tid < r) {
-      colk[tid] = A[tid * ld + k];
-      rowk[tid] = A[k * ld + tid];
-    }
-    if (tid == 0) {
-      const double pv = A[k * ld + k];
-      pinv_sh = pv > 0.0 ? recip_pos(pv) : NAN;
-    }
-    __syncthreads();
-    const double pinv = pinv_sh;
+    const int cur = k & 1, nxt = cur ^ 1;
+    const double pv = rowb[cur][k];
+    const double pinv = pv > 0.0 ? recip_pos(pv) : NAN;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int i = ei[q], j = ej[q];
       if (i >= 0) {
         double v;
         if (i == k)
-          v = (j == k) ? pinv : rowk[j] * pinv;
+          v = (j == k) ? pinv : rowb[cur][j] * pinv;
         else if (j == k)
-          v = -colk[i] * pinv;
+          v = -colb[cur][i] * pinv;
         else
-          v = A[i * ld + j] - colk[i] * rowk[j] * pinv;
+          v = A[i * ld + j] - colb[cur][i] * rowb[cur][j] * pinv;
         A[i * ld + j] = v;
+        if (i == k + 1) rowb[nxt][j] = v;
+        if (j == k + 1) colb[nxt][i] = v;
       }
     }
     __syncthreads();
@@ -688,13 +692,13 @@ __device__ __forceinline__ void spass_stats(const DevParams& p, int ci, int b, d
   }
 }
 
-// S-pass epilogue of the FP32 form (512 threads): the client's U-step term for the work-group's 128 rows from P = Lambda V_i and
+// S-pass epilogue of the FP32 form (NW waves): the client's U-step term for the work-group's 128 rows from P = Lambda V_i and
 // U_i staged in LDS (Lemma 2 proof for the gradient, argmin_U L_i for the
 // closed form):
 //   GRAD   T = U_i - eta (c_i U_i - P)
 //   CLOSED T = P A_i + U_i B_i,  A_i = (V_i^T V_i + c_i I)^{-1}, B_i = V_i^T V_i A_i
 // in FP64, stored FP32 into the client's slot of p.P; then the statistics.
-template <int RP>
+template <int RP, int NW>
 __device__ __forceinline__ void spass_terms_and_stats(const DevParams& p, const ClientDev& cl, int b,
                                                       const float (*ptile)[RP + 1],
                                                       const float (*utile)[RP + 1],
@@ -732,12 +736,14 @@ __device__ __forceinline__ void spass_terms_and_stats(const DevParams& p, const 
       Ti[(int64_t)(c0 + j) * p.MP + row0 + rl] = c0 + j < p.r ? (float)t[j] : 0.f;
   }
 
-  spass_stats<8>(p, ci, b, sl2, sl1, nnz);
+  spass_stats<NW>(p, ci, b, sl2, sl1, nnz);
 }
 
 // ---------------------------------------------------------------------------
-// S-pass: one work-group per (128-row block, client); each of the 4 waves owns
-// 32 rows (two 16-row tiles) and sweeps the client's columns 16 at a time.
+// S-pass: one work-group per (128-row block, client); each of its 4 row waves
+// owns 32 rows (two 16-row tiles) and sweeps the client's columns 16 at a time,
+// alone (NPH = 1, 256 threads) or with a partner wave taking alternate column
+// chunks (NPH = 2, 512 threads).
 // MFMA 1 forms (U V^T)^T for a 16x16 tile with V as the A operand and U^T as
 // the B operand, so lane l ends up with row l%16 and columns 4*(l/16)+v.
 // That is exactly the A-operand layout of MFMA 2 (P += Lambda V, contraction
@@ -747,8 +753,8 @@ __device__ __forceinline__ void spass_terms_and_stats(const DevParams& p, const 
 // The contraction index of MFMA 1 is split as k-group g = l/16 taking rank
 // indices g*NS + s, s < NS = ceil(r/4), so no padding steps run for r % 16.
 // ---------------------------------------------------------------------------
-template <int RT, int NS, bool STORE>
-__global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restrict__ Ubase,
+template <int RT, int NS, bool STORE, int NPH>
+__global__ __launch_bounds__(256 * NPH) void k_spass(DevParams p, const float* __restrict__ Ubase,
                                                int64_t u_stride, float* __restrict__ Sout,
                                                int64_t lds_out, int emit_only, int client_base) {
   constexpr int RP = 16 * RT;
@@ -763,9 +769,10 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
   const int ci = cl.idx;
   const float* __restrict__ U = Ubase + (int64_t)ci * u_stride;
   const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) & 3;
+  // NPH column phases of four waves each, phase q taking chunks q, q + NPH, ...
   // Wave-uniform (waves 0-3: phase 0, waves 4-7: phase 1); readfirstlane tells
   // the compiler so, which keeps the chunk addressing in scalar registers.
-  const int phase = __builtin_amdgcn_readfirstlane(tid >> 8);
+  const int phase = NPH == 2 ? __builtin_amdgcn_readfirstlane(tid >> 8) : 0;
   const int li = lane & 15, lg = lane >> 4;
   const int arow0 = b * kSRows + w * 32;
 
@@ -795,14 +802,14 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
   __shared__ float utile[kSRows][RP + 1];
   __shared__ double fab[2][RP * RP];
   const bool closed = p.u_mode != 0;
-  constexpr int kFabPer = (RP * RP + 511) / 512;
+  constexpr int kFabPer = (RP * RP + 256 * NPH - 1) / (256 * NPH);
   double fa[kFabPer], fbv[kFabPer];
   if (!emit_only && closed) {
     const double* __restrict__ Af = p.Afac + (int64_t)ci * RP * RP;
     const double* __restrict__ Bf = p.Bfac + (int64_t)ci * RP * RP;
 #pragma unroll
     for (int q = 0; q < kFabPer; ++q) {
-      const int e = tid + q * 512;
+      const int e = tid + q * 256 * NPH;
       fa[q] = e < RP * RP ? Af[e] : 0.0;
       fbv[q] = e < RP * RP ? Bf[e] : 0.0;
     }
@@ -835,7 +842,7 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
   // Operands of one 16-column chunk; a ring of kSDepth chunks is kept in
   // flight so that each wave has several chunks of M loads outstanding (vector
   // loads complete in order, so everything a chunk needs is issued together).
-  // The two halves of the work-group (phase 0, 1) take alternate chunks; their
+  // With two phases the halves of the work-group take alternate chunks; their
   // partial P are summed in LDS at the end.
   struct Chunk {
     float m[2][4];   // M[row][col] for this lane's rows (two 16-row tiles) and 4 columns
@@ -846,9 +853,9 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
   constexpr int kSDepth = 3;
   Chunk ring[kSDepth];
   const int nch = (cl.n + 15) >> 4;
-  const int nk = (nch - phase + 1) >> 1;  // chunks phase, phase + 2, ... below nch
+  const int nk = (nch - phase + NPH - 1) / NPH;  // chunks phase, phase + NPH, ... below nch
   auto load_chunk = [&](Chunk& c, int k) {
-    const int j0 = (phase + 2 * k) << 4;
+    const int j0 = (phase + NPH * k) << 4;
     const uint32_t vch = (uint32_t)((cl.vrow0 + j0) >> 4);
 #pragma unroll
     for (int s = 0; s < NS; ++s) c.va[s] = bload(rVa, (uint32_t)lane * 4u, ((vch * NS + s) * 64u) * 4u);
@@ -863,7 +870,7 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
       for (int v = 0; v < 4; ++v) c.m[rt][v] = bload(rM, vm[rt][v], 0);
   };
   auto compute_chunk = [&](const Chunk& c, int k) {
-    const int j0 = (phase + 2 * k) << 4;
+    const int j0 = (phase + NPH * k) << 4;
     float l2 = 0.f, l1 = 0.f;
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
@@ -911,7 +918,7 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
     if (!emit_only && closed) {
 #pragma unroll
       for (int q = 0; q < kFabPer; ++q) {
-        const int e = tid + q * 512;
+        const int e = tid + q * 256 * NPH;
         if (e < RP * RP) {
           fab[0][e] = fa[q];
           fab[1][e] = fbv[q];
@@ -937,7 +944,7 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
     // share of A_i and B_i.
 #pragma unroll
     for (int q = 0; q < kFabPer; ++q) {
-      const int e = tid + q * 512;
+      const int e = tid + q * 256 * NPH;
       if (e < RP * RP) {
         fab[0][e] = fa[q];
         fab[1][e] = fbv[q];
@@ -977,14 +984,15 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
 #pragma unroll
       for (int s = 0; s < NS; ++s) utile[w * 32 + 16 * rt + li][lg * NS + s] = ub[rt][s];
     }
-  } else {
+  }
+  if (phase == NPH - 1) {
     for (int c = 4 * NS + lg; c < RP; c += 4) {
       utile[w * 32 + li][c] = 0.f;
       utile[w * 32 + 16 + li][c] = 0.f;
     }
   }
   __syncthreads();
-  if (phase == 1) {
+  if (NPH == 2 && phase == 1) {
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
 #pragma unroll
@@ -999,7 +1007,7 @@ __global__ __launch_bounds__(512) void k_spass(DevParams p, const float* __restr
     }
   }
   __syncthreads();
-  spass_terms_and_stats<RP>(p, cl, b, ptile, utile, fab, closed, sl2, sl1, nnz);
+  spass_terms_and_stats<RP, 4 * NPH>(p, cl, b, ptile, utile, fab, closed, sl2, sl1, nnz);
 }
 
 // Partial Gram of kURows rows held in LDS (FP64, row stride kMaxRank).
@@ -1428,12 +1436,24 @@ template <int RT, int NS>
 static hipError_t launch_spass_t(const DevParams& p, const float* U, int64_t u_stride, float* Sout,
                                  int64_t lds_out, int emit_only, int client_base,
                                  int client_count, hipStream_t st) {
-  if (Sout)
-    hipLaunchKernelGGL((k_spass<RT, NS, true>), dim3(p.nrb, client_count), dim3(512), 0, st, p, U,
-                       u_stride, Sout, lds_out, emit_only, client_base);
-  else
-    hipLaunchKernelGGL((k_spass<RT, NS, false>), dim3(p.nrb, client_count), dim3(512), 0, st, p, U,
-                       u_stride, Sout, lds_out, emit_only, client_base);
+  // Stored-S rounds and the rebuilt-S ones take the same column phases, so
+  // both sum P in the same order.
+  const dim3 grid(p.nrb, client_count);
+  if (p.sphases == 1) {
+    if (Sout)
+      hipLaunchKernelGGL((k_spass<RT, NS, true, 1>), grid, dim3(256), 0, st, p, U, u_stride, Sout,
+                         lds_out, emit_only, client_base);
+    else
+      hipLaunchKernelGGL((k_spass<RT, NS, false, 1>), grid, dim3(256), 0, st, p, U, u_stride, Sout,
+                         lds_out, emit_only, client_base);
+  } else {
+    if (Sout)
+      hipLaunchKernelGGL((k_spass<RT, NS, true, 2>), grid, dim3(512), 0, st, p, U, u_stride, Sout,
+                         lds_out, emit_only, client_base);
+    else
+      hipLaunchKernelGGL((k_spass<RT, NS, false, 2>), grid, dim3(512), 0, st, p, U, u_stride, Sout,
+                         lds_out, emit_only, client_base);
+  }
   return hipGetLastError();
 }
 

@@ -16,13 +16,16 @@ def announce(msg: str):
     sys.stdout.flush()
 
 
-def run_gpu(inst: Instance, U0: np.ndarray, r: int, rho: float, lam: float, T: int, **kw):
+def run_gpu(inst: Instance, U0: np.ndarray, r: int, rho: float, lam: float, T: int,
+            shape: dict | None = None, **kw):
     import torch
 
     from paper_2207_11669_amd import DCFPCA, colmajor
     M_cols = colmajor(inst.M)
     U0_cols = colmajor(U0)
     s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, **kw)
+    if shape:
+        s.set_launch_shape(**shape)
     s.step(T)
     L, S = s.get_LS(-1)
     torch.cuda.synchronize()
@@ -57,13 +60,14 @@ TOL = 1e-5
 
 
 def parity(inst: Instance, r: int, T: int, seed: int = 7, rho: float = 0.1, lam=None,
-           tol: float = TOL, **kw):
+           tol: float = TOL, shape: dict | None = None, **kw):
     """Run both paths for T rounds and require relative Frobenius differences
-    <= tol on L and on S."""
+    <= tol on L and on S (shape: launch shapes of the HIP path)."""
     lam = default_lam(inst) if lam is None else lam
     U0 = init_for(inst, r, seed)
-    announce(f"m={inst.m} widths={inst.widths[:8]}{'...' if inst.E > 8 else ''} r={r} T={T} {kw}")
-    s, Lg, Sg, hist = run_gpu(inst, U0, r, rho, lam, T, **kw)
+    announce(f"m={inst.m} widths={inst.widths[:8]}{'...' if inst.E > 8 else ''} r={r} T={T} "
+             f"{kw} shape={shape}")
+    s, Lg, Sg, hist = run_gpu(inst, U0, r, rho, lam, T, shape=shape, **kw)
     res = run_oracle(inst, U0, r, rho, lam, T, **kw)
     eL = rel(Lg, res.L_full())
     eS = rel(Sg, res.S_full())
