@@ -261,8 +261,8 @@ def main() -> int:
                     help="replay steady-state rounds from HIP graphs (RPCA_FLAG_GRAPH)")
     ap.add_argument("--autotune", type=int, default=30, metavar="ROUNDS",
                     help="before timing, pick the launch shapes (V-pass row splits and column "
-                         "groups per wave, FP32 S-pass column phases) with rpca_autotune; 0 keeps "
-                         "the defaults (ROUNDS timed rounds per candidate)")
+                         "groups per wave, FP32 S-pass column phases) with "
+                         "rpca_autotune; 0 keeps the defaults (ROUNDS timed rounds per candidate)")
     ap.add_argument("--profile-rounds", type=int, default=50)
     ap.add_argument("--relerr-rounds", type=int, default=None,
                     help="round budget of the time-to-relerr runs (default: 3000; 6000 for "
@@ -335,13 +335,21 @@ def main() -> int:
     dom = max(("vpass", "spass"), key=lambda k: total[k])
     avg_s = prof[dom][0] / 1e3
     roofline = roofline_of(costs[dom], avg_s, args.precision)
+    # The launch shape selects the kernel instance of an FP32 pass: counters
+    # are kept per instance ("spass:phases=2", "vpass:column_groups=1", ...).
+    shape_now = s.launch_shape()
+    variant = dom
+    if args.precision == "fp32":
+        variant += (f":phases={shape_now['spass_phases']}" if dom == "spass"
+                    else f":column_groups={shape_now['column_groups']}")
     traffic = None
     if os.path.exists(traffic_file(workload, args.precision)):
         with open(traffic_file(workload, args.precision)) as f:
             tr = json.load(f)
-        if tr.get("kernel_source_sha256_16") == src_hash() and dom in tr.get("bytes_per_launch", {}):
-            traffic = tr["bytes_per_launch"][dom]
-    roofline.update({"traffic": traffic, "kernel": dom,
+        per = tr.get("bytes_per_launch", {})
+        if tr.get("kernel_source_sha256_16") == src_hash():
+            traffic = per.get(variant, per.get(dom))
+    roofline.update({"traffic": traffic, "kernel": variant,
                      "algorithmic_bytes": costs[dom]["bytes"],
                      "algorithmic_flops": costs[dom]["flops"],
                      "avg_launch_us": {k: round(v[0] * 1e3, 2) for k, v in prof.items()},

@@ -217,33 +217,41 @@ typedef enum {
  * launches (launches[RPCA_NUM_PHASES]). The rounds count as real rounds. */
 rpca_status rpca_profile(rpca_ctx* c, int32_t rounds, double* avg_ms, int64_t* launches);
 
-/* Autotuner for the launch shapes of the two streaming passes. First the
- * V-pass: the split of the row dimension (the split-K of
- * W = (M_i - S_i)^T U over m) and the 16-column groups each FP32 V-pass wave
- * takes (1: waves on distinct columns share U operands through the cache; 4:
- * a wave takes all 64 columns of its tile and shares them in registers, the
- * waves splitting the rows), with candidates the default split count, half
- * of it and twice it (within what the workspace holds), each with 1 and 4
- * column groups. Then, when the rounds run in FP32, the S-pass column phases
- * at the chosen V-pass shape: 2 (work-groups of 8 waves, two per 32-row strip
- * taking alternate 16-column chunks, their partial P = Lambda V_i summed at
- * the end) or 1 (4 waves, each sweeping all chunks of its strip), each timed
- * twice, alternately. Every timing runs `rounds` timed rounds (plus one
- * untimed); the fastest candidate is kept and returned in *vsplit_out, *vcols_out and *sphases_out (all
- * optional). Synchronises. The rounds are real rounds of the method. The
- * shapes change only the summation orders of W and P, so results stay within
- * FP32 rounding of the default and are deterministic for a given choice; the
- * choice itself depends on timing. */
-rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int32_t* vcols_out,
-                          int32_t* sphases_out);
+/* Launch shapes of the streaming passes. None changes what a round
+ * computes beyond the summation orders of W = (M_i - S_i)^T U and
+ * P = Lambda V_i: results stay within FP32 rounding of one another and are
+ * deterministic for a given shape. */
+typedef struct rpca_launch_shape {
+  /* V-pass row splits (the split-K of W over m): 1 .. twice the default
+   * count; rounded so that each split holds a multiple of 16 rows (32 in
+   * contexts that may run BF16 rounds), so the count in effect can be lower */
+  int32_t vsplit;
+  /* 16-column groups per FP32 V-pass wave: 1 (waves on distinct columns share
+   * U operands through the cache) or 4 (a wave takes all 64 columns of its
+   * tile, the waves splitting the rows) */
+  int32_t vcols;
+  /* FP32 S-pass column phases: 2 (work-groups of 8 waves, two per 32-row
+   * strip taking alternate 16-column chunks, their partial P summed at the
+   * end) or 1 (4 waves, one per strip) */
+  int32_t sphases;
+} rpca_launch_shape;
 
-/* Set the launch shapes the autotuner chooses among, for reproducible runs:
- * V-pass row splits (1 .. the workspace's maximum, twice the default count;
- * rounded so that each split holds a multiple of 16 rows, 32 in contexts that
- * may run BF16 rounds, so the count in effect can be lower), column groups per
- * FP32 V-pass wave (1 or 4) and FP32 S-pass column phases (1 or 2). A 0 keeps
- * the current value; anything else is RPCA_EINVAL. Drops captured graphs. */
-rpca_status rpca_set_launch_shape(rpca_ctx* c, int32_t vsplit, int32_t vcols, int32_t sphases);
+/* Autotuner for the launch shapes. First the V-pass: candidates are the
+ * default row-split count, half of it and twice it (within what the workspace
+ * holds), each with 1 and 4 column groups, at the current S-pass shape. Then,
+ * when the rounds run in FP32, the S-pass at the chosen V-pass shape: two
+ * column phases and one, timed in turn twice each. Every timing runs `rounds` timed rounds (plus one
+ * untimed); the fastest candidate is kept and returned in *out (optional).
+ * Synchronises. The rounds are real rounds of the method; the choice depends
+ * on timing. */
+rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out);
+
+/* The launch shapes in effect. */
+rpca_status rpca_get_launch_shape(rpca_ctx* c, rpca_launch_shape* out);
+
+/* Set the launch shapes (for reproducible runs); every field must be valid
+ * (RPCA_EINVAL otherwise, shapes unchanged). Drops captured graphs. */
+rpca_status rpca_set_launch_shape(rpca_ctx* c, const rpca_launch_shape* shape);
 
 /* Copy the whole iterate of src into dst: factors, the S state, statistics,
  * round count, precision, lambda and launch shape (not the borrowed M or the

@@ -59,6 +59,14 @@ class RpcaStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class RpcaLaunchShape(ctypes.Structure):
+    _fields_ = [("vsplit", c_int32), ("vcols", c_int32), ("sphases", c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"row_splits": int(self.vsplit), "column_groups": int(self.vcols),
+                "spass_phases": int(self.sphases)}
+
+
 class RpcaError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"rpca status {status}: {msg}")
@@ -88,9 +96,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rpca_init": (c_int32, [POINTER(vp), POINTER(RpcaParams), POINTER(vp), POINTER(c_int64),
                                 vp, c_int64, vp, c_size_t, vp]),
         "rpca_step": (c_int32, [vp, c_int32]),
-        "rpca_autotune": (c_int32, [vp, c_int32, POINTER(c_int32), POINTER(c_int32),
-                                    POINTER(c_int32)]),
-        "rpca_set_launch_shape": (c_int32, [vp, c_int32, c_int32, c_int32]),
+        "rpca_autotune": (c_int32, [vp, c_int32, POINTER(RpcaLaunchShape)]),
+        "rpca_get_launch_shape": (c_int32, [vp, POINTER(RpcaLaunchShape)]),
+        "rpca_set_launch_shape": (c_int32, [vp, POINTER(RpcaLaunchShape)]),
         "rpca_set_precision": (c_int32, [vp, c_int32]),
         "rpca_set_lambda": (c_int32, [vp, c_double]),
         "rpca_copy_state": (c_int32, [vp, vp]),
@@ -247,19 +255,26 @@ class DCFPCA:
 
     def autotune(self, rounds: int = 10) -> dict:
         """Pick the launch shapes of the V-pass and the FP32 S-pass by timing
-        real rounds; returns them as
-        {"row_splits": ..., "column_groups": ..., "spass_phases": ...}."""
-        v, g, ph = c_int32(0), c_int32(0), c_int32(0)
-        self._check(self._lib.rpca_autotune(self.ctx, int(rounds), ctypes.byref(v),
-                                            ctypes.byref(g), ctypes.byref(ph)))
-        return {"row_splits": int(v.value), "column_groups": int(g.value),
-                "spass_phases": int(ph.value)}
+        real rounds; returns them as {"row_splits", "column_groups",
+        "spass_phases"}."""
+        k = RpcaLaunchShape()
+        self._check(self._lib.rpca_autotune(self.ctx, int(rounds), ctypes.byref(k)))
+        return k.as_dict()
 
-    def set_launch_shape(self, row_splits: int = 0, column_groups: int = 0,
-                         spass_phases: int = 0):
-        """Fix the launch shapes (see rpca_set_launch_shape; 0 keeps a value)."""
-        self._check(self._lib.rpca_set_launch_shape(self.ctx, int(row_splits), int(column_groups),
-                                                    int(spass_phases)))
+    def launch_shape(self) -> dict:
+        k = RpcaLaunchShape()
+        self._check(self._lib.rpca_get_launch_shape(self.ctx, ctypes.byref(k)))
+        return k.as_dict()
+
+    def set_launch_shape(self, row_splits: int | None = None, column_groups: int | None = None,
+                         spass_phases: int | None = None):
+        """Fix the launch shapes (rpca_set_launch_shape); None keeps a value."""
+        cur = self.launch_shape()
+        k = RpcaLaunchShape(
+            cur["row_splits"] if row_splits is None else int(row_splits),
+            cur["column_groups"] if column_groups is None else int(column_groups),
+            cur["spass_phases"] if spass_phases is None else int(spass_phases))
+        self._check(self._lib.rpca_set_launch_shape(self.ctx, ctypes.byref(k)))
 
     def copy_state_from(self, other: "DCFPCA"):
         """Take over other's whole iterate (same parameters; see rpca_copy_state)."""

@@ -613,22 +613,24 @@ static void set_vsplit(rpca_ctx* c, int64_t vs) {
   c->p.vsplit = (int32_t)((m + rows - 1) / rows);
 }
 
-rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int32_t* vcols_out,
-                          int32_t* sphases_out) {
+static rpca_launch_shape shape_of(const rpca_ctx* c) {
+  return rpca_launch_shape{c->p.vsplit, c->p.vcols, c->p.sphases};
+}
+
+static void apply_shape(rpca_ctx* c, const rpca_launch_shape& k) {
+  set_vsplit(c, k.vsplit);
+  c->p.vcols = k.vcols;
+  c->p.sphases = k.sphases;
+}
+
+static bool same_shape(const rpca_launch_shape& a, const rpca_launch_shape& b) {
+  return a.vsplit == b.vsplit && a.vcols == b.vcols && a.sphases == b.sphases;
+}
+
+rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
   if (rpca_status s = guard(c)) return s;
   if (rounds < 1) return fail(c, RPCA_EINVAL, "rounds must be >= 1");
-  struct Shape {
-    int32_t vsplit, vcols, sphases;
-    bool operator==(const Shape& o) const {
-      return vsplit == o.vsplit && vcols == o.vcols && sphases == o.sphases;
-    }
-  };
-  const Shape start{c->p.vsplit, c->p.vcols, c->p.sphases};
-  auto apply = [&](const Shape& k) {
-    set_vsplit(c, k.vsplit);
-    c->p.vcols = k.vcols;
-    c->p.sphases = k.sphases;
-  };
+  const rpca_launch_shape start = shape_of(c);
   hipEvent_t a = nullptr, b = nullptr;
   RPCA_HIP(c, hipEventCreate(&a), "event");
   const hipError_t eb = hipEventCreate(&b);
@@ -639,8 +641,8 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int3
   rpca_status result = RPCA_OK;
   // Milliseconds of `rounds` rounds at shape k, after one untimed round; < 0
   // on failure (result set).
-  auto time_shape = [&](const Shape& k) -> float {
-    apply(k);
+  auto time_shape = [&](const rpca_launch_shape& k) -> float {
+    apply_shape(c, k);
     if ((result = enqueue_round(c)) != RPCA_OK) return -1.f;
     hipError_t e = hipEventRecord(a, c->stream);
     for (int32_t t = 0; t < rounds && e == hipSuccess && result == RPCA_OK; ++t)
@@ -657,19 +659,20 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int3
     return ms;
   };
   // Stage 1, the V-pass: (row splits, column groups per wave) at the current
-  // S-pass phases.
-  std::vector<Shape> cand;
+  // S-pass shape.
+  std::vector<rpca_launch_shape> cand;
   for (int64_t v : {(int64_t)(start.vsplit + 1) / 2, (int64_t)start.vsplit, (int64_t)c->vsplit_max}) {
     if (v < 1 || v > c->vsplit_max) continue;
     set_vsplit(c, v);
     for (int32_t g : {1, 4}) {
-      const Shape k{c->p.vsplit, g, start.sphases};
-      if (std::find(cand.begin(), cand.end(), k) == cand.end()) cand.push_back(k);
+      const rpca_launch_shape k{c->p.vsplit, g, start.sphases};
+      if (std::none_of(cand.begin(), cand.end(), [&](const rpca_launch_shape& x) { return same_shape(x, k); }))
+        cand.push_back(k);
     }
   }
-  Shape best = start;
+  rpca_launch_shape best = start;
   float best_ms = -1.f;
-  for (const Shape& k : cand) {
+  for (const rpca_launch_shape& k : cand) {
     const float ms = time_shape(k);
     if (ms < 0.f) break;
     if (best_ms < 0.f || ms < best_ms) {
@@ -677,41 +680,47 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, int32_t* vsplit_out, int3
       best = k;
     }
   }
-  // Stage 2, the FP32 S-pass: both column-phase counts at the chosen V-pass
-  // shape, timed alternately twice each (the gap is a few percent of a
-  // round; BF16 rounds run their own S-pass).
+  // Stage 2, the FP32 S-pass at the chosen V-pass shape: two column phases
+  // and one, timed in turn twice each (the gap is a few percent of a round;
+  // BF16 rounds run their own S-pass).
   if (result == RPCA_OK && c->prec == RPCA_PREC_FP32) {
-    const Shape ks[2] = {best, {best.vsplit, best.vcols, best.sphases == 1 ? 2 : 1}};
-    float tot[2] = {0.f, 0.f};
-    for (int rep = 0; rep < 4 && result == RPCA_OK; ++rep) {
-      const float ms = time_shape(ks[rep & 1]);
-      if (ms >= 0.f) tot[rep & 1] += ms;
-    }
-    if (result == RPCA_OK && tot[1] < tot[0]) best = ks[1];
+    const std::vector<rpca_launch_shape> ks = {{best.vsplit, best.vcols, 2},
+                                               {best.vsplit, best.vcols, 1}};
+    std::vector<float> tot(ks.size(), 0.f);
+    for (int rep = 0; rep < 2 && result == RPCA_OK; ++rep)
+      for (size_t q = 0; q < ks.size() && result == RPCA_OK; ++q) {
+        const float ms = time_shape(ks[q]);
+        if (ms >= 0.f) tot[q] += ms;
+      }
+    if (result == RPCA_OK)
+      best = ks[std::min_element(tot.begin(), tot.end()) - tot.begin()];
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (result != RPCA_OK) best = start;
-  apply(best);
+  apply_shape(c, best);
   drop_graphs(c);
-  if (vsplit_out) *vsplit_out = c->p.vsplit;
-  if (vcols_out) *vcols_out = c->p.vcols;
-  if (sphases_out) *sphases_out = c->p.sphases;
+  if (out) *out = shape_of(c);
   return result;
 }
 
-rpca_status rpca_set_launch_shape(rpca_ctx* c, int32_t vsplit, int32_t vcols, int32_t sphases) {
+rpca_status rpca_get_launch_shape(rpca_ctx* c, rpca_launch_shape* out) {
   if (rpca_status s = guard(c)) return s;
-  if (vsplit < 0 || vsplit > c->vsplit_max)
-    return fail(c, RPCA_EINVAL, "row splits must lie in [1, " + std::to_string(c->vsplit_max) +
-                                    "] (0 keeps the current count)");
-  if (vcols != 0 && vcols != 1 && vcols != 4)
-    return fail(c, RPCA_EINVAL, "column groups per V-pass wave must be 1 or 4 (0 keeps)");
-  if (sphases != 0 && sphases != 1 && sphases != 2)
-    return fail(c, RPCA_EINVAL, "S-pass column phases must be 1 or 2 (0 keeps)");
-  if (vsplit) set_vsplit(c, vsplit);
-  if (vcols) c->p.vcols = vcols;
-  if (sphases) c->p.sphases = sphases;
+  if (!out) return fail(c, RPCA_EINVAL, "out is NULL");
+  *out = shape_of(c);
+  return RPCA_OK;
+}
+
+rpca_status rpca_set_launch_shape(rpca_ctx* c, const rpca_launch_shape* k) {
+  if (rpca_status s = guard(c)) return s;
+  if (!k) return fail(c, RPCA_EINVAL, "shape is NULL");
+  if (k->vsplit < 1 || k->vsplit > c->vsplit_max)
+    return fail(c, RPCA_EINVAL, "row splits must lie in [1, " + std::to_string(c->vsplit_max) + "]");
+  if (k->vcols != 1 && k->vcols != 4)
+    return fail(c, RPCA_EINVAL, "column groups per V-pass wave must be 1 or 4");
+  if (k->sphases != 1 && k->sphases != 2)
+    return fail(c, RPCA_EINVAL, "S-pass column phases must be 1 or 2");
+  apply_shape(c, *k);
   drop_graphs(c);
   return RPCA_OK;
 }

@@ -66,22 +66,29 @@ def test_autotune_keeps_parity():
     Sg = S[:, :inst.m].T.double().cpu().numpy()
     res = O.dcfpca(inst.blocks(), 8, 0.1, lam, T, U0)
     eL, eS = rel(Lg, res.L_full()), rel(Sg, res.S_full())
-    announce(f"autotune picked {v} row splits, {g} column groups, {ph} S-pass phases; {T} rounds; "
+    announce(f"autotune picked {v} row splits, {g} column groups, {ph} S-pass phases; "
+             f"{T} rounds; "
              f"relL={eL:.3e} relS={eS:.3e}")
-    assert 1 <= v <= 64 and g in (1, 4) and ph in (1, 2) and eL <= 1e-5 and eS <= 1e-5
+    assert 1 <= v <= 64 and g in (1, 4) and ph in (1, 2) and s.launch_shape() == shape
+    assert eL <= 1e-5 and eS <= 1e-5
     s.close()
 
 
-@pytest.mark.parametrize("ph", [1, 2])
+SHAPES = {"two_phases": {"spass_phases": 2}, "one_phase": {"spass_phases": 1}}
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
 @pytest.mark.parametrize("r,widths", [(5, [100, 16, 9, 77, 300]), (20, [40, 21, 130, 64]),
-                                      (36, [36, 90, 200]), (64, [64, 150, 80])])
-def test_spass_phases_parity(ph, r, widths):
+                                      (32, [600, 40, 1100]), (36, [36, 90, 200]),
+                                      (64, [64, 150, 80])])
+def test_spass_shapes_parity(name, r, widths):
     """Both S-pass column-phase counts match the oracle on every rank-tile
     count, with clients of one 16-column chunk or less (a phase with no chunk
-    when there are two) and ragged chunk tails."""
+    when there are two), ragged chunk tails, and clients of more than 16
+    V-finish groups (client factors summed over several blocks of groups)."""
     inst = planted_instance(333, widths, min(r, 12), 0.05, values="uniform", hi=10.0,
                             seed=40 + r)
-    parity(inst, r, 25, u_mode="closed", shape={"spass_phases": ph})
+    parity(inst, r, 25, u_mode="closed", shape=SHAPES[name])
 
 
 def test_spass_one_phase_grad_and_stored_S():
@@ -107,11 +114,14 @@ def test_set_launch_shape_rejects_bad_values():
     inst = planted_instance(200, [60, 70], 3, 0.05, values="uniform", hi=10.0, seed=2)
     s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 3, 0.1, default_lam(inst),
                colmajor(init_for(inst, 3, 1)), u_mode="closed")
+    before = s.launch_shape()
     for kw, frag in ((dict(row_splits=-1), "row splits"), (dict(row_splits=1000), "row splits"),
                      (dict(column_groups=2), "column groups"), (dict(spass_phases=3), "phases")):
         with pytest.raises(RpcaError, match=frag):
             s.set_launch_shape(**kw)
+        assert s.launch_shape() == before
     s.set_launch_shape(row_splits=1, column_groups=4, spass_phases=1)
+    assert s.launch_shape() == {"row_splits": 1, "column_groups": 4, "spass_phases": 1}
     s.step(2)
     assert np.isfinite(s.stats()["objective"])
     s.close()
