@@ -1010,18 +1010,42 @@ __global__ __launch_bounds__(256 * NPH) void k_spass(DevParams p, const float* _
   spass_terms_and_stats<RP, 4 * NPH>(p, cl, b, ptile, utile, fab, closed, sl2, sl1, nnz);
 }
 
-// Partial Gram of kURows rows held in LDS (FP64, row stride kMaxRank).
-__device__ void gram_rows_partial(const double* ul, int RP, double* out) {
-  for (int e = threadIdx.x; e < RP * RP; e += blockDim.x) {
-    const int a = e / RP, b = e % RP;
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < kURows; j += 2) {
-      s0 += ul[j * kMaxRank + a] * ul[j * kMaxRank + b];
-      s1 += ul[(j + 1) * kMaxRank + a] * ul[(j + 1) * kMaxRank + b];
+// Partial Gram of kURows rows held in LDS (FP64, row stride kMaxRank), by a
+// 256-thread work-group: thread (ta, tb) = (tid / 16, tid % 16) forms the
+// RT x RT block of entries (RT ta + x, RT tb + y), so each LDS read feeds RT
+// FMAs. Every entry is summed as two chains, even rows and odd rows, each in
+// row order, then added.
+template <int RT>
+__device__ void gram_rows_partial(const double* ul, double* out) {
+  constexpr int RP = 16 * RT;
+  const int a0 = RT * (threadIdx.x >> 4), b0 = RT * (threadIdx.x & 15);
+  double s0[RT][RT], s1[RT][RT];
+#pragma unroll
+  for (int x = 0; x < RT; ++x)
+#pragma unroll
+    for (int y = 0; y < RT; ++y) s0[x][y] = s1[x][y] = 0.0;
+#pragma unroll 4
+  for (int j = 0; j < kURows; j += 2) {
+    double va0[RT], vb0[RT], va1[RT], vb1[RT];
+#pragma unroll
+    for (int x = 0; x < RT; ++x) {
+      va0[x] = ul[j * kMaxRank + a0 + x];
+      vb0[x] = ul[j * kMaxRank + b0 + x];
+      va1[x] = ul[(j + 1) * kMaxRank + a0 + x];
+      vb1[x] = ul[(j + 1) * kMaxRank + b0 + x];
     }
-    out[e] = s0 + s1;
+#pragma unroll
+    for (int x = 0; x < RT; ++x)
+#pragma unroll
+      for (int y = 0; y < RT; ++y) {
+        s0[x][y] += va0[x] * vb0[y];
+        s1[x][y] += va1[x] * vb1[y];
+      }
   }
+#pragma unroll
+  for (int x = 0; x < RT; ++x)
+#pragma unroll
+    for (int y = 0; y < RT; ++y) out[(a0 + x) * RP + b0 + y] = s0[x][y] + s1[x][y];
 }
 
 // ---------------------------------------------------------------------------
@@ -1091,7 +1115,7 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
   if ((tid & 63) == 0) dred[tid >> 6] = dsq;
   __syncthreads();
   const int slot = final_step ? 0 : (int)blockIdx.y;
-  gram_rows_partial(ul, RP, p.gram_part + ((int64_t)slot * p.nub + blockIdx.x) * RP * RP);
+  gram_rows_partial<RT>(ul, p.gram_part + ((int64_t)slot * p.nub + blockIdx.x) * RP * RP);
   if (final_step && tid == 0) p.upart[blockIdx.x] = dred[0] + dred[1] + dred[2] + dred[3];
 }
 
@@ -1104,7 +1128,13 @@ __global__ __launch_bounds__(256) void k_gram_init(DevParams p, const float* __r
     ul[al * kMaxRank + c] = (double)U[(int64_t)c * p.MP + blockIdx.x * kURows + al];
   }
   __syncthreads();
-  gram_rows_partial(ul, RP, p.gram_part + (int64_t)blockIdx.x * RP * RP);
+  double* out = p.gram_part + (int64_t)blockIdx.x * RP * RP;
+  switch (RP / 16) {
+    case 1: gram_rows_partial<1>(ul, out); break;
+    case 2: gram_rows_partial<2>(ul, out); break;
+    case 3: gram_rows_partial<3>(ul, out); break;
+    default: gram_rows_partial<4>(ul, out); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
