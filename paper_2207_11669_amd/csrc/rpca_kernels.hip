@@ -353,7 +353,9 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
     f4 uq[NQ > 0 ? NQ : 1];   // quads: U[row][rank RP - 16 + 4 q + l%4] for the 4 rows
     float uo[NS];             // previous U, A operand of the S rebuild: Uo[row l%16][rank g*NS + s]
   };
-  constexpr int kVDepth = RT <= 2 ? 3 : 2;
+  // Two chunks in flight per wave: deeper rings measured slower at r = 20
+  // (more outstanding loads per compute unit, no better latency cover).
+  constexpr int kVDepth = 2;
   Chunk ring[kVDepth];
   auto load_chunk = [&](Chunk& c, int k) {
     const int row0 = rbeg + ((ph + kPh * k) << 4);
@@ -840,8 +842,10 @@ __global__ __launch_bounds__(256 * NPH) void k_spass(DevParams p, const float* _
     }
 
   // Operands of one 16-column chunk; a ring of kSDepth chunks is kept in
-  // flight so that each wave has several chunks of M loads outstanding (vector
-  // loads complete in order, so everything a chunk needs is issued together).
+  // flight so that each wave has the next chunk's M loads outstanding while it
+  // computes (vector loads complete in order, so everything a chunk needs is
+  // issued together). Two measured faster than three, four or five at r = 20
+  // and r = 40 (39 against 41, 49 and 52 us at 4000 x 8000, r = 20).
   // With two phases the halves of the work-group take alternate chunks; their
   // partial P are summed in LDS at the end.
   struct Chunk {
@@ -850,7 +854,7 @@ __global__ __launch_bounds__(256 * NPH) void k_spass(DevParams p, const float* _
     f4 vb[RTF > 0 ? RTF : 1];  // MFMA 2 B operand (V B-packing): V[col j0 + 4*(l/16) + e][rank 16*ct + l%16]
     f4 vq[NQ > 0 ? NQ : 1];    // quads: V[col j0 + 4*(l/16) + e][rank RP - 16 + 4 q + l%4]
   };
-  constexpr int kSDepth = 3;
+  constexpr int kSDepth = 2;
   Chunk ring[kSDepth];
   const int nch = (cl.n + 15) >> 4;
   const int nk = (nch - phase + NPH - 1) / NPH;  // chunks phase, phase + NPH, ... below nch
