@@ -240,7 +240,8 @@ typedef struct rpca_launch_shape {
  * default row-split count, half of it and twice it (within what the workspace
  * holds), each with 1 and 4 column groups, at the current S-pass shape. Then,
  * when the rounds run in FP32, the S-pass at the chosen V-pass shape: two
- * column phases and one, timed in turn twice each. Every timing runs `rounds` timed rounds (plus one
+ * column phases and one. Each stage times its candidates in turn, twice over,
+ * and compares the sums. Every timing runs `rounds` timed rounds (plus one
  * untimed); the fastest candidate is kept and returned in *out (optional).
  * Synchronises. The rounds are real rounds of the method; the choice depends
  * on timing. */
