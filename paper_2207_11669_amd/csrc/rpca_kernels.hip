@@ -522,7 +522,7 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
 #pragma unroll
     for (int q = 0; q < kGPer; ++q) {
       const int e = tid + q * 256;
-      gv_[q] = e < RP * RP ? Gi[e] : 0.0;
+      gv_[q] = Gi[e];  // RP^2 is a multiple of 256
     }
     double acc[kPer];
 #pragma unroll
@@ -535,9 +535,14 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
         const int e = tid + q * 256;
         const int j = e / RP, c = e % RP;
         const float* src = p.Wpart + (int64_t)(vrow + j) * RP + c;
+        // Every load is unconditional (splits past the last re-read it and
+        // are masked afterwards): a load under a branch gets its own wait,
+        // which serialised the batch.
 #pragma unroll
-        for (int u = 0; u < kWB; ++u)
-          wv[q][u] = (e < kVCols * RP && s0 + u < p.vsplit) ? src[(int64_t)(s0 + u) * split_stride] : 0.f;
+        for (int u = 0; u < kWB; ++u) {
+          const float x = src[(int64_t)min(s0 + u, p.vsplit - 1) * split_stride];
+          wv[q][u] = s0 + u < p.vsplit ? x : 0.f;
+        }
       }
 #pragma unroll
       for (int q = 0; q < kPer; ++q)
@@ -1075,6 +1080,15 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  // The previous consensus U (final step) is loaded up front, without a
+  // branch (a load under a branch gets its own wait): other steps read a
+  // valid stand-in and ignore it.
+  float uprev[NQ];
+  {
+    const float* __restrict__ Upv = final_step ? Uprev : p.P;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) uprev[q] = Upv[(int64_t)(cq + 4 * q) * MP + a];
+  }
   // Clients are summed in order, kUB at a time so that their loads are in
   // flight together.
   constexpr int kUB = RT <= 2 ? 8 : 4;
@@ -1111,7 +1125,7 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
     if (p.bf16) hb_store(u_hb(Uo, p), MP, p, a, c, v);
     ul[al * kMaxRank + c] = (double)v;
     if (final_step) {
-      const double d = (double)v - (double)Uprev[(int64_t)c * MP + a];
+      const double d = (double)v - (double)uprev[q];
       dsq += d * d;
     }
   }
