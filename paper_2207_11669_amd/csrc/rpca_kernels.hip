@@ -90,7 +90,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 constexpr int kFinThreads = 256;                             // finalize work-groups
-constexpr int kFinEPT = kMaxRank * kMaxRank / kFinThreads;   // sweep entries per thread
+constexpr int kFinEPT = (kMaxRank * (kMaxRank + 1) / 2 + kFinThreads - 1) / kFinThreads;  // sweep entries per thread
 
 // 1/x for x > 0 without the correctly rounded division sequence: the
 // hardware reciprocal estimate refined by two Newton steps (each squares the
@@ -105,35 +105,45 @@ __device__ __forceinline__ double recip_pos(double x) {
 
 // In-place inverse of an r x r SPD matrix A (row stride ld, in LDS) by a
 // Gauss-Jordan sweep without pivoting, run by the whole work-group (EPT *
-// blockDim.x >= r * r): the k-th pivot is a diagonal entry of a Schur
-// complement of an SPD matrix, hence positive, and every step updates all r^2
-// entries in parallel (no serial triangular solves). Each thread owns up to
-// EPT entries, indexed once, and is the only one to touch them during the
-// sweep; the only values a step needs from other threads are the pivot's row
-// and column, which the threads owning row and column k + 1 publish during
-// step k into a second pair of LDS vectors (double-buffered by step parity),
-// so each step costs one barrier. A pivot that is not positive (non-SPD or
-// NaN input) turns the result into NaN, which the round statistics then
-// expose.
+// blockDim.x >= r (r + 1) / 2): the k-th pivot is a diagonal entry of a Schur
+// complement of an SPD matrix, hence positive, and every step updates the
+// matrix in parallel (no serial triangular solves). Step k sets
+//   A[k][k] <- 1/p,  A[k][j] <- A[k][j] / p,  A[i][k] <- -A[i][k] / p,
+//   A[i][j] <- A[i][j] - A[i][k] A[k][j] / p     (p = A[k][k]).
+// Throughout the sweep A[j][i] = A[i][j] when i and j are both swept or both
+// not, and -A[i][j] otherwise, exactly (the mirrored update multiplies the
+// same two factors), so only the lower triangle is updated and the upper one
+// is mirrored at the end, where every index is swept. Step k then needs only
+// the cross x_t = A[max(t,k)][min(t,k)]: A[k][j] = x_j, and A[i][k] = x_i for
+// i >= k, -x_i for i < k. The threads owning the next step's cross publish it
+// during this step into a second LDS vector (double-buffered by step parity),
+// so each step costs one barrier. Each thread owns up to EPT lower-triangle
+// entries, indexed once. A pivot that is not positive (non-SPD or NaN input)
+// turns the result into NaN, which the round statistics then expose.
 template <int EPT>
 __device__ void spd_inverse(double* A, int r, int ld) {
-  __shared__ double rowb[2][kMaxRank], colb[2][kMaxRank];
+  __shared__ double xb[2][kMaxRank];
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int nl = r * (r + 1) / 2;
   int ei[EPT], ej[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int e = tid + q * nt;
-    ei[q] = e < r * r ? e / r : -1;
-    ej[q] = e < r * r ? e % r : -1;
+    int i = -1, j = -1;
+    if (e < nl) {
+      i = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
+      while (i * (i + 1) / 2 > e) --i;
+      while ((i + 1) * (i + 2) / 2 <= e) ++i;
+      j = e - i * (i + 1) / 2;
+    }
+    ei[q] = i;
+    ej[q] = j;
   }
-  if (tid < r) {
-    rowb[0][tid] = A[tid];
-    colb[0][tid] = A[tid * ld];
-  }
+  if (tid < r) xb[0][tid] = A[tid * ld];
   __syncthreads();
   for (int k = 0; k < r; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
-    const double pv = rowb[cur][k];
+    const double pv = xb[cur][k];
     const double pinv = pv > 0.0 ? recip_pos(pv) : NAN;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -141,18 +151,24 @@ __device__ void spd_inverse(double* A, int r, int ld) {
       if (i >= 0) {
         double v;
         if (i == k)
-          v = (j == k) ? pinv : rowb[cur][j] * pinv;
+          v = (j == k) ? pinv : xb[cur][j] * pinv;
         else if (j == k)
-          v = -colb[cur][i] * pinv;
-        else
-          v = A[i * ld + j] - colb[cur][i] * rowb[cur][j] * pinv;
+          v = -xb[cur][i] * pinv;
+        else {
+          const double ci = i < k ? -xb[cur][i] : xb[cur][i];
+          v = A[i * ld + j] - ci * xb[cur][j] * pinv;
+        }
         A[i * ld + j] = v;
-        if (i == k + 1) rowb[nxt][j] = v;
-        if (j == k + 1) colb[nxt][i] = v;
+        if (i == k + 1) xb[nxt][j] = v;
+        if (j == k + 1) xb[nxt][i] = v;
       }
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int q = 0; q < EPT; ++q)
+    if (ei[q] > ej[q]) A[ej[q] * ld + ei[q]] = A[ei[q] * ld + ej[q]];
+  __syncthreads();
 }
 
 __device__ __forceinline__ double eta_of_round(const DevParams& p, int64_t t) {
@@ -655,7 +671,7 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
     A[e] = s + (a == b ? cl.c : 0.0);
   }
   __syncthreads();
-  spd_inverse<4>(A, r, r);  // 1024 threads x 4 >= 64^2
+  spd_inverse<3>(A, r, r);  // 1024 threads x 3 >= 64 x 65 / 2
   double* Af = p.Afac + (int64_t)blockIdx.x * RR;
   double* Bf = p.Bfac + (int64_t)blockIdx.x * RR;
   for (int e = tid; e < RR; e += blockDim.x) {
