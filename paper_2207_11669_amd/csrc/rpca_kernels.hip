@@ -144,23 +144,51 @@ __device__ void spd_inverse(double* A, int r, int ld) {
   for (int k = 0; k < r; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
     const double pv = xb[cur][k];
-    const double pinv = pv > 0.0 ? recip_pos(pv) : NAN;
+    if constexpr (EPT <= 4) {
+      // The step's LDS reads go out together, before the pivot's reciprocal;
+      // the three cases are then selects. (With many entries per thread the
+      // held reads would cost more registers than the latency they save.)
+      double xi[EPT], xj[EPT], aa[EPT];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int i = ei[q], j = ej[q];
-      if (i >= 0) {
-        double v;
-        if (i == k)
-          v = (j == k) ? pinv : xb[cur][j] * pinv;
-        else if (j == k)
-          v = -xb[cur][i] * pinv;
-        else {
-          const double ci = i < k ? -xb[cur][i] : xb[cur][i];
-          v = A[i * ld + j] - ci * xb[cur][j] * pinv;
+      for (int q = 0; q < EPT; ++q)
+        if (ei[q] >= 0) {
+          xi[q] = xb[cur][ei[q]];
+          xj[q] = xb[cur][ej[q]];
+          aa[q] = A[ei[q] * ld + ej[q]];
         }
-        A[i * ld + j] = v;
-        if (i == k + 1) xb[nxt][j] = v;
-        if (j == k + 1) xb[nxt][i] = v;
+      const double pinv = pv > 0.0 ? recip_pos(pv) : NAN;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int i = ei[q], j = ej[q];
+        if (i >= 0) {
+          const double ci = i < k ? -xi[q] : xi[q];
+          double v = aa[q] - ci * xj[q] * pinv;
+          v = j == k ? -xi[q] * pinv : v;
+          v = i == k ? (j == k ? pinv : xj[q] * pinv) : v;
+          A[i * ld + j] = v;
+          if (i == k + 1) xb[nxt][j] = v;
+          if (j == k + 1) xb[nxt][i] = v;
+        }
+      }
+    } else {
+      const double pinv = pv > 0.0 ? recip_pos(pv) : NAN;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int i = ei[q], j = ej[q];
+        if (i >= 0) {
+          double v;
+          if (i == k)
+            v = (j == k) ? pinv : xb[cur][j] * pinv;
+          else if (j == k)
+            v = -xb[cur][i] * pinv;
+          else {
+            const double ci = i < k ? -xb[cur][i] : xb[cur][i];
+            v = A[i * ld + j] - ci * xb[cur][j] * pinv;
+          }
+          A[i * ld + j] = v;
+          if (i == k + 1) xb[nxt][j] = v;
+          if (j == k + 1) xb[nxt][i] = v;
+        }
       }
     }
     __syncthreads();
