@@ -279,6 +279,82 @@ __device__ __forceinline__ void hb_store(uint16_t* hb, int64_t rows, const DevPa
   h[lo_off + ib] = lo;
 }
 
+// The same layouts written for NR consecutive rows [row0, row0 + NR) at once
+// (row0 and NR multiples of 32) by a 256-thread work-group, from an accessor
+// x(i, c) for row row0 + i and rank c < RP (0 at ranks past r): every layout's
+// span for these rows is contiguous, so threads walk it in order and each
+// store instruction covers whole cache lines, where the per-entry stores
+// above scatter one dword or one bf16 per line. hb is null when the context
+// keeps no BF16 packings. Same values, same places.
+template <int RT, int NR, class X>
+__device__ __forceinline__ void factor_store_rows(float* fb, uint16_t* hb, int64_t rows,
+                                                  const DevParams& p, int row0, X x) {
+  constexpr int RP = 16 * RT;
+  static_assert(NR % 32 == 0, "whole 32-row chunks");
+  const int tid = threadIdx.x, NS = p.NS, NQ = nquads(RP, NS);
+  const int ch16 = row0 >> 4, ch32 = row0 >> 5;
+  for (int e = tid; e < RP * NR; e += 256) {  // column-major
+    const int c = e / NR, i = e - c * NR;
+    fb[(int64_t)c * rows + row0 + i] = x(i, c);
+  }
+  {  // A-operand packing: per 16-row chunk, NS blocks of 64 lanes
+    float* d = fb + fb_pa_off(rows, RP) + (int64_t)ch16 * NS * 64;
+    for (int e = tid; e < (NR / 16) * NS * 64; e += 256) {
+      const int lane = e & 63, s = (e >> 6) % NS, chl = (e >> 6) / NS;
+      d[e] = x(16 * chl + (lane & 15), (lane >> 4) * NS + s);
+    }
+  }
+  {  // B-operand packing: per 16-row chunk, RT tiles of 64 lanes x 4
+    float* d = fb + fb_pb_off(rows, RP, NS) + (int64_t)ch16 * RT * 256;
+    for (int e = tid; e < (NR / 16) * RT * 256; e += 256) {
+      const int el = e & 3, lane = (e >> 2) & 63, ct = (e >> 8) % RT, chl = (e >> 8) / RT;
+      d[e] = x(16 * chl + 4 * (lane >> 4) + el, 16 * ct + (lane & 15));
+    }
+  }
+  if (NQ > 0) {  // rank quads of the last tile
+    float* d = fb + fb_pq_off(rows, RP, NS) + (int64_t)ch16 * NQ * 64;
+    for (int e = tid; e < (NR / 16) * NQ * 64; e += 256) {
+      const int el = e & 3, jq = (e >> 2) & 3, g = (e >> 4) & 3, q = (e >> 6) % NQ,
+                chl = (e >> 6) / NQ;
+      d[e] = x(16 * chl + 4 * g + el, RP - 16 + 4 * q + jq);
+    }
+  }
+  if (hb) {
+    __bf16* h = reinterpret_cast<__bf16*>(hb);
+    const int NK = p.NK;
+    const int64_t lo_off = hb_elems(rows, p.RK, RP);
+    auto put = [&](int64_t at, float v) {
+      const __bf16 hi = (__bf16)v;
+      h[at] = hi;
+      h[lo_off + at] = (__bf16)(v - (float)hi);
+    };
+    auto xr = [&](int i, int c) { return c < RP ? x(i, c) : 0.f; };  // RK may exceed RP
+    {  // hA: per 16-row chunk, NK blocks of 64 lanes x 8
+      const int64_t base = (int64_t)ch16 * NK * 512;
+      for (int e = tid; e < (NR / 16) * NK * 512; e += 256) {
+        const int el = e & 7, lane = (e >> 3) & 63, kb = (e >> 9) % NK, chl = (e >> 9) / NK;
+        put(base + e, xr(16 * chl + (lane & 15), 32 * kb + 8 * (lane >> 4) + el));
+      }
+    }
+    {  // hP: per 32-row chunk, two halves of NK blocks, rows permuted
+      const int64_t base = rows * p.RK + (int64_t)ch32 * 2 * NK * 512;
+      for (int e = tid; e < (NR / 32) * 2 * NK * 512; e += 256) {
+        const int el = e & 7, lane = (e >> 3) & 63, kb = (e >> 9) % NK, t = ((e >> 9) / NK) & 1,
+                  chl = (e >> 9) / (2 * NK);
+        const int il = lane & 15, w = 8 * (il >> 2) + 4 * t + (il & 3);
+        put(base + e, xr(32 * chl + w, 32 * kb + 8 * (lane >> 4) + el));
+      }
+    }
+    {  // hB: per 32-row chunk, RT tiles of 64 lanes x 8
+      const int64_t base = 2 * rows * p.RK + (int64_t)ch32 * RT * 512;
+      for (int e = tid; e < (NR / 32) * RT * 512; e += 256) {
+        const int el = e & 7, lane = (e >> 3) & 63, ct = (e >> 9) % RT, chl = (e >> 9) / RT;
+        put(base + e, x(32 * chl + 8 * (lane >> 4) + el, 16 * ct + (lane & 15)));
+      }
+    }
+  }
+}
+
 // v_mfma_f32_4x4x1f32: 16 independent 4x4x1 products; block b = l/4 takes
 // A_b[i] from lane 4b + i and B_b[j] from lane 4b + j, and D_b[i][j] lands in
 // lane 4b + j, element i.
@@ -636,20 +712,17 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
     }
   }
   __syncthreads();
-  // One entry at a time: unrolled, the eight layouts' addresses of every
-  // entry would be live together.
-#pragma unroll 1
+  // V to LDS and its row-major copy (consecutive threads, consecutive ranks),
+  // then the packed layouts from LDS, each walked in its own order.
+#pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int e = tid + q * 256;
-    if (e < kVCols * RP) {
-      const int j = e / RP, c = e % RP;
-      wd[j][c] = (double)vres[q];
-      p.V[(int64_t)(vrow + j) * RP + c] = vres[q];
-      fb_store(v_fb(p.V, p.NVP, RP), p.NVP, RP, p.NS, vrow + j, c, vres[q]);
-      if (p.bf16) hb_store(v_hb(p.V, p), p.NVP, p, vrow + j, c, vres[q]);
-    }
+    const int e = tid + q * 256, j = e / RP, c = e % RP;
+    wd[j][c] = (double)vres[q];
+    p.V[(int64_t)(vrow + j) * RP + c] = vres[q];
   }
   __syncthreads();
+  factor_store_rows<RT, kVCols>(v_fb(p.V, p.NVP, RP), p.bf16 ? v_hb(p.V, p) : nullptr, p.NVP, p,
+                                vrow, [&](int i, int c) { return (float)wd[i][c]; });
   // Partial V^T V of these columns: thread (ta, tb) = (tid / 16, tid % 16)
   // forms the RT x RT block of entries (RT ta + x, RT tb + y), each a sum over
   // the 32 columns in order (each LDS read feeds RT FMAs).
@@ -1124,15 +1197,6 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  // The previous consensus U (final step) is loaded up front, without a
-  // branch (a load under a branch gets its own wait): other steps read a
-  // valid stand-in and ignore it.
-  float uprev[NQ];
-  {
-    const float* __restrict__ Upv = final_step ? Uprev : p.P;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) uprev[q] = Upv[(int64_t)(cq + 4 * q) * MP + a];
-  }
   // Clients are summed in order, kUB at a time so that their loads are in
   // flight together.
   constexpr int kUB = RT <= 2 ? 8 : 4;
@@ -1157,6 +1221,15 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
     for (int q = 0; q < NQ; ++q) tv[q] = Ti[(int64_t)(cq + 4 * q) * MP];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] += (double)tv[q];
+  }
+  // The previous consensus U (final step), loaded as one batch without a
+  // branch (a load under a branch gets its own wait): other steps read a
+  // valid stand-in and ignore it.
+  float uprev[NQ];
+  {
+    const float* __restrict__ Upv = final_step ? Uprev : p.P;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) uprev[q] = Upv[(int64_t)(cq + 4 * q) * MP + a];
   }
   const double scale = final_step ? 1.0 / (double)p.E : 1.0;
   float* __restrict__ Uo = Uout + (final_step ? 0 : (int64_t)blockIdx.y * uout_stride);
