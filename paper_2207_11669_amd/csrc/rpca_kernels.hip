@@ -2122,15 +2122,19 @@ __global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __res
     for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
 
   // A_i and B_i of the closed-form step, rounded to FP32, for the epilogue
-  // (made visible by the barriers that add the phases' P).
-  __shared__ float fab[2][RP * RP];
+  // (made visible by the barriers that add the phases' P). Rows are padded to
+  // RP + 16 floats, so that the epilogue's operand reads (four rows of 16
+  // consecutive entries per wave) fall in distinct banks.
+  constexpr int kFS = RP + 16;
+  __shared__ float fab[2][RP * kFS];
   const bool closed = p.u_mode != 0;
   if (closed) {
     const double* __restrict__ Af = p.Afac + (int64_t)ci * RP * RP;
     const double* __restrict__ Bf = p.Bfac + (int64_t)ci * RP * RP;
     for (int e = tid; e < RP * RP; e += blockDim.x) {
-      fab[0][e] = (float)Af[e];
-      fab[1][e] = (float)Bf[e];
+      const int at = (e / RP) * kFS + e % RP;
+      fab[0][at] = (float)Af[e];
+      fab[1][at] = (float)Bf[e];
     }
   }
 
@@ -2277,43 +2281,69 @@ __global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __res
   }
   // U-step term of these 128 rows, as in the FP32 form's epilogue but in
   // FP32 (the BF16 rounds' operands carry 8-bit significands, so FP32 here
-  // adds nothing measurable): thread tid owns row tid % 128 and the rank
-  // columns 8 (tid / 128) + 16 q .. + 7; its row of U_i (FP32, from the
-  // factor's column-major layout) sits in registers, P and A_i, B_i in LDS
-  // (the A_i, B_i reads are uniform across a wave).
+  // adds nothing measurable).
   const int row0 = b * kSRows;
-  const int rl = tid & (kSRows - 1);
-  float uk[RP];
-  {
-    const GLOBAL float* Uc = gptr(U) + row0 + rl;
-#pragma unroll
-    for (int k = 0; k < RP; ++k) uk[k] = Uc[(int64_t)k * MP];  // ranks past r are zero
-  }
   float* Ti = p.P + (int64_t)ci * RP * p.MP;
-  const float eta = (float)eta_of_round(p, p.dstate->t);
-  const float cc = (float)cl.c;
-  for (int c0 = 8 * (tid >> 7); c0 < RP; c0 += 16) {
-    float t[8];
-    if (closed) {
+  if (closed) {
+    // T_i = P A_i + U_i B_i on FP32 MFMA, as its transpose A_i^T P^T +
+    // B_i^T U_i^T in 16-rank x 16-row tiles: wave wv takes rows 32 wv .. +31
+    // of the block, and lane l ends with T[row l%16][rank 4 (l/16) + v] of a
+    // tile, so each store covers 16 consecutive rows of a rank column. P comes
+    // from LDS, U_i (FP32) from its column-major layout.
+    constexpr int kK = RP / 4;
+    const int rb = 32 * wv;
+    float ua[2][kK];  // U[row0 + rb + 16 rt + l%16][4 kk + l/16]
+    {
+      const GLOBAL float* Uc = gptr(U) + row0 + rb + li;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) t[j] = 0.f;
+      for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int k = 0; k < RP; ++k) {
-        const float pk = ptile[rl][k];
+        for (int kk = 0; kk < kK; ++kk) ua[rt][kk] = Uc[(int64_t)(4 * kk + lg) * MP + 16 * rt];
+    }
+    f4 acc[2][RT];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          t[j] = fmaf(pk, fab[0][k * RP + c0 + j], fmaf(uk[k], fab[1][k * RP + c0 + j], t[j]));
-      }
-    } else {
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const float u = gptr(U)[(int64_t)(c0 + j) * MP + row0 + rl];
-        t[j] = u - eta * (cc * u - ptile[rl][c0 + j]);
+      for (int ct = 0; ct < RT; ++ct) acc[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int kk = 0; kk < kK; ++kk) {
+      float pb[2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) pb[rt] = ptile[rb + 16 * rt + li][4 * kk + lg];
+#pragma unroll
+      for (int ct = 0; ct < RT; ++ct) {
+        const float a0 = fab[0][(4 * kk + lg) * kFS + 16 * ct + li];
+        const float a1 = fab[1][(4 * kk + lg) * kFS + 16 * ct + li];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+          acc[rt][ct] = mfma4(a0, pb[rt], acc[rt][ct]);
+          acc[rt][ct] = mfma4(a1, ua[rt][kk], acc[rt][ct]);
+        }
       }
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      Ti[(int64_t)(c0 + j) * MP + row0 + rl] = c0 + j < p.r ? t[j] : 0.f;
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = 16 * ct + 4 * lg + v;
+          Ti[(int64_t)c * MP + row0 + rb + 16 * rt + li] = c < p.r ? acc[rt][ct][v] : 0.f;
+        }
+  } else {
+    // Gradient step: thread tid owns row tid % 128 and the rank columns
+    // 8 (tid / 128) + 16 q .. + 7.
+    const int rl = tid & (kSRows - 1);
+    const float eta = (float)eta_of_round(p, p.dstate->t);
+    const float cc = (float)cl.c;
+    for (int c0 = 8 * (tid >> 7); c0 < RP; c0 += 16) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float u = gptr(U)[(int64_t)(c0 + j) * MP + row0 + rl];
+        const float t = u - eta * (cc * u - ptile[rl][c0 + j]);
+        Ti[(int64_t)(c0 + j) * MP + row0 + rl] = c0 + j < p.r ? t : 0.f;
+      }
+    }
   }
   spass_stats<4>(p, ci, b, sl2, sl1, nnz);
 }
