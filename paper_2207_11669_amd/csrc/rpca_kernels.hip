@@ -765,11 +765,74 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
   const int64_t RR = (int64_t)RP * RP;
   const ClientDev cl = p.clients[blockIdx.x];
   const int tid = threadIdx.x;
-  for (int e = tid; e < r * r; e += blockDim.x) {
-    const int a = e / r, b = e % r;
-    const double s = sum_strided(p.gv_part + (int64_t)cl.g0 * RR + a * RP + b, cl.g1 - cl.g0, RR);
-    G[e] = s;
-    A[e] = s + (a == b ? cl.c : 0.0);
+  if (cl.g1 - cl.g0 <= 16) {
+    // One block of groups: one batch of loads per entry.
+    for (int e = tid; e < r * r; e += blockDim.x) {
+      const int a = e / r, b = e % r;
+      const double s = sum_strided(p.gv_part + (int64_t)cl.g0 * RR + a * RP + b, cl.g1 - cl.g0, RR);
+      G[e] = s;
+      A[e] = s + (a == b ? cl.c : 0.0);
+    }
+  } else {
+    // G = V_i^T V_i from the V finish's per-group partials, which are
+    // symmetric bit for bit (each partial multiplies the same two factors
+    // both ways round): the lower triangle is summed and mirrored. Sums run
+    // in blocks of 16 groups as in sum_strided, same bits, but all of a
+    // thread's entries load together, 8 groups at a time, with no load
+    // under a branch: out-of-range groups and entries re-read a valid,
+    // finite partial and are multiplied by 0 (a select would let the
+    // compiler move the load into a branch of its own, with its own wait).
+    constexpr int kCE = 3;  // 1024 threads x 3 >= 64 x 65 / 2
+    const int nl = r * (r + 1) / 2, ng = cl.g1 - cl.g0;
+    const double* __restrict__ gp = p.gv_part + (int64_t)cl.g0 * RR;
+    int ia[kCE], ib[kCE];
+    double s[kCE];
+#pragma unroll
+    for (int q = 0; q < kCE; ++q) {
+      const int e = tid + q * 1024;
+      int a = -1, b = 0;
+      if (e < nl) {
+        a = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
+        while (a * (a + 1) / 2 > e) --a;
+        while ((a + 1) * (a + 2) / 2 <= e) ++a;
+        b = e - a * (a + 1) / 2;
+      }
+      ia[q] = a;
+      ib[q] = b;
+      s[q] = 0.0;
+    }
+    for (int g0 = 0; g0 < ng; g0 += 16) {
+      double t[kCE];
+#pragma unroll
+      for (int q = 0; q < kCE; ++q) t[q] = 0.0;
+#pragma unroll
+      for (int h = 0; h < 16; h += 8) {
+        double v[kCE][8];
+#pragma unroll
+        for (int q = 0; q < kCE; ++q)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int g = g0 + h + u;
+            const double x = gp[(int64_t)min(g, ng - 1) * RR + max(ia[q], 0) * RP + ib[q]];
+            v[q][u] = x * (double)(ia[q] >= 0 && g < ng);
+          }
+#pragma unroll
+        for (int q = 0; q < kCE; ++q)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) t[q] += v[q][u];
+      }
+#pragma unroll
+      for (int q = 0; q < kCE; ++q) s[q] += t[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kCE; ++q)
+      if (ia[q] >= 0) {
+        const int a = ia[q], b = ib[q];
+        G[a * r + b] = s[q];
+        G[b * r + a] = s[q];
+        A[a * r + b] = s[q] + (a == b ? cl.c : 0.0);
+        A[b * r + a] = s[q] + (a == b ? cl.c : 0.0);
+      }
   }
   __syncthreads();
   spd_inverse<3>(A, r, r);  // 1024 threads x 3 >= 64 x 65 / 2
