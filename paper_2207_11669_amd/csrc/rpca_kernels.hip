@@ -2144,7 +2144,7 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
 // loads from the caller's block), and the A operand of MFMA 2 (P += Lambda V
 // with V's hB packing as B; X3: every product as three BF16 products of
 // hi/lo splits). The phases' partial P are added in LDS in phase order. LDS
-// holds P and FP32 copies of A_i and B_i (65 KB at r = 64), so two
+// holds P and FP32 copies of A_i and B_i (74 KB at r = 64), so two
 // work-groups fit on a compute unit and one's epilogue overlaps the other's
 // sweep.
 // ---------------------------------------------------------------------------
