@@ -35,7 +35,9 @@ MFMA_PEAK_TFS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 3}
 def traffic_file(workload: str, precision: str = "fp32") -> str:
     suffix = "" if precision == "fp32" else f"_{precision}"
     return os.path.join(ROOT, "profiles", f"traffic_{workload}{suffix}.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2207_11669_amd", "csrc", "rpca_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_11669_amd", "csrc", f)
+               for f in ("rpca_device.h", "rpca_internal.h", "rpca_vpass.hip", "rpca_spass.hip",
+                         "rpca_bf16.hip", "rpca_tail.hip")]
 
 
 def kernel_costs(m: int, n: int, E: int, r: int, precision: str = "fp32") -> dict:
@@ -78,8 +80,12 @@ def roofline_of(cost: dict, avg_s: float, precision: str = "fp32") -> dict:
 
 
 def src_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the kernel sources, which the hardware counters were taken on."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(inst, U0, r, rho, lam, budget_s: float = 12.0, max_rounds: int = 10) -> dict:

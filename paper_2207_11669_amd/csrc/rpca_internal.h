@@ -190,7 +190,8 @@ __host__ __device__ inline const uint16_t* v_hb(const float* V, const DevParams&
   return reinterpret_cast<const uint16_t*>(V + vbuf_floats(p.NVP, p.RP, p.NS));
 }
 
-// Launch helpers (kernels live in rpca_kernels.hip).
+// Launch helpers (kernels live in rpca_vpass.hip, rpca_spass.hip, rpca_bf16.hip
+// and rpca_tail.hip).
 constexpr int kDistBlocks = 64;  // work-groups per side of the factor-distance kernel
 // S source for the V-pass: zero, the stored S buffer, or recomputed from the
 // previous round's factors.
