@@ -56,10 +56,16 @@ typedef enum {
   RPCA_ETA_SQRT = 1    /* eta_t = eta0 / sqrt(t + 1): a decaying rate (Section 4.2) */
 } rpca_eta_sched;
 
+/* Size limits (rpca_params_error names the one a problem breaks). Besides the
+ * per-field ranges below, the kernels address whole factor layouts with 32-bit
+ * byte ranges, so with RP = r rounded up to 16:
+ *   (m rounded up to 128) * RP * 4 < 2^31          (m < 2^23 at r = 64), and
+ *   (sum of the n_i each rounded up to 64) * RP * 4 < 2^31
+ *                                                   (n < 2^23 at r = 64). */
 typedef struct {
   int64_t m;               /* rows of M (all clients share them), 1 <= m < 2^26 */
   int32_t E;               /* number of clients, 1 <= E <= 4096 */
-  const int64_t* n_cols;   /* host array [E]: n_i >= 1 columns of client i */
+  const int64_t* n_cols;   /* host array [E]: 1 <= n_i <= 2^30 columns of client i */
   int32_t r;               /* factor rank, 1 <= r <= 64 */
   double rho;              /* rho > 0 (Frobenius penalty on U and V) */
   double lambda;           /* lambda >= 0 (l1 penalty on S) */
@@ -69,6 +75,7 @@ typedef struct {
   double eta0;             /* step size for RPCA_U_GRAD (> 0 there) */
   int32_t eta_sched;       /* rpca_eta_sched */
   uint32_t flags;          /* RPCA_FLAG_* bits */
+  uint64_t seed;           /* seed of the U^(0) draw when rpca_init gets U0 = NULL */
 } rpca_params;
 
 /* With K = 1 and one alternation the library does not store S between rounds:
@@ -149,13 +156,23 @@ rpca_status rpca_workspace_bytes(const rpca_params* p, size_t* bytes);
  *            lives. Each pointer must be 16-byte aligned, m <= ldm[i] < 2^26
  *            and ldm[i] % 4 == 0.
  *  U0:       device m x r column-major start U^(0) with leading dimension
- *            ldu >= m (copied; not retained).
+ *            ldu >= m (copied; not retained), or NULL: Algorithm 1 leaves the
+ *            start open, and the library then draws U^(0) on the device with
+ *            i.i.d. N(0, 1) entries from p->seed. Entry (i, c) uses the
+ *            outputs j = 2k and 2k + 1, k = c m + i, of the counter form of
+ *            SplitMix64 (Steele, Lea and Flood, 2014): x_j = mix(seed +
+ *            (j + 1) 0x9E3779B97F4A7C15 mod 2^64), mix(z) = z ^= z >> 30,
+ *            z *= 0xBF58476D1CE4E5B9, z ^= z >> 27, z *= 0x94D049BB133111EB,
+ *            z ^= z >> 31; u_j = (x_j >> 11) 2^-53; and the Box-Muller value
+ *            sqrt(-2 ln(1 - u_2k)) cos(2 pi u_2k+1), formed in FP64 and
+ *            rounded to FP32.
  *  workspace/ws_bytes: caller-owned device memory of at least
  *            rpca_workspace_bytes() bytes, 256-byte aligned; the library
  *            allocates no device memory of its own.
  *  stream:   hipStream_t (as void*) all work is enqueued on; NULL = default.
  * S_i^(0) = 0. Returns RPCA_WARN_THM2 (context still valid) when
- * rho^2 > lambda^2 m n. On error *out is NULL. */
+ * rho^2 > lambda^2 m n. On error *out is NULL and rpca_last_error(NULL)
+ * names the cause. */
 rpca_status rpca_init(rpca_ctx** out, const rpca_params* p,
                       const float* const* M_blocks, const int64_t* ldm,
                       const float* U0, int64_t ldu,
@@ -308,7 +325,9 @@ rpca_status rpca_mlp_train_step(float* params, const float* x, const float* targ
 /* Rounds enqueued so far. */
 int64_t rpca_rounds(const rpca_ctx* c);
 
-/* Text of the last error on this context (never NULL). */
+/* Text of the last error on this context (never NULL). With c = NULL: the
+ * cause of the last failed context creation on the calling thread (empty if
+ * none failed). */
 const char* rpca_last_error(const rpca_ctx* c);
 
 /* Destroy a context (does not free the workspace or M). NULL is a no-op. */

@@ -14,7 +14,8 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32, c_void_p
+from ctypes import (POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32,
+                    c_uint64, c_void_p)
 from typing import Optional, Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -48,6 +49,7 @@ class RpcaParams(ctypes.Structure):
         ("eta0", c_double),
         ("eta_sched", c_int32),
         ("flags", c_uint32),
+        ("seed", c_uint64),
     ]
 
 
@@ -135,14 +137,15 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 def make_params(m: int, widths: Sequence[int], r: int, rho: float, lam: float, K: int = 1,
                 inner: int = 1, u_mode: str = "closed", eta0: float = 0.0,
                 eta_sched: str = "const", store_s: bool = False, graph: bool = False,
-                bf16: bool = False, bf16x3: bool = False):
+                bf16: bool = False, bf16x3: bool = False, seed: int = 0):
     """Build an rpca_params struct; returns (params, n_cols array to keep alive)."""
     ncols = (c_int64 * len(widths))(*[int(w) for w in widths])
     flags = ((RPCA_FLAG_STORE_S if store_s else 0) | (RPCA_FLAG_GRAPH if graph else 0)
              | (RPCA_FLAG_BF16 if bf16 else 0) | (RPCA_FLAG_BF16X3 if bf16x3 else 0))
     p = RpcaParams(m=int(m), E=len(widths), n_cols=ncols, r=int(r), rho=float(rho),
                    lam=float(lam), K=int(K), inner=int(inner), u_mode=U_MODES[u_mode],
-                   eta0=float(eta0), eta_sched=ETA_SCHEDS[eta_sched], flags=flags)
+                   eta0=float(eta0), eta_sched=ETA_SCHEDS[eta_sched], flags=flags,
+                   seed=int(seed) & 0xFFFFFFFFFFFFFFFF)
     return p, ncols
 
 
@@ -183,7 +186,9 @@ class DCFPCA:
 
     M_cols: (n, ldm) FP32 CUDA tensor, M column-major (see `colmajor`); client i
     owns columns offsets[i]:offsets[i+1] in order. U0_cols: (r, ldu) tensor
-    with U^(0) column-major. bf16=True creates the context with
+    with U^(0) column-major, or None: the library draws U^(0) on the device
+    from `seed` (i.i.d. N(0, 1), the rule stated with rpca_init). bf16=True
+    creates the context with
     RPCA_FLAG_BF16: rounds run in BF16 until set_precision("fp32").
     bf16x3=True (RPCA_FLAG_BF16X3): rounds run as three-product BF16.
     """
@@ -191,13 +196,15 @@ class DCFPCA:
     def __init__(self, M_cols, widths: Sequence[int], m: int, r: int, rho: float, lam: float,
                  U0_cols, K: int = 1, inner: int = 1, u_mode: str = "closed",
                  eta0: float = 0.0, eta_sched: str = "const", store_s: bool = False,
-                 graph: bool = False, stream=None, bf16: bool = False, bf16x3: bool = False):
+                 graph: bool = False, stream=None, bf16: bool = False, bf16x3: bool = False,
+                 seed: int = 0):
         import torch
         self._lib = load_library()
         if not (M_cols.is_cuda and M_cols.dtype == torch.float32 and M_cols.is_contiguous()):
             raise ValueError("M_cols must be a contiguous float32 CUDA tensor")
-        if not (U0_cols.is_cuda and U0_cols.dtype == torch.float32 and U0_cols.is_contiguous()):
-            raise ValueError("U0_cols must be a contiguous float32 CUDA tensor")
+        if U0_cols is not None and not (U0_cols.is_cuda and U0_cols.dtype == torch.float32
+                                        and U0_cols.is_contiguous()):
+            raise ValueError("U0_cols must be a contiguous float32 CUDA tensor or None")
         self.m, self.r = int(m), int(r)
         self.widths = [int(w) for w in widths]
         self.n = sum(self.widths)
@@ -205,7 +212,8 @@ class DCFPCA:
             raise ValueError("M_cols must have one row per column of M")
         self.ldm = int(M_cols.shape[1])
         self.params, self._ncols = make_params(m, self.widths, r, rho, lam, K, inner, u_mode,
-                                               eta0, eta_sched, store_s, graph, bf16, bf16x3)
+                                               eta0, eta_sched, store_s, graph, bf16, bf16x3,
+                                               seed)
         err = params_error(self.params)
         if err:
             raise ValueError(err)
@@ -230,12 +238,13 @@ class DCFPCA:
         self._ptrs = (c_void_p * len(ptrs))(*ptrs)
         self._ldms = (c_int64 * len(lds))(*lds)
         ctx = c_void_p()
+        u0 = c_void_p(U0_cols.data_ptr()) if U0_cols is not None else c_void_p(None)
+        ldu = int(U0_cols.shape[1]) if U0_cols is not None else 0
         st = self._lib.rpca_init(ctypes.byref(ctx), ctypes.byref(self.params), self._ptrs,
-                                 self._ldms, c_void_p(U0_cols.data_ptr()),
-                                 int(U0_cols.shape[1]), c_void_p(self.ws.data_ptr()),
+                                 self._ldms, u0, ldu, c_void_p(self.ws.data_ptr()),
                                  self.ws.numel(), c_void_p(self.stream.cuda_stream))
         if st < 0:
-            raise RpcaError(st, "rpca_init failed")
+            raise RpcaError(st, "rpca_init failed: " + last_init_error())
         self.warning = st
         self.ctx = ctx
 
@@ -358,6 +367,11 @@ class DCFPCA:
             self.close()
         except Exception:
             pass
+
+
+def last_init_error() -> str:
+    """Cause of the last failed context creation on this thread."""
+    return load_library().rpca_last_error(None).decode()
 
 
 def mlp_param_count() -> int:

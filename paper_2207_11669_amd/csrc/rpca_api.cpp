@@ -89,6 +89,20 @@ const char* check_params(const rpca_params* p) {
   }
   if (n > (int64_t)1 << 31) return "total columns n must be <= 2^31";
   if (p->r < 1 || p->r > kMaxRank) return "r must be in [1, 64]";
+  {
+    // The kernels address whole factor layouts through buffer resources with
+    // 32-bit byte ranges: (m rounded up to 128) x (r rounded up to 16) and
+    // (the clients' widths each rounded up to 64, summed) x (r rounded up to
+    // 16) floats must each span fewer than 2^31 bytes.
+    const int64_t RP = round_up(p->r, 16);
+    int64_t nvp = 0;
+    for (int i = 0; i < p->E; ++i) nvp += round_up(p->n_cols[i], kVPad);
+    if (round_up(p->m, kSRows) * RP * 4 >= ((int64_t)1 << 31))
+      return "m rounded up to 128, times r rounded up to 16, times 4 bytes must be < 2^31";
+    if (nvp * RP * 4 >= ((int64_t)1 << 31))
+      return "the sum of the n_i rounded up to 64, times r rounded up to 16, times 4 bytes must "
+             "be < 2^31";
+  }
   if (!(p->rho > 0.0) || !std::isfinite(p->rho)) return "rho must be finite and > 0";
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return "lambda must be finite and >= 0";
   if (p->K < 1 || p->K > 1024) return "K must be in [1, 1024]";
@@ -202,6 +216,15 @@ rpca_status fail(rpca_ctx* c, rpca_status st, const std::string& msg) {
     c->err = msg;
     if (st == RPCA_EDEVICE || st == RPCA_ENONFINITE) c->poisoned = true;
   }
+  return st;
+}
+
+// Cause of the last failed context creation on this thread (rpca_last_error
+// with no context).
+thread_local std::string g_init_err;
+
+rpca_status init_fail(rpca_status st, const std::string& msg) {
+  g_init_err = msg;
   return st;
 }
 
@@ -371,24 +394,35 @@ rpca_status rpca_workspace_bytes(const rpca_params* p, size_t* bytes) {
 rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const* M_blocks,
                       const int64_t* ldm, const float* U0, int64_t ldu, void* workspace,
                       size_t ws_bytes, void* stream) {
-  if (!out) return RPCA_EINVAL;
+  g_init_err.clear();
+  if (!out) return init_fail(RPCA_EINVAL, "out is NULL");
   *out = nullptr;
-  if (check_params(prm)) return RPCA_EINVAL;
-  if (!M_blocks || !ldm || !U0 || ldu < prm->m) return RPCA_EINVAL;
+  if (const char* msg = check_params(prm)) return init_fail(RPCA_EINVAL, msg);
+  if (!M_blocks || !ldm) return init_fail(RPCA_EINVAL, "M_blocks or ldm is NULL");
+  if (U0 && ldu < prm->m) return init_fail(RPCA_EINVAL, "ldu < m");
   for (int i = 0; i < prm->E; ++i) {
     // Kernels address 16 columns of a block with 32-bit byte offsets.
     if (!M_blocks[i] || ldm[i] < prm->m || ldm[i] % 4 != 0 || ldm[i] >= ((int64_t)1 << 26) ||
         reinterpret_cast<uintptr_t>(M_blocks[i]) % 16 != 0)
-      return RPCA_EINVAL;
+      return init_fail(RPCA_EINVAL, "M block " + std::to_string(i) +
+                                        ": NULL, not 16-byte aligned, or ldm not a multiple of 4 "
+                                        "in [m, 2^26)");
   }
   const Layout L = make_layout(prm);
-  if (!workspace || ws_bytes < L.total || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
-    return RPCA_EWORKSPACE;
+  if (!workspace) return init_fail(RPCA_EWORKSPACE, "workspace is NULL");
+  if (ws_bytes < L.total)
+    return init_fail(RPCA_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) +
+                                          " bytes; these parameters need " +
+                                          std::to_string(L.total));
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return init_fail(RPCA_EWORKSPACE, "workspace is not 256-byte aligned");
 
-  if ((prm->flags & RPCA_FLAG_GRAPH) && !stream) return RPCA_EINVAL;
+  if ((prm->flags & RPCA_FLAG_GRAPH) && !stream)
+    return init_fail(RPCA_EINVAL, "RPCA_FLAG_GRAPH needs a stream other than the null stream");
   if (prm->flags & RPCA_FLAG_BF16X3)
     for (int i = 0; i < prm->E; ++i)
-      if (ldm[i] >= ((int64_t)1 << 24)) return RPCA_EINVAL;
+      if (ldm[i] >= ((int64_t)1 << 24))
+        return init_fail(RPCA_EINVAL, "RPCA_FLAG_BF16X3 needs every ldm < 2^24");
   rpca_ctx* c = new rpca_ctx();
   c->stream = reinterpret_cast<hipStream_t>(stream);
   c->inner = prm->inner;
@@ -524,7 +558,8 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + L.vg64, c->vg64.data(), c->vg64.size() * sizeof(VTile),
                        hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = launch_copy_in_U(p, U0, ldu, c->U[0], st);
+  if (e == hipSuccess)
+    e = U0 ? launch_copy_in_U(p, U0, ldu, c->U[0], st) : launch_init_U_gauss(p, prm->seed, c->U[0], st);
   if (e == hipSuccess && L.mcopy) e = launch_m_to_bf16(p, st);
   if (e == hipSuccess) e = launch_gram_init(p, c->U[0], st);
   if (e == hipSuccess) e = launch_finalize(p, c->Ginv, 0, 0, 0, st);
@@ -532,7 +567,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete c;
-    return RPCA_EDEVICE;
+    return init_fail(RPCA_EDEVICE, std::string("initialisation: ") + hipGetErrorString(e));
   }
   *out = c;
   const double mn = (double)prm->m * (double)L.n;
@@ -959,7 +994,7 @@ rpca_status rpca_profile(rpca_ctx* c, int32_t rounds, double* avg_ms, int64_t* l
 int64_t rpca_rounds(const rpca_ctx* c) { return c ? c->rounds : -1; }
 
 const char* rpca_last_error(const rpca_ctx* c) {
-  if (!c) return "context is NULL";
+  if (!c) return g_init_err.c_str();
   return c->err.c_str();
 }
 

@@ -64,6 +64,12 @@ __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
 __device__ __forceinline__ f4 bload4(rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
 }
+// Byte range of a whole factor layout. The parameter checks keep every such
+// layout below 2^31 bytes; a larger value would be a broken invariant, and
+// the range is then 0 (every load reads 0) rather than a wrapped 32-bit size.
+__device__ __forceinline__ uint32_t range32(int64_t bytes) {
+  return bytes >= 0 && bytes < ((int64_t)1 << 31) ? (uint32_t)bytes : 0u;
+}
 // Bytes of a client block from column j0 on (0 past the end), capped to the
 // 32-bit range of a buffer resource.
 __device__ __forceinline__ uint32_t block_bytes_from(int n, int j0, int64_t ldm) {

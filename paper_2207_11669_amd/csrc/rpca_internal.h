@@ -223,6 +223,9 @@ hipError_t launch_finalize(const DevParams& p, double* Ginv, int64_t g_stride, i
 hipError_t launch_gram_init(const DevParams& p, const float* Ucol, hipStream_t st);
 hipError_t launch_copy_in_U(const DevParams& p, const float* U0, int64_t ldu, float* Ufb,
                             hipStream_t st);
+// U^(0) with i.i.d. N(0, 1) entries drawn from `seed` (SplitMix64 counters and
+// Box-Muller; the rule is stated with rpca_init) into a factor block.
+hipError_t launch_init_U_gauss(const DevParams& p, uint64_t seed, float* Ufb, hipStream_t st);
 hipError_t launch_materialize(const DevParams& p, const ClientDev* host_clients,
                               const int64_t* col_off, const float* Ucol, int client_begin,
                               int client_end, float* L, int64_t ldl, float* S, int64_t lds,

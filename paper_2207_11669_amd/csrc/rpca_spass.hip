@@ -132,9 +132,9 @@ __global__ __launch_bounds__(256 * NPH) void k_spass(DevParams p, const float* _
   const float lam = p.lam;
   GLOBAL float* Sblk = STORE ? gptr_w(Sout) + cl.col0 * lds_out : nullptr;
   // V operands: packed, always in range (lane offset + scalar chunk offset).
-  const rsrc_t rVa = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pa_off(p.NVP, RP), (uint32_t)(p.NVP * 4 * NS * 4));
-  const rsrc_t rVb = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pb_off(p.NVP, RP, NS), (uint32_t)(p.NVP * RP * 4));
-  const rsrc_t rVq = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pq_off(p.NVP, RP, NS), (uint32_t)(p.NVP * 4 * NQ * 4));
+  const rsrc_t rVa = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pa_off(p.NVP, RP), range32((int64_t)p.NVP * 4 * NS * 4));
+  const rsrc_t rVb = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pb_off(p.NVP, RP, NS), range32((int64_t)p.NVP * RP * 4));
+  const rsrc_t rVq = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pq_off(p.NVP, RP, NS), range32((int64_t)p.NVP * 4 * NQ * 4));
   const uint32_t vq_off = (uint32_t)(((lane >> 4) * 4 + (lane & 3)) * 16);
   // M: one buffer resource per 16-column chunk (base at the chunk's first
   // column, range = the rest of the block, at most kChunkRange), fixed per-lane

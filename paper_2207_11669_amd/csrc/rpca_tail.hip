@@ -416,6 +416,35 @@ __global__ void k_copy_in_U(DevParams p, const float* __restrict__ U0, int64_t l
   if (p.bf16) hb_store(u_hb(Ufb, p), p.MP, p, a, c, v);
 }
 
+// Output j >= 0 of SplitMix64 (Steele, Lea and Flood, 2014) seeded with
+// `seed`, in counter form: the generator's state after j + 1 steps is
+// seed + (j + 1) times the golden-ratio increment, and the output is the
+// state's mix.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
+  uint64_t z = seed + (j + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// U^(0) into a factor block, entry (a, c) = the Box-Muller normal of outputs
+// 2k and 2k + 1, k = c m + a: sqrt(-2 ln(1 - u1)) cos(2 pi u2) with
+// u = (x >> 11) 2^-53, in FP64, rounded to FP32 (zeros outside m x r).
+__global__ void k_init_U_gauss(DevParams p, uint64_t seed, float* __restrict__ Ufb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)p.RP * p.MP) return;
+  const int a = (int)(e % p.MP), c = (int)(e / p.MP);
+  float v = 0.f;
+  if (a < p.m && c < p.r) {
+    const uint64_t k = (uint64_t)c * (uint64_t)p.m + (uint64_t)a;
+    const double u1 = (double)(splitmix64_at(seed, 2 * k) >> 11) * 0x1.0p-53;
+    const double u2 = (double)(splitmix64_at(seed, 2 * k + 1) >> 11) * 0x1.0p-53;
+    v = (float)(sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586476925 * u2));
+  }
+  fb_store(Ufb, p.MP, p.RP, p.NS, a, c, v);
+  if (p.bf16) hb_store(u_hb(Ufb, p), p.MP, p, a, c, v);
+}
+
 // L_i = U V_i^T (FP64 accumulation) and S_i, for one client, column-major out.
 // grid.y strides over the client's columns.
 __global__ void k_materialize(DevParams p, const float* __restrict__ Ucol, int client,
@@ -598,6 +627,13 @@ hipError_t launch_copy_in_U(const DevParams& p, const float* U0, int64_t ldu, fl
   const int64_t tot = (int64_t)p.RP * p.MP;
   hipLaunchKernelGGL(k_copy_in_U, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, p, U0,
                      ldu, Ufb);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_U_gauss(const DevParams& p, uint64_t seed, float* Ufb, hipStream_t st) {
+  const int64_t tot = (int64_t)p.RP * p.MP;
+  hipLaunchKernelGGL(k_init_U_gauss, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, p,
+                     seed, Ufb);
   return hipGetLastError();
 }
 

@@ -99,10 +99,10 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
       rS[g] = make_rsrc(p.S + cl.s_off + (int64_t)min(j0, cl.n) * p.lds, block_bytes_from(cl.n, j0, p.lds));
   }
   const uint32_t vM = (uint32_t)(li * cl.ldm) * 4u, vS = (uint32_t)(li * p.lds) * 4u;
-  const rsrc_t rUb = make_rsrc(gUpb_raw, (uint32_t)(p.MP * RP * 4));
-  const rsrc_t rUq = make_rsrc(U + fb_pq_off(p.MP, RP, NS), (uint32_t)(p.MP * 4 * NQ * 4));
+  const rsrc_t rUb = make_rsrc(gUpb_raw, range32((int64_t)p.MP * RP * 4));
+  const rsrc_t rUq = make_rsrc(U + fb_pq_off(p.MP, RP, NS), range32((int64_t)p.MP * 4 * NQ * 4));
   const uint32_t vq_off = (uint32_t)(((lane >> 4) * 4 + (lane & 3)) * 16);
-  const rsrc_t rUa = make_rsrc(gUopa_raw, (uint32_t)(p.MP * 4 * NS * 4));
+  const rsrc_t rUa = make_rsrc(gUopa_raw, range32((int64_t)p.MP * 4 * NS * 4));
 
   // Operands of one 16-row chunk; kVDepth chunks are kept in flight (vector
   // loads complete in order, so everything a chunk needs is issued together).

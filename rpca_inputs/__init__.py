@@ -39,6 +39,8 @@ __all__ = [
     "equal_widths",
     "loguniform_widths",
     "gaussian_init",
+    "splitmix64_outputs",
+    "splitmix_gaussian_init",
     "recipe",
     "RECIPES",
     "controller_family",
@@ -126,6 +128,34 @@ def gaussian_init(m: int, r: int, seed: int) -> np.ndarray:
     """U^(0) with i.i.d. N(0,1) entries, FP32-rounded (Algorithm 1 leaves the
     distribution open; a Gaussian start avoids the stationary point U = 0)."""
     return _f32(_rng(seed, _STREAM_INIT).standard_normal((m, r)))
+
+
+_GOLDEN64 = 0x9E3779B97F4A7C15
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64_outputs(seed: int, first: int, count: int) -> np.ndarray:
+    """Outputs first .. first + count - 1 of SplitMix64 (Steele, Lea and Flood,
+    2014) seeded with `seed`: output j mixes the state seed + (j + 1) times
+    the golden-ratio increment (mod 2^64). uint64 array."""
+    with np.errstate(over="ignore"):
+        j = np.arange(first, first + count, dtype=np.uint64)
+        z = np.uint64(int(seed) & _MASK64) + (j + np.uint64(1)) * np.uint64(_GOLDEN64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def splitmix_gaussian_init(m: int, r: int, seed: int) -> np.ndarray:
+    """The U^(0) that the library draws on the device when given no start:
+    entry (i, c) is the Box-Muller normal sqrt(-2 ln(1 - u1)) cos(2 pi u2) of
+    the SplitMix64 outputs 2k and 2k + 1, k = c m + i, with u = (x >> 11)
+    2^-53, formed in FP64 and rounded to FP32. (m, r) float64 array."""
+    x = splitmix64_outputs(seed, 0, 2 * m * r)
+    u = (x >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u1, u2 = u[0::2], u[1::2]
+    z = np.sqrt(-2.0 * np.log(1.0 - u1)) * np.cos(2.0 * np.pi * u2)
+    return _f32(z.reshape(r, m).T)
 
 
 def _planted_factors(m: int, n: int, rstar: int, seed: int, spectrum: str, sigma_hi: float,

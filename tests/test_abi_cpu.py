@@ -89,3 +89,55 @@ def test_bf16_flag_rules_and_workspace(lib):
     mp, nvp = 4096, 16 * 512
     assert extra >= 2 * 2 * mp * nvp
     assert extra < 2 * 2 * mp * nvp + 16 * (mp + nvp) * 64 * 4
+
+
+def test_size_limits_of_the_32_bit_buffer_ranges(lib):
+    """Factor layouts are addressed with 32-bit byte ranges: (m rounded up to
+    128) x (r rounded up to 16) x 4 B and (sum of the widths rounded up to 64)
+    x (r rounded up to 16) x 4 B must stay below 2^31; one past either edge is
+    refused with a message, the edge itself accepted."""
+    from paper_2207_11669_amd import make_params, params_error
+    # r = 64 (RP = 64): m rounded up to 128 must be < 2^23.
+    ok, _a = make_params((1 << 23) - 128, [64], 64, 0.1, 0.1)
+    assert params_error(ok) is None
+    bad, _b = make_params((1 << 23) - 127, [64], 64, 0.1, 0.1)
+    msg = params_error(bad)
+    assert msg is not None and "m rounded up to 128" in msg, msg
+    # r = 16 (RP = 16): the same bound is 2^25 rows, beyond which m < 2^26 decides.
+    ok16, _c = make_params((1 << 25) - 128, [64], 16, 0.1, 0.1)
+    assert params_error(ok16) is None
+    # Columns: widths rounded up to 64 and summed, times RP = 64, below 2^29 floats.
+    w_ok = [(1 << 22), (1 << 22) - 64]
+    okc, _d = make_params(100, w_ok, 64, 0.1, 0.1)
+    assert params_error(okc) is None
+    badc, _e = make_params(100, [(1 << 22), (1 << 22) - 64, 1], 64, 0.1, 0.1)
+    msg = params_error(badc)
+    assert msg is not None and "n_i rounded up to 64" in msg, msg
+
+
+def test_init_rejects_bad_workspace_before_any_device_call(lib):
+    """rpca_init checks the workspace on the host: NULL, too small and
+    misaligned workspaces give RPCA_EWORKSPACE (nothing is enqueued), and
+    rpca_last_error(NULL) names the cause. The device pointers are never
+    dereferenced on these paths, so stand-in addresses serve."""
+    import ctypes
+
+    from paper_2207_11669_amd import binding as B
+    p, _k = B.make_params(64, [32, 32], 4, 0.1, 0.1)
+    need = B.workspace_bytes(p)
+    fake = 1 << 20  # 16-byte and 256-byte aligned stand-in address
+    ptrs = (ctypes.c_void_p * 2)(fake, fake + 64 * 32 * 4)
+    lds = (ctypes.c_int64 * 2)(64, 64)
+    ctx = ctypes.c_void_p()
+    cases = [(None, need, "NULL"), (fake, need - 256, "need"), (fake + 128, need, "aligned")]
+    for ws, size, frag in cases:
+        st = lib.rpca_init(ctypes.byref(ctx), ctypes.byref(p), ptrs, lds, ctypes.c_void_p(fake),
+                           64, ctypes.c_void_p(ws), size, None)
+        assert st == B.RPCA_EWORKSPACE, (ws, size, st)
+        assert ctx.value is None
+        assert frag in B.last_init_error(), B.last_init_error()
+    # Invalid parameters are reported the same way (RPCA_EINVAL).
+    bad, _b = B.make_params(64, [32, 32], 0, 0.1, 0.1)
+    st = lib.rpca_init(ctypes.byref(ctx), ctypes.byref(bad), ptrs, lds, None, 0,
+                       ctypes.c_void_p(fake), need, None)
+    assert st == B.RPCA_EINVAL and "r must" in B.last_init_error()

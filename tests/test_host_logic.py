@@ -63,3 +63,46 @@ def test_precision_flag_rules():
     b32, bx3, bb = workspace_bytes(p32), workspace_bytes(px3), workspace_bytes(pb)
     assert b32 < bx3 < b32 + 8 * 2 * (4096 + 8192) * 64 * 2
     assert bb >= bx3 + 2 * 2 * 4096 * 8192
+
+
+def test_splitmix64_counter_form_matches_the_published_generator():
+    """The counter form used for U^(0) equals the stateful SplitMix64
+    recurrence (state += golden-ratio increment, output the state's mix),
+    whose first outputs for seed 0 are the published e220a8397b1dcdaf,
+    6e789e6aa1b965f4, 06c45d188009454f."""
+    from rpca_inputs import splitmix64_outputs
+    mask = (1 << 64) - 1
+
+    def mix(z):
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        return z ^ (z >> 31)
+
+    assert [int(x) for x in splitmix64_outputs(0, 0, 3)] == [
+        0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    for seed in (1, 12345, (1 << 64) - 7):
+        state, ref = seed, []
+        for _ in range(40):
+            state = (state + 0x9E3779B97F4A7C15) & mask
+            ref.append(mix(state))
+        assert [int(x) for x in splitmix64_outputs(seed, 0, 40)] == ref
+        assert [int(x) for x in splitmix64_outputs(seed, 17, 5)] == ref[17:22]
+
+
+def test_splitmix_gaussian_init_is_standard_normal():
+    """Box-Muller on the SplitMix64 uniforms: mean 0, variance 1, and the
+    normal's 1-sigma and 2-sigma masses, within sampling error at 2e5 draws;
+    distinct seeds give distinct starts; the layout is entry (i, c) from
+    counter pair k = c m + i."""
+    from rpca_inputs import splitmix64_outputs, splitmix_gaussian_init
+    U = splitmix_gaussian_init(4000, 50, 9)
+    x = U.ravel()
+    assert abs(x.mean()) < 0.01 and abs(x.var() - 1.0) < 0.01
+    assert abs(np.mean(np.abs(x) < 1.0) - 0.682689) < 0.005
+    assert abs(np.mean(np.abs(x) < 2.0) - 0.954500) < 0.003
+    assert not np.array_equal(U, splitmix_gaussian_init(4000, 50, 10))
+    i, c, m = 123, 7, 4000
+    k = c * m + i
+    a, b = (int(v) >> 11 for v in splitmix64_outputs(9, 2 * k, 2))
+    z = math.sqrt(-2.0 * math.log(1.0 - a * 2.0 ** -53)) * math.cos(2.0 * math.pi * b * 2.0 ** -53)
+    assert U[i, c] == float(np.float32(z))
