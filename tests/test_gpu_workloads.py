@@ -1,0 +1,185 @@
+"""The named workloads at full size against the FP64 oracle, through the C ABI.
+
+* m = 4000, n = 8000, E = 16, r = 20: the whole 200-round trajectory in FP32
+  rounds and in three-product BF16 rounds, with the launch shape pinned to the
+  one the autotuner keeps on this workload (16 V-pass row splits, one column
+  group per V-pass wave, two S-pass column phases).
+* m = 8000, n = 32000, E = 32, r = 40, 15% corruption (the controller's
+  evaluation instance): three full rounds in FP32 and three-product BF16;
+  and an instance of the same recipe at 800 x 3200 (eight clients of 400
+  columns) through 300 rounds under the lambda continuation.
+* m = 20000, n = 100000, E = 50, r = 64, geometric spectrum: the oracle cannot
+  run whole rounds of it in test time, so the first round is checked on
+  outputs it computes one by one (as in test_gpu_uneven): V^(1) of every
+  client (eq. "condition1" with S^(0) = 0), S^(1) on sampled rows (eq.
+  "optS"), and U^(1) on sampled rows (closed-form client step and the mean
+  over clients, eq. "U_agg"); each depends only on the rows or columns
+  compared.
+
+Bars: 1e-5 relative Frobenius for FP32 rounds (the workload definition's);
+2e-5 for three-product BF16 rounds, whose products carry about 2^-17
+relative error each (16 significand bits of the hi/lo splits)."""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import oracle.reference as O
+from gpu_helpers import TOL, announce, init_for, rel
+from rpca_inputs import RECIPES, planted_instance_large, equal_widths, recipe
+
+pytestmark = pytest.mark.gpu
+
+X3_TOL = 2e-5
+
+
+def _LS(s, m):
+    import torch
+    L, S = s.get_LS(-1)
+    torch.cuda.synchronize()
+    return L[:, :m].T.double().cpu().numpy(), S[:, :m].T.double().cpu().numpy()
+
+
+@functools.lru_cache(maxsize=1)
+def _c1():
+    inst = recipe("plain_4000x8000_r20", seed=0)
+    U0 = init_for(inst, 20, 7)
+    lam = 1.0 / math.sqrt(inst.n)
+    announce("oracle: 4000 x 8000, r = 20, 200 rounds")
+    res = O.dcfpca(inst.blocks(), 20, 0.1, lam, 200, U0, record=False)
+    return inst, U0, lam, res.L_full(), res.S_full()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_4000x8000_r20_200_rounds(precision):
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    inst, U0, lam, Lo, So = _c1()
+    announce(f"4000 x 8000 r=20, 200 rounds, {precision}, shape (16, 1, 2)")
+    s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 20, 0.1, lam, colmajor(U0),
+               bf16x3=precision == "bf16x3")
+    s.set_launch_shape(row_splits=16, column_groups=1, spass_phases=2)
+    s.step(200)
+    Lg, Sg = _LS(s, inst.m)
+    eL, eS = rel(Lg, Lo), rel(Sg, So)
+    announce(f"{precision}: relL={eL:.3e} relS={eS:.3e} shape={s.launch_shape()}")
+    tol = TOL if precision == "fp32" else X3_TOL
+    assert eL <= tol and eS <= tol
+
+
+@functools.lru_cache(maxsize=1)
+def _c4():
+    inst = recipe("plain_8000x32000_r40", seed=0)
+    U0 = init_for(inst, 40, 7)
+    lam = 1.0 / math.sqrt(inst.n)
+    announce("oracle: 8000 x 32000, r = 40, 3 rounds")
+    res = O.dcfpca(inst.blocks(), 40, 0.1, lam, 3, U0, record=False)
+    return inst, U0, lam, res.L_full(), res.S_full()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_8000x32000_r40_three_rounds(precision):
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    inst, U0, lam, Lo, So = _c4()
+    announce(f"8000 x 32000 r=40, 3 rounds, {precision}")
+    s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 40, 0.1, lam, colmajor(U0),
+               bf16x3=precision == "bf16x3")
+    s.step(3)
+    Lg, Sg = _LS(s, inst.m)
+    eL, eS = rel(Lg, Lo), rel(Sg, So)
+    announce(f"{precision}: relL={eL:.3e} relS={eS:.3e}")
+    tol = TOL if precision == "fp32" else X3_TOL
+    assert eL <= tol and eS <= tol
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_8000x32000_recipe_reduced_300_rounds_continuation(precision):
+    """800 x 3200 with the evaluation workload's recipe (rank 40, 15%
+    Bernoulli corruption of magnitude U[5, 20], r = 40), eight clients of 400
+    columns: lambda_t = max(lambda, max|M| 0.8^t) until it reaches lambda,
+    then lambda, 300 rounds in all, against the oracle run with the same
+    schedule (FP32 values of lambda_t on both sides)."""
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    cfg = RECIPES["plain_8000x32000_r40"]
+    inst = planted_instance_large(800, equal_widths(3200, 8), cfg["rstar"], cfg["s"],
+                                  values=cfg["values"], lo=cfg["lo"], hi=cfg["hi"], seed=3)
+    inst.M = np.asarray(inst.M, dtype=np.float64)
+    U0 = init_for(inst, 40, 7)
+    lam = float(np.float32(1.0 / math.sqrt(inst.n)))
+    mx = float(np.abs(inst.M).max())
+    sched = []
+    while len(sched) < 300:
+        sched.append(float(np.float32(max(lam, mx * 0.8 ** len(sched)))))
+    announce(f"800 x 3200 r=40 continuation, 300 rounds, {precision}; "
+             f"lambda reached at round {sched.index(lam)}")
+    s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 40, 0.1, lam, colmajor(U0),
+               bf16x3=precision == "bf16x3")
+    for lt in sched:
+        s.set_lambda(lt)
+        s.step(1)
+    Lg, Sg = _LS(s, inst.m)
+    res = O.dcfpca(inst.blocks(), 40, 0.1, lam, len(sched), U0, lam_schedule=sched)
+    eL, eS = rel(Lg, res.L_full()), rel(Sg, res.S_full())
+    hist = [s.stats(t) for t in range(len(sched))]
+    ef = max(abs(g["objective"] - o["objective"]) / abs(o["objective"])
+             for g, o in zip(hist, res.history))
+    announce(f"{precision}: relL={eL:.3e} relS={eS:.3e} max objective rel={ef:.3e} "
+             f"relerr vs L*={rel(Lg, inst.Ustar @ inst.Vstar.T):.3e}")
+    tol = TOL if precision == "fp32" else X3_TOL
+    assert eL <= tol and eS <= tol and ef <= tol
+
+
+@functools.lru_cache(maxsize=1)
+def _c3():
+    """The instance, U^(0), and the oracle's first-round outputs: V of every
+    client, S and U on 48 sampled rows."""
+    inst = recipe("geom_20000x100000_r64", seed=0)
+    m, n, r, rho = inst.m, inst.n, 64, 0.1
+    lam = 1.0 / math.sqrt(n)
+    U0 = init_for(inst, r, 7)
+    rows = np.sort(np.random.default_rng(13).choice(m, size=48, replace=False))
+    announce(f"oracle: first round of 20000 x 100000, r = 64 (V of all clients, rows {rows[:4]}...)")
+    off = inst.offsets
+    Vo, So, Uo = [], [], np.zeros((rows.size, r))
+    for i in range(inst.E):
+        Mi = np.asarray(inst.M[:, off[i]:off[i + 1]], dtype=np.float64)
+        Vi = O.ridge_V(U0, Mi, rho)                          # S^(0) = 0
+        Vo.append(Vi)
+        Si = O.soft_threshold(Mi[rows] - U0[rows] @ Vi.T, lam)
+        So.append(Si)
+        Uo += O.closed_U(Vi, Si, Mi[rows], rho, Mi.shape[1], n) / inst.E
+    return inst, U0, lam, rows, np.concatenate(Vo, axis=0), So, Uo
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_20000x100000_r64_first_round(precision):
+    import torch
+
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    inst, U0, lam, rows, Vo, So, Uo = _c3()
+    m, n = inst.m, inst.n
+    announce(f"20000 x 100000 r=64 first round, {precision}")
+    s = DCFPCA(colmajor(inst.M), inst.widths, m, 64, 0.1, lam, colmajor(U0),
+               bf16x3=precision == "bf16x3")
+    s.step(1)
+    Ug, Vg = s.get_factors()
+    torch.cuda.synchronize()
+    Ug = Ug[:, :m].T.double().cpu().numpy()
+    Vg = Vg[:, :n].T.double().cpu().numpy()
+    Sg = []
+    for i in range(inst.E):
+        _, S_i = s.get_LS(i)
+        torch.cuda.synchronize()
+        Sg.append(S_i[:, rows].T.double().cpu().numpy())
+        del S_i
+    s.close()
+    eV = rel(Vg, Vo)
+    eS = rel(np.concatenate(Sg, axis=1), np.concatenate(So, axis=1))
+    eU = rel(Ug[rows], Uo)
+    announce(f"{precision}: relV={eV:.3e} relS(rows)={eS:.3e} relU(rows)={eU:.3e}")
+    tol = TOL if precision == "fp32" else X3_TOL
+    assert eV <= tol and eS <= tol and eU <= tol
