@@ -42,11 +42,15 @@ Readings taken where the paper is silent, garbled or ambiguous:
   (V, S) update of the round, with U_i the client's factor before its U step.
 * A lambda schedule (lambda_t per round; the paper fixes lambda, so this is
   the caller's choice, e.g. a continuation down to the target) is read as:
-  every soft-threshold of round t uses lambda_t, and S^(t), which round t's V
-  update consumes, is re-evaluated at lambda_t from the residual that produced
-  it (M_i - U V_i^T of the previous round). With one alternation and K = 1 the
-  previous S is exactly that soft-threshold, so a constant schedule is the
-  plain method.
+  round t minimises the objective at lambda_t, so its alternation starts with
+  the S-subproblem (eq. "optS") at lambda_t solved exactly for the factors
+  that produced the last residual, S^(t) = soft(M_i - U^(t-1) V_i^(t)T,
+  lambda_t), the S that objective prescribes for those factors; every later
+  soft-threshold of the round uses lambda_t too. With one alternation and
+  K = 1 the stored S of the previous round is exactly that soft-threshold
+  when lambda does not change, so a constant schedule is the plain method.
+  (Keeping the stored S instead would start round t from an S that is optimal
+  for lambda_{t-1}, not for the objective the round descends.)
 
 Parity pins live in the test suite; every function here is pinned by at least
 one check that does not retype its formula (closed forms, library routines of

@@ -238,6 +238,55 @@ def test_hand_worked_round_golden():
         assert h["nnz"] == exp["nnz"]
 
 
+def test_hand_worked_decaying_step_golden():
+    """Two GRAD rounds with eta_t = eta0 / sqrt(t + 1) (Section 4.2's decaying
+    rate, rounds indexed from 0), worked by hand: pins the schedule's index
+    (a constant step or a schedule indexed from 1 gives other values)."""
+    with open(os.path.join(GOLDEN, "hand_2x2_eta_sqrt_two_rounds.json")) as f:
+        gold = json.load(f)
+    inp, exp = gold["inputs"], gold["expected"]
+    M = np.array(inp["M"])
+    Ms = [M[:, :1], M[:, 1:]]
+    U0 = np.array(inp["U0"])
+    res = O.dcfpca(Ms, inp["r"], inp["rho"], inp["lambda"], inp["T"], U0, K=1, inner=1,
+                   u_mode="grad", eta0=inp["eta0"], eta_sched="sqrt")
+    np.testing.assert_allclose(res.U, np.array(exp["U"]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(np.vstack(res.V), np.array(exp["V"]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(res.S_full(), np.array(exp["S"]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(res.L_full(), np.array(exp["L"]), rtol=0, atol=1e-15)
+    h = res.history[1]
+    assert abs(h["objective"] - exp["objective_round1"]) <= 1e-14
+    assert abs(h["lambda_fro_sq"] - exp["lambda_fro_sq_round1"]) <= 1e-15
+    assert h["nnz"] == exp["nnz_round1"]
+    # The same rounds with a constant step differ.
+    res_c = O.dcfpca(Ms, inp["r"], inp["rho"], inp["lambda"], inp["T"], U0, u_mode="grad",
+                     eta0=inp["eta0"], eta_sched="const")
+    assert np.max(np.abs(res_c.U - np.array(exp["U"]))) > 1e-3
+
+
+def test_hand_worked_lambda_schedule_golden():
+    """A lambda schedule (0.5, then 0.25), worked by hand: round 1's V update
+    consumes S re-solved at lambda_1 for the factors that produced the last
+    residual, not the stored S of round 0 (whose V would differ)."""
+    with open(os.path.join(GOLDEN, "hand_2x2_lambda_schedule.json")) as f:
+        gold = json.load(f)
+    inp, exp = gold["inputs"], gold["expected"]
+    M = np.array(inp["M"])
+    Ms = [M[:, :1], M[:, 1:]]
+    U0 = np.array(inp["U0"])
+    res = O.dcfpca(Ms, inp["r"], inp["rho"], inp["lambda"], inp["T"], U0, K=1, inner=1,
+                   u_mode="grad", eta0=inp["eta0"], lam_schedule=inp["lam_schedule"])
+    np.testing.assert_allclose(res.U, np.array(exp["U"]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(np.vstack(res.V), np.array(exp["V"]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(res.S_full(), np.array(exp["S"]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(res.L_full(), np.array(exp["L"]), rtol=0, atol=1e-15)
+    h = res.history[1]
+    assert abs(h["objective"] - exp["objective_round1"]) <= 1e-14
+    assert abs(h["lambda_fro_sq"] - exp["lambda_fro_sq_round1"]) <= 1e-15
+    assert h["nnz"] == exp["nnz_round1"]
+    assert np.max(np.abs(np.vstack(res.V) - np.array(exp["stored_reading_V"]))) > 1e-2
+
+
 def _tiny_instance(seed=11, m=40, widths=(7, 13, 5, 15), r=3, s=0.08):
     inst = planted_instance(m, list(widths), r, s, values="uniform", hi=10.0, seed=seed)
     return inst, gaussian_init(m, r, seed + 100)
