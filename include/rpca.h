@@ -178,6 +178,26 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* p,
                       const float* U0, int64_t ldu,
                       void* workspace, size_t ws_bytes, void* stream);
 
+/* rpca_init for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * workspace is a static device array of the library,
+ * RPCA_STATIC_WORKSPACE_BYTES per GPU, which each GPU the library runs on
+ * holds until the process ends. The call allocates no device memory and
+ * calls no allocating routine; inputs, parameters, stream and every later
+ * call behave as with rpca_init. The GPU is the current device.
+ *  - Parameters whose rpca_workspace_bytes exceed the array are refused with
+ *    RPCA_EWORKSPACE (rpca_last_error(NULL) gives both sizes).
+ *  - The array is shared by every context created this way on one GPU, so at
+ *    most one such context may live per GPU: a second rpca_init_static there
+ *    returns RPCA_ESTATE until the first is destroyed. The array keeps the
+ *    last context's contents; rpca_init_static clears it as rpca_init clears
+ *    its workspace. Calls from several threads that overlap on one GPU race.
+ */
+#define RPCA_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+rpca_status rpca_init_static(rpca_ctx** out, const rpca_params* p,
+                             const float* const* M_blocks, const int64_t* ldm,
+                             const float* U0, int64_t ldu, void* stream);
+
 /* Enqueue `rounds` rounds of Algorithm 1 (rounds >= 0). Asynchronous. */
 rpca_status rpca_step(rpca_ctx* c, int32_t rounds);
 

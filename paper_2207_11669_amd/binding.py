@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rpca_workspace_bytes": (c_int32, [POINTER(RpcaParams), POINTER(c_size_t)]),
         "rpca_init": (c_int32, [POINTER(vp), POINTER(RpcaParams), POINTER(vp), POINTER(c_int64),
                                 vp, c_int64, vp, c_size_t, vp]),
+        "rpca_init_static": (c_int32, [POINTER(vp), POINTER(RpcaParams), POINTER(vp),
+                                       POINTER(c_int64), vp, c_int64, vp]),
         "rpca_step": (c_int32, [vp, c_int32]),
         "rpca_autotune": (c_int32, [vp, c_int32, POINTER(RpcaLaunchShape)]),
         "rpca_get_launch_shape": (c_int32, [vp, POINTER(RpcaLaunchShape)]),
@@ -188,7 +190,9 @@ class DCFPCA:
     owns columns offsets[i]:offsets[i+1] in order. U0_cols: (r, ldu) tensor
     with U^(0) column-major, or None: the library draws U^(0) on the device
     from `seed` (i.i.d. N(0, 1), the rule stated with rpca_init). bf16=True
-    creates the context with
+    static_workspace=True creates the context with rpca_init_static (the
+    library's static device workspace; no workspace tensor is allocated).
+    bf16=True creates the context with
     RPCA_FLAG_BF16: rounds run in BF16 until set_precision("fp32").
     bf16x3=True (RPCA_FLAG_BF16X3): rounds run as three-product BF16.
     """
@@ -197,7 +201,7 @@ class DCFPCA:
                  U0_cols, K: int = 1, inner: int = 1, u_mode: str = "closed",
                  eta0: float = 0.0, eta_sched: str = "const", store_s: bool = False,
                  graph: bool = False, stream=None, bf16: bool = False, bf16x3: bool = False,
-                 seed: int = 0):
+                 seed: int = 0, static_workspace: bool = False):
         import torch
         self._lib = load_library()
         if not (M_cols.is_cuda and M_cols.dtype == torch.float32 and M_cols.is_contiguous()):
@@ -219,7 +223,8 @@ class DCFPCA:
             raise ValueError(err)
         self.device = M_cols.device
         self.M_cols = M_cols  # borrowed by the library: keep it alive
-        self.ws = torch.empty(workspace_bytes(self.params), dtype=torch.uint8, device=self.device)
+        self.ws = None if static_workspace else torch.empty(
+            workspace_bytes(self.params), dtype=torch.uint8, device=self.device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
             if graph and stream.cuda_stream == 0:
@@ -240,9 +245,14 @@ class DCFPCA:
         ctx = c_void_p()
         u0 = c_void_p(U0_cols.data_ptr()) if U0_cols is not None else c_void_p(None)
         ldu = int(U0_cols.shape[1]) if U0_cols is not None else 0
-        st = self._lib.rpca_init(ctypes.byref(ctx), ctypes.byref(self.params), self._ptrs,
-                                 self._ldms, u0, ldu, c_void_p(self.ws.data_ptr()),
-                                 self.ws.numel(), c_void_p(self.stream.cuda_stream))
+        if static_workspace:
+            st = self._lib.rpca_init_static(ctypes.byref(ctx), ctypes.byref(self.params),
+                                            self._ptrs, self._ldms, u0, ldu,
+                                            c_void_p(self.stream.cuda_stream))
+        else:
+            st = self._lib.rpca_init(ctypes.byref(ctx), ctypes.byref(self.params), self._ptrs,
+                                     self._ldms, u0, ldu, c_void_p(self.ws.data_ptr()),
+                                     self.ws.numel(), c_void_p(self.stream.cuda_stream))
         if st < 0:
             raise RpcaError(st, "rpca_init failed: " + last_init_error())
         self.warning = st

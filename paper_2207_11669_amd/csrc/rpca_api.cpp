@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -59,6 +60,7 @@ struct rpca_ctx {
   size_t ws_bytes = 0;
   std::vector<std::pair<size_t, size_t>> own_ranges;
   std::vector<int64_t> widths;
+  int static_dev = -1;  // GPU whose static workspace this context uses (rpca_init_static)
 };
 
 namespace {
@@ -578,6 +580,61 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   return RPCA_OK;
 }
 
+}  // extern "C"
+
+// The static workspace of rpca_init_static: one array per GPU (each device's
+// code object holds its own copy), at most one live context per GPU. Host code
+// never passes the array's name to a kernel or a HIP call: the name is a
+// host-side stand-in, and the device address comes from hipGetSymbolAddress,
+// taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[RPCA_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+rpca_ctx* g_static_owner[kMaxDevices] = {};
+}  // namespace
+
+extern "C" {
+
+rpca_status rpca_init_static(rpca_ctx** out, const rpca_params* prm, const float* const* M_blocks,
+                             const int64_t* ldm, const float* U0, int64_t ldu, void* stream) {
+  g_init_err.clear();
+  if (!out) return init_fail(RPCA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (const char* msg = check_params(prm)) return init_fail(RPCA_EINVAL, msg);
+  const size_t need = make_layout(prm).total;
+  if (need > RPCA_STATIC_WORKSPACE_BYTES)
+    return init_fail(RPCA_EWORKSPACE, "these parameters need " + std::to_string(need) +
+                                          " bytes of workspace; the static workspace holds " +
+                                          std::to_string(RPCA_STATIC_WORKSPACE_BYTES));
+  int dev = -1;
+  const hipError_t ed = hipGetDevice(&dev);
+  if (ed != hipSuccess) return init_fail(RPCA_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(ed));
+  if (dev < 0 || dev >= kMaxDevices)
+    return init_fail(RPCA_EINVAL, "device index beyond the library's table of " +
+                                      std::to_string(kMaxDevices));
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (g_static_owner[dev])
+    return init_fail(RPCA_ESTATE, "another context uses this GPU's static workspace; destroy it first");
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return init_fail(RPCA_EDEVICE, std::string("hipGetSymbolAddress of the static workspace: ") +
+                                         hipGetErrorString(e));
+    g_static_ptr[dev] = ptr;
+  }
+  const rpca_status st = rpca_init(out, prm, M_blocks, ldm, U0, ldu, g_static_ptr[dev],
+                                   RPCA_STATIC_WORKSPACE_BYTES, stream);
+  if (st >= 0 && *out) {
+    (*out)->static_dev = dev;
+    g_static_owner[dev] = *out;
+  }
+  return st;
+}
+
 // Two rounds from a steady state (rebuilt S, finalize deferred) as one graph
 // launch; the graph for this buffer parity is captured on first use. The host
 // state after two rounds equals the state before them except for the count.
@@ -1000,6 +1057,10 @@ const char* rpca_last_error(const rpca_ctx* c) {
 
 void rpca_destroy(rpca_ctx* c) {
   if (!c) return;
+  if (c->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
+  }
   for (hipGraphExec_t& g : c->gexec)
     if (g) (void)hipGraphExecDestroy(g);
   delete c;
