@@ -169,7 +169,8 @@ def test_solve_to_target_and_relative_error():
 
 
 def test_full_size_4000x8000_r20_parity():
-    """The m = 4000, n = 8000, E = 16, r = 20 workload at full size, in the
-    launch configuration the benchmark times, for a few rounds."""
+    """The m = 4000, n = 8000, E = 16, r = 20 workload at full size, default
+    launch shape, for a few rounds (test_gpu_workloads runs its 200 rounds in
+    the autotuner's shape)."""
     inst = recipe("plain_4000x8000_r20", seed=0)
     _parity(inst, 20, 3, u_mode="closed")

@@ -17,8 +17,12 @@
   compared.
 
 Bars: 1e-5 relative Frobenius for FP32 rounds (the workload definition's);
-2e-5 for three-product BF16 rounds, whose products carry about 2^-17
-relative error each (16 significand bits of the hi/lo splits)."""
+2e-5 for a few three-product BF16 rounds, whose products carry about 2^-17
+relative error each (16 significand bits of the hi/lo splits), 128 times
+FP32's unit roundoff. A long trajectory amplifies the per-round rounding:
+on the 4000 x 8000 workload 200 FP32 rounds end 2.2e-6 from the oracle, about
+40 times FP32's 6e-8 unit roundoff; the three-product rounds get 5e-5 there,
+which leaves a factor of 2.5 over their observed 1.9e-5."""
 import functools
 import math
 
@@ -32,6 +36,7 @@ from rpca_inputs import RECIPES, planted_instance_large, equal_widths, recipe
 pytestmark = pytest.mark.gpu
 
 X3_TOL = 2e-5
+X3_TOL_LONG = 5e-5  # 200-round trajectories (module docstring)
 
 
 def _LS(s, m):
@@ -64,7 +69,7 @@ def test_4000x8000_r20_200_rounds(precision):
     Lg, Sg = _LS(s, inst.m)
     eL, eS = rel(Lg, Lo), rel(Sg, So)
     announce(f"{precision}: relL={eL:.3e} relS={eS:.3e} shape={s.launch_shape()}")
-    tol = TOL if precision == "fp32" else X3_TOL
+    tol = TOL if precision == "fp32" else X3_TOL_LONG
     assert eL <= tol and eS <= tol
 
 
