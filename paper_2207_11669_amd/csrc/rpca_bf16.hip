@@ -133,15 +133,28 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct) acc[g][ct] = f4{0.f, 0.f, 0.f, 0.f};
 
-  struct Chunk {
+  // Operands of one 32-row chunk. M streams from HBM and is kept two chunks
+  // ahead (ring of two). The U operands come from L2 and each has a single
+  // buffer, refilled for the next chunk right after its last use in this
+  // one: the previous U's hP halves (the S rebuild) once the rebuild's MFMA
+  // has issued, U's hB once the W products have. Holding them two chunks
+  // ahead as well cost 64 registers in three-product rounds (hi and lo) and
+  // left one wave per SIMD at r = 64.
+  struct MChunk {
     u4 m[KG];                    // BF16 copy: M rows 32 ch + 8 (l/16) + e of column 16 g + l%16
     f4 mf[X3 ? KG : 1][2];       // X3: the same rows in FP32
+  };
+  struct OpA {
     bf8 uo[2][NK], uol[X3 ? 2 : 1][NK];  // previous U, hP halves (hi, lo)
+  };
+  struct OpB {
     bf8 u[RT], ul[X3 ? RT : 1];          // U, hB (hi, lo)
   };
   constexpr int kDepth = 2;
-  Chunk ring[kDepth];
-  auto load_chunk = [&](Chunk& c, int k) {
+  MChunk ring[kDepth];
+  OpA oa;
+  OpB ob;
+  auto load_m = [&](MChunk& c, int k) {
     const int ch = ch0 + ph + kPh * k;
     if constexpr (X3) {
       const uint32_t rowb = (uint32_t)(32 * ch + 8 * lg) * 4u;
@@ -154,7 +167,10 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
 #pragma unroll
       for (int g = 0; g < KG; ++g) c.m[g] = Mv[g * gstride + (int64_t)ch * 64];
     }
+  };
+  auto load_a = [&](OpA& c, int k) {
     if (MODE == kSRecompute) {
+      const int ch = ch0 + ph + kPh * k;
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -164,6 +180,9 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
           if constexpr (X3) c.uol[t][kb] = UohP[uhl + o];
         }
     }
+  };
+  auto load_b = [&](OpB& c, int k) {
+    const int ch = ch0 + ph + kPh * k;
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct) {
       const int64_t o = ((int64_t)ch * RT + ct) * 64 + lane;
@@ -171,7 +190,29 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
       if constexpr (X3) c.ul[ct] = UhB[uhl + o];
     }
   };
-  auto compute_chunk = [&](const Chunk& c, int k) {
+  // The S rebuild's product for every column group: (Uo Vo^T) rows
+  // 8 (l/16) + e of column 16 g + l%16, two 16x16 halves.
+  f4 o[KG][2];
+  auto mfma1 = [&]() {
+    if (MODE == kSRecompute) {
+#pragma unroll
+      for (int g = 0; g < KG; ++g) {
+        o[g][0] = f4{0.f, 0.f, 0.f, 0.f};
+        o[g][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < NK; ++kb) {
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            if constexpr (X3)
+              o[g][t] = mfma3(oa.uo[t][kb], oa.uol[t][kb], vb[g][kb], vbl[g][kb], o[g][t]);
+            else
+              o[g][t] = mfma_bf16(oa.uo[t][kb], vb[g][kb], o[g][t]);
+          }
+        }
+      }
+    }
+  };
+  auto residual_mfma2 = [&](const MChunk& c, int k) {
     // Rows past m and columns past n_i are zero in the BF16 copy and in the
     // factors' packings, so they give d = 0 without a mask; the FP32 block
     // holds the caller's rows past m, which are masked.
@@ -191,20 +232,9 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
         unpack8(c.m[g], x);
       }
       if (MODE == kSRecompute) {
-        f4 o[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-        for (int kb = 0; kb < NK; ++kb) {
-#pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            if constexpr (X3)
-              o[t] = mfma3(c.uo[t][kb], c.uol[t][kb], vb[g][kb], vbl[g][kb], o[t]);
-            else
-              o[t] = mfma_bf16(c.uo[t][kb], vb[g][kb], o[t]);
-          }
-        }
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float a1 = o[e >> 2][e & 3];
+          const float a1 = o[g][e >> 2][e & 3];
           // M - S = Uo Vo^T + clip(M - Uo Vo^T, -lambda, lambda)
           d[e] = a1 + __builtin_amdgcn_fmed3f(x[e] - a1, -lam, lam);
         }
@@ -216,30 +246,38 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
         bf8 dh, dl;
         split8(d, dh, dl);
 #pragma unroll
-        for (int ct = 0; ct < RT; ++ct) acc[g][ct] = mfma3(dh, dl, c.u[ct], c.ul[ct], acc[g][ct]);
+        for (int ct = 0; ct < RT; ++ct) acc[g][ct] = mfma3(dh, dl, ob.u[ct], ob.ul[ct], acc[g][ct]);
       } else {
         const bf8 dh = pack8(d);
 #pragma unroll
-        for (int ct = 0; ct < RT; ++ct) acc[g][ct] = mfma_bf16(dh, c.u[ct], acc[g][ct]);
+        for (int ct = 0; ct < RT; ++ct) acc[g][ct] = mfma_bf16(dh, ob.u[ct], acc[g][ct]);
       }
     }
   };
   if (nk > 0) {
-    // Uniform ring as in k_vpass: every iteration loads (index clamped to the
-    // wave's last chunk), so the wait counts stay exact.
+    // Uniform loop as in k_vpass: every iteration issues the same loads
+    // (indices clamped to the wave's last chunk), so the wait counts stay
+    // exact; the fences keep each refill where it is written.
     const int nkp = (nk + kDepth - 1) / kDepth * kDepth;
-#pragma unroll
-    for (int d = 0; d < kDepth; ++d) {
-      load_chunk(ring[d], min(d, nk - 1));
-      __builtin_amdgcn_sched_barrier(0);
-    }
+    load_m(ring[0], 0);
+    load_a(oa, 0);
+    load_b(ob, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_m(ring[1], min(1, nk - 1));
+    __builtin_amdgcn_sched_barrier(0);
     for (int k0 = 0; k0 < nkp; k0 += kDepth) {
 #pragma unroll
       for (int d = 0; d < kDepth; ++d) {
         const int k = k0 + d;
-        if (k < nk) compute_chunk(ring[d], k);
+        const int kn = min(k + 1, nk - 1);
+        if (k < nk) mfma1();  // wave-uniform
         __builtin_amdgcn_sched_barrier(0);
-        load_chunk(ring[d], min(k + kDepth, nk - 1));
+        load_a(oa, kn);
+        __builtin_amdgcn_sched_barrier(0);
+        if (k < nk) residual_mfma2(ring[d], k);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b(ob, kn);
+        load_m(ring[d], min(k + kDepth, nk - 1));
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -357,19 +395,30 @@ __global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __res
         vm[rt][e] = row < p.m ? ((uint32_t)((8 * lg + e) * cl.ldm) + (uint32_t)row) * 4u : kOffNone;
     }
   }
-  struct Chunk {
+  // Operands of one 32-column chunk. M streams from HBM and is kept two
+  // chunks ahead (ring of two). The V operands come from L2 and each has a
+  // single buffer, refilled for the next chunk right after its last use in
+  // this one: the hP halves (MFMA 1) once MFMA 1 has issued, hB (MFMA 2) once
+  // MFMA 2 has. Holding them two chunks ahead as well cost 64 registers in
+  // three-product rounds (hi and lo) and left one wave per SIMD at r = 64.
+  struct MChunk {
     u4 m[kRT];                  // M[row arow0 + 16 rt + l%16][col 32 cc + 8 (l/16) + e]
     float mf[X3 ? kRT : 1][8];  // X3: the same entries in FP32
+  };
+  struct OpA {
     bf8 va[2][NK], val[X3 ? 2 : 1][NK];  // V hP halves (hi, lo)
+  };
+  struct OpB {
     bf8 vb[RT], vbl[X3 ? RT : 1];        // V hB (hi, lo)
   };
   constexpr int kDepth = 2;
-  Chunk ring[kDepth];
+  MChunk ring[kDepth];
+  OpA oa;
+  OpB ob;
   const int nch = (cl.n + 31) >> 5;
   const int nk = (nch - phase + kPh - 1) / kPh;  // chunks phase, phase + kPh, ... below nch
-  auto load_chunk = [&](Chunk& c, int k) {
+  auto load_m = [&](MChunk& c, int k) {
     const int cc = phase + kPh * k;
-    const int64_t vch = (cl.vrow0 >> 5) + cc;
     if constexpr (X3) {
       const rsrc_t rM = make_rsrc(cl.M + (int64_t)32 * cc * cl.ldm, chunk_bytes_from(cl.n, 32 * cc, cl.ldm));
 #pragma unroll
@@ -380,6 +429,9 @@ __global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __res
 #pragma unroll
       for (int rt = 0; rt < kRT; ++rt) c.m[rt] = Ms[((int64_t)rt * nvc32 + cc) * 64];
     }
+  };
+  auto load_a = [&](OpA& c, int k) {
+    const int64_t vch = (cl.vrow0 >> 5) + phase + kPh * k;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -388,6 +440,9 @@ __global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __res
         c.va[t][kb] = VhP[o];
         if constexpr (X3) c.val[t][kb] = VhP[vhl + o];
       }
+  };
+  auto load_b = [&](OpB& c, int k) {
+    const int64_t vch = (cl.vrow0 >> 5) + phase + kPh * k;
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct) {
       const int64_t o = (vch * RT + ct) * 64 + lane;
@@ -395,21 +450,30 @@ __global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __res
       if constexpr (X3) c.vbl[ct] = VhB[vhl + o];
     }
   };
-  auto compute_chunk = [&](const Chunk& c) {
-    float l2 = 0.f, l1 = 0.f;
+  // MFMA 1 for every row tile: (U V^T)^T, two 16x16 halves per tile.
+  f4 o[kRT][2];
+  auto mfma1 = [&]() {
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) {
-      f4 o[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+      o[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
+      o[rt][1] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kb = 0; kb < NK; ++kb) {
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           if constexpr (X3)
-            o[t] = mfma3(c.va[t][kb], c.val[t][kb], ub[rt][kb], ubl[rt][kb], o[t]);
+            o[rt][t] = mfma3(oa.va[t][kb], oa.val[t][kb], ub[rt][kb], ubl[rt][kb], o[rt][t]);
           else
-            o[t] = mfma_bf16(c.va[t][kb], ub[rt][kb], o[t]);
+            o[rt][t] = mfma_bf16(oa.va[t][kb], ub[rt][kb], o[rt][t]);
         }
       }
+    }
+  };
+  // Residual, soft-threshold and statistics per row tile, then MFMA 2.
+  auto threshold_mfma2 = [&](const MChunk& c) {
+    float l2 = 0.f, l1 = 0.f;
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt) {
       float x[8], lamv[8];
       if constexpr (X3) {
 #pragma unroll
@@ -419,7 +483,7 @@ __global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __res
       }
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float R = x[e] - o[e >> 2][e & 3];
+        const float R = x[e] - o[rt][e >> 2][e & 3];
         const float L = __builtin_amdgcn_fmed3f(R, -lam, lam);  // clip(R, -lam, lam)
         const float Sv = R - L;
         lamv[e] = L;
@@ -431,30 +495,41 @@ __global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __res
         bf8 lh, ll;
         split8(lamv, lh, ll);
 #pragma unroll
-        for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = mfma3(lh, ll, c.vb[ct], c.vbl[ct], accp[rt][ct]);
+        for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = mfma3(lh, ll, ob.vb[ct], ob.vbl[ct], accp[rt][ct]);
       } else {
         const bf8 lh = pack8(lamv);
 #pragma unroll
-        for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = mfma_bf16(lh, c.vb[ct], accp[rt][ct]);
+        for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = mfma_bf16(lh, ob.vb[ct], accp[rt][ct]);
       }
     }
     sl2 += (double)l2;
     sl1 += (double)l1;
   };
   if (nk > 0) {
+    // Uniform loop: every iteration issues the same loads (chunk indices
+    // clamped to the wave's last chunk), so the wait counts stay exact, and
+    // the fences keep each refill where it is written (left alone, the
+    // scheduler sinks loads towards their first use).
     const int nkp = (nk + kDepth - 1) / kDepth * kDepth;
-#pragma unroll
-    for (int d = 0; d < kDepth; ++d) {
-      load_chunk(ring[d], min(d, nk - 1));
-      __builtin_amdgcn_sched_barrier(0);
-    }
+    load_m(ring[0], 0);
+    load_a(oa, 0);
+    load_b(ob, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_m(ring[1], min(1, nk - 1));
+    __builtin_amdgcn_sched_barrier(0);
     for (int k0 = 0; k0 < nkp; k0 += kDepth) {
 #pragma unroll
       for (int d = 0; d < kDepth; ++d) {
         const int k = k0 + d;
-        if (k < nk) compute_chunk(ring[d]);
+        const int kn = min(k + 1, nk - 1);
+        if (k < nk) mfma1();  // wave-uniform
         __builtin_amdgcn_sched_barrier(0);
-        load_chunk(ring[d], min(k + kDepth, nk - 1));
+        load_a(oa, kn);
+        __builtin_amdgcn_sched_barrier(0);
+        if (k < nk) threshold_mfma2(ring[d]);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b(ob, kn);
+        load_m(ring[d], min(k + kDepth, nk - 1));
         __builtin_amdgcn_sched_barrier(0);
       }
     }
