@@ -1,15 +1,28 @@
 #!/usr/bin/env python3
-"""DCF-PCA benchmark on one MI355X: rounds of Algorithm 1 per second.
+"""DCF-PCA benchmark on one MI355X: rounds of Algorithm 1 per second, and the
+wall time to a relative error of 1e-4 against the planted low-rank part.
 
-Workload: m = 4000, n = 8000 planted rank 20 (Gaussian factors), 10% of the
-entries corrupted with magnitude U[5, 20] and a random sign, E = 16 clients of
-500 columns, r = 20, lambda = 1/sqrt(n), rho = 0.1, closed-form U step, K = 1.
-Inputs are synthetic, seeded, and resident in HBM before timing starts.
+Headline workload (`value`, rounds/s in FP32): m = 20000, n = 100000, planted
+rank 64 with singular values geometric from 100 down to 1, 5% of the entries
+corrupted (Bernoulli) with magnitude U[1, 100] and a random sign, E = 50
+clients of 2000 columns, r = 64, lambda = 1/sqrt(n), rho = 0.1, closed-form U
+step, K = 1. Inputs are synthetic, seeded, and resident in HBM before timing.
 
-Prints one JSON line with the throughput (`value`, rounds/s), the roofline of
-the dominant kernel (HIP events around every launch), the time to reach a
-relative error of 1e-4 against the planted low-rank part, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+Next to it, on the same workload: BF16 rounds (BF16 copies of M, U and V on
+BF16 MFMA) and three-product BF16 rounds (FP32 M, hi/lo splits), each with its
+rounds/s and its error against the FP64 oracle on the workload's 2000 x 2000
+sub-instance after a fixed schedule of low-precision rounds followed by FP32
+closing rounds.
+
+Time to relative error 1e-4 (where it is reachable): m = 8000, n = 32000,
+planted rank 40, 15% corruption with magnitude U[5, 20], E = 32, r = 40, for
+plain FP32 rounds, the fixed lambda continuation, the learned controller, and
+the learned controller driving three-product BF16 rounds.
+
+The FP64 CPU oracle is timed on bounded samples of both workloads, on all the
+host's cores and on one.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -25,19 +38,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DCF-PCA iters/sec + time-to-relerr 1e-4 (BF16/learned vs plain FP32), 1 GPU"
-WORKLOAD = "plain_4000x8000_r20"
-WORKLOADS = ("plain_4000x8000_r20", "uneven_10000_r32", "geom_20000x100000_r64",
+WORKLOAD = "geom_20000x100000_r64"
+EVAL_WORKLOAD = "plain_8000x32000_r40"
+SUB_WORKLOAD = "geom_2000x2000_r64"
+WORKLOADS = ("geom_20000x100000_r64", "plain_4000x8000_r20", "uneven_10000_r32",
              "plain_8000x32000_r40", "plain_500x500_r5")
 HBM_PEAK_GBS = 8000.0
 # Dense MFMA peaks of one MI355X, per algorithmic flop: three-product BF16
 # rounds run three BF16 products per product of the method.
 MFMA_PEAK_TFS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 3}
-def traffic_file(workload: str, precision: str = "fp32") -> str:
-    suffix = "" if precision == "fp32" else f"_{precision}"
-    return os.path.join(ROOT, "profiles", f"traffic_{workload}{suffix}.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_11669_amd", "csrc", f)
                for f in ("rpca_device.h", "rpca_internal.h", "rpca_vpass.hip", "rpca_spass.hip",
                          "rpca_bf16.hip", "rpca_tail.hip")]
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def traffic_file(workload: str, precision: str = "fp32") -> str:
+    suffix = "" if precision == "fp32" else f"_{precision}"
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}{suffix}.json")
 
 
 def kernel_costs(m: int, n: int, E: int, r: int, precision: str = "fp32") -> dict:
@@ -88,43 +109,62 @@ def src_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(inst, U0, r, rho, lam, budget_s: float = 12.0, max_rounds: int = 10) -> dict:
-    """The FP64 oracle timed on this host's cores. Small workloads run whole
-    rounds of the same instance; for an instance too large for it, one round
-    over a prefix of the clients (about 1/16 of the columns) is timed and
-    scaled to the full column count (the work of a round is linear in n)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_sample_rate(inst, U0, r, rho, lam, threads=None) -> dict:
+    """One round of the FP64 oracle over a prefix of the clients (about 1/16
+    of the columns), after an untimed warm-up on a sliver, scaled to the full
+    column count (a round's work is linear in n); `threads` limits the BLAS
+    threads (None: all)."""
+    import contextlib
+
     import numpy as np
     import oracle.reference as O
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
     blocks = inst.blocks()
-    if inst.M.dtype != np.float64:
-        ncols, k = 0, 0
-        while k < len(blocks) and ncols < inst.n / 16:
-            ncols += blocks[k].shape[1]
-            k += 1
-        sub = [np.asarray(b, dtype=np.float64) for b in blocks[:k]]
+    ncols, k = 0, 0
+    while k < len(blocks) and ncols < inst.n / 16:
+        ncols += blocks[k].shape[1]
+        k += 1
+    sub = [np.asarray(b, dtype=np.float64) for b in blocks[:k]]
+    ctx = threadpool_limits(limits=threads) if threads else contextlib.nullcontext()
+    with ctx:
+        used = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
         O.dcfpca([b[:, :8] for b in sub[:1]], r, rho, lam, 1, U0, record=False)
         t0 = time.perf_counter()
         O.dcfpca(sub, r, rho, lam, 1, U0, record=False)
         dt = (time.perf_counter() - t0) * inst.n / ncols
-        return {"value": 1.0 / dt, "unit": "iters/s", "cores": int(cores), "kind": "oracle",
-                "sample": f"one round of the FP64 numpy oracle over the first {k} clients "
-                          f"({ncols} of {inst.n} columns, m={inst.m}, r={r}), time scaled by "
-                          f"{inst.n / ncols:.2f} to the full instance"}
-    t0 = time.perf_counter()
-    O.dcfpca(blocks, r, rho, lam, 1, U0, record=False)
-    one = time.perf_counter() - t0
-    rounds = int(max(1, min(max_rounds, budget_s // max(one, 1e-3))))
-    t0 = time.perf_counter()
-    O.dcfpca(blocks, r, rho, lam, rounds, U0, record=False)
-    dt = time.perf_counter() - t0
-    return {"value": rounds / dt, "unit": "iters/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{rounds} rounds of the FP64 numpy oracle on the same {inst.m}x{inst.n} "
-                      f"instance (E={inst.E}, r={r}), after one untimed round"}
+    return {"value": round(1.0 / dt, 5), "cores": int(used),
+            "sample": f"one round of the FP64 numpy oracle over the first {k} of {inst.E} clients "
+                      f"({ncols} of {inst.n} columns, m={inst.m}, r={r}), time scaled by "
+                      f"{inst.n / ncols:.2f} to the full instance"}
+
+
+def cpu_baseline(inst, U0, r, rho, lam, eval_inst=None, eval_U0=None, eval_r=None) -> dict:
+    """The oracle as it stands, timed on this host: all cores and one core,
+    on the headline workload and (when given) the evaluation workload."""
+    allc = oracle_sample_rate(inst, U0, r, rho, lam)
+    one = oracle_sample_rate(inst, U0, r, rho, lam, threads=1)
+    out = {"value": allc["value"], "unit": "iters/s", "cores": allc["cores"], "kind": "oracle",
+           "sample": allc["sample"], "cpu_model": cpu_model(),
+           "host_cpus": os.cpu_count(), "single_thread_value": one["value"]}
+    if eval_inst is not None:
+        ea = oracle_sample_rate(eval_inst, eval_U0, eval_r, rho, 1.0 / math.sqrt(eval_inst.n))
+        e1 = oracle_sample_rate(eval_inst, eval_U0, eval_r, rho, 1.0 / math.sqrt(eval_inst.n),
+                                threads=1)
+        out["eval_workload"] = {"workload": EVAL_WORKLOAD, "value": ea["value"],
+                                "cores": ea["cores"], "single_thread_value": e1["value"],
+                                "sample": ea["sample"]}
+    return out
 
 
 def continuation(lam: float, lam0: float, gamma: float = 0.8) -> list:
@@ -135,7 +175,105 @@ def continuation(lam: float, lam0: float, gamma: float = 0.8) -> list:
     return out
 
 
-def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_rounds,
+def measure(M_cols, inst, r, rho, lam, U0_cols, args, precision: str, workload: str) -> dict:
+    """Rounds/s of one precision on a resident instance: warm-up rounds, the
+    autotuner, then `steps` rounds between HIP events on the library's stream,
+    and per-kernel HIP events over `profile_rounds` more rounds."""
+    import torch
+
+    from paper_2207_11669_amd import DCFPCA
+    eta0 = 0.0 if args.u_mode == "closed" else 1e-4
+    s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode, eta0=eta0,
+               graph=args.graph, bf16=precision == "bf16", bf16x3=precision == "bf16x3")
+    log(f"{precision}: warmup {args.warmup}")
+    s.step(args.warmup)
+    shape = s.autotune(args.autotune) if args.autotune > 0 else s.launch_shape()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    log(f"{precision}: timing {args.steps} rounds")
+    ev0.record(s.stream)
+    s.step(args.steps)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    st = s.stats()
+    if not math.isfinite(st["objective"]):
+        raise RuntimeError(f"{precision}: non-finite objective")
+    log(f"{precision}: per-kernel events over {args.profile_rounds} rounds")
+    prof = s.profile(args.profile_rounds)
+    s.close()
+    costs = kernel_costs(inst.m, inst.n, inst.E, r, precision)
+    total = {k: v[0] * v[1] for k, v in prof.items()}
+    dom = max(("vpass", "spass"), key=lambda k: total[k])
+    roof = roofline_of(costs[dom], prof[dom][0] / 1e3, precision)
+    # The launch shape selects the kernel instance of an FP32 pass: counters
+    # are kept per instance ("spass:phases=2", "vpass:column_groups=1", ...).
+    variant = dom
+    if precision == "fp32":
+        variant += (f":phases={shape['spass_phases']}" if dom == "spass"
+                    else f":column_groups={shape['column_groups']}")
+    traffic = None
+    path = traffic_file(workload, precision)
+    if os.path.exists(path):
+        with open(path) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha256_16") == src_hash():
+            per = tr.get("bytes_per_launch", {})
+            traffic = per.get(variant, per.get(dom))
+    roof.update({"traffic": traffic, "kernel": variant,
+                 "algorithmic_bytes": costs[dom]["bytes"], "algorithmic_flops": costs[dom]["flops"],
+                 "avg_launch_us": {k: round(v[0] * 1e3, 2) for k, v in prof.items()},
+                 "launches_per_round": {k: v[1] / args.profile_rounds for k, v in prof.items()}})
+    return {"iters_per_s": round(args.steps / (ms / 1e3), 2), "ms_per_step": round(ms / args.steps, 5),
+            "autotuned_launch_shape": shape, "roofline": roof}
+
+
+def error_vs_oracle(precision: str, low_rounds: int, closing_rounds: int) -> dict:
+    """Relative Frobenius error of L and S against the FP64 oracle on the
+    2000 x 2000 sub-instance of the headline recipe (rank 64, geometric
+    spectrum, 5% corruption of magnitude U[1, 100], one client, r = 64):
+    after `low_rounds` rounds in `precision`, and after `closing_rounds`
+    further FP32 rounds (against the oracle's iterate after as many rounds)."""
+    import numpy as np
+    import torch
+
+    import oracle.reference as O
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    from rpca_inputs import gaussian_init, recipe
+    inst = recipe(SUB_WORKLOAD, seed=0)
+    r, rho = 64, 0.1
+    lam = 1.0 / math.sqrt(inst.n)
+    U0 = gaussian_init(inst.m, r, 7)
+    a = O.dcfpca(inst.blocks(), r, rho, lam, low_rounds, U0, record=False)
+    b = O.dcfpca(inst.blocks(), r, rho, lam, closing_rounds, a.U, S0=a.S, t0=low_rounds,
+                 record=False)
+
+    def LS(s):
+        L, S = s.get_LS(-1)
+        torch.cuda.synchronize()
+        return (L[:, :inst.m].T.double().cpu().numpy(), S[:, :inst.m].T.double().cpu().numpy())
+
+    def rel(x, y):
+        return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+    s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, r, rho, lam, colmajor(U0),
+               bf16=precision == "bf16", bf16x3=precision == "bf16x3")
+    s.step(low_rounds)
+    L1, S1 = LS(s)
+    if precision != "fp32":
+        s.set_precision("fp32")
+    s.step(closing_rounds)
+    L2, S2 = LS(s)
+    s.close()
+    return {"instance": f"{SUB_WORKLOAD} (m=n=2000, r=64, one client)",
+            "schedule": f"{low_rounds} {precision} rounds, then {closing_rounds} fp32 rounds",
+            f"after_{low_rounds}_{precision}_rounds": {"relL": rel(L1, a.L_full()),
+                                                        "relS": rel(S1, a.S_full())},
+            f"after_{closing_rounds}_fp32_closing_rounds": {"relL": rel(L2, b.L_full()),
+                                                            "relS": rel(S2, b.S_full())}}
+
+
+def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target, max_rounds,
                    schedule=None, ctl=None, lam0=None, precision="fp32") -> dict:
     """Wall time from U^(0) until ||U V^T - X Y^T||_F / ||X Y^T||_F <= 1e-4 for
     the target factors (X, Y), checked every 10 rounds with r x r Gram
@@ -143,10 +281,10 @@ def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_r
     list, or a controller deciding round by round from the recorded
     statistics), its rounds run first and count."""
     import torch
+
     from paper_2207_11669_amd import DCFPCA
     from paper_2207_11669_amd import controller as C
-    print("[bench] time to relative error 1e-4" +
-          (" (lambda schedule)" if schedule or ctl else ""), file=sys.stderr, flush=True)
+    eta0 = 0.0 if args.u_mode == "closed" else 1e-4
     s2 = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
                 eta0=eta0, bf16x3=precision == "bf16x3")
     s2.set_target(*target)
@@ -166,61 +304,24 @@ def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, max_r
     s2.close()
     return {"tol": 1e-4, "reached": bool(err <= 1e-4), "rounds": pre + done,
             "seconds": round(secs, 4), "final_relerr": err, "max_rounds": max_rounds,
-            "check_every": 10}
+            "check_every": 10, "precision": precision}
 
 
-def bf16_comparison(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target, rounds) -> dict:
-    """The same workload with BF16 rounds (RPCA_FLAG_BF16: BF16 copies of M,
-    one product each) and three-product BF16 rounds (RPCA_FLAG_BF16X3: FP32
-    M, hi/lo splits): rounds/s, and the relative error against the planted
-    L* after `rounds` rounds next to the FP32 rounds' error after as many."""
-    import torch
-    from paper_2207_11669_amd import DCFPCA
-    out = {}
-    for prec in ("bf16", "bf16x3", "fp32"):
-        print(f"[bench] {prec} rounds", file=sys.stderr, flush=True)
-        kw = {"bf16": dict(bf16=True), "bf16x3": dict(bf16x3=True), "fp32": {}}[prec]
-        d = {}
-        if prec != "fp32":
-            s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-                       eta0=eta0, **kw)
-            s.step(args.warmup)
-            if args.autotune > 0:
-                s.autotune(args.autotune)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s.step(args.steps)
-            torch.cuda.synchronize()
-            d["iters_per_s"] = round(args.steps / (time.perf_counter() - t0), 2)
-            d["avg_launch_us"] = {k: round(v[0] * 1e3, 2) for k, v in s.profile(20).items()}
-            s.close()
-        s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-                   eta0=eta0, **kw)
-        s.set_target(*target)
-        s.step(rounds)
-        d[f"relerr_after_{rounds}_rounds"] = s.target_error()
-        s.close()
-        out[prec] = d
-    return out
-
-
-def learned_controller(args, instances: int = 40, n: int = 256):
+def learned_controller(instances: int = 40, n: int = 256):
     """Train the learned lambda controller on method-generated instances
     (greedy per-round targets, MLP trained on the GPU); returns it with a
     description of its training."""
-    import math as _m
-
     import numpy as np
+
     from paper_2207_11669_amd import DCFPCA, colmajor
     from paper_2207_11669_amd import controller as C
     from rpca_inputs import controller_family, gaussian_init
-    print(f"[bench] training the learned controller on {instances} instances", file=sys.stderr,
-          flush=True)
+    log(f"training the learned controller on {instances} instances")
 
     def cases():
         for k in range(instances):
             inst, r = controller_family(10_000 + k, n)
-            lam = 1.0 / _m.sqrt(inst.n)
+            lam = 1.0 / math.sqrt(inst.n)
 
             def make(inst=inst, r=r, lam=lam):
                 s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, r, 0.1, lam,
@@ -238,6 +339,54 @@ def learned_controller(args, instances: int = 40, n: int = 256):
     return C.LearnedContinuation(params), info
 
 
+def relerr_suite(args, dev) -> tuple:
+    """Time to relative error 1e-4 against L* on the evaluation workload for
+    plain FP32 rounds, the fixed continuation, the learned controller and the
+    learned controller with three-product BF16 rounds."""
+    import numpy as np
+    import torch
+
+    from paper_2207_11669_amd import colmajor
+    from rpca_inputs import RECIPES, gaussian_init, recipe
+    log(f"generating {EVAL_WORKLOAD}")
+    inst = recipe(EVAL_WORKLOAD, seed=0)
+    cfg = RECIPES[EVAL_WORKLOAD]
+    r, rho = cfg["r"], cfg["rho"]
+    lam = 1.0 / math.sqrt(inst.n)
+    U0 = gaussian_init(inst.m, r, 7)
+    M_cols = colmajor(inst.M, device=dev)
+    U0_cols = colmajor(U0, device=dev)
+    target = (colmajor(inst.Ustar, device=dev), colmajor(inst.Vstar, device=dev), cfg["rstar"])
+    lam0 = float(np.abs(inst.M).max())
+    out = {"workload": EVAL_WORKLOAD, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
+           "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam, "rho": rho}
+    log("time to 1e-4: plain fp32")
+    out["plain_fp32"] = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target,
+                                       args.relerr_rounds)
+    log("time to 1e-4: fixed continuation")
+    sched = continuation(lam, lam0)
+    out["fixed_continuation"] = dict(
+        time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target, args.relerr_rounds,
+                       schedule=sched),
+        kind="lambda_t = max(lambda, max|M| 0.8^t)", schedule_rounds=len(sched))
+    ctl, info = learned_controller()
+    out["controller_training"] = info
+    log("time to 1e-4: learned controller")
+    out["learned"] = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target,
+                                    args.relerr_rounds, ctl=ctl, lam0=lam0)
+    log("time to 1e-4: learned controller, three-product BF16 rounds")
+    out["learned_bf16x3"] = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target,
+                                           args.relerr_rounds, ctl=ctl, lam0=lam0,
+                                           precision="bf16x3")
+    base = out["plain_fp32"]["seconds"]
+    out["speedup_vs_plain_fp32"] = {k: round(base / out[k]["seconds"], 3)
+                                    for k in ("fixed_continuation", "learned", "learned_bf16x3")
+                                    if out[k]["reached"] and out["plain_fp32"]["reached"]}
+    del M_cols, U0_cols, target
+    torch.cuda.empty_cache()
+    return out, inst, U0, r
+
+
 def copy_calibration() -> int:
     import torch
     n = (256 << 20) // 4
@@ -251,31 +400,31 @@ def copy_calibration() -> int:
 
 
 def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD, choices=WORKLOADS,
-                    help="plain_4000x8000_r20 (default): m=4000, n=8000, E=16 x 500, r=20; "
-                         "uneven_10000_r32: m=10000, E=64 log-uniform widths in [64, 4096], r=32")
-    ap.add_argument("--steps", type=int, default=200)
+                    help="workload of the timed rounds (default: the 20000 x 100000, r = 64 "
+                         "geometric-spectrum workload)")
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--u-mode", default="closed", choices=["closed", "grad"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x3"],
-                    help="arithmetic of the timed rounds' streaming passes: fp32; bf16 "
-                         "(RPCA_FLAG_BF16: BF16 copies of M, U, V on BF16 MFMA, FP32 accumulation); "
-                         "bf16x3 (RPCA_FLAG_BF16X3: FP32 M, hi/lo BF16 splits, three products)")
+                    help="arithmetic of the headline rounds' streaming passes")
     ap.add_argument("--graph", action="store_true",
                     help="replay steady-state rounds from HIP graphs (RPCA_FLAG_GRAPH)")
-    ap.add_argument("--autotune", type=int, default=30, metavar="ROUNDS",
-                    help="before timing, pick the launch shapes (V-pass row splits and column "
-                         "groups per wave, FP32 S-pass column phases) with "
-                         "rpca_autotune; 0 keeps the defaults (ROUNDS timed rounds per candidate)")
-    ap.add_argument("--profile-rounds", type=int, default=50)
-    ap.add_argument("--relerr-rounds", type=int, default=None,
-                    help="round budget of the time-to-relerr runs (default: 3000; 6000 for "
-                         "plain_8000x32000_r40)")
-    ap.add_argument("--fixed-point-rounds", type=int, default=8000)
+    ap.add_argument("--autotune", type=int, default=20, metavar="ROUNDS",
+                    help="before timing, pick the launch shapes with rpca_autotune (ROUNDS timed "
+                         "rounds per candidate); 0 keeps the defaults")
+    ap.add_argument("--profile-rounds", type=int, default=20)
+    ap.add_argument("--relerr-rounds", type=int, default=6000,
+                    help="round budget of the time-to-relerr runs")
+    ap.add_argument("--low-rounds", type=int, default=20,
+                    help="low-precision rounds before the FP32 closing rounds in the error check")
+    ap.add_argument("--closing-rounds", type=int, default=20)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the BF16 legs")
+    ap.add_argument("--no-relerr", action="store_true", help="skip the time-to-relerr legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-relerr", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device three times (a kernel of known "
                          "traffic, to scale hardware byte counters) and exit")
@@ -288,16 +437,15 @@ def main() -> int:
               "single MI355X, so --gpus must be 1.", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
-    from paper_2207_11669_amd import DCFPCA, colmajor
+    from paper_2207_11669_amd import colmajor
     from rpca_inputs import RECIPES, gaussian_init, recipe
 
     workload = args.workload
     cfg = RECIPES[workload]
     r, rho = cfg["r"], cfg["rho"]
-    print(f"[bench] generating {workload}", file=sys.stderr, flush=True)
+    log(f"generating {workload}")
     inst = recipe(workload, seed=0)
     lam = 1.0 / math.sqrt(inst.n)
     U0 = gaussian_init(inst.m, r, 7)
@@ -305,139 +453,51 @@ def main() -> int:
     torch.cuda.set_device(dev)
     M_cols = colmajor(inst.M, device=dev)
     U0_cols = colmajor(U0, device=dev)
-    eta0 = 0.0 if args.u_mode == "closed" else 1e-4
-    bf16 = args.precision != "fp32"
-    s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-               eta0=eta0, graph=args.graph, bf16=args.precision == "bf16",
-               bf16x3=args.precision == "bf16x3")
     torch.cuda.synchronize()
 
-    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
-    s.step(args.warmup)
-    shape = s.autotune(args.autotune) if args.autotune > 0 else None
-    torch.cuda.synchronize()
-    stream = s.stream
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    print(f"[bench] timing {args.steps} rounds", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    s.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    ms_per_step = ms / args.steps
-    value = args.steps / (ms / 1e3)
-    st = s.stats()
-    if not math.isfinite(st["objective"]):
-        print("[bench] non-finite objective", file=sys.stderr)
-        return 1
+    head = measure(M_cols, inst, r, rho, lam, U0_cols, args, args.precision, workload)
+    mixed = None
+    if not args.no_mixed and args.precision == "fp32":
+        mixed = {}
+        for prec in ("bf16", "bf16x3"):
+            mixed[prec] = measure(M_cols, inst, r, rho, lam, U0_cols, args, prec, workload)
+            mixed[prec]["speedup_vs_fp32"] = round(mixed[prec]["iters_per_s"] /
+                                                   head["iters_per_s"], 3)
+            log(f"{prec}: error against the FP64 oracle on the 2000 x 2000 sub-instance")
+            mixed[prec]["error_vs_fp64_oracle"] = error_vs_oracle(prec, args.low_rounds,
+                                                                  args.closing_rounds)
+        mixed["fp32_error_vs_fp64_oracle"] = error_vs_oracle("fp32", args.low_rounds,
+                                                             args.closing_rounds)
+    del M_cols, U0_cols
+    torch.cuda.empty_cache()
 
-    # Per-kernel durations from HIP events around every launch, on the stream
-    # the library launches on.
-    print(f"[bench] per-kernel events over {args.profile_rounds} rounds", file=sys.stderr, flush=True)
-    prof = s.profile(args.profile_rounds)
-    costs = kernel_costs(inst.m, inst.n, inst.E, r, args.precision)
-    total = {k: v[0] * v[1] for k, v in prof.items()}
-    dom = max(("vpass", "spass"), key=lambda k: total[k])
-    avg_s = prof[dom][0] / 1e3
-    roofline = roofline_of(costs[dom], avg_s, args.precision)
-    # The launch shape selects the kernel instance of an FP32 pass: counters
-    # are kept per instance ("spass:phases=2", "vpass:column_groups=1", ...).
-    shape_now = s.launch_shape()
-    variant = dom
-    if args.precision == "fp32":
-        variant += (f":phases={shape_now['spass_phases']}" if dom == "spass"
-                    else f":column_groups={shape_now['column_groups']}")
-    traffic = None
-    if os.path.exists(traffic_file(workload, args.precision)):
-        with open(traffic_file(workload, args.precision)) as f:
-            tr = json.load(f)
-        per = tr.get("bytes_per_launch", {})
-        if tr.get("kernel_source_sha256_16") == src_hash():
-            traffic = per.get(variant, per.get(dom))
-    roofline.update({"traffic": traffic, "kernel": variant,
-                     "algorithmic_bytes": costs[dom]["bytes"],
-                     "algorithmic_flops": costs[dom]["flops"],
-                     "avg_launch_us": {k: round(v[0] * 1e3, 2) for k, v in prof.items()},
-                     "launches_per_round": {k: v[1] / args.profile_rounds
-                                            for k, v in prof.items()}})
-
-    ttr = ttf = mixed = cont = None
-    if args.relerr_rounds is None:
-        args.relerr_rounds = 6000 if workload == "plain_8000x32000_r40" else 3000
-    if not args.no_relerr and (not cfg.get("large") or cfg.get("recovery")):
-        target = (colmajor(inst.Ustar, device=dev), colmajor(inst.Vstar, device=dev), cfg["rstar"])
-        ttr = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target,
-                             args.relerr_rounds)
-        if not bf16:
-            mixed = bf16_comparison(M_cols, inst, r, rho, lam, U0_cols, args, eta0, target,
-                                    args.relerr_rounds)
-        # The penalised objective's minimiser sits a little away from L*; also
-        # time the approach to the method's own fixed point (the factors after
-        # a long run) to the same relative tolerance.
-        print(f"[bench] fixed point: {args.fixed_point_rounds} rounds", file=sys.stderr, flush=True)
-        s3 = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-                    eta0=eta0)
-        s3.step(args.fixed_point_rounds)
-        Uf, Vf = s3.get_factors()
-        torch.cuda.synchronize()
-        s3.close()
-        ttf = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0, (Uf, Vf, r),
-                             args.fixed_point_rounds)
-        ttf["fixed_point_rounds"] = args.fixed_point_rounds
-        # The lambda continuation (a schedule from max|M| down to lambda): the
-        # same two targets, same fixed point (the schedule ends at lambda).
-        lam0 = float(np.abs(inst.M).max())
-        sched = continuation(lam, lam0)
-        cont = {"fixed": {"kind": "lambda continuation", "lambda0": lam0, "gamma": 0.8,
-                          "schedule_rounds": len(sched),
-                          "time_to_relerr": time_to_target(M_cols, inst, r, rho, lam, U0_cols,
-                                                           args, eta0, target, args.relerr_rounds,
-                                                           sched),
-                          "time_to_fixed_point": time_to_target(M_cols, inst, r, rho, lam,
-                                                                U0_cols, args, eta0, (Uf, Vf, r),
-                                                                args.fixed_point_rounds, sched)}}
-        ctl, info = learned_controller(args)
-        cont["learned"] = dict(info, **{
-            "time_to_relerr": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
-                                             target, args.relerr_rounds, ctl=ctl, lam0=lam0),
-            "time_to_fixed_point": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
-                                                  (Uf, Vf, r), args.fixed_point_rounds, ctl=ctl,
-                                                  lam0=lam0)})
-        # The learned controller driving three-product BF16 rounds.
-        cont["learned_bf16x3"] = {
-            "time_to_relerr": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
-                                             target, args.relerr_rounds, ctl=ctl, lam0=lam0,
-                                             precision="bf16x3"),
-            "time_to_fixed_point": time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, eta0,
-                                                  (Uf, Vf, r), args.fixed_point_rounds, ctl=ctl,
-                                                  lam0=lam0, precision="bf16x3")}
+    relerr = eval_inst = eval_U0 = eval_r = None
+    if not args.no_relerr:
+        relerr, eval_inst, eval_U0, eval_r = relerr_suite(args, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(inst, U0, r, rho, lam)
+        log("CPU oracle baseline")
+        cpu = cpu_baseline(inst, U0, r, rho, lam, eval_inst, eval_U0, eval_r)
 
     out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "iters/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "metric": METRIC, "value": head["iters_per_s"], "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3 (hi/lo splits, f32 M)"}[args.precision],
+        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3 (hi/lo splits, f32 M)"}[
+            args.precision],
         "data": "synthetic",
         "config": {"workload": workload, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
                    "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam,
                    "rho": rho, "K": 1, "inner": 1, "u_mode": args.u_mode,
-                   "graph": bool(args.graph), "autotuned_launch_shape": shape,
-                   "precision": args.precision},
-        "roofline": roofline,
-        "time_to_relerr": ttr,
-        "time_to_fixed_point": ttf,
+                   "graph": bool(args.graph), "precision": args.precision,
+                   "autotuned_launch_shape": head["autotuned_launch_shape"]},
+        "roofline": head["roofline"],
         "mixed_precision": mixed,
-        "controller": cont,
+        "time_to_relerr": relerr,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    del np
     return 0
 
 
