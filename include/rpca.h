@@ -271,14 +271,23 @@ typedef struct rpca_launch_shape {
    * strip taking alternate 16-column chunks, their partial P summed at the
    * end) or 1 (4 waves, one per strip) */
   int32_t sphases;
+  /* Launch forms of the V-pass and the S-pass: 0, one work-group per tile
+   * (a 64-column group by row split, or a 128-row block of a client); 1, a
+   * persistent launch of the work-groups resident at once, each taking tiles
+   * in the same order from a queue in the workspace until none is left. Each
+   * tile writes its own slots of the partial sums, so both forms give
+   * bitwise the same results. */
+  int32_t vqueue;
+  int32_t squeue;
 } rpca_launch_shape;
 
 /* Autotuner for the launch shapes. First the V-pass: candidates are the
  * default row-split count, half of it and twice it (within what the workspace
  * holds), each with 1 and 4 column groups, at the current S-pass shape. Then,
  * when the rounds run in FP32, the S-pass at the chosen V-pass shape: two
- * column phases and one. Each stage times its candidates in turn, twice over,
- * and compares the sums. Every timing runs `rounds` timed rounds (plus one
+ * column phases and one. Last, the launch forms (per-tile grid or tile queue)
+ * of the two passes, four combinations. Each stage times its candidates in
+ * turn, twice over, and compares the sums. Every timing runs `rounds` timed rounds (plus one
  * untimed); the fastest candidate is kept and returned in *out (optional).
  * Synchronises. The rounds are real rounds of the method; the choice depends
  * on timing. */

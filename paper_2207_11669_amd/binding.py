@@ -62,11 +62,13 @@ class RpcaStats(ctypes.Structure):
 
 
 class RpcaLaunchShape(ctypes.Structure):
-    _fields_ = [("vsplit", c_int32), ("vcols", c_int32), ("sphases", c_int32)]
+    _fields_ = [("vsplit", c_int32), ("vcols", c_int32), ("sphases", c_int32),
+                ("vqueue", c_int32), ("squeue", c_int32)]
 
     def as_dict(self) -> dict:
         return {"row_splits": int(self.vsplit), "column_groups": int(self.vcols),
-                "spass_phases": int(self.sphases)}
+                "spass_phases": int(self.sphases), "vpass_queue": int(self.vqueue),
+                "spass_queue": int(self.squeue)}
 
 
 class RpcaError(RuntimeError):
@@ -286,13 +288,14 @@ class DCFPCA:
         return k.as_dict()
 
     def set_launch_shape(self, row_splits: int | None = None, column_groups: int | None = None,
-                         spass_phases: int | None = None):
+                         spass_phases: int | None = None, vpass_queue: int | None = None,
+                         spass_queue: int | None = None):
         """Fix the launch shapes (rpca_set_launch_shape); None keeps a value."""
         cur = self.launch_shape()
-        k = RpcaLaunchShape(
-            cur["row_splits"] if row_splits is None else int(row_splits),
-            cur["column_groups"] if column_groups is None else int(column_groups),
-            cur["spass_phases"] if spass_phases is None else int(spass_phases))
+        pick = lambda key, v: cur[key] if v is None else int(v)  # noqa: E731
+        k = RpcaLaunchShape(pick("row_splits", row_splits), pick("column_groups", column_groups),
+                            pick("spass_phases", spass_phases), pick("vpass_queue", vpass_queue),
+                            pick("spass_queue", spass_queue))
         self._check(self._lib.rpca_set_launch_shape(self.ctx, ctypes.byref(k)))
 
     def copy_state_from(self, other: "DCFPCA"):

@@ -73,7 +73,7 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 struct Layout {
   size_t S, U0, U1, Uc0, Uc1, V0, V1, Mbv, Mbs, Wpart, P, gv, Af, Bf, gram, spart, upart,
       ucl, Ginv, dstate, hist, stat_part, clients, clients_lpt, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
-      total;
+      queue, total;
   int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows, vsplit_max, RK;
   bool recompute, bf16, mcopy;
   int64_t lds, n, Sfloats;
@@ -209,6 +209,7 @@ Layout make_layout(const rpca_params* p) {
   L.dpart = take((size_t)2 * kDistBlocks * 3 * kMaxRank * kMaxRank * d);
   L.dpart2 = take((size_t)48 * d);
   L.dout = take((size_t)2 * d);
+  L.queue = take(4 * sizeof(uint32_t));
   L.total = o;
   return L;
 }
@@ -499,6 +500,9 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.dstate = reinterpret_cast<DevState*>(ws + L.dstate);
   p.hist = reinterpret_cast<StatsRec*>(ws + L.hist);
   p.stat_part = reinterpret_cast<double*>(ws + L.stat_part);
+  p.queue = reinterpret_cast<uint32_t*>(ws + L.queue);
+  p.vqueue = 0;
+  p.squeue = 0;
   c->U[0] = reinterpret_cast<float*>(ws + L.U0);
   c->U[1] = reinterpret_cast<float*>(ws + L.U1);
   c->Uc[0] = reinterpret_cast<float*>(ws + L.Uc0);
@@ -706,17 +710,20 @@ static void set_vsplit(rpca_ctx* c, int64_t vs) {
 }
 
 static rpca_launch_shape shape_of(const rpca_ctx* c) {
-  return rpca_launch_shape{c->p.vsplit, c->p.vcols, c->p.sphases};
+  return rpca_launch_shape{c->p.vsplit, c->p.vcols, c->p.sphases, c->p.vqueue, c->p.squeue};
 }
 
 static void apply_shape(rpca_ctx* c, const rpca_launch_shape& k) {
   set_vsplit(c, k.vsplit);
   c->p.vcols = k.vcols;
   c->p.sphases = k.sphases;
+  c->p.vqueue = k.vqueue;
+  c->p.squeue = k.squeue;
 }
 
 static bool same_shape(const rpca_launch_shape& a, const rpca_launch_shape& b) {
-  return a.vsplit == b.vsplit && a.vcols == b.vcols && a.sphases == b.sphases;
+  return a.vsplit == b.vsplit && a.vcols == b.vcols && a.sphases == b.sphases &&
+         a.vqueue == b.vqueue && a.squeue == b.squeue;
 }
 
 rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
@@ -757,7 +764,7 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
     if (v < 1 || v > c->vsplit_max) continue;
     set_vsplit(c, v);
     for (int32_t g : {1, 4}) {
-      const rpca_launch_shape k{c->p.vsplit, g, start.sphases};
+      const rpca_launch_shape k{c->p.vsplit, g, start.sphases, start.vqueue, start.squeue};
       if (std::none_of(cand.begin(), cand.end(), [&](const rpca_launch_shape& x) { return same_shape(x, k); }))
         cand.push_back(k);
     }
@@ -777,8 +784,24 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
   // and one, timed in turn twice each (the gap is a few percent of a round;
   // BF16 rounds run their own S-pass).
   if (result == RPCA_OK && c->prec == RPCA_PREC_FP32) {
-    const std::vector<rpca_launch_shape> ks = {{best.vsplit, best.vcols, 2},
-                                               {best.vsplit, best.vcols, 1}};
+    const std::vector<rpca_launch_shape> ks = {
+        {best.vsplit, best.vcols, 2, best.vqueue, best.squeue},
+        {best.vsplit, best.vcols, 1, best.vqueue, best.squeue}};
+    std::vector<float> ts(ks.size(), 0.f);
+    for (int rep = 0; rep < 2 && result == RPCA_OK; ++rep)
+      for (size_t q = 0; q < ks.size() && result == RPCA_OK; ++q) {
+        const float ms = time_shape(ks[q]);
+        if (ms >= 0.f) ts[q] += ms;
+      }
+    if (result == RPCA_OK)
+      best = ks[std::min_element(ts.begin(), ts.end()) - ts.begin()];
+  }
+  // Stage 3, the launch form of both passes at the chosen shapes: one
+  // work-group per tile, or a persistent launch over a tile queue, for each.
+  if (result == RPCA_OK) {
+    std::vector<rpca_launch_shape> ks;
+    for (int32_t vq : {0, 1})
+      for (int32_t sq : {0, 1}) ks.push_back({best.vsplit, best.vcols, best.sphases, vq, sq});
     std::vector<float> ts(ks.size(), 0.f);
     for (int rep = 0; rep < 2 && result == RPCA_OK; ++rep)
       for (size_t q = 0; q < ks.size() && result == RPCA_OK; ++q) {
@@ -813,6 +836,8 @@ rpca_status rpca_set_launch_shape(rpca_ctx* c, const rpca_launch_shape* k) {
     return fail(c, RPCA_EINVAL, "column groups per V-pass wave must be 1 or 4");
   if (k->sphases != 1 && k->sphases != 2)
     return fail(c, RPCA_EINVAL, "S-pass column phases must be 1 or 2");
+  if ((k->vqueue != 0 && k->vqueue != 1) || (k->squeue != 0 && k->squeue != 1))
+    return fail(c, RPCA_EINVAL, "launch forms must be 0 (one work-group per tile) or 1 (tile queue)");
   apply_shape(c, *k);
   drop_graphs(c);
   return RPCA_OK;
@@ -853,6 +878,8 @@ rpca_status rpca_copy_state(rpca_ctx* dst, rpca_ctx* src) {
   dst->p.vsplit_rows = src->p.vsplit_rows;
   dst->p.vcols = src->p.vcols;
   dst->p.sphases = src->p.sphases;
+  dst->p.vqueue = src->p.vqueue;
+  dst->p.squeue = src->p.squeue;
   drop_graphs(dst);
   return RPCA_OK;
 }

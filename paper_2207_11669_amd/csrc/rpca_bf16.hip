@@ -63,21 +63,12 @@ __global__ __launch_bounds__(256) void k_m_to_bf16(DevParams p) {
 // every product as three BF16 products of hi/lo splits (mfma3), KG = 2.
 // ---------------------------------------------------------------------------
 template <int RT, int NK, int MODE, bool X3>
-__global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __restrict__ Ubase,
-                                                 const float* __restrict__ Uold,
-                                                 const float* __restrict__ Vold,
-                                                 double* __restrict__ fin_Ginv, int fin) {
+__device__ __forceinline__ void vpass_h_tile(const DevParams& p, const float* __restrict__ Ubase,
+                                             const float* __restrict__ Uold,
+                                             const float* __restrict__ Vold, int tile) {
   constexpr int RP = 16 * RT;
   constexpr int KG = X3 ? 2 : 4, kPh = KG;  // column groups per wave, row phases
-  int bid = (int)blockIdx.x;
-  if (fin) {
-    if (bid < 2) {
-      finalize_role(p, fin_Ginv, bid);
-      return;
-    }
-    bid -= 2;
-  }
-  const int gx = bid % p.ng64, gy = bid / p.ng64;
+  const int gx = tile % p.ng64, gy = tile / p.ng64;
   const VTile vt = p.vg64[gx];
   const ClientDev& cl = vt.cl;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
@@ -304,6 +295,27 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
   for (int e = tid; e < kVStreamCols * RP; e += blockDim.x) wp[e] = red[e / RP][e % RP];
 }
 
+// Work-group roles and tiles as in k_vpass (Q: persistent launch over the
+// tile queue).
+template <int RT, int NK, int MODE, bool X3, bool Q>
+__global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __restrict__ Ubase,
+                                                 const float* __restrict__ Uold,
+                                                 const float* __restrict__ Vold,
+                                                 double* __restrict__ fin_Ginv, int fin) {
+  if constexpr (!Q) {
+    if (fin && blockIdx.x < 2) {
+      finalize_role(p, fin_Ginv, (int)blockIdx.x);
+      return;
+    }
+    vpass_h_tile<RT, NK, MODE, X3>(p, Ubase, Uold, Vold, (int)blockIdx.x - (fin ? 2 : 0));
+  } else {
+    if (fin && blockIdx.x < 2) finalize_role(p, fin_Ginv, (int)blockIdx.x);
+    const int ntiles = p.ng64 * p.vsplit;
+    for (int t = queue_next(p.queue, ntiles); t < ntiles; t = queue_next(p.queue, ntiles))
+      vpass_h_tile<RT, NK, MODE, X3>(p, Ubase, Uold, Vold, t);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // BF16 S-pass: same grid (128-row blocks x clients, widest client first) and
 // outputs as k_spass, over 32-column chunks, with 256 threads. Each wave
@@ -321,14 +333,14 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
 // sweep.
 // ---------------------------------------------------------------------------
 template <int RT, int NK, bool X3>
-__global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __restrict__ U) {
+__device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __restrict__ U, int b,
+                                             int yi) {
   constexpr int RP = 16 * RT;
   constexpr int kRT = X3 ? 2 : 4;   // 16-row tiles per wave
   constexpr int kPh = X3 ? 1 : 2;   // column phases
   constexpr int kRG = 4 / kPh;      // row groups of 16 kRT rows
   static_assert(kRG * 16 * kRT == kSRows, "row groups cover the work-group's rows");
-  const int b = blockIdx.x;
-  const ClientDev cl = p.clients_lpt[blockIdx.y];
+  const ClientDev cl = p.clients_lpt[yi];
   const int ci = cl.idx;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -620,6 +632,19 @@ __global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __res
   spass_stats<4>(p, ci, b, sl2, sl1, nnz);
 }
 
+// One work-group per tile (grid = row blocks x clients), or (Q) a persistent
+// launch over the tile queue, tiles as in k_spass.
+template <int RT, int NK, bool X3, bool Q>
+__global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __restrict__ U) {
+  if constexpr (!Q) {
+    spass_h_tile<RT, NK, X3>(p, U, (int)blockIdx.x, (int)blockIdx.y);
+  } else {
+    const int ntiles = p.nrb * p.E;
+    for (int t = queue_next(p.queue + 2, ntiles); t < ntiles; t = queue_next(p.queue + 2, ntiles))
+      spass_h_tile<RT, NK, X3>(p, U, t % p.nrb, t / p.nrb);
+  }
+}
+
 hipError_t launch_m_to_bf16(const DevParams& p, hipStream_t st) {
   hipLaunchKernelGGL(k_m_to_bf16, dim3(1024, p.E), dim3(256), 0, st, p);
   return hipGetLastError();
@@ -632,10 +657,20 @@ static hipError_t launch_vpass_h_t(const DevParams& p, int mode, const float* U,
                                    const float* Vold, double* fin_Ginv, int x3, hipStream_t st) {
   constexpr int NK = (RT + 1) / 2;
   const int fin = fin_Ginv ? 1 : 0;
-  const dim3 grid((unsigned)(p.ng64 * p.vsplit + 2 * fin));
+  const int ntiles = p.ng64 * p.vsplit;
+  // The first round (S = 0) always runs one work-group per tile.
   auto go = [&](auto m, auto x) {
-    hipLaunchKernelGGL((k_vpass_h<RT, NK, decltype(m)::value, decltype(x)::value>), grid,
-                       dim3(256), 0, st, p, U, Uold, Vold, fin_Ginv, fin);
+    constexpr int kMode = decltype(m)::value;
+    constexpr bool kX3 = decltype(x)::value;
+    if (kMode == kSRecompute && p.vqueue) {
+      auto kernel = k_vpass_h<RT, NK, kSRecompute, kX3, true>;
+      const int groups = pass_groups(kernel, 256, ntiles, 1);
+      hipLaunchKernelGGL(kernel, dim3((unsigned)(groups + 2 * fin)), dim3(256), 0, st, p, U, Uold,
+                         Vold, fin_Ginv, fin);
+    } else {
+      hipLaunchKernelGGL((k_vpass_h<RT, NK, kMode, kX3, false>), dim3((unsigned)(ntiles + 2 * fin)),
+                         dim3(256), 0, st, p, U, Uold, Vold, fin_Ginv, fin);
+    }
   };
   using Z = std::integral_constant<int, kSZero>;
   using R = std::integral_constant<int, kSRecompute>;
@@ -663,11 +698,19 @@ hipError_t launch_vpass_h(const DevParams& p, int mode, const float* U, const fl
 template <int RT>
 static hipError_t launch_spass_h_t(const DevParams& p, const float* U, int x3, hipStream_t st) {
   constexpr int NK = (RT + 1) / 2;
-  const dim3 grid(p.nrb, p.E);
+  const int ntiles = p.nrb * p.E;
+  auto go = [&](auto persistent, auto per_tile) {
+    if (p.squeue) {
+      const int groups = pass_groups(persistent, 256, ntiles, 1);
+      hipLaunchKernelGGL(persistent, dim3(groups), dim3(256), 0, st, p, U);
+    } else {
+      hipLaunchKernelGGL(per_tile, dim3(p.nrb, p.E), dim3(256), 0, st, p, U);
+    }
+  };
   if (x3)
-    hipLaunchKernelGGL((k_spass_h<RT, NK, true>), grid, dim3(256), 0, st, p, U);
+    go(k_spass_h<RT, NK, true, true>, k_spass_h<RT, NK, true, false>);
   else
-    hipLaunchKernelGGL((k_spass_h<RT, NK, false>), grid, dim3(256), 0, st, p, U);
+    go(k_spass_h<RT, NK, false, true>, k_spass_h<RT, NK, false, false>);
   return hipGetLastError();
 }
 

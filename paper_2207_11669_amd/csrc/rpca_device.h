@@ -64,6 +64,34 @@ __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
 __device__ __forceinline__ f4 bload4(rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
 }
+// Tile queue of a persistent launch (a streaming pass whose grid holds only
+// as many work-groups as are resident at once). q[0] is the next tile, q[1]
+// counts the work-groups that found the queue empty. One lane takes a tile
+// with a vector-memory atomic and the work-group reads it from LDS; the
+// leading barrier keeps the previous tile's LDS readers ahead of the next
+// tile's writers. Every work-group leaves once the count passes ntiles, so
+// the launch always drains; the last one to leave resets both counters for
+// the next launch (no memset, so the launch can be replayed from a graph).
+// Each tile writes only its own slots of the outputs, so which work-group
+// takes which tile changes no result.
+__device__ __forceinline__ int queue_next(uint32_t* q, int ntiles) {
+  __shared__ int s_tile;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int t = (int)atomicAdd(&q[0], 1u);
+    if (t >= ntiles) {
+      const uint32_t left = atomicAdd(&q[1], 1u);
+      if (left + 1 == gridDim.x * gridDim.y) {
+        atomicExch(&q[0], 0u);
+        atomicExch(&q[1], 0u);
+      }
+    }
+    s_tile = t;
+  }
+  __syncthreads();
+  return s_tile;
+}
+
 // Byte range of a whole factor layout. The parameter checks keep every such
 // layout below 2^31 bytes; a larger value would be a broken invariant, and
 // the range is then 0 (every load reads 0) rather than a wrapped 32-bit size.
@@ -578,6 +606,34 @@ __device__ __forceinline__ f4 mfma3(bf8 ah, bf8 al, bf8 bh, bf8 bl, f4 c) {
   c = mfma_bf16(al, bh, c);
   c = mfma_bf16(ah, bl, c);
   return mfma_bf16(ah, bh, c);
+}
+
+// Work-groups of `kernel` (block threads, no dynamic LDS) that are resident
+// on the current device at once, for the grid of a persistent launch; kept
+// per device after the first query (0 if the runtime cannot tell).
+template <class K>
+static int resident_groups(K kernel, int block) {
+  constexpr int kDevs = 64;
+  static int cache[kDevs] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev < kDevs && cache[dev] > 0) return cache[dev];
+  int cus = 0, nb = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kernel), block,
+                                                    0) != hipSuccess)
+    return 0;
+  if (dev < kDevs) cache[dev] = nb * cus;
+  return nb * cus;
+}
+
+// Grid of a streaming pass over ntiles tiles: one work-group per tile, or
+// (persistent) the resident work-groups, at most one per tile.
+template <class K>
+static int pass_groups(K kernel, int block, int ntiles, int persistent) {
+  if (!persistent) return ntiles;
+  const int res = resident_groups(kernel, block);
+  return res > 0 && res < ntiles ? res : ntiles;
 }
 
 // Compile-time (RT, NS) dispatch: NS = ceil(r/4) lies in [4 RT - 3, 4 RT].

@@ -145,6 +145,9 @@ struct DevParams {
   int32_t vsplit_rows;   // rows per V-pass row split (multiple of 16)
   int32_t vcols;         // 16-column groups per FP32 V-pass wave (1 or 4)
   int32_t sphases;       // column phases of the FP32 S-pass work-groups (1: 256, 2: 512 threads)
+  int32_t vqueue;        // 1: V-pass as a persistent launch over a tile queue
+  int32_t squeue;        // 1: S-pass as a persistent launch over a tile queue
+  uint32_t* queue;       // tile-queue counters: [0, 1] V-pass, [2, 3] S-pass (zero between launches)
   int32_t u_mode, eta_sched;
   float lam;             // lambda of the rounds being enqueued
   float lam_rec;         // lambda of the last enqueued round (its deferred record)

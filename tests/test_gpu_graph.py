@@ -116,12 +116,14 @@ def test_set_launch_shape_rejects_bad_values():
                colmajor(init_for(inst, 3, 1)), u_mode="closed")
     before = s.launch_shape()
     for kw, frag in ((dict(row_splits=-1), "row splits"), (dict(row_splits=1000), "row splits"),
-                     (dict(column_groups=2), "column groups"), (dict(spass_phases=3), "phases")):
+                     (dict(column_groups=2), "column groups"), (dict(spass_phases=3), "phases"),
+                     (dict(vpass_queue=2), "launch forms"), (dict(spass_queue=-1), "launch forms")):
         with pytest.raises(RpcaError, match=frag):
             s.set_launch_shape(**kw)
         assert s.launch_shape() == before
     s.set_launch_shape(row_splits=1, column_groups=4, spass_phases=1)
-    assert s.launch_shape() == {"row_splits": 1, "column_groups": 4, "spass_phases": 1}
+    assert s.launch_shape() == {"row_splits": 1, "column_groups": 4, "spass_phases": 1,
+                                "vpass_queue": 0, "spass_queue": 0}
     s.step(2)
     assert np.isfinite(s.stats()["objective"])
     s.close()
