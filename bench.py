@@ -48,8 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # rounds run three BF16 products per product of the method.
 MFMA_PEAK_TFS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 3}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_11669_amd", "csrc", f)
-               for f in ("rpca_device.h", "rpca_internal.h", "rpca_vpass.hip", "rpca_spass.hip",
-                         "rpca_bf16.hip", "rpca_tail.hip")]
+               for f in ("rpca_device.h", "rpca_internal.h", "rpca_vpass_kernel.h",
+                         "rpca_vpass.hip", "rpca_vpass_q.hip", "rpca_spass_kernel.h",
+                         "rpca_spass.hip", "rpca_spass_q.hip", "rpca_bf16.hip", "rpca_tail.hip")]
 
 
 def log(msg: str):
@@ -295,48 +296,35 @@ def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target, max_rounds,
         s2.set_lambda(lt)
         s2.step(1)
         pre += 1
+    ctrl = None
     if ctl is not None:
-        pre += C.run_controlled(s2, lam, lam0, ctl, float(inst.m) * inst.n)["control_rounds"]
+        ctrl = C.run_controlled(s2, lam, lam0, ctl, float(inst.m) * inst.n)
+        pre += ctrl["control_rounds"]
     s2.set_lambda(lam)
     done, err = s2.solve(max_rounds - pre, 1e-4, check_every=10)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     s2.close()
-    return {"tol": 1e-4, "reached": bool(err <= 1e-4), "rounds": pre + done,
-            "seconds": round(secs, 4), "final_relerr": err, "max_rounds": max_rounds,
-            "check_every": 10, "precision": precision}
+    out = {"tol": 1e-4, "reached": bool(err <= 1e-4), "rounds": pre + done,
+           "seconds": round(secs, 4), "final_relerr": err, "max_rounds": max_rounds,
+           "check_every": 10, "precision": precision}
+    if ctrl is not None:
+        out["control"] = {"rounds": ctrl["control_rounds"], "rejected": ctrl["rejected"],
+                          "decays": [round(g, 3) for g in ctrl["gammas"]],
+                          "steps": [round(w, 3) for w in ctrl["omegas"]]}
+    return out
 
 
-def learned_controller(instances: int = 40, n: int = 256):
-    """Train the learned lambda controller on method-generated instances
-    (greedy per-round targets, MLP trained on the GPU); returns it with a
-    description of its training."""
-    import numpy as np
-
-    from paper_2207_11669_amd import DCFPCA, colmajor
+def learned_controller():
+    """The learned controller with the parameters committed next to the
+    package (paper_2207_11669_amd/controller_weights.json, written by
+    paper_2207_11669_amd/train_controller.py on instances of the evaluation
+    workload's family), and the description of their training."""
     from paper_2207_11669_amd import controller as C
-    from rpca_inputs import controller_family, gaussian_init
-    log(f"training the learned controller on {instances} instances")
-
-    def cases():
-        for k in range(instances):
-            inst, r = controller_family(10_000 + k, n)
-            lam = 1.0 / math.sqrt(inst.n)
-
-            def make(inst=inst, r=r, lam=lam):
-                s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, r, 0.1, lam,
-                           colmajor(gaussian_init(inst.m, r, 7)))
-                s.set_target(colmajor(inst.Ustar), colmajor(inst.Vstar), r)
-                return s
-            yield make, lam, float(np.abs(inst.M).max()), float(inst.m * inst.n)
-
-    t0 = time.perf_counter()
-    params, (X, Y), losses = C.fit(cases())
-    info = {"kind": "learned (MLP 8-64-64-1, greedy per-round decay targets)",
-            "training_instances": instances, "training_size": f"{n}x{n}", "samples": int(len(Y)),
-            "train_seconds": round(time.perf_counter() - t0, 2),
-            "final_train_loss": round(losses[-1], 5)}
-    return C.LearnedContinuation(params), info
+    ctl, info = C.LearnedContinuation.load()
+    log(f"learned controller: {info.get('training_instances')} training instances of "
+        f"{info.get('training_size')}")
+    return ctl, info
 
 
 def relerr_suite(args, dev) -> tuple:

@@ -133,12 +133,15 @@ typedef enum {
 /* Per-round statistics, FP64, recorded at the last local step of round t:
  * objective = sum_i L_i(U_i, V_i, S_i) with U_i the client factor that the
  * (V_i, S_i) update used (Section 2.2 local objectives; for K = 1 this is the
- * global objective at (U^(t), V^(t+1), S^(t+1))); lambda_fro_sq =
- * ||M - U V^T - S||_F^2; nnz = number of nonzeros of S; du_sq =
- * ||U^(t+1) - U^(t)||_F^2; u_sq = ||U^(t+1)||_F^2; v_sq = ||V||_F^2;
- * l1 = ||S||_1. */
+ * global objective at (U^(t), V^(t+1), S^(t+1))), at the round's lambda;
+ * lambda_fro_sq = ||M - U V^T - S||_F^2; nnz = number of nonzeros of S;
+ * du_sq = ||U^(t+1) - U^(t)||_F^2; u_sq = ||U^(t+1)||_F^2; v_sq = ||V||_F^2;
+ * l1 = ||S||_1; objective_target = the same objective at the problem's own
+ * lambda with S at its optimum for the round's factors, sum of H_lambda(M -
+ * U V^T) + the penalties (Appendix A.2's Huber identity; equal to objective
+ * in rounds at that lambda). A lambda schedule's rounds can be judged by it. */
 typedef struct {
-  double t, objective, lambda_fro_sq, nnz, du_sq, u_sq, v_sq, l1;
+  double t, objective, lambda_fro_sq, nnz, du_sq, u_sq, v_sq, l1, objective_target;
 } rpca_stats;
 
 /* NULL when the parameters are valid, else a static text naming the first
@@ -319,6 +322,14 @@ rpca_status rpca_copy_state(rpca_ctx* dst, rpca_ctx* src);
  * fixed point is that of the last lambda. */
 rpca_status rpca_set_lambda(rpca_ctx* c, double lambda);
 
+/* Multiplier omega of the U step for the rounds enqueued from now on:
+ * U^(t+1) = U^(t) + omega (mean_i U_i - U^(t)) (eq. "U_agg" relaxed; with
+ * the gradient step this is the step size omega eta, Theorem 1 asks
+ * eta < 1/L). omega = 1 (the default) is the method's step, computed exactly
+ * as without the multiplier. 0 < omega <= 4, else RPCA_EINVAL. A change drops
+ * captured graphs. For step-size control (the library's controller). */
+rpca_status rpca_set_step(rpca_ctx* c, double omega);
+
 /* Precision of the rounds enqueued from now on (rpca_precision). BF16 needs
  * a context created with RPCA_FLAG_BF16, BF16X3 one with RPCA_FLAG_BF16X3 or
  * RPCA_FLAG_BF16 (RPCA_EINVAL otherwise). Switching drops captured graphs.
@@ -327,27 +338,34 @@ rpca_status rpca_set_lambda(rpca_ctx* c, double lambda);
  * BF16X3. */
 rpca_status rpca_set_precision(rpca_ctx* c, int32_t precision);
 
-/* A small MLP for round-by-round control (a learned lambda schedule):
- * RPCA_MLP_IN = 8 inputs, two tanh layers of RPCA_MLP_HIDDEN = 64 units, and
- * one output y = g_min + (1 - g_min) sigmoid(z) in [g_min, 1] with
- * g_min = RPCA_MLP_GMIN (a per-round decay factor). Parameters are one FP32
- * device array of rpca_mlp_param_count() floats, in this order: W1 (64 x 8,
- * row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1).
- * Not part of Algorithm 1; the library's own controller runs on it. */
-#define RPCA_MLP_IN 8
+/* A small MLP for round-by-round control (a learned lambda schedule and U
+ * step): RPCA_MLP_IN = 10 inputs, two tanh layers of RPCA_MLP_HIDDEN = 64
+ * units, and RPCA_MLP_OUT = 2 outputs y_k = lo_k + (hi_k - lo_k) sigmoid(z_k):
+ * y_0 in [RPCA_MLP_GMIN, 1], a per-round decay of the lambda scale, and y_1 in
+ * [RPCA_MLP_WMIN, RPCA_MLP_WMAX], a multiplier of the U step (rpca_set_step).
+ * Parameters are one FP32 device array of rpca_mlp_param_count() floats, in
+ * this order: W1 (64 x 10, row-major), b1 (64), W2 (64 x 64), b2 (64), W3
+ * (2 x 64), b3 (2). Not part of Algorithm 1; the library's own controller
+ * runs on it. */
+#define RPCA_MLP_IN 10
 #define RPCA_MLP_HIDDEN 64
+#define RPCA_MLP_OUT 2
 #define RPCA_MLP_GMIN 0.5f
+#define RPCA_MLP_WMIN 0.5f
+#define RPCA_MLP_WMAX 2.0f
 int64_t rpca_mlp_param_count(void);
 
-/* y[i] = MLP(x[i]) for n samples (x: n x 8 row-major, y: n; device
- * pointers). Enqueued on `stream` (hipStream_t as void*, NULL = default). */
+/* y[i] = MLP(x[i]) for n samples (x: n x 10 row-major, y: n x 2 row-major;
+ * device pointers). Enqueued on `stream` (hipStream_t as void*, NULL =
+ * default). */
 rpca_status rpca_mlp_forward(const float* params, const float* x, int64_t n, float* y,
                              void* stream);
 
 /* One step of gradient descent on the mean over n samples of
- * 1/2 (MLP(x[i]) - target[i])^2: params -= lr * mean gradient, the samples'
- * gradients summed in index order (bitwise reproducible). grad_ws: device
- * scratch of n * rpca_mlp_param_count() floats. 1 <= n <= 65535. */
+ * 1/2 ||MLP(x[i]) - target[i]||^2 (target: n x 2 row-major): params -= lr *
+ * mean gradient, the samples' gradients summed in index order (bitwise
+ * reproducible). grad_ws: device scratch of n * rpca_mlp_param_count()
+ * floats. 1 <= n <= 65535. */
 rpca_status rpca_mlp_train_step(float* params, const float* x, const float* target, int64_t n,
                                 float lr, float* grad_ws, void* stream);
 

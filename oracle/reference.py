@@ -179,7 +179,8 @@ def dcfpca(Ms: Sequence[np.ndarray], r: int, rho: float, lam: float, T: int,
            U0: np.ndarray, K: int = 1, inner: int = 1, u_mode: str = "closed",
            eta0: float = 0.0, eta_sched: str = "const",
            S0: Optional[Sequence[np.ndarray]] = None, t0: int = 0,
-           record: bool = True, lam_schedule: Optional[Sequence[float]] = None) -> Result:
+           record: bool = True, lam_schedule: Optional[Sequence[float]] = None,
+           omega_schedule: Optional[Sequence[float]] = None) -> Result:
     """Algorithm 1 (Section 2.2): T rounds of broadcast, K local steps per
     client, and the mean of the client factors.
 
@@ -187,6 +188,12 @@ def dcfpca(Ms: Sequence[np.ndarray], r: int, rho: float, lam: float, T: int,
     starting S_i (default zeros). t0: index of the first round (for the eta
     schedule when resuming). lam_schedule: optional lambda_t for each of the T
     rounds (K = 1 and inner = 1 only; see the module's readings).
+    omega_schedule: optional multiplier omega_t of each round's consensus
+    step, U^(t+1) = U^(t) + omega_t (mean_i U_i - U^(t)) (a relaxation of eq.
+    "U_agg"; for the gradient step, the step size omega_t eta). The recorded
+    objective_target is the objective at lambda (the problem's, not lambda_t)
+    with S at its optimum for the round's factors: by the Huber identity of
+    Appendix A.2, sum_i H_lambda(M_i - U_i V_i^T) plus the penalties.
     """
     Ms = [np.asarray(Mi, dtype=np.float64) for Mi in Ms]
     E = len(Ms)
@@ -203,6 +210,8 @@ def dcfpca(Ms: Sequence[np.ndarray], r: int, rho: float, lam: float, T: int,
             raise ValueError("a lambda schedule needs K = 1 and inner = 1")
         if len(lam_schedule) < T:
             raise ValueError("lam_schedule needs one lambda per round")
+    if omega_schedule is not None and len(omega_schedule) < T:
+        raise ValueError("omega_schedule needs one multiplier per round")
     R_last: List[Optional[np.ndarray]] = [None] * E
     history = []
     for t in range(int(t0), int(t0) + int(T)):
@@ -210,6 +219,7 @@ def dcfpca(Ms: Sequence[np.ndarray], r: int, rho: float, lam: float, T: int,
         eta = eta_at(eta0, eta_sched, t) if u_mode == "grad" else 0.0
         client_U = []
         F = 0.0
+        F_target = 0.0
         lam_sq = 0.0
         nnz = 0
         for i in range(E):  # clients one after another (Section 4.1)
@@ -221,6 +231,8 @@ def dcfpca(Ms: Sequence[np.ndarray], r: int, rho: float, lam: float, T: int,
                 R_last[i] = Ri
                 if record and _k == K - 1:
                     F += local_objective(Ui, Vi, Si, Ms[i], rho, lam_t, widths[i], n)
+                    F_target += (huber(Ri, lam) + 0.5 * rho * float(np.sum(Vi * Vi))
+                                 + 0.5 * rho * (widths[i] / n) * float(np.sum(Ui * Ui)))
                     Lam = Ri - Si
                     lam_sq += float(np.sum(Lam * Lam))
                     nnz += int(np.count_nonzero(Si))
@@ -234,10 +246,13 @@ def dcfpca(Ms: Sequence[np.ndarray], r: int, rho: float, lam: float, T: int,
                 S[i] = Si
             client_U.append(Ui)
         U_new = sum(client_U) / E  # eq. "U_agg"
+        if omega_schedule is not None:
+            U_new = U + float(omega_schedule[t - int(t0)]) * (U_new - U)
         if record:
             du = U_new - U
             history.append(dict(t=t, objective=F, lambda_fro_sq=lam_sq, nnz=nnz,
-                                du_sq=float(np.sum(du * du)), u_sq=float(np.sum(U_new * U_new))))
+                                du_sq=float(np.sum(du * du)), u_sq=float(np.sum(U_new * U_new)),
+                                objective_target=F_target))
         U = U_new
     return Result(U=U, V=[v for v in V], S=S, history=history)
 

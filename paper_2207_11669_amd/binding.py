@@ -55,7 +55,8 @@ class RpcaParams(ctypes.Structure):
 
 class RpcaStats(ctypes.Structure):
     _fields_ = [(k, c_double) for k in
-                ("t", "objective", "lambda_fro_sq", "nnz", "du_sq", "u_sq", "v_sq", "l1")]
+                ("t", "objective", "lambda_fro_sq", "nnz", "du_sq", "u_sq", "v_sq", "l1",
+                 "objective_target")]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -107,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "rpca_set_launch_shape": (c_int32, [vp, POINTER(RpcaLaunchShape)]),
         "rpca_set_precision": (c_int32, [vp, c_int32]),
         "rpca_set_lambda": (c_int32, [vp, c_double]),
+        "rpca_set_step": (c_int32, [vp, c_double]),
         "rpca_copy_state": (c_int32, [vp, vp]),
         "rpca_mlp_param_count": (c_int64, []),
         "rpca_mlp_forward": (c_int32, [vp, vp, c_int64, vp, vp]),
@@ -306,6 +308,10 @@ class DCFPCA:
         """lambda of the following rounds (rebuilt-S form only)."""
         self._check(self._lib.rpca_set_lambda(self.ctx, float(lam)))
 
+    def set_step(self, omega: float):
+        """Multiplier of the U step for the following rounds (1: the method's)."""
+        self._check(self._lib.rpca_set_step(self.ctx, float(omega)))
+
     def set_precision(self, precision: str):
         """Precision of the following rounds' streaming passes: "fp32", "bf16" or
         "bf16x3"."""
@@ -392,11 +398,12 @@ def mlp_param_count() -> int:
 
 
 def mlp_forward(params, x, stream=None):
-    """MLP outputs for the rows of x ((n, 8) FP32 CUDA tensor); params: FP32
-    CUDA tensor of mlp_param_count() floats."""
+    """MLP outputs (n, 2) -- the decay and the step multiplier -- for the rows
+    of x ((n, 10) FP32 CUDA tensor); params: FP32 CUDA tensor of
+    mlp_param_count() floats."""
     import torch
     n = int(x.shape[0])
-    y = torch.empty(n, dtype=torch.float32, device=x.device)
+    y = torch.empty((n, 2), dtype=torch.float32, device=x.device)
     st = stream if stream is not None else torch.cuda.current_stream(x.device)
     s = load_library().rpca_mlp_forward(c_void_p(params.data_ptr()), c_void_p(x.data_ptr()), n,
                                         c_void_p(y.data_ptr()), c_void_p(st.cuda_stream))
@@ -406,7 +413,8 @@ def mlp_forward(params, x, stream=None):
 
 
 def mlp_train_step(params, x, target, lr: float, grad_ws, stream=None):
-    """One gradient-descent step of params on the mean squared-error loss."""
+    """One gradient-descent step of params on the mean squared-error loss
+    (target: (n, 2) FP32 CUDA tensor)."""
     import torch
     n = int(x.shape[0])
     st = stream if stream is not None else torch.cuda.current_stream(x.device)

@@ -1,25 +1,39 @@
-"""Round-by-round lambda control for DCF-PCA: a fixed continuation and a
-learned one driven by the library's MLP (rpca_mlp_*).
+"""Round-by-round control of DCF-PCA: a fixed lambda continuation and a
+learned controller driven by the library's MLP (rpca_mlp_*).
 
-The paper fixes lambda. A controller runs the same rounds but chooses each
-round's lambda_t = lambda * s_t with a scale s_t >= 1 that only decreases,
-s_t = max(1, s_{t-1} g_t), starting from s_0 = lambda0 / lambda (by default
-lambda0 = max|M|, so that no entry is thresholded at first and L takes the
-bulk of M before S takes the outliers). Once s reaches 1 the plain method
-runs on, so the fixed point is the plain method's; the plain fixed-lambda
-rounds are also the fallback when the controller has decided nothing after
-max_control rounds. The fixed continuation uses g_t = 0.8. The learned
-controller takes g_t in [0.5, 1] from the MLP, fed with eight features of the
-last recorded rounds (all scale-free).
+The paper fixes lambda and the step. A controller runs the same rounds but
+chooses, each round, lambda_t = lambda * s_t with a scale s_t >= 1 that only
+decreases, s_t = max(1, s_{t-1} g_t), starting from s_0 = lambda0 / lambda (by
+default lambda0 = max|M|, so that no entry is thresholded at first and L takes
+the bulk of M before S takes the outliers), and a multiplier w_t of the U step
+(rpca_set_step: U^(t+1) = U^(t) + w_t (mean_i U_i - U^(t)); for the gradient
+step, the step size w_t eta). Once s reaches 1 the plain method runs on, so
+the fixed point is the plain method's.
 
-Training targets come from a per-round greedy search: from the current state,
-each candidate decay is tried for a few lookahead rounds on a copy of the
-iterate (rpca_copy_state), and the one whose iterate is closest to the
-planted L* wins.
+The plain step is the fallback and the judge: every controlled round records
+its objective at the problem's lambda with S at its optimum (rpca_stats
+objective_target, the Huber form of Appendix A.2), the objective the plain
+step descends. From the third controlled round on, a round whose target
+objective is above the previous round's by more than JUDGE_TOL rejects the
+controller: the plain step (s = 1, w = 1) runs from there on. (The first
+rounds from U^(0) are exempt: while L absorbs the bulk of M the target
+objective rises by 6-13% even under the fixed continuation, and is then flat
+or falling by a few tenths of a percent per round.) A non-finite proposal
+takes the fixed continuation's decay and w = 1, and the controlled phase ends
+after at most max_control rounds.
+
+The fixed continuation uses g_t = 0.8 and w_t = 1. The learned controller
+takes (g_t, w_t) from the MLP, fed with ten scale-free features of the last
+recorded rounds. Its training targets come from a per-round greedy search:
+from the current state each candidate (g, w) is tried for a few lookahead
+rounds on a copy of the iterate (rpca_copy_state), and the pair whose iterate
+is closest to the planted L* wins.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 from typing import Callable, List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -27,107 +41,150 @@ import numpy as np
 from .binding import DCFPCA, mlp_forward, mlp_param_count, mlp_train_step
 
 GAMMAS = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0)
-N_FEATURES = 8
+OMEGAS = (1.0, 1.3)
+N_FEATURES = 10
+JUDGE_TOL = 0.01   # allowed relative rise of the target objective per controlled round
+JUDGE_FROM = 2     # controlled rounds exempt from the judge
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "controller_weights.json")
 
 
 def features(st: dict, prev: Optional[dict], scale: float, gamma_prev: float, t: int,
-             lam: float, mn: float) -> List[float]:
-    """Eight scale-free features of the last finished round (st, recorded at
+             lam: float, mn: float, omega_prev: float = 1.0) -> List[float]:
+    """Ten scale-free features of the last finished round (st, recorded at
     lambda * scale) and the one before it (prev)."""
     lt = lam * scale
     sat = st["lambda_fro_sq"] / max(mn * lt * lt, 1e-300)        # ||Lambda||^2 / (mn lambda_t^2)
     nnz = st["nnz"] / mn                                          # fraction of S's support
     du = math.log10(st["du_sq"] / max(st["u_sq"], 1e-300) + 1e-12) / 12.0 + 1.0
     grow = 0.0
+    drop = 0.0
     if prev is not None and prev["u_sq"] > 0:
         grow = max(-1.0, min(1.0, math.log(max(st["u_sq"], 1e-300) / prev["u_sq"])))
+    if prev is not None and prev.get("objective_target", 0) > 0 and st.get("objective_target", 0) > 0:
+        # relative change of the objective at the target lambda (negative: decreasing)
+        drop = max(-1.0, min(1.0, math.log(st["objective_target"] / prev["objective_target"])))
     l1 = math.log10(st["l1"] / max(mn * lt, 1e-300) + 1e-12) / 6.0
     return [math.log10(max(scale, 1.0)) / 4.0, min(t, 100) / 100.0, min(sat, 1.0), nnz, du,
-            grow, gamma_prev, l1]
+            grow, gamma_prev, l1, omega_prev - 1.0, drop]
 
 
 class FixedContinuation:
-    def __init__(self, gamma: float = 0.8):
+    def __init__(self, gamma: float = 0.8, omega: float = 1.0):
         self.gamma = float(gamma)
+        self.omega = float(omega)
 
-    def decide(self, feats: Sequence[float]) -> float:
-        return self.gamma
+    def decide(self, feats: Sequence[float]) -> Tuple[float, float]:
+        return self.gamma, self.omega
 
 
 class LearnedContinuation:
-    """g_t from the MLP (inference on the GPU, rpca_mlp_forward)."""
+    """(g_t, w_t) from the MLP (inference on the GPU, rpca_mlp_forward)."""
 
     def __init__(self, params):
         self.params = params  # FP32 CUDA tensor of mlp_param_count() floats
 
-    def decide(self, feats: Sequence[float]) -> float:
+    def decide(self, feats: Sequence[float]) -> Tuple[float, float]:
         import torch
         x = torch.tensor([list(feats)], dtype=torch.float32, device=self.params.device)
-        g = float(mlp_forward(self.params, x).cpu()[0])
+        g, w = (float(v) for v in mlp_forward(self.params, x).cpu()[0])
         # Fallback for a non-finite proposal: the fixed continuation's decay.
-        return g if math.isfinite(g) else 0.8
+        if not (math.isfinite(g) and math.isfinite(w)):
+            return 0.8, 1.0
+        return g, w
+
+    @classmethod
+    def load(cls, path: str = WEIGHTS, device="cuda") -> Tuple["LearnedContinuation", dict]:
+        """The trained parameters committed with the package (written by
+        train_controller.py), and the description of their training."""
+        import torch
+        with open(path) as f:
+            d = json.load(f)
+        p = np.asarray(d["params"], dtype=np.float32)
+        if p.size != mlp_param_count():
+            raise ValueError(f"{path}: {p.size} parameters, the MLP has {mlp_param_count()}")
+        return cls(torch.from_numpy(p).to(device)), d["training"]
 
 
 def run_controlled(s: DCFPCA, lam: float, lam0: float, controller, mn: float,
-                   max_control: int = 200) -> dict:
-    """Run the controlled rounds on session s until the scale reaches 1 (or
-    max_control rounds); leaves lambda at its target. Returns the decays."""
+                   max_control: int = 200, judge: bool = True) -> dict:
+    """Run the controlled rounds on session s until the scale reaches 1, the
+    plain step's judge rejects the controller (judge=True), or max_control
+    rounds; leaves lambda at its target and the step at 1. Returns the
+    decisions."""
     scale = max(1.0, lam0 / lam)
     gammas: List[float] = []
+    omegas: List[float] = []
     prev = None
     t = 0
-    g = 1.0
+    g, w = 1.0, 1.0
+    rejected = False
     while scale > 1.0 and t < max_control:
         s.set_lambda(lam * scale)
+        s.set_step(w)
         s.step(1)
         st = s.stats(-1)
-        g = float(min(1.0, max(0.5, controller.decide(features(st, prev, scale, g, t, lam, mn)))))
+        if (judge and t >= JUDGE_FROM and prev is not None
+                and st["objective_target"] > (1.0 + JUDGE_TOL) * prev["objective_target"]):
+            rejected = True  # the plain step takes over from here
+            t += 1
+            break
+        g, w = controller.decide(features(st, prev, scale, g, t, lam, mn, w))
+        g = float(min(1.0, max(0.5, g)))
+        w = float(min(2.0, max(0.5, w)))
         gammas.append(g)
+        omegas.append(w)
         prev = st
         scale = max(1.0, scale * g)
         t += 1
     s.set_lambda(lam)
-    return {"control_rounds": t, "gammas": gammas}
+    s.set_step(1.0)
+    return {"control_rounds": t, "gammas": gammas, "omegas": omegas, "rejected": rejected}
 
 
 def greedy_samples(make_session: Callable[[], DCFPCA], lam: float, lam0: float, mn: float,
-                   horizon: int = 5, gammas: Sequence[float] = GAMMAS,
+                   horizon: int = 10, gammas: Sequence[float] = GAMMAS,
+                   omegas: Sequence[float] = OMEGAS,
                    max_control: int = 80) -> Tuple[np.ndarray, np.ndarray]:
-    """(features, best decay) pairs along one greedy trajectory: at each round
-    every candidate decay runs `horizon` lookahead rounds on a copy of the
-    iterate, and the one closest to the target (set on the sessions) wins.
-    make_session returns a fresh session with the target registered."""
+    """(features, best (decay, multiplier)) pairs along one greedy trajectory:
+    at each round every candidate pair runs `horizon` lookahead rounds on a
+    copy of the iterate, and the one closest to the target (set on the
+    sessions) wins. make_session returns a fresh session with the target
+    registered."""
     main, probe = make_session(), make_session()
     scale = max(1.0, lam0 / lam)
     X, Y = [], []
     prev = None
-    g = 1.0
+    g, w = 1.0, 1.0
     t = 0
     main.set_lambda(lam * scale)
     main.step(1)
+    cands = [(a, b) for a in gammas for b in omegas]
     while scale > 1.0 and t < max_control:
         st = main.stats(-1)
-        f = features(st, prev, scale, g, t, lam, mn)
+        f = features(st, prev, scale, g, t, lam, mn, w)
         errs = []
-        for cand in gammas:
+        for cg, cw in cands:
             probe.copy_state_from(main)
+            probe.set_step(cw)
             sc = scale
             for _ in range(horizon):
-                sc = max(1.0, sc * cand)
+                sc = max(1.0, sc * cg)
                 probe.set_lambda(lam * sc)
                 probe.step(1)
-            errs.append(probe.target_error())
-        g = float(gammas[int(np.argmin(errs))])
+            err = probe.target_error()
+            errs.append(err if math.isfinite(err) else math.inf)
+        g, w = cands[int(np.argmin(errs))]
         X.append(f)
-        Y.append(g)
+        Y.append((g, w))
         prev = st
         scale = max(1.0, scale * g)
         main.set_lambda(lam * scale)
+        main.set_step(w)
         main.step(1)
         t += 1
     main.close()
     probe.close()
-    return np.asarray(X, dtype=np.float32), np.asarray(Y, dtype=np.float32)
+    return np.asarray(X, dtype=np.float32), np.asarray(Y, dtype=np.float32).reshape(-1, 2)
 
 
 def init_params(seed: int = 0) -> np.ndarray:
@@ -136,7 +193,7 @@ def init_params(seed: int = 0) -> np.ndarray:
     h, k = 64, N_FEATURES
     parts = [rng.standard_normal(h * k) / math.sqrt(k), np.zeros(h),
              rng.standard_normal(h * h) / math.sqrt(h), np.zeros(h),
-             rng.standard_normal(h) / math.sqrt(h), np.zeros(1)]
+             rng.standard_normal(2 * h) / math.sqrt(h), np.zeros(2)]
     p = np.concatenate(parts).astype(np.float32)
     assert p.size == mlp_param_count()
     return p
@@ -144,23 +201,26 @@ def init_params(seed: int = 0) -> np.ndarray:
 
 def train(X: np.ndarray, Y: np.ndarray, steps: int = 2000, lr: float = 0.5, seed: int = 0,
           device="cuda") -> Tuple["object", List[float]]:
-    """Full-batch gradient descent on the GPU (rpca_mlp_train_step); returns
-    the parameters (CUDA tensor) and the loss every 100 steps."""
+    """Full-batch gradient descent on the GPU (rpca_mlp_train_step, at most
+    65535 samples per step); returns the parameters (CUDA tensor) and the loss
+    every 100 steps."""
     import torch
     p = torch.from_numpy(init_params(seed)).to(device)
     x = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(device)
     y = torch.from_numpy(np.ascontiguousarray(Y, dtype=np.float32)).to(device)
-    ws = torch.empty(int(x.shape[0]) * mlp_param_count(), dtype=torch.float32, device=device)
+    n = min(int(x.shape[0]), 65535)
+    x, y = x[:n].contiguous(), y[:n].contiguous()
+    ws = torch.empty(n * mlp_param_count(), dtype=torch.float32, device=device)
     losses = []
     for k in range(steps):
         if k % 100 == 0:
             pred = mlp_forward(p, x)
-            losses.append(float(0.5 * torch.mean((pred - y) ** 2)))
+            losses.append(float(0.5 * torch.mean(torch.sum((pred - y) ** 2, dim=1))))
         mlp_train_step(p, x, y, lr, ws)
     return p, losses
 
 
-def fit(cases, horizon: int = 15, steps: int = 2000, lr: float = 0.5, seed: int = 0):
+def fit(cases, horizon: int = 10, steps: int = 2000, lr: float = 0.5, seed: int = 0):
     """Train the learned controller: greedy samples along each training case,
     then full-batch gradient descent. cases yields (make_session, lam, lam0,
     mn) per training instance, make_session returning a fresh session with

@@ -283,6 +283,9 @@ DevParams with_v(const rpca_ctx* c, int v) {
 // One round of Algorithm 1: K local steps (each: `inner` V/S alternations,
 // then the U step) and the consensus mean at the last one.
 rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
+  // Rounds at another lambda than the problem's sum the Huber form of the
+  // objective at the target lambda in their S-pass.
+  c->p.huber = c->p.lam != c->p.lam_target ? 1 : 0;
   const DevParams& p = c->p;
   hipStream_t st = c->stream;
   const int64_t ustride = p.ublock;
@@ -468,6 +471,9 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.eta_sched = prm->eta_sched;
   p.lam = (float)prm->lambda;
   p.lam_rec = p.lam;
+  p.lam_target = p.lam;
+  p.huber = 0;
+  p.omega = 1.0;
   p.rho = prm->rho;
   p.eta0 = prm->eta0;
   p.bf16 = L.bf16 ? 1 : 0;
@@ -874,6 +880,7 @@ rpca_status rpca_copy_state(rpca_ctx* dst, rpca_ctx* src) {
   dst->prec = src->prec;
   dst->p.lam = src->p.lam;
   dst->p.lam_rec = src->p.lam_rec;
+  dst->p.omega = src->p.omega;
   dst->p.vsplit = src->p.vsplit;
   dst->p.vsplit_rows = src->p.vsplit_rows;
   dst->p.vcols = src->p.vcols;
@@ -892,6 +899,15 @@ rpca_status rpca_set_lambda(rpca_ctx* c, double lambda) {
     return fail(c, RPCA_EINVAL, "rpca_set_lambda needs K = 1, inner = 1 and no RPCA_FLAG_STORE_S");
   if ((float)lambda != c->p.lam) drop_graphs(c);
   c->p.lam = (float)lambda;
+  return RPCA_OK;
+}
+
+rpca_status rpca_set_step(rpca_ctx* c, double omega) {
+  if (rpca_status s = guard(c)) return s;
+  if (!(omega > 0.0) || !(omega <= 4.0))
+    return fail(c, RPCA_EINVAL, "the step multiplier must lie in (0, 4]");
+  if (omega != c->p.omega) drop_graphs(c);
+  c->p.omega = omega;
   return RPCA_OK;
 }
 

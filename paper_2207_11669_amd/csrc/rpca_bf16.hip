@@ -385,9 +385,11 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
     }
   }
 
-  double sl2 = 0.0, sl1 = 0.0;
+  double sl2 = 0.0, sl1 = 0.0, shb = 0.0;
   uint32_t nnz = 0;
   const float lam = p.lam;
+  const bool hub = p.huber != 0;  // Huber sum at the target lambda
+  const float lt = p.lam_target;
   const GLOBAL bf8* Vh = reinterpret_cast<const GLOBAL bf8*>(gptr(v_hb(p.V, p)));
   const GLOBAL bf8* VhP = Vh + (int64_t)p.NVP * p.RK / 8;
   const GLOBAL bf8* VhB = Vh + 2 * (int64_t)p.NVP * p.RK / 8;
@@ -483,7 +485,7 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
   };
   // Residual, soft-threshold and statistics per row tile, then MFMA 2.
   auto threshold_mfma2 = [&](const MChunk& c) {
-    float l2 = 0.f, l1 = 0.f;
+    float l2 = 0.f, l1 = 0.f, hb = 0.f;
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) {
       float x[8], lamv[8];
@@ -501,6 +503,7 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
         lamv[e] = L;
         l2 = fmaf(L, L, l2);
         l1 += fabsf(Sv);
+        if (hub) hb += huber1(R, lt);
         nnz += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(Sv != 0.f));
       }
       if constexpr (X3) {
@@ -516,6 +519,7 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
     }
     sl2 += (double)l2;
     sl1 += (double)l1;
+    shb += (double)hb;
   };
   if (nk > 0) {
     // Uniform loop: every iteration issues the same loads (chunk indices
@@ -629,7 +633,7 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
       }
     }
   }
-  spass_stats<4>(p, ci, b, sl2, sl1, nnz);
+  spass_stats<4>(p, ci, b, sl2, sl1, nnz, shb);
 }
 
 // One work-group per tile (grid = row blocks x clients), or (Q) a persistent

@@ -401,33 +401,43 @@ __device__ __forceinline__ f4 mfma4x4(float a, float b, f4 c) {
 }
 
 
-// S-pass statistics: the work-group's sums of Lambda^2, |S| and nnz(S) over
-// its NW waves, added in wave order, into p.spart.
+// S-pass statistics: the work-group's sums of Lambda^2, |S|, nnz(S) and (in
+// rounds whose lambda is not the target) the Huber sum H_{lambda_target}(R)
+// over its NW waves, added in wave order, into p.spart.
 template <int NW>
 __device__ __forceinline__ void spass_stats(const DevParams& p, int ci, int b, double sl2,
-                                            double sl1, uint32_t nnz) {
+                                            double sl1, uint32_t nnz, double shb) {
   const int tid = threadIdx.x, lane = tid & 63;
-  __shared__ double sred[NW][3];
+  __shared__ double sred[NW][4];
   sl2 = wave_sum(sl2);
   sl1 = wave_sum(sl1);
+  shb = wave_sum(shb);
   const int wv = tid >> 6;
   if (lane == 0) {
     sred[wv][0] = sl2;
     sred[wv][1] = sl1;
     sred[wv][2] = (double)nnz;
+    sred[wv][3] = shb;
   }
   __syncthreads();
   if (tid == 0) {
     double* o = p.spart + ((int64_t)ci * p.nrb + b) * 4;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 4; ++q) {
       double t = 0.0;
 #pragma unroll
       for (int k = 0; k < NW; ++k) t += sred[k][q];
       o[q] = t;
     }
-    o[3] = 0.0;
   }
+}
+
+// H_lt(R) of one residual entry (Appendix A.2's Huber function): R^2 / 2
+// within the threshold, lt |R| - lt^2 / 2 beyond it. By the Huber identity it
+// is the least value over S of (R - S)^2 / 2 + lt |S|.
+__device__ __forceinline__ float huber1(float R, float lt) {
+  const float a = fabsf(R);
+  return a <= lt ? 0.5f * R * R : lt * a - 0.5f * lt * lt;
 }
 
 // ---------------------------------------------------------------------------
@@ -451,10 +461,11 @@ static __device__ void fin_gram(const DevParams& p, int gi, double* A) {
 }
 
 // Round statistics from the partials of the round's kernels; result in
-// out[0..5] of thread 0: ||Lambda||^2, ||S||_1, nnz(S), ||V||^2, ||dU||^2 and
-// the U penalty of the objective at the round's start.
+// out[0..6] of thread 0: ||Lambda||^2, ||S||_1, nnz(S), ||V||^2, ||dU||^2,
+// the U penalty of the objective at the round's start, and the Huber sum at
+// the target lambda (rounds at another lambda only).
 static __device__ void fin_stats(const DevParams& p, double* out) {
-  __shared__ double red[kFinThreads / 64][5];
+  __shared__ double red[kFinThreads / 64][6];
   const int tid = threadIdx.x, r = p.r, RP = p.RP;
   const int64_t RR = (int64_t)RP * RP;
   if (tid < kFinThreads) {
@@ -462,6 +473,7 @@ static __device__ void fin_stats(const DevParams& p, double* out) {
     double l2 = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 0]; }, kFinThreads);
     double l1 = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 1]; }, kFinThreads);
     double nz = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 2]; }, kFinThreads);
+    double hb = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 3]; }, kFinThreads);
     double vsq = block_strided_sum(p.ngroups * r, [&](int k) {
       const int g = k / r, d = k - g * r;
       return p.gv_part[(int64_t)g * RR + d * RP + d];
@@ -472,12 +484,14 @@ static __device__ void fin_stats(const DevParams& p, double* out) {
     nz = wave_sum(nz);
     vsq = wave_sum(vsq);
     du = wave_sum(du);
+    hb = wave_sum(hb);
     if ((tid & 63) == 0) {
       red[tid >> 6][0] = l2;
       red[tid >> 6][1] = l1;
       red[tid >> 6][2] = nz;
       red[tid >> 6][3] = vsq;
       red[tid >> 6][4] = du;
+      red[tid >> 6][5] = hb;
     }
   }
   __syncthreads();
@@ -495,6 +509,9 @@ static __device__ void fin_stats(const DevParams& p, double* out) {
       for (int i = 0; i < p.E; ++i) ureg += 0.5 * p.clients[i].c * p.ucl_sq[i];
     }
     out[5] = ureg;
+    double t = 0.0;
+    for (int k = 0; k < kFinThreads / 64; ++k) t += red[k][5];
+    out[6] = t;
   }
 }
 
@@ -527,6 +544,11 @@ static __device__ void fin_record(const DevParams& p, const double* stats, doubl
   StatsRec rec;
   rec.t = (double)t;
   rec.objective = 0.5 * stats[0] + 0.5 * p.rho * stats[3] + (double)p.lam_rec * stats[1] + stats[5];
+  // At the target lambda the objective with S = soft(R) is the Huber form
+  // itself (Huber identity); at another lambda the S-pass summed it.
+  rec.objective_target = p.lam_rec == p.lam_target
+                             ? rec.objective
+                             : stats[6] + 0.5 * p.rho * stats[3] + stats[5];
   rec.lambda_fro_sq = stats[0];
   rec.nnz = stats[2];
   rec.du_sq = stats[4];
@@ -551,10 +573,10 @@ static __device__ void finalize_role(const DevParams& p, double* Ginv, int role)
     const double tr = fin_inverse(p, A, Ginv, 0, 0);
     if (threadIdx.x == 0) p.dstate->u_sq_next = tr;
   } else {
-    __shared__ double st[6];
+    __shared__ double st[7];
     fin_stats(p, st);
     if (threadIdx.x == 0)
-      for (int q = 0; q < 6; ++q) p.stat_part[q] = st[q];
+      for (int q = 0; q < 7; ++q) p.stat_part[q] = st[q];
   }
 }
 

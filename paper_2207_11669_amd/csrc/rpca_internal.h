@@ -128,7 +128,7 @@ struct DevState {
 };
 
 struct StatsRec {  // mirrors rpca_stats
-  double t, objective, lambda_fro_sq, nnz, du_sq, u_sq, v_sq, l1;
+  double t, objective, lambda_fro_sq, nnz, du_sq, u_sq, v_sq, l1, objective_target;
 };
 
 struct DevParams {
@@ -151,6 +151,9 @@ struct DevParams {
   int32_t u_mode, eta_sched;
   float lam;             // lambda of the rounds being enqueued
   float lam_rec;         // lambda of the last enqueued round (its deferred record)
+  float lam_target;      // lambda of the problem (rpca_params), the schedule's target
+  int32_t huber;         // 1: the S-pass sums H_{lam_target}(R) (lam != lam_target)
+  double omega;          // multiplier of the consensus U step (1: the method's step)
   double rho, eta0;
   const ClientDev* clients;
   const ClientDev* clients_lpt;  // the same records, widest client first (S-pass order)
@@ -169,7 +172,7 @@ struct DevParams {
   double* ucl_sq;        // per-client ||U_i||^2 of the current local factors
   DevState* dstate;
   StatsRec* hist;
-  double* stat_part;     // six round statistics (finalize folded into the V-pass)
+  double* stat_part;     // seven round statistics (finalize folded into the V-pass)
   // Mixed precision (RPCA_FLAG_BF16): factor blocks carry the BF16 packings
   // after their FP32 layouts (U: at ublock floats; V: at vbuf_floats), and M
   // has two BF16 copies.

@@ -7,12 +7,18 @@
 
 namespace {
 
-constexpr int kIn = RPCA_MLP_IN, kH = RPCA_MLP_HIDDEN;
+constexpr int kIn = RPCA_MLP_IN, kH = RPCA_MLP_HIDDEN, kOut = RPCA_MLP_OUT;
 static_assert(kH == 64, "one wave per sample, one lane per hidden unit");
-// Parameter offsets: W1 (kH x kIn), b1, W2 (kH x kH), b2, w3, b3.
+static_assert(kOut == 2, "two outputs: the decay and the step multiplier");
+// Parameter offsets: W1 (kH x kIn), b1, W2 (kH x kH), b2, W3 (kOut x kH), b3.
 constexpr int kW1 = 0, kB1 = kW1 + kH * kIn, kW2 = kB1 + kH, kB2 = kW2 + kH * kH,
-              kW3 = kB2 + kH, kB3 = kW3 + kH, kP = kB3 + 1;
-constexpr float kGMin = RPCA_MLP_GMIN;
+              kW3 = kB2 + kH, kB3 = kW3 + kOut * kH, kP = kB3 + kOut;
+// Output k = lo_k + (hi_k - lo_k) sigmoid(z_k): the decay in [GMIN, 1], the
+// step multiplier in [WMIN, WMAX].
+__device__ __forceinline__ float out_lo(int k) { return k == 0 ? RPCA_MLP_GMIN : RPCA_MLP_WMIN; }
+__device__ __forceinline__ float out_span(int k) {
+  return k == 0 ? 1.f - RPCA_MLP_GMIN : RPCA_MLP_WMAX - RPCA_MLP_WMIN;
+}
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -21,7 +27,8 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 struct Fwd {
-  float h1, h2, z, sg, y;  // lane j: hidden units j of both layers; z, sigmoid, output
+  float h1, h2;              // lane j: hidden units j of both layers
+  float sg[kOut], y[kOut];   // sigmoids and outputs (every lane)
 };
 
 // Forward pass of sample x for lane j; h1 of all lanes is left in sh1.
@@ -39,9 +46,12 @@ __device__ __forceinline__ Fwd forward(const float* __restrict__ P, const float*
 #pragma unroll 8
   for (int k = 0; k < kH; ++k) a2 = fmaf(P[kW2 + j * kH + k], sh1[k], a2);
   f.h2 = tanhf(a2);
-  f.z = wave_sum(P[kW3 + j] * f.h2) + P[kB3];
-  f.sg = 1.f / (1.f + expf(-f.z));
-  f.y = kGMin + (1.f - kGMin) * f.sg;
+#pragma unroll
+  for (int k = 0; k < kOut; ++k) {
+    const float z = wave_sum(P[kW3 + k * kH + j] * f.h2) + P[kB3 + k];
+    f.sg[k] = 1.f / (1.f + expf(-z));
+    f.y[k] = out_lo(k) + out_span(k) * f.sg[k];
+  }
   return f;
 }
 
@@ -51,12 +61,12 @@ __global__ __launch_bounds__(64) void k_mlp_forward(const float* __restrict__ P,
   __shared__ float sh1[kH];
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
     const Fwd f = forward(P, X + i * kIn, sh1);
-    if (threadIdx.x == 0) Y[i] = f.y;
+    if (threadIdx.x < kOut) Y[i * kOut + threadIdx.x] = threadIdx.x == 0 ? f.y[0] : f.y[1];
     __syncthreads();  // sh1 is rewritten by the next sample
   }
 }
 
-// Per-sample gradient of 1/2 (y - t)^2 by back-propagation, into G[i].
+// Per-sample gradient of 1/2 sum_k (y_k - t_k)^2 by back-propagation, into G[i].
 __global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ P,
                                                  const float* __restrict__ X,
                                                  const float* __restrict__ T,
@@ -67,10 +77,15 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ P,
   const float* x = X + i * kIn;
   const Fwd f = forward(P, x, sh1);
   float* g = G + i * (int64_t)kP;
-  const float dz = (f.y - T[i]) * (1.f - kGMin) * f.sg * (1.f - f.sg);
-  g[kW3 + j] = dz * f.h2;
-  if (j == 0) g[kB3] = dz;
-  const float dz2 = dz * P[kW3 + j] * (1.f - f.h2 * f.h2);
+  float back = 0.f;  // d loss / d h2_j
+#pragma unroll
+  for (int k = 0; k < kOut; ++k) {
+    const float dz = (f.y[k] - T[i * kOut + k]) * out_span(k) * f.sg[k] * (1.f - f.sg[k]);
+    g[kW3 + k * kH + j] = dz * f.h2;
+    if (j == 0) g[kB3 + k] = dz;
+    back = fmaf(dz, P[kW3 + k * kH + j], back);
+  }
+  const float dz2 = back * (1.f - f.h2 * f.h2);
   g[kB2 + j] = dz2;
   for (int k = 0; k < kH; ++k) g[kW2 + j * kH + k] = dz2 * sh1[k];
   sdz2[j] = dz2;

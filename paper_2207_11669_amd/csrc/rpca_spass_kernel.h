@@ -18,7 +18,8 @@ __device__ __forceinline__ void spass_terms_and_stats(const DevParams& p, const 
                                                       const float (*ptile)[RP + 1],
                                                       const float (*utile)[RP + 1],
                                                       const double (*fab)[RP * RP], bool closed,
-                                                      double sl2, double sl1, uint32_t nnz) {
+                                                      double sl2, double sl1, uint32_t nnz,
+                                                      double shb) {
   const int tid = threadIdx.x;
   const int ci = cl.idx;
   const int row0 = b * kSRows;
@@ -51,7 +52,7 @@ __device__ __forceinline__ void spass_terms_and_stats(const DevParams& p, const 
       Ti[(int64_t)(c0 + j) * p.MP + row0 + rl] = c0 + j < p.r ? (float)t[j] : 0.f;
   }
 
-  spass_stats<NW>(p, ci, b, sl2, sl1, nnz);
+  spass_stats<NW>(p, ci, b, sl2, sl1, nnz, shb);
 }
 
 // ---------------------------------------------------------------------------
@@ -129,8 +130,10 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
     }
   }
 
-  double sl2 = 0.0, sl1 = 0.0;
+  double sl2 = 0.0, sl1 = 0.0, shb = 0.0;
   uint32_t nnz = 0;  // wave-uniform count of nonzero S entries
+  const bool hub = p.huber != 0;  // Huber sum at the target lambda
+  const float lt = p.lam_target;
   const float lam = p.lam;
   GLOBAL float* Sblk = STORE ? gptr_w(Sout) + cl.col0 * lds_out : nullptr;
   // V operands: packed, always in range (lane offset + scalar chunk offset).
@@ -187,7 +190,7 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
   };
   auto compute_chunk = [&](const Chunk& c, int k) {
     const int j0 = (phase + NPH * k) << 4;
-    float l2 = 0.f, l1 = 0.f;
+    float l2 = 0.f, l1 = 0.f, hb = 0.f;
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
       f4 a1 = {0.f, 0.f, 0.f, 0.f};
@@ -206,6 +209,7 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
         lamv[v] = L;
         l2 = fmaf(L, L, l2);
         l1 += fabsf(Sv);
+        if (hub) hb += huber1(R, lt);
         nnz += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(Sv != 0.f));
       }
 #pragma unroll
@@ -218,6 +222,7 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
     }
     sl2 += (double)l2;
     sl1 += (double)l1;
+    shb += (double)hb;
   };
   // Uniform loop: every iteration loads (chunk index clamped to the wave's
   // last chunk), so the wait counts stay exact; iterations past the wave's
@@ -323,7 +328,7 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
     }
   }
   __syncthreads();
-  spass_terms_and_stats<RP, 4 * NPH>(p, cl, b, ptile, utile, fab, closed, sl2, sl1, nnz);
+  spass_terms_and_stats<RP, 4 * NPH>(p, cl, b, ptile, utile, fab, closed, sl2, sl1, nnz, shb);
 }
 
 // The kernel: Q = false, one work-group per tile (grid = row blocks x

@@ -16,8 +16,8 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
   constexpr int RP = 16 * RT;
   // rec = 1: record the previous round, whose finalize ran in the V-pass.
   if (rec && blockIdx.x == 0 && threadIdx.x == 0) {
-    double st[6];
-    for (int q = 0; q < 6; ++q) st[q] = p.stat_part[q];
+    double st[7];
+    for (int q = 0; q < 7; ++q) st[q] = p.stat_part[q];
     fin_record(p, st, p.dstate->u_sq_next);
   }
   __shared__ double wd[kVCols][RP + 1];
@@ -343,12 +343,17 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
     for (int q = 0; q < NQ; ++q) uprev[q] = Upv[(int64_t)(cq + 4 * q) * MP + a];
   }
   const double scale = final_step ? 1.0 / (double)p.E : 1.0;
+  // A step multiplier omega != 1 scales the consensus step: U^(t+1) = U^(t) +
+  // omega (mean_i T_i - U^(t)) (for the gradient step, eta becomes omega eta).
+  const bool relax = final_step && p.omega != 1.0;
   float* __restrict__ Uo = Uout + (final_step ? 0 : (int64_t)blockIdx.y * uout_stride);
   double dsq = 0.0;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int c = cq + 4 * q;
-    const float v = (a < p.m && c < r) ? (float)(acc[q] * scale) : 0.f;
+    double x = acc[q] * scale;
+    if (relax) x = (double)uprev[q] + p.omega * (x - (double)uprev[q]);
+    const float v = (a < p.m && c < r) ? (float)x : 0.f;
     fb_store(Uo, MP, RP, p.NS, a, c, v);
     if (p.bf16) hb_store(u_hb(Uo, p), MP, p, a, c, v);
     ul[al * kMaxRank + c] = (double)v;

@@ -318,16 +318,17 @@ RECIPES = {
 }
 
 
-def controller_family(seed: int, n: int = 256):
-    """A training instance for the learned lambda controller: m = n, four
-    equal clients, rank uniform in {4..24}, corruption fraction uniform in
-    [0.02, 0.2] with magnitude U[5, 20] and a random sign. Returns
+def controller_family(seed: int, n: int = 2000):
+    """A training instance for the learned controller, drawn from the
+    evaluation workload's family: m = n, clients of 250 columns (at least
+    one), rank uniform in {5..50} (capped at n / 4), corruption fraction
+    uniform in [0.01, 0.2] with magnitude U[5, 20] and a random sign. Returns
     (instance, rank)."""
     rng = _rng(seed, _STREAM_WIDTHS + 1)
-    r = int(rng.integers(4, 25))
-    s = float(rng.uniform(0.02, 0.2))
-    return planted_instance(n, equal_widths(n, 4), r, s, values="signed", lo=5.0, hi=20.0,
-                            seed=seed), r
+    r = int(min(rng.integers(5, 51), max(1, n // 4)))
+    s = float(rng.uniform(0.01, 0.20))
+    return planted_instance(n, equal_widths(n, max(1, n // 250)), r, s, values="signed", lo=5.0,
+                            hi=20.0, seed=seed), r
 
 
 def recipe(name: str, seed: int = 0, E: Optional[int] = None) -> Instance:

@@ -17,7 +17,8 @@ def _mlp_case(seed, n):
     rng = np.random.default_rng(seed)
     p = (0.3 * rng.standard_normal(OC.N_PARAMS)).astype(np.float32)
     X = rng.standard_normal((n, OC.N_IN)).astype(np.float32)
-    T = rng.uniform(OC.G_MIN, 1.0, n).astype(np.float32)
+    T = np.stack([rng.uniform(OC.G_MIN, 1.0, n), rng.uniform(OC.W_MIN, OC.W_MAX, n)],
+                 axis=1).astype(np.float32)
     return p, X, T
 
 
@@ -97,7 +98,8 @@ def test_fixed_continuation_controller_schedule():
     lam = default_lam(inst)
     lam0 = float(np.abs(inst.M).max())
     s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 4, 0.1, lam, colmajor(init_for(inst, 4, 1)))
-    out = C.run_controlled(s, lam, lam0, C.FixedContinuation(0.8), float(inst.m * inst.n))
+    out = C.run_controlled(s, lam, lam0, C.FixedContinuation(0.8), float(inst.m * inst.n),
+                           judge=False)
     expect = math.ceil(math.log(lam / lam0) / math.log(0.8))
     assert out["control_rounds"] == expect and all(g == 0.8 for g in out["gammas"])
     s.step(1)

@@ -85,3 +85,72 @@ def test_set_lambda_rules():
         g.close()
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     assert outs[0][2] == outs[1][2]
+
+
+@pytest.mark.parametrize("mode,eta", [("closed", 0.0), ("grad", 2e-3)])
+def test_step_multiplier_matches_oracle(mode, eta):
+    """U steps multiplied by omega (rpca_set_step), changing between rounds,
+    against the oracle run with the same multipliers; omega = 1 is the plain
+    step bitwise."""
+    import torch
+
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    inst = planted_instance(300, [100, 70, 130], 5, 0.10, values="signed", lo=5.0, hi=20.0,
+                            seed=8)
+    lam = 1.0 / math.sqrt(inst.n)
+    U0 = init_for(inst, 5, 7)
+    omegas = [1.3] * 12 + [0.8] * 8 + [1.0] * 10
+    s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 5, 0.1, lam, colmajor(U0), u_mode=mode,
+               eta0=eta)
+    for w in omegas:
+        s.set_step(w)
+        s.step(1)
+    L, S = s.get_LS(-1)
+    torch.cuda.synchronize()
+    Lg, Sg = L[:, :inst.m].T.double().cpu().numpy(), S[:, :inst.m].T.double().cpu().numpy()
+    res = O.dcfpca(inst.blocks(), 5, 0.1, lam, len(omegas), U0, u_mode=mode, eta0=eta,
+                   omega_schedule=omegas)
+    eL, eS = rel(Lg, res.L_full()), rel(Sg, res.S_full())
+    announce(f"step multipliers ({mode}): relL={eL:.3e} relS={eS:.3e}")
+    assert eL <= TOL and eS <= TOL
+    # omega = 1 set explicitly is the plain step, bit for bit.
+    a = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 5, 0.1, lam, colmajor(U0), u_mode=mode,
+               eta0=eta)
+    b = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 5, 0.1, lam, colmajor(U0), u_mode=mode,
+               eta0=eta)
+    b.set_step(1.0)
+    a.step(10)
+    b.step(10)
+    La, Sa = a.get_LS(-1)
+    Lb, Sb = b.get_LS(-1)
+    torch.cuda.synchronize()
+    assert torch.equal(La, Lb) and torch.equal(Sa, Sb)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_target_objective_matches_oracle(precision):
+    """Each round's objective at the problem's lambda (rpca_stats
+    objective_target: the Huber form, S at its optimum) along a continuation,
+    against the oracle's; in rounds at that lambda it is the recorded
+    objective itself."""
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    inst = planted_instance(300, [100, 100, 100], 5, 0.10, values="signed", lo=5.0, hi=20.0,
+                            seed=3)
+    lam = float(np.float32(1.0 / math.sqrt(inst.n)))
+    U0 = init_for(inst, 5, 7)
+    sched = _continuation(inst, lam, 40) + [lam] * 10
+    s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, 5, 0.1, lam, colmajor(U0),
+               bf16x3=precision == "bf16x3")
+    for lt in sched:
+        s.set_lambda(lt)
+        s.step(1)
+    res = O.dcfpca(inst.blocks(), 5, 0.1, lam, len(sched), U0, lam_schedule=sched)
+    tol = TOL if precision == "fp32" else 2e-5
+    worst = 0.0
+    for t, (lt, o) in enumerate(zip(sched, res.history)):
+        g = s.stats(t)
+        worst = max(worst, abs(g["objective_target"] - o["objective_target"]) / o["objective_target"])
+        if lt == lam:
+            assert g["objective_target"] == g["objective"]
+    announce(f"target objective ({precision}): worst relative difference {worst:.3e}")
+    assert worst <= tol

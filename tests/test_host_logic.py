@@ -25,27 +25,30 @@ def test_continuation_schedule():
 
 
 def test_controller_features_are_scale_free():
-    """The eight features stay in fixed ranges, and scaling M (hence lambda,
+    """The ten features stay in fixed ranges, and scaling M (hence lambda,
     the statistics and the objective) leaves them unchanged."""
     from paper_2207_11669_amd import controller as C
     st = dict(t=3, objective=5.0, lambda_fro_sq=12.0, nnz=900.0, du_sq=0.02, u_sq=40.0,
               v_sq=30.0, l1=300.0)
     prev = dict(st, u_sq=38.0)
-    f = C.features(st, prev, 20.0, 0.8, 3, 0.05, 1e4)
+    st["objective_target"], prev["objective_target"] = 6.0, 6.5
+    f = C.features(st, prev, 20.0, 0.8, 3, 0.05, 1e4, 1.3)
     assert len(f) == C.N_FEATURES and all(math.isfinite(x) for x in f)
     assert 0.0 <= f[2] <= 1.0 and 0.0 <= f[3] <= 1.0 and -1.0 <= f[5] <= 1.0
+    assert -1.0 <= f[9] < 0.0 and abs(f[8] - 0.3) < 1e-12
     k = 7.0  # M -> k M: Lambda, S scale by k; U, V by sqrt(k); lambda by k
     st2 = dict(st, lambda_fro_sq=st["lambda_fro_sq"] * k * k, l1=st["l1"] * k,
-               du_sq=st["du_sq"] * k, u_sq=st["u_sq"] * k)
-    prev2 = dict(prev, u_sq=prev["u_sq"] * k)
-    f2 = C.features(st2, prev2, 20.0, 0.8, 3, 0.05 * k, 1e4)
+               du_sq=st["du_sq"] * k, u_sq=st["u_sq"] * k,
+               objective_target=st["objective_target"] * k * k)
+    prev2 = dict(prev, u_sq=prev["u_sq"] * k, objective_target=prev["objective_target"] * k * k)
+    f2 = C.features(st2, prev2, 20.0, 0.8, 3, 0.05 * k, 1e4, 1.3)
     assert np.allclose(f, f2, rtol=1e-12, atol=1e-12)
 
 
 def test_controller_decisions():
     from paper_2207_11669_amd import controller as C
-    assert C.FixedContinuation(0.8).decide([0.0] * 8) == 0.8
-    assert C.GAMMAS == (0.5, 0.6, 0.7, 0.8, 0.9, 1.0)
+    assert C.FixedContinuation(0.8).decide([0.0] * C.N_FEATURES) == (0.8, 1.0)
+    assert C.GAMMAS == (0.5, 0.6, 0.7, 0.8, 0.9, 1.0) and C.OMEGAS[0] == 1.0
 
 
 def test_precision_flag_rules():

@@ -285,6 +285,51 @@ def test_hand_worked_lambda_schedule_golden():
     assert abs(h["lambda_fro_sq"] - exp["lambda_fro_sq_round1"]) <= 1e-15
     assert h["nnz"] == exp["nnz_round1"]
     assert np.max(np.abs(np.vstack(res.V) - np.array(exp["stored_reading_V"]))) > 1e-2
+    # The objective at the target lambda: round 0 ran at lambda_0, round 1 at the target.
+    assert abs(res.history[0]["objective_target"] - exp["objective_target_round0"]) <= 1e-14
+    assert res.history[1]["objective_target"] == pytest.approx(exp["objective_round1"], abs=1e-14)
+
+
+def test_hand_worked_step_multiplier_golden():
+    """The consensus step relaxed by omega = 3/2, worked by hand for both U
+    steps; for the gradient step it equals one round with step omega eta."""
+    with open(os.path.join(GOLDEN, "hand_2x2_step_multiplier.json")) as f:
+        gold = json.load(f)
+    inp, exp = gold["inputs"], gold["expected"]
+    M = np.array(inp["M"])
+    Ms = [M[:, :1], M[:, 1:]]
+    U0 = np.array(inp["U0"])
+    for mode in ("closed", "grad"):
+        res = O.dcfpca(Ms, inp["r"], inp["rho"], inp["lambda"], 1, U0, u_mode=mode,
+                       eta0=inp["eta"], omega_schedule=[inp["omega"]])
+        np.testing.assert_allclose(res.U, np.array(exp[mode]["U"]), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(res.L_full(), np.array(exp[mode]["L"]), rtol=0, atol=1e-15)
+    g = O.dcfpca(Ms, inp["r"], inp["rho"], inp["lambda"], 1, U0, u_mode="grad",
+                 eta0=inp["eta"] * inp["omega"])
+    np.testing.assert_allclose(g.U, np.array(exp["grad"]["U"]), rtol=0, atol=1e-15)
+
+
+def test_target_objective_is_the_objective_at_the_target_lambda():
+    """Rounds at the problem's lambda: the Huber form of the objective (S at
+    its optimum, Appendix A.2's identity) equals the recorded objective with
+    S = soft(R), also in the rounds of a continuation that have reached
+    lambda. A multiplier of one is the plain step (to rounding: U + 1 (x - U)
+    is x up to an ulp)."""
+    inst = planted_instance(60, [20, 25], 3, 0.1, values="signed", lo=5.0, hi=20.0, seed=4)
+    lam = 1.0 / math.sqrt(inst.n)
+    U0 = gaussian_init(inst.m, 3, 1)
+    a = O.dcfpca(inst.blocks(), 3, 0.1, lam, 8, U0)
+    for h in a.history:
+        assert h["objective_target"] == pytest.approx(h["objective"], rel=1e-12)
+    mx = float(np.abs(inst.M).max())
+    sched = [max(lam, mx * 0.5 ** t) for t in range(12)]
+    b = O.dcfpca(inst.blocks(), 3, 0.1, lam, 12, U0, lam_schedule=sched)
+    for lt, h in zip(sched, b.history):
+        if lt == lam:
+            assert h["objective_target"] == pytest.approx(h["objective"], rel=1e-12)
+    c = O.dcfpca(inst.blocks(), 3, 0.1, lam, 8, U0, omega_schedule=[1.0] * 8)
+    assert O.relative_error(c.L_full(), a.L_full()) <= 1e-12
+    assert O.relative_error(c.S_full(), a.S_full()) <= 1e-12
 
 
 def _tiny_instance(seed=11, m=40, widths=(7, 13, 5, 15), r=3, s=0.08):
@@ -466,7 +511,7 @@ def _mlp_case(seed=0, n=12):
     rng = np.random.default_rng(seed)
     p = 0.3 * rng.standard_normal(C.N_PARAMS)
     X = rng.standard_normal((n, C.N_IN))
-    T = rng.uniform(C.G_MIN, 1.0, n)
+    T = np.stack([rng.uniform(C.G_MIN, 1.0, n), rng.uniform(C.W_MIN, C.W_MAX, n)], axis=1)
     return C, p, X, T
 
 
@@ -486,15 +531,19 @@ def test_mlp_gradient_matches_finite_differences():
 
 
 def test_mlp_special_cases_and_descent():
-    """Zero weights give y = g_min + (1 - g_min) sigmoid(b3) for every input;
-    output stays in [g_min, 1]; small gradient steps decrease the loss."""
+    """Zero weights give y_k = lo_k + (hi_k - lo_k) sigmoid(b3_k) for every
+    input; the outputs stay in [g_min, 1] and [w_min, w_max]; small gradient
+    steps decrease the loss."""
     C, p, X, T = _mlp_case(seed=2)
     z = np.zeros(C.N_PARAMS)
-    z[-1] = 0.7
+    z[-2], z[-1] = 0.7, -1.3
     y, _ = C.forward(z, X)
-    assert np.allclose(y, C.G_MIN + (1 - C.G_MIN) / (1 + math.exp(-0.7)), rtol=0, atol=1e-15)
+    assert np.allclose(y[:, 0], C.G_MIN + (1 - C.G_MIN) / (1 + math.exp(-0.7)), rtol=0, atol=1e-15)
+    assert np.allclose(y[:, 1], C.W_MIN + (C.W_MAX - C.W_MIN) / (1 + math.exp(1.3)), rtol=0,
+                       atol=1e-15)
     y, _ = C.forward(p * 20, X)
-    assert np.all(y >= C.G_MIN) and np.all(y <= 1.0)
+    assert np.all(y[:, 0] >= C.G_MIN) and np.all(y[:, 0] <= 1.0)
+    assert np.all(y[:, 1] >= C.W_MIN) and np.all(y[:, 1] <= C.W_MAX)
     losses = [C.loss(p, X, T)]
     for _ in range(20):
         p = C.sgd_step(p, X, T, 0.5)
