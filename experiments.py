@@ -225,7 +225,8 @@ def controller(args) -> dict:
             s = session(inst, r, lam)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            ctrl = C.run_controlled(s, lam, lam0, ctl, float(inst.m * inst.n)) if ctl else \
+            ctrl = C.run_controlled(s, lam, lam0, ctl, float(inst.m * inst.n),
+                                    judge=cname == "learned") if ctl else \
                 {"control_rounds": 0, "gammas": []}
             control_s = time.perf_counter() - t1
             trajs[cname] = _trajectory(s, budget, start=ctrl["control_rounds"])
