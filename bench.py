@@ -49,8 +49,9 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 3}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_11669_amd", "csrc", f)
                for f in ("rpca_device.h", "rpca_internal.h", "rpca_vpass_kernel.h",
-                         "rpca_vpass.hip", "rpca_vpass_q.hip", "rpca_spass_kernel.h",
-                         "rpca_spass.hip", "rpca_spass_q.hip", "rpca_bf16.hip", "rpca_tail.hip")]
+                         "rpca_vpass.hip", "rpca_vpass_q.hip", "rpca_vpass_s.hip",
+                         "rpca_spass_kernel.h", "rpca_spass.hip", "rpca_spass_q.hip",
+                         "rpca_spass_s.hip", "rpca_bf16.hip", "rpca_tail.hip")]
 
 
 def log(msg: str):

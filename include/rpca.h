@@ -122,6 +122,17 @@ typedef struct {
  * RPCA_FLAG_STORE_S and every ldm < 2^24. RPCA_FLAG_BF16 also keeps the
  * splits, so a context with it can run either BF16 precision. */
 #define RPCA_FLAG_BF16X3 8u
+/* Sparse S between the passes of FP32 rounds. Each FP32 S-pass also writes
+ * the S it forms (eq. "optS") in sparse form: per 16 x 16 tile of (row,
+ * padded column), four 64-bit support words and the nonzero values packed in
+ * order. The next round's V-pass reads that instead of rebuilding S from the
+ * previous factors: about 0.125 B per entry plus 4 B per nonzero of extra
+ * traffic, 2 r fewer flops per entry. S is the same bit for bit, so results
+ * are bitwise those without the flag. A round rebuilds S as without the flag
+ * when the previous round was not an FP32 round or ran at another lambda.
+ * Workspace: (n rounded per client to 64) x (m rounded to 128) x 4.125 bytes
+ * more. Needs K = 1, inner = 1 and no RPCA_FLAG_STORE_S. */
+#define RPCA_FLAG_SPARSE_S 16u
 
 /* Arithmetic of a round's streaming passes (rpca_set_precision). */
 typedef enum {

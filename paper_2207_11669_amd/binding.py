@@ -137,17 +137,20 @@ RPCA_FLAG_STORE_S = 1
 RPCA_FLAG_GRAPH = 2
 RPCA_FLAG_BF16 = 4
 RPCA_FLAG_BF16X3 = 8
+RPCA_FLAG_SPARSE_S = 16
 PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 
 
 def make_params(m: int, widths: Sequence[int], r: int, rho: float, lam: float, K: int = 1,
                 inner: int = 1, u_mode: str = "closed", eta0: float = 0.0,
                 eta_sched: str = "const", store_s: bool = False, graph: bool = False,
-                bf16: bool = False, bf16x3: bool = False, seed: int = 0):
+                bf16: bool = False, bf16x3: bool = False, seed: int = 0,
+                sparse_s: bool = False):
     """Build an rpca_params struct; returns (params, n_cols array to keep alive)."""
     ncols = (c_int64 * len(widths))(*[int(w) for w in widths])
     flags = ((RPCA_FLAG_STORE_S if store_s else 0) | (RPCA_FLAG_GRAPH if graph else 0)
-             | (RPCA_FLAG_BF16 if bf16 else 0) | (RPCA_FLAG_BF16X3 if bf16x3 else 0))
+             | (RPCA_FLAG_BF16 if bf16 else 0) | (RPCA_FLAG_BF16X3 if bf16x3 else 0)
+             | (RPCA_FLAG_SPARSE_S if sparse_s else 0))
     p = RpcaParams(m=int(m), E=len(widths), n_cols=ncols, r=int(r), rho=float(rho),
                    lam=float(lam), K=int(K), inner=int(inner), u_mode=U_MODES[u_mode],
                    eta0=float(eta0), eta_sched=ETA_SCHEDS[eta_sched], flags=flags,
@@ -199,13 +202,15 @@ class DCFPCA:
     bf16=True creates the context with
     RPCA_FLAG_BF16: rounds run in BF16 until set_precision("fp32").
     bf16x3=True (RPCA_FLAG_BF16X3): rounds run as three-product BF16.
+    sparse_s=True (RPCA_FLAG_SPARSE_S): FP32 rounds hand S from the S-pass to
+    the next V-pass in sparse form instead of rebuilding it.
     """
 
     def __init__(self, M_cols, widths: Sequence[int], m: int, r: int, rho: float, lam: float,
                  U0_cols, K: int = 1, inner: int = 1, u_mode: str = "closed",
                  eta0: float = 0.0, eta_sched: str = "const", store_s: bool = False,
                  graph: bool = False, stream=None, bf16: bool = False, bf16x3: bool = False,
-                 seed: int = 0, static_workspace: bool = False):
+                 seed: int = 0, static_workspace: bool = False, sparse_s: bool = False):
         import torch
         self._lib = load_library()
         if not (M_cols.is_cuda and M_cols.dtype == torch.float32 and M_cols.is_contiguous()):
@@ -221,7 +226,7 @@ class DCFPCA:
         self.ldm = int(M_cols.shape[1])
         self.params, self._ncols = make_params(m, self.widths, r, rho, lam, K, inner, u_mode,
                                                eta0, eta_sched, store_s, graph, bf16, bf16x3,
-                                               seed)
+                                               seed, sparse_s)
         err = params_error(self.params)
         if err:
             raise ValueError(err)

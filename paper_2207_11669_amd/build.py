@@ -20,9 +20,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "librpca.so")
-SOURCES = ["rpca_vpass.hip", "rpca_vpass_q.hip", "rpca_spass.hip", "rpca_spass_q.hip",
-           "rpca_bf16.hip", "rpca_tail.hip", "rpca_api.cpp",
-           "rpca_mlp.hip"]
+SOURCES = ["rpca_vpass.hip", "rpca_vpass_q.hip", "rpca_vpass_s.hip", "rpca_spass.hip",
+           "rpca_spass_q.hip", "rpca_spass_s.hip", "rpca_bf16.hip", "rpca_tail.hip",
+           "rpca_api.cpp", "rpca_mlp.hip"]
 ARCH = "gfx950"
 # hipcc's host pass warns that it does not know the packed-fp32 feature.
 _NOISE = "packed-fp32-ops"

@@ -36,6 +36,9 @@ struct rpca_ctx {
   int vcur = 0;  // V buffer holding the latest V
   int inner = 1;
   bool recompute = false;  // S rebuilt from (U_prev, V) instead of stored
+  // RPCA_FLAG_SPARSE_S: the sparse S in the workspace is that of the last
+  // round's S-pass (an FP32 round); lam_rec is its lambda.
+  bool sparse_valid = false;
   float* V[2] = {nullptr, nullptr};  // V buffers (row-major copy + factor block)
   std::vector<VTile> vg64;
   bool poisoned = false;
@@ -71,7 +74,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t S, U0, U1, Uc0, Uc1, V0, V1, Mbv, Mbs, Wpart, P, gv, Af, Bf, gram, spart, upart,
+  size_t S, Smask, Sval, U0, U1, Uc0, Uc1, V0, V1, Mbv, Mbs, Wpart, P, gv, Af, Bf, gram, spart, upart,
       ucl, Ginv, dstate, hist, stat_part, clients, clients_lpt, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
       queue, total;
   int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows, vsplit_max, RK;
@@ -113,8 +116,12 @@ const char* check_params(const rpca_params* p) {
   if (p->u_mode == RPCA_U_GRAD && (!(p->eta0 > 0.0) || !std::isfinite(p->eta0)))
     return "eta0 must be finite and > 0 for RPCA_U_GRAD";
   if (p->eta_sched != RPCA_ETA_CONST && p->eta_sched != RPCA_ETA_SQRT) return "unknown eta_sched";
-  if (p->flags & ~(uint32_t)(RPCA_FLAG_STORE_S | RPCA_FLAG_GRAPH | RPCA_FLAG_BF16 | RPCA_FLAG_BF16X3))
+  if (p->flags & ~(uint32_t)(RPCA_FLAG_STORE_S | RPCA_FLAG_GRAPH | RPCA_FLAG_BF16 |
+                             RPCA_FLAG_BF16X3 | RPCA_FLAG_SPARSE_S))
     return "unknown flags";
+  if ((p->flags & RPCA_FLAG_SPARSE_S) &&
+      (p->K != 1 || p->inner != 1 || (p->flags & RPCA_FLAG_STORE_S)))
+    return "RPCA_FLAG_SPARSE_S needs K = 1, inner = 1 and no RPCA_FLAG_STORE_S";
   if ((p->flags & (RPCA_FLAG_BF16 | RPCA_FLAG_BF16X3)) &&
       (p->K != 1 || p->inner != 1 || (p->flags & RPCA_FLAG_STORE_S)))
     return "RPCA_FLAG_BF16 and RPCA_FLAG_BF16X3 need K = 1, inner = 1 and no RPCA_FLAG_STORE_S";
@@ -171,6 +178,12 @@ Layout make_layout(const rpca_params* p) {
     return at;
   };
   L.S = take((size_t)L.Sfloats * f);
+  // Sparse S: per 16 x 16 tile of (row, padded column), 4 support words and
+  // room for 256 values.
+  const bool sparse = (p->flags & RPCA_FLAG_SPARSE_S) != 0;
+  const size_t tiles = sparse ? (size_t)(L.NVP / 16) * (size_t)(L.MP / 16) : 0;
+  L.Smask = take(tiles * 4 * sizeof(uint64_t));
+  L.Sval = take(tiles * kSparseVals * f);
   const size_t ub = (size_t)fb_floats(L.MP, L.RP, L.NS);
   // BF16 packings (hi, then lo) follow the FP32 layouts of each U block and V
   // buffer.
@@ -294,12 +307,17 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
   if (c->recompute) {
     // K = 1, one alternation: S of the previous round is rebuilt inside the
     // V-pass from (U^(t-1), V^(t)) and never stored.
-    const int mode = c->rounds == 0 ? kSZero : kSRecompute;
+    const bool h = c->prec != RPCA_PREC_FP32;
+    // With RPCA_FLAG_SPARSE_S an FP32 round reads the S of the previous
+    // round's S-pass when that was an FP32 round at this lambda.
+    const bool sparse_in = !h && c->sparse_valid && p.lam == p.lam_rec;
+    const int mode = c->rounds == 0 ? kSZero : sparse_in ? kSSparse : kSRecompute;
     const int vn = c->vcur ^ 1;
-    const DevParams q = with_v(c, vn);
+    DevParams q = with_v(c, vn);
+    // BF16 rounds write no sparse S.
+    if (h) q.Smask = nullptr, q.Sval = nullptr;
     double* fin = c->fin_pending ? c->Ginv : nullptr;
     c->fin_pending = false;
-    const bool h = c->prec != RPCA_PREC_FP32;
     const int x3 = c->prec == RPCA_PREC_BF16X3 ? 1 : 0;
     RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
                 h ? launch_vpass_h(q, mode, Ucons, c->U[c->cur ^ 1], c->V[c->vcur], fin, x3, st)
@@ -319,6 +337,7 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     c->cur ^= 1;
     c->rounds += 1;
     c->p.lam_rec = c->p.lam;
+    c->sparse_valid = q.Smask != nullptr;
     return RPCA_OK;
   }
   for (int k = 0; k < p.K; ++k) {
@@ -488,6 +507,9 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.vgroups = reinterpret_cast<const VGroup*>(ws + L.vgroups);
   p.vg64 = reinterpret_cast<const VTile*>(ws + L.vg64);
   p.S = L.recompute ? nullptr : reinterpret_cast<float*>(ws + L.S);
+  const bool sparse = (prm->flags & RPCA_FLAG_SPARSE_S) != 0;
+  p.Smask = sparse ? reinterpret_cast<uint64_t*>(ws + L.Smask) : nullptr;
+  p.Sval = sparse ? reinterpret_cast<float*>(ws + L.Sval) : nullptr;
   c->recompute = L.recompute;
   c->use_graph = L.recompute && (prm->flags & RPCA_FLAG_GRAPH);
   c->V[0] = reinterpret_cast<float*>(ws + L.V0);
@@ -685,8 +707,11 @@ rpca_status rpca_step(rpca_ctx* c, int32_t rounds) {
     // A graph bakes its launches' parameters, including the lambda the first
     // round's deferred record uses: capture only in a steady state, where
     // that is the lambda of every round.
+    // With sparse S the graph's first round reads the sparse S, which must
+    // then be there.
+    const bool sparse_ok = !c->p.Smask || c->prec != RPCA_PREC_FP32 || c->sparse_valid;
     if (c->use_graph && rounds - t >= 2 && c->rounds >= 1 && c->fin_pending &&
-        c->p.lam_rec == c->p.lam) {
+        c->p.lam_rec == c->p.lam && sparse_ok) {
       if (rpca_status s = enqueue_round_pair_graph(c)) return s;
       t += 2;
     } else {
@@ -857,7 +882,7 @@ rpca_status rpca_copy_state(rpca_ctx* dst, rpca_ctx* src) {
   if (dst->ws_bytes != src->ws_bytes || dst->widths != src->widths || a.m != b.m || a.r != b.r ||
       a.K != b.K || a.u_mode != b.u_mode || a.bf16 != b.bf16 || a.eta_sched != b.eta_sched ||
       a.rho != b.rho || a.eta0 != b.eta0 || dst->inner != src->inner ||
-      dst->recompute != src->recompute)
+      dst->recompute != src->recompute || (a.Smask == nullptr) != (b.Smask == nullptr))
     return fail(dst, RPCA_EINVAL, "rpca_copy_state needs contexts created with the same parameters");
   RPCA_HIP(src, hipStreamSynchronize(src->stream), "synchronize");
   size_t at = 0;
@@ -875,6 +900,7 @@ rpca_status rpca_copy_state(rpca_ctx* dst, rpca_ctx* src) {
   dst->vcur = src->vcur;
   dst->fin_pending = src->fin_pending;
   dst->have_prev = src->have_prev;
+  dst->sparse_valid = src->sparse_valid;
   dst->have_target = src->have_target;
   dst->RPT = src->RPT;
   dst->prec = src->prec;

@@ -48,6 +48,14 @@ __device__ __forceinline__ GLOBAL T* gptr_w(T* p) {
   return (GLOBAL T*)p;
 }
 
+// Constant-address-space view: loads from a wave-uniform address through it
+// go through the scalar cache (used only for data an earlier launch wrote).
+#define CONSTANT __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const CONSTANT T* cptr(const T* p) {
+  return (const CONSTANT T*)p;
+}
+
 // Raw buffer loads. A buffer resource holds a base address and a byte range;
 // lanes whose offset falls outside the range read 0 instead of memory, and the
 // per-lane offset is 32-bit, so addresses need no 64-bit arithmetic per load.
@@ -63,6 +71,14 @@ __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
 }
 __device__ __forceinline__ f4 bload4(rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+// Raw buffer stores; lanes whose offset falls outside the range write nothing.
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, float x) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, (int)voff, 0, 0);
+}
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void bstore64(rsrc_t r, uint32_t voff, uint64_t x) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, (int)voff, 0, 0);
 }
 // Tile queue of a persistent launch (a streaming pass whose grid holds only
 // as many work-groups as are resident at once). q[0] is the next tile, q[1]

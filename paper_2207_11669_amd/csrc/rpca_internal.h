@@ -91,6 +91,18 @@ __host__ __device__ inline int64_t hb_hB(int a, int c, int RT) {
 //   S-pass layout, 16-row tile rt, 32-column chunk cc:
 //        M[16 rt + l%16][32 cc + 8 (l/16) + e]   at ((rt (NVc/32) + cc) 64 + l) 8 + e
 
+// Sparse S (RPCA_FLAG_SPARSE_S). The S-pass writes S in tiles of 16 rows by
+// 16 columns of the padded V rows: tile = (column / 16) * (MP / 16) + row / 16.
+// A tile has four 64-bit support words, word v holding bit j for the entry
+// (row j % 16, column 4 (j / 16) + v) of the tile, and room for 256 values,
+// of which the nonzero entries fill the front in (word, bit) order.
+constexpr int kSparseVals = 256;
+__host__ __device__ inline int64_t sparse_tile(int MP, int64_t vcol, int row) {
+  return (vcol >> 4) * (int64_t)(MP >> 4) + (row >> 4);
+}
+// What of S an S-pass tile writes besides its statistics and U-step term.
+enum SOutMode { kSOutNone = 0, kSOutDense = 1, kSOutSparse = 2 };
+
 // One client (Section 2.1): its borrowed block M_i and where its private
 // state lives in the workspace.
 struct ClientDev {
@@ -180,6 +192,9 @@ struct DevParams {
   int32_t RK, NK;        // contraction-side ranks (32 NK) and blocks
   uint16_t* Mbv;         // BF16 M, V-pass layout
   uint16_t* Mbs;         // BF16 M, S-pass layout
+  // Sparse S (RPCA_FLAG_SPARSE_S): support words and values of every piece.
+  uint64_t* Smask;
+  float* Sval;
 };
 
 // BF16 packings of a U factor block / a V buffer.
@@ -199,9 +214,9 @@ __host__ __device__ inline const uint16_t* v_hb(const float* V, const DevParams&
 // Launch helpers (kernels live in rpca_vpass.hip, rpca_spass.hip, rpca_bf16.hip
 // and rpca_tail.hip).
 constexpr int kDistBlocks = 64;  // work-groups per side of the factor-distance kernel
-// S source for the V-pass: zero, the stored S buffer, or recomputed from the
-// previous round's factors.
-enum VMode { kSZero = 0, kSStored = 1, kSRecompute = 2 };
+// S source for the V-pass: zero, the stored S buffer, recomputed from the
+// previous round's factors, or the sparse S the previous S-pass wrote.
+enum VMode { kSZero = 0, kSStored = 1, kSRecompute = 2, kSSparse = 3 };
 // V-pass, streaming part: partial W = (M_i - S_i)^T U_i per row split into
 // p.Wpart. U: factor block of the input U (client stride u_stride); Uold /
 // Vold: previous U factor block and previous V buffer (kSRecompute).

@@ -68,8 +68,11 @@ __device__ __forceinline__ void spass_terms_and_stats(const DevParams& p, const 
 // (16 consecutive rows per column per instruction).
 // The contraction index of MFMA 1 is split as k-group g = l/16 taking rank
 // indices g*NS + s, s < NS = ceil(r/4), so no padding steps run for r % 16.
+// SOUT: what of S the tile writes besides its statistics and U-step term:
+// kSOutNone, kSOutDense (column-major into Sout) or kSOutSparse (support
+// words and packed nonzero values per 16 x 16 tile, sparse_tile).
 // ---------------------------------------------------------------------------
-template <int RT, int NS, bool STORE, int NPH>
+template <int RT, int NS, int SOUT, int NPH>
 __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __restrict__ Ubase,
                                            int64_t u_stride, float* __restrict__ Sout,
                                            int64_t lds_out, int emit_only, int client_base,
@@ -135,6 +138,7 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
   const bool hub = p.huber != 0;  // Huber sum at the target lambda
   const float lt = p.lam_target;
   const float lam = p.lam;
+  constexpr bool STORE = SOUT == kSOutDense;
   GLOBAL float* Sblk = STORE ? gptr_w(Sout) + cl.col0 * lds_out : nullptr;
   // V operands: packed, always in range (lane offset + scalar chunk offset).
   const rsrc_t rVa = make_rsrc(v_fb(p.V, p.NVP, RP) + fb_pa_off(p.NVP, RP), range32((int64_t)p.NVP * 4 * NS * 4));
@@ -191,12 +195,27 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
   auto compute_chunk = [&](const Chunk& c, int k) {
     const int j0 = (phase + NPH * k) << 4;
     float l2 = 0.f, l1 = 0.f, hb = 0.f;
+    // Sparse S of this wave's two 16 x 16 tiles (consecutive tile indices):
+    // four support words each (lane 4 rt + v keeps word v of tile rt), values
+    // packed in (word, lane) order. Stores go through buffer resources; zero
+    // entries take an offset outside the range and write nothing.
+    [[maybe_unused]] uint64_t myword = 0;
+    // (The row strip via readfirstlane: wave-uniform, so the resources built
+    // from it stay in scalar registers.)
+    [[maybe_unused]] const int64_t tile0 =
+        SOUT == kSOutSparse
+            ? sparse_tile(p.MP, cl.vrow0 + j0, __builtin_amdgcn_readfirstlane(arow0))
+            : 0;
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
       f4 a1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < NS; ++s) a1 = mfma4(c.va[s], ub[rt][s], a1);
       f4 lamv;
+      [[maybe_unused]] uint32_t run = 0;  // nonzero entries of this tile so far
+      [[maybe_unused]] rsrc_t rSv;
+      if constexpr (SOUT == kSOutSparse)
+        rSv = make_rsrc(p.Sval + (tile0 + rt) * kSparseVals, kSparseVals * 4u);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const float R = c.m[rt][v] - a1[v];
@@ -210,7 +229,17 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
         l2 = fmaf(L, L, l2);
         l1 += fabsf(Sv);
         if (hub) hb += huber1(R, lt);
-        nnz += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(Sv != 0.f));
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(Sv != 0.f);
+        nnz += (uint32_t)__builtin_popcountll(bal);
+        if constexpr (SOUT == kSOutSparse) {
+          // This lane's value goes after every set bit before it in the
+          // tile's order: earlier words (run) and lower lanes of this one.
+          const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+          bstore(rSv, Sv != 0.f ? (run + below) * 4u : kOffNone, Sv);
+          run += (uint32_t)__builtin_popcountll(bal);
+          myword = lane == 4 * rt + v ? bal : myword;
+        }
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -223,6 +252,11 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
     sl2 += (double)l2;
     sl1 += (double)l1;
     shb += (double)hb;
+    if constexpr (SOUT == kSOutSparse) {
+      // Lanes 0..7 write the two tiles' support words.
+      const rsrc_t rSm = make_rsrc(p.Smask + tile0 * 4, 8 * 8u);
+      bstore64(rSm, lane < 8 ? (uint32_t)lane * 8u : kOffNone, myword);
+    }
   };
   // Uniform loop: every iteration loads (chunk index clamped to the wave's
   // last chunk), so the wait counts stay exact; iterations past the wave's
@@ -335,18 +369,18 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
 // clients); Q = true, a persistent launch whose work-groups take tiles
 // t = (row block t % nrb, client t / nrb) from the queue (never for the S
 // emission).
-template <int RT, int NS, bool STORE, int NPH, bool Q>
+template <int RT, int NS, int SOUT, int NPH, bool Q>
 __global__ __launch_bounds__(256 * NPH) void k_spass(DevParams p, const float* __restrict__ Ubase,
                                                      int64_t u_stride, float* __restrict__ Sout,
                                                      int64_t lds_out, int emit_only,
                                                      int client_base) {
   if constexpr (!Q) {
-    spass_tile<RT, NS, STORE, NPH>(p, Ubase, u_stride, Sout, lds_out, emit_only, client_base,
+    spass_tile<RT, NS, SOUT, NPH>(p, Ubase, u_stride, Sout, lds_out, emit_only, client_base,
                                    (int)blockIdx.x, (int)blockIdx.y);
   } else {
     const int ntiles = p.nrb * p.E;
     for (int t = queue_next(p.queue + 2, ntiles); t < ntiles; t = queue_next(p.queue + 2, ntiles))
-      spass_tile<RT, NS, STORE, NPH>(p, Ubase, u_stride, Sout, lds_out, 0, 0, t % p.nrb,
+      spass_tile<RT, NS, SOUT, NPH>(p, Ubase, u_stride, Sout, lds_out, 0, 0, t % p.nrb,
                                      t / p.nrb);
   }
 }
@@ -355,5 +389,9 @@ __global__ __launch_bounds__(256 * NPH) void k_spass(DevParams p, const float* _
 // (rpca_spass_q.hip).
 hipError_t launch_spass_queue(const DevParams& p, const float* U, int64_t u_stride,
                               float* Sout, int64_t lds_out, hipStream_t st);
+// S-pass over all clients writing sparse S (p.Smask, p.Sval), in the launch
+// form p.squeue picks (rpca_spass_s.hip).
+hipError_t launch_spass_sparse(const DevParams& p, const float* U, int64_t u_stride,
+                               hipStream_t st);
 
 }  // namespace rpca

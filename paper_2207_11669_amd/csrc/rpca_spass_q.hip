@@ -14,14 +14,14 @@ static hipError_t launch_spass_q_t(const DevParams& p, const float* U, int64_t u
   };
   if (p.sphases == 1) {
     if (Sout)
-      launch(k_spass<RT, NS, true, 1, true>, 256);
+      launch(k_spass<RT, NS, kSOutDense, 1, true>, 256);
     else
-      launch(k_spass<RT, NS, false, 1, true>, 256);
+      launch(k_spass<RT, NS, kSOutNone, 1, true>, 256);
   } else {
     if (Sout)
-      launch(k_spass<RT, NS, true, 2, true>, 512);
+      launch(k_spass<RT, NS, kSOutDense, 2, true>, 512);
     else
-      launch(k_spass<RT, NS, false, 2, true>, 512);
+      launch(k_spass<RT, NS, kSOutNone, 2, true>, 512);
   }
   return hipGetLastError();
 }

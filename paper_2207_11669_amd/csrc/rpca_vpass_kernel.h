@@ -24,6 +24,10 @@ namespace rpca {
 // MODE kSRecompute rebuilds S = soft(M - Uo Vo^T) of the previous round on the
 // fly: its MFMA puts Uo rows on the A side and Vo^T on the B side, so the
 // 16x16 residual tile comes out in exactly the float4 layout of M.
+// MODE kSSparse reads the S the previous S-pass wrote in sparse form (support
+// words and packed values per 16 x 16 tile, sparse_tile): lane l's four
+// entries are bits 4 (l/16) + e + 16 ((l%16)/4) of word (l%16)%4 of the
+// chunk's tile, and sit at consecutive places among the tile's nonzeros.
 
 
 template <int RT, int NS, int MODE, int KG>
@@ -93,11 +97,32 @@ __device__ __forceinline__ void vpass_tile(const DevParams& p, const float* __re
   const rsrc_t rUq = make_rsrc(U + fb_pq_off(p.MP, RP, NS), range32((int64_t)p.MP * 4 * NQ * 4));
   const uint32_t vq_off = (uint32_t)(((lane >> 4) * 4 + (lane & 3)) * 16);
   const rsrc_t rUa = make_rsrc(gUopa_raw, range32((int64_t)p.MP * 4 * NS * 4));
+  // Sparse S: the support words of the next chunk to load are fetched (into
+  // scalar registers) one chunk ahead of the values they address.
+  constexpr bool SPARSE = MODE == kSSparse;
+  const int sp_v = li & 3, sp_b0 = 4 * lg + 16 * (li >> 2);
+  const uint64_t sp_low = ((uint64_t)1 << sp_b0) - 1u;
+  uint64_t mk[SPARSE ? kG : 1][4];
+  auto load_masks = [&](int k) {
+    const int row0 = rbeg + ((ph + kPh * k) << 4);
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int j0 = jw + 16 * g;
+      if (j0 < cl.n) {  // wave-uniform; column groups past n_i hold no tile of this client
+        const CONSTANT uint64_t* src = cptr(p.Smask + sparse_tile(p.MP, cl.vrow0 + j0, row0) * 4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mk[g][q] = src[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mk[g][q] = 0;
+      }
+    }
+  };
 
   // Operands of one 16-row chunk; kVDepth chunks are kept in flight (vector
   // loads complete in order, so everything a chunk needs is issued together).
   struct Chunk {
-    f4 m[kG], s[kG];          // M (and stored S) rows 4*(l/16)..+3 of column 16 g + l%16
+    f4 m[kG], s[kG];          // M (and stored or sparse S) rows 4*(l/16)..+3 of column 16 g + l%16
     f4 u[RTF > 0 ? RTF : 1];  // U^T operand: U[row][rank 16*ct + l%16] for the 4 rows
     f4 uq[NQ > 0 ? NQ : 1];   // quads: U[row][rank RP - 16 + 4 q + l%4] for the 4 rows
     float uo[NS];             // previous U, A operand of the S rebuild: Uo[row l%16][rank g*NS + s]
@@ -124,6 +149,31 @@ __device__ __forceinline__ void vpass_tile(const DevParams& p, const float* __re
 #pragma unroll
       for (int s = 0; s < NS; ++s) c.uo[s] = bload(rUa, (uint32_t)lane * 4u, ((chg * NS + s) * 64u) * 4u);
     }
+    if constexpr (SPARSE) {
+      // mk holds this chunk's support words. The lane's value e lies after
+      // the tile's nonzeros in earlier words (pre), those of lower bits of its
+      // own word, and its own earlier set entries; unset entries read 0.
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const uint64_t w0 = mk[g][0], w1 = mk[g][1], w2 = mk[g][2], w3 = mk[g][3];
+        const uint32_t p1 = (uint32_t)__builtin_popcountll(w0);
+        const uint32_t p2 = p1 + (uint32_t)__builtin_popcountll(w1);
+        const uint32_t p3 = p2 + (uint32_t)__builtin_popcountll(w2);
+        const uint64_t word = sp_v == 0 ? w0 : sp_v == 1 ? w1 : sp_v == 2 ? w2 : w3;
+        const uint32_t pre = sp_v == 0 ? 0u : sp_v == 1 ? p1 : sp_v == 2 ? p2 : p3;
+        const uint32_t base = pre + (uint32_t)__builtin_popcountll(word & sp_low);
+        const uint32_t nib = (uint32_t)(word >> sp_b0) & 15u;
+        const int j0 = jw + 16 * g;
+        const rsrc_t rSv = make_rsrc(p.Sval + sparse_tile(p.MP, cl.vrow0 + j0, row0) * kSparseVals,
+                                     kSparseVals * 4u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t at = base + (uint32_t)__builtin_popcount(nib & ((1u << e) - 1u));
+          c.s[g][e] = bload(rSv, ((nib >> e) & 1u) ? at * 4u : kOffNone, 0);
+        }
+      }
+      load_masks(min(k + 1, nk - 1));
+    }
   };
   auto compute_chunk = [&](const Chunk& c, int k) {
     // Columns past n_i read 0 from M (and S) and have zero rows in the old V,
@@ -147,7 +197,8 @@ __device__ __forceinline__ void vpass_tile(const DevParams& p, const float* __re
         }
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) d[e] = c.m[g][e] - (MODE == kSStored ? c.s[g][e] : 0.f);
+        for (int e = 0; e < 4; ++e)
+          d[e] = c.m[g][e] - ((MODE == kSStored || SPARSE) ? c.s[g][e] : 0.f);
       }
       if (tail) {
 #pragma unroll
@@ -169,6 +220,7 @@ __device__ __forceinline__ void vpass_tile(const DevParams& p, const float* __re
     const int nkp = (nk + kVDepth - 1) / kVDepth * kVDepth;
     // The prologue issues the ring in slot order (fenced like the loop body),
     // so that at the loop head slot 0 holds the oldest loads on every path.
+    if constexpr (SPARSE) load_masks(0);
 #pragma unroll
     for (int d = 0; d < kVDepth; ++d) {
       load_chunk(ring[d], min(d, nk - 1));
@@ -267,5 +319,9 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
 hipError_t launch_vpass_queue(const DevParams& p, int mode, const float* U, int64_t u_stride,
                               const float* Uold, const float* Vold, double* fin_Ginv,
                               hipStream_t st);
+// V-pass reading sparse S, in the launch form p.vqueue picks
+// (rpca_vpass_s.hip).
+hipError_t launch_vpass_sparse(const DevParams& p, const float* U, int64_t u_stride,
+                               double* fin_Ginv, hipStream_t st);
 
 }  // namespace rpca

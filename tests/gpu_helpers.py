@@ -38,7 +38,9 @@ def run_gpu(inst: Instance, U0: np.ndarray, r: int, rho: float, lam: float, T: i
 
 def run_oracle(inst: Instance, U0: np.ndarray, r: int, rho: float, lam: float, T: int,
                K: int = 1, inner: int = 1, u_mode: str = "closed", eta0: float = 0.0,
-               eta_sched: str = "const", store_s: bool = False):
+               eta_sched: str = "const", store_s: bool = False, sparse_s: bool = False):
+    # store_s and sparse_s choose how the HIP path keeps S between its passes;
+    # the oracle's arithmetic has no such choice.
     return O.dcfpca(inst.blocks(), r, rho, lam, T, U0, K=K, inner=inner, u_mode=u_mode,
                     eta0=eta0, eta_sched=eta_sched)
 
