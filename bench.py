@@ -186,7 +186,8 @@ def measure(M_cols, inst, r, rho, lam, U0_cols, args, precision: str, workload: 
     from paper_2207_11669_amd import DCFPCA
     eta0 = 0.0 if args.u_mode == "closed" else 1e-4
     s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode, eta0=eta0,
-               graph=args.graph, bf16=precision == "bf16", bf16x3=precision == "bf16x3")
+               graph=args.graph, bf16=precision == "bf16", bf16x3=precision == "bf16x3",
+               sparse_s=args.sparse_s and precision == "fp32")
     log(f"{precision}: warmup {args.warmup}")
     s.step(args.warmup)
     shape = s.autotune(args.autotune) if args.autotune > 0 else s.launch_shape()
@@ -402,6 +403,9 @@ def main() -> int:
                     help="arithmetic of the headline rounds' streaming passes")
     ap.add_argument("--graph", action="store_true",
                     help="replay steady-state rounds from HIP graphs (RPCA_FLAG_GRAPH)")
+    ap.add_argument("--sparse-s", action="store_true",
+                    help="FP32 rounds hand S from the S-pass to the next V-pass in sparse form "
+                         "(RPCA_FLAG_SPARSE_S) instead of rebuilding it")
     ap.add_argument("--autotune", type=int, default=20, metavar="ROUNDS",
                     help="before timing, pick the launch shapes with rpca_autotune (ROUNDS timed "
                          "rounds per candidate); 0 keeps the defaults")
@@ -479,7 +483,8 @@ def main() -> int:
         "config": {"workload": workload, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
                    "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam,
                    "rho": rho, "K": 1, "inner": 1, "u_mode": args.u_mode,
-                   "graph": bool(args.graph), "precision": args.precision,
+                   "graph": bool(args.graph), "sparse_s": bool(args.sparse_s),
+                   "precision": args.precision,
                    "autotuned_launch_shape": head["autotuned_launch_shape"]},
         "roofline": head["roofline"],
         "mixed_precision": mixed,

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
 // loads from the caller's block), and the A operand of MFMA 2 (P += Lambda V
 // with V's hB packing as B; X3: every product as three BF16 products of
 // hi/lo splits). The phases' partial P are added in LDS in phase order. LDS
-// holds P and FP32 copies of A_i and B_i (74 KB at r = 64), so two
+// holds P and an FP32 copy of A_i (54 KB at r = 64), so two
 // work-groups fit on a compute unit and one's epilogue overlaps the other's
 // sweep.
 // ---------------------------------------------------------------------------
@@ -368,21 +368,16 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct) accp[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // A_i and B_i of the closed-form step, rounded to FP32, for the epilogue
-  // (made visible by the barriers that add the phases' P). Rows are padded to
-  // RP + 16 floats, so that the epilogue's operand reads (four rows of 16
-  // consecutive entries per wave) fall in distinct banks.
-  constexpr int kFS = RP + 16;
-  __shared__ float fab[2][RP * kFS];
+  // A_i of the closed-form step, rounded to FP32, for the epilogue (made
+  // visible by the barriers that add the phases' P). Rows are padded to an
+  // odd multiple of 16 floats, so that the epilogue's operand reads (four
+  // rows of 16 consecutive entries per wave) fall in distinct banks.
+  constexpr int kFS = 16 * ((RP / 16) | 1);
+  __shared__ float fal[RP * kFS];
   const bool closed = p.u_mode != 0;
   if (closed) {
     const double* __restrict__ Af = p.Afac + (int64_t)ci * RP * RP;
-    const double* __restrict__ Bf = p.Bfac + (int64_t)ci * RP * RP;
-    for (int e = tid; e < RP * RP; e += blockDim.x) {
-      const int at = (e / RP) * kFS + e % RP;
-      fab[0][at] = (float)Af[e];
-      fab[1][at] = (float)Bf[e];
-    }
+    for (int e = tid; e < RP * RP; e += blockDim.x) fal[(e / RP) * kFS + e % RP] = (float)Af[e];
   }
 
   double sl2 = 0.0, sl1 = 0.0, shb = 0.0;
@@ -410,11 +405,14 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
     }
   }
   // Operands of one 32-column chunk. M streams from HBM and is kept two
-  // chunks ahead (ring of two). The V operands come from L2 and each has a
+  // chunks ahead (ring of two). The V operands come from L2. In one-product
+  // rounds they ride in the same ring. In three-product rounds each has a
   // single buffer, refilled for the next chunk right after its last use in
   // this one: the hP halves (MFMA 1) once MFMA 1 has issued, hB (MFMA 2) once
-  // MFMA 2 has. Holding them two chunks ahead as well cost 64 registers in
-  // three-product rounds (hi and lo) and left one wave per SIMD at r = 64.
+  // MFMA 2 has. Holding them two chunks ahead there cost 64 registers (hi and
+  // lo) and left one wave per SIMD at r = 64; with one-product rounds the
+  // single buffers left the L2 latency of every chunk exposed (S-pass 1.12 ->
+  // 1.82 ms at 20000 x 100000, r = 64).
   struct MChunk {
     u4 m[kRT];                  // M[row arow0 + 16 rt + l%16][col 32 cc + 8 (l/16) + e]
     float mf[X3 ? kRT : 1][8];  // X3: the same entries in FP32
@@ -426,9 +424,10 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
     bf8 vb[RT], vbl[X3 ? RT : 1];        // V hB (hi, lo)
   };
   constexpr int kDepth = 2;
+  constexpr int kOD = X3 ? 1 : 2;  // V operand buffers
   MChunk ring[kDepth];
-  OpA oa;
-  OpB ob;
+  OpA oa[kOD];
+  OpB ob[kOD];
   const int nch = (cl.n + 31) >> 5;
   const int nk = (nch - phase + kPh - 1) / kPh;  // chunks phase, phase + kPh, ... below nch
   auto load_m = [&](MChunk& c, int k) {
@@ -466,7 +465,7 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
   };
   // MFMA 1 for every row tile: (U V^T)^T, two 16x16 halves per tile.
   f4 o[kRT][2];
-  auto mfma1 = [&]() {
+  auto mfma1 = [&](const OpA& a) {
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) {
       o[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
@@ -476,18 +475,35 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           if constexpr (X3)
-            o[rt][t] = mfma3(oa.va[t][kb], oa.val[t][kb], ub[rt][kb], ubl[rt][kb], o[rt][t]);
+            o[rt][t] = mfma3(a.va[t][kb], a.val[t][kb], ub[rt][kb], ubl[rt][kb], o[rt][t]);
           else
-            o[rt][t] = mfma_bf16(oa.va[t][kb], ub[rt][kb], o[rt][t]);
+            o[rt][t] = mfma_bf16(a.va[t][kb], ub[rt][kb], o[rt][t]);
         }
       }
     }
   };
-  // Residual, soft-threshold and statistics per row tile, then MFMA 2.
-  auto threshold_mfma2 = [&](const MChunk& c) {
+  // Residual, soft-threshold and statistics per row tile, then MFMA 2; with
+  // FUSED, each row tile's MFMA 1 runs just before its threshold, so only one
+  // tile's (U V^T)^T is live at a time.
+  auto threshold_mfma2 = [&](const MChunk& c, const OpA& oa, const OpB& ob, auto fused) {
+    constexpr bool FUSED = decltype(fused)::value;
     float l2 = 0.f, l1 = 0.f, hb = 0.f;
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) {
+      if constexpr (FUSED) {
+        o[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
+        o[rt][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < NK; ++kb) {
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            if constexpr (X3)
+              o[rt][t] = mfma3(oa.va[t][kb], oa.val[t][kb], ub[rt][kb], ubl[rt][kb], o[rt][t]);
+            else
+              o[rt][t] = mfma_bf16(oa.va[t][kb], ub[rt][kb], o[rt][t]);
+          }
+        }
+      }
       float x[8], lamv[8];
       if constexpr (X3) {
 #pragma unroll
@@ -527,26 +543,51 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
     // the fences keep each refill where it is written (left alone, the
     // scheduler sinks loads towards their first use).
     const int nkp = (nk + kDepth - 1) / kDepth * kDepth;
-    load_m(ring[0], 0);
-    load_a(oa, 0);
-    load_b(ob, 0);
-    __builtin_amdgcn_sched_barrier(0);
-    load_m(ring[1], min(1, nk - 1));
-    __builtin_amdgcn_sched_barrier(0);
-    for (int k0 = 0; k0 < nkp; k0 += kDepth) {
+    if constexpr (kOD == 1) {
+      load_m(ring[0], 0);
+      load_a(oa[0], 0);
+      load_b(ob[0], 0);
+      __builtin_amdgcn_sched_barrier(0);
+      load_m(ring[1], min(1, nk - 1));
+      __builtin_amdgcn_sched_barrier(0);
+      for (int k0 = 0; k0 < nkp; k0 += kDepth) {
+#pragma unroll
+        for (int d = 0; d < kDepth; ++d) {
+          const int k = k0 + d;
+          const int kn = min(k + 1, nk - 1);
+          if (k < nk) mfma1(oa[0]);  // wave-uniform
+          __builtin_amdgcn_sched_barrier(0);
+          load_a(oa[0], kn);
+          __builtin_amdgcn_sched_barrier(0);
+          if (k < nk) threshold_mfma2(ring[d], oa[0], ob[0], std::false_type{});
+          __builtin_amdgcn_sched_barrier(0);
+          load_b(ob[0], kn);
+          load_m(ring[d], min(k + kDepth, nk - 1));
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    } else {
+      // Every operand of a chunk in the same ring slot, issued together.
 #pragma unroll
       for (int d = 0; d < kDepth; ++d) {
-        const int k = k0 + d;
-        const int kn = min(k + 1, nk - 1);
-        if (k < nk) mfma1();  // wave-uniform
+        const int k = min(d, nk - 1);
+        load_m(ring[d], k);
+        load_a(oa[d], k);
+        load_b(ob[d], k);
         __builtin_amdgcn_sched_barrier(0);
-        load_a(oa, kn);
-        __builtin_amdgcn_sched_barrier(0);
-        if (k < nk) threshold_mfma2(ring[d]);
-        __builtin_amdgcn_sched_barrier(0);
-        load_b(ob, kn);
-        load_m(ring[d], min(k + kDepth, nk - 1));
-        __builtin_amdgcn_sched_barrier(0);
+      }
+      for (int k0 = 0; k0 < nkp; k0 += kDepth) {
+#pragma unroll
+        for (int d = 0; d < kDepth; ++d) {
+          const int k = k0 + d;
+          if (k < nk) threshold_mfma2(ring[d], oa[d], ob[d], std::true_type{});  // wave-uniform
+          __builtin_amdgcn_sched_barrier(0);
+          const int kn = min(k + kDepth, nk - 1);
+          load_m(ring[d], kn);
+          load_a(oa[d], kn);
+          load_b(ob[d], kn);
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
   }
@@ -573,21 +614,18 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
   const int row0 = b * kSRows;
   float* Ti = p.P + (int64_t)ci * RP * p.MP;
   if (closed) {
-    // T_i = P A_i + U_i B_i on FP32 MFMA, as its transpose A_i^T P^T +
-    // B_i^T U_i^T in 16-rank x 16-row tiles: wave wv takes rows 32 wv .. +31
-    // of the block, and lane l ends with T[row l%16][rank 4 (l/16) + v] of a
-    // tile, so each store covers 16 consecutive rows of a rank column. P comes
-    // from LDS, U_i (FP32) from its column-major layout.
-    constexpr int kK = RP / 4;
+    // T_i = P A_i + U_i V_i^T V_i A_i = U_i + X A_i with X = P - c_i U_i
+    // (V_i^T V_i A_i = I - c_i A_i), on FP32 MFMA as (X A_i)^T = A_i^T X^T in
+    // 16-rank x 16-row tiles, U_i added at the end: wave wv takes rows
+    // 32 wv .. +31 of the block, and lane l ends with
+    // T[row l%16][rank 4 (l/16) + v] of a tile, so each store covers 16
+    // consecutive rows of a rank column. P comes from LDS, U_i (FP32) from its
+    // column-major layout; both are zero past rank r, so the contraction stops
+    // at 4 ceil(r/4).
+    const int kK = (p.r + 3) / 4;
     const int rb = 32 * wv;
-    float ua[2][kK];  // U[row0 + rb + 16 rt + l%16][4 kk + l/16]
-    {
-      const GLOBAL float* Uc = gptr(U) + row0 + rb + li;
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int kk = 0; kk < kK; ++kk) ua[rt][kk] = Uc[(int64_t)(4 * kk + lg) * MP + 16 * rt];
-    }
+    const GLOBAL float* Uc = gptr(U) + row0 + rb + li;
+    const float cf = (float)cl.c;
     f4 acc[2][RT];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -595,18 +633,16 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
       for (int ct = 0; ct < RT; ++ct) acc[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
     for (int kk = 0; kk < kK; ++kk) {
-      float pb[2];
+      float xb[2];
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt) pb[rt] = ptile[rb + 16 * rt + li][4 * kk + lg];
+      for (int rt = 0; rt < 2; ++rt)
+        xb[rt] = fmaf(-cf, Uc[(int64_t)(4 * kk + lg) * MP + 16 * rt],
+                      ptile[rb + 16 * rt + li][4 * kk + lg]);
 #pragma unroll
       for (int ct = 0; ct < RT; ++ct) {
-        const float a0 = fab[0][(4 * kk + lg) * kFS + 16 * ct + li];
-        const float a1 = fab[1][(4 * kk + lg) * kFS + 16 * ct + li];
+        const float a0 = fal[(4 * kk + lg) * kFS + 16 * ct + li];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt) {
-          acc[rt][ct] = mfma4(a0, pb[rt], acc[rt][ct]);
-          acc[rt][ct] = mfma4(a1, ua[rt][kk], acc[rt][ct]);
-        }
+        for (int rt = 0; rt < 2; ++rt) acc[rt][ct] = mfma4(a0, xb[rt], acc[rt][ct]);
       }
     }
 #pragma unroll
@@ -616,7 +652,8 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int c = 16 * ct + 4 * lg + v;
-          Ti[(int64_t)c * MP + row0 + rb + 16 * rt + li] = c < p.r ? acc[rt][ct][v] : 0.f;
+          const float t = acc[rt][ct][v] + Uc[(int64_t)c * MP + 16 * rt];
+          Ti[(int64_t)c * MP + row0 + rb + 16 * rt + li] = c < p.r ? t : 0.f;
         }
   } else {
     // Gradient step: thread tid owns row tid % 128 and the rank columns
@@ -638,15 +675,19 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
 
 // One work-group per tile (grid = row blocks x clients), or (Q) a persistent
 // launch over the tile queue, tiles as in k_spass.
-template <int RT, int NK, bool X3, bool Q>
-__global__ __launch_bounds__(256) void k_spass_h(DevParams p, const float* __restrict__ U) {
-  if constexpr (!Q) {
-    spass_h_tile<RT, NK, X3>(p, U, (int)blockIdx.x, (int)blockIdx.y);
-  } else {
-    const int ntiles = p.nrb * p.E;
-    for (int t = queue_next(p.queue + 2, ntiles); t < ntiles; t = queue_next(p.queue + 2, ntiles))
-      spass_h_tile<RT, NK, X3>(p, U, t % p.nrb, t / p.nrb);
-  }
+// The per-tile form asks for two work-groups per compute unit (the LDS
+// allows it): at most 256 registers per lane, which it fits without spilling,
+// so that one work-group's epilogue overlaps the other's sweep. The queue
+// form's loop needs more registers and keeps the default bound.
+template <int RT, int NK, bool X3>
+__global__ __launch_bounds__(256, 2) void k_spass_h_tile(DevParams p, const float* __restrict__ U) {
+  spass_h_tile<RT, NK, X3>(p, U, (int)blockIdx.x, (int)blockIdx.y);
+}
+template <int RT, int NK, bool X3>
+__global__ __launch_bounds__(256) void k_spass_h_queue(DevParams p, const float* __restrict__ U) {
+  const int ntiles = p.nrb * p.E;
+  for (int t = queue_next(p.queue + 2, ntiles); t < ntiles; t = queue_next(p.queue + 2, ntiles))
+    spass_h_tile<RT, NK, X3>(p, U, t % p.nrb, t / p.nrb);
 }
 
 hipError_t launch_m_to_bf16(const DevParams& p, hipStream_t st) {
@@ -712,9 +753,9 @@ static hipError_t launch_spass_h_t(const DevParams& p, const float* U, int x3, h
     }
   };
   if (x3)
-    go(k_spass_h<RT, NK, true, true>, k_spass_h<RT, NK, true, false>);
+    go(k_spass_h_queue<RT, NK, true>, k_spass_h_tile<RT, NK, true>);
   else
-    go(k_spass_h<RT, NK, false, true>, k_spass_h<RT, NK, false, false>);
+    go(k_spass_h_queue<RT, NK, false>, k_spass_h_tile<RT, NK, false>);
   return hipGetLastError();
 }
 

@@ -177,7 +177,6 @@ struct DevParams {
   float* P;              // per-client U-step term T_i, column-major MP x RP
   double* gv_part;       // per V-finalize group partial V^T V, RP x RP
   double* Afac;          // per-client (V_i^T V_i + c_i I)^{-1}, RP x RP
-  double* Bfac;          // per-client V_i^T V_i (V_i^T V_i + c_i I)^{-1}
   double* gram_part;     // per (client,) U row block partial U^T U, RP x RP
   double* spart;         // per S-pass work-group: sums of Lambda^2, |S|, nnz(S)
   double* upart;         // per U row block: ||dU||^2

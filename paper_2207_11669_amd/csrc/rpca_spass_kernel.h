@@ -7,52 +7,71 @@ namespace rpca {
 
 
 
-// S-pass epilogue of the FP32 form (NW waves): the client's U-step term for the work-group's 128 rows from P = Lambda V_i and
-// U_i staged in LDS (Lemma 2 proof for the gradient, argmin_U L_i for the
-// closed form):
-//   GRAD   T = U_i - eta (c_i U_i - P)
-//   CLOSED T = P A_i + U_i B_i,  A_i = (V_i^T V_i + c_i I)^{-1}, B_i = V_i^T V_i A_i
-// in FP64, stored FP32 into the client's slot of p.P; then the statistics.
-template <int RP, int NW>
-__device__ __forceinline__ void spass_terms_and_stats(const DevParams& p, const ClientDev& cl, int b,
-                                                      const float (*ptile)[RP + 1],
-                                                      const float (*utile)[RP + 1],
-                                                      const double (*fab)[RP * RP], bool closed,
-                                                      double sl2, double sl1, uint32_t nnz,
-                                                      double shb) {
-  const int tid = threadIdx.x;
-  const int ci = cl.idx;
+// S-pass epilogue of the FP32 form: the client's U-step term for the
+// work-group's 128 rows (Lemma 2's proof for the gradient, argmin_U L_i for
+// the closed form). With X = P - c_i U_i (P = Lambda V_i, c_i = rho n_i / n)
+// and A_i = (V_i^T V_i + c_i I)^{-1}:
+//   GRAD   T = U_i - eta (c_i U_i - P) = U_i + eta X
+//   CLOSED T = P A_i + U_i V_i^T V_i A_i = U_i + X A_i
+// (V_i^T V_i A_i = I - c_i A_i). ptile holds X (row stride PS), fa A_i in
+// FP32 (row stride FS). The closed form runs on FP32 MFMA as (X A_i)^T =
+// A_i^T X^T in 16-rank x 16-row tiles: lane l ends with
+// (X A_i)[row l%16][rank 16 ct + 4 (l/16) + v] of a tile, and U_i is added
+// once at the end (accumulating onto U_i would round every partial sum to
+// the size of U_i), so each store covers 16 consecutive rows of a rank
+// column. Wave w of phase ph takes the row tiles rt = ph, ph + NPH, ... of
+// its 32-row strip.
+template <int RT, int NS, int NPH, int PS, int FS>
+__device__ __forceinline__ void spass_terms(const DevParams& p, const ClientDev& cl,
+                                            const float* __restrict__ U, int b, int w, int phase,
+                                            const float* xtile, const float* fa, bool closed) {
+  constexpr int RP = 16 * RT;
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int MP = p.MP;
   const int row0 = b * kSRows;
-  float* Ti = p.P + (int64_t)ci * RP * p.MP;
+  float* __restrict__ Ti = p.P + (int64_t)cl.idx * RP * MP;
+  const GLOBAL float* Uc = gptr(U);  // column-major layout, zero past m and r
   const double eta = eta_of_round(p, p.dstate->t);
-  const double cc = cl.c;
-  // Thread: one row, eight rank columns (register blocking: each LDS read of
-  // P or U feeds eight FMAs).
-  for (int e = tid; e < kSRows * (RP / 8); e += blockDim.x) {
-    const int rl = e % kSRows, c0 = (e / kSRows) * 8;
-    double t[8];
+#pragma unroll
+  for (int rt = phase; rt < 2; rt += NPH) {
+    const int rl = w * 32 + 16 * rt;  // the tile's first row in the block
+    const int64_t grow = row0 + rl + li;
+    f4 acc[RT], uv[RT];
+#pragma unroll
+    for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) uv[ct][v] = Uc[(int64_t)(16 * ct + 4 * lg + v) * MP + grow];
+    const float* xr = xtile + (rl + li) * PS;
     if (closed) {
+      // P and U_i are zero past rank r, so the contraction stops at 4 NS.
 #pragma unroll
-      for (int j = 0; j < 8; ++j) t[j] = 0.0;
-      for (int k = 0; k < p.r; ++k) {
-        const double pk = (double)ptile[rl][k], uk = (double)utile[rl][k];
+      for (int ct = 0; ct < RT; ++ct) acc[ct] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+      for (int kk = 0; kk < NS; ++kk) {
+        const float xb = xr[4 * kk + lg];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          t[j] = fma(pk, fab[0][k * RP + c0 + j], fma(uk, fab[1][k * RP + c0 + j], t[j]));
+        for (int ct = 0; ct < RT; ++ct)
+          acc[ct] = mfma4(fa[(4 * kk + lg) * FS + 16 * ct + li], xb, acc[ct]);
       }
+#pragma unroll
+      for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[ct][v] += uv[ct][v];
     } else {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const double u = utile[rl][c0 + j];
-        t[j] = u - eta * (cc * u - (double)ptile[rl][c0 + j]);
-      }
+      for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          acc[ct][v] = (float)((double)uv[ct][v] + eta * (double)xr[16 * ct + 4 * lg + v]);
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      Ti[(int64_t)(c0 + j) * p.MP + row0 + rl] = c0 + j < p.r ? (float)t[j] : 0.f;
+    for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * ct + 4 * lg + v;
+        Ti[(int64_t)c * MP + grow] = c < p.r ? acc[ct][v] : 0.f;
+      }
   }
-
-  spass_stats<NW>(p, ci, b, sl2, sl1, nnz, shb);
 }
 
 // ---------------------------------------------------------------------------
@@ -114,24 +133,34 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
   }
 
   // Epilogue operands that do not depend on the sweep: the closed-form
-  // factors A_i and B_i are fetched now (into registers, stored to LDS once
-  // the ring's first loads are in flight), so the epilogue waits on no memory.
-  __shared__ float ptile[kSRows][RP + 1];
-  __shared__ float utile[kSRows][RP + 1];
-  __shared__ double fab[2][RP * RP];
+  // factor A_i is fetched now (into registers, stored to LDS as FP32 once the
+  // ring's first loads are in flight), so the epilogue waits on no memory.
+  // Row strides: P (and X) RP + 4 floats, so that a wave's column reads (16
+  // rows by 4 ranks) and its accumulator writes (4 rows by 16 ranks) fall in
+  // distinct banks; A_i an odd multiple of 16 floats, so that four rows of 16
+  // consecutive entries do. 55 KB at r = 64: two work-groups of 256 threads
+  // share a compute unit, one's epilogue overlapping the other's sweep.
+  constexpr int kPS = RP + 4, kFS = 16 * ((RP / 16) | 1);
+  __shared__ float ptile[kSRows * kPS];
+  __shared__ float fal[RP * kFS];
   const bool closed = p.u_mode != 0;
   constexpr int kFabPer = (RP * RP + 256 * NPH - 1) / (256 * NPH);
-  double fa[kFabPer], fbv[kFabPer];
+  float fa[kFabPer];
   if (!emit_only && closed) {
     const double* __restrict__ Af = p.Afac + (int64_t)ci * RP * RP;
-    const double* __restrict__ Bf = p.Bfac + (int64_t)ci * RP * RP;
 #pragma unroll
     for (int q = 0; q < kFabPer; ++q) {
       const int e = tid + q * 256 * NPH;
-      fa[q] = e < RP * RP ? Af[e] : 0.0;
-      fbv[q] = e < RP * RP ? Bf[e] : 0.0;
+      fa[q] = e < RP * RP ? (float)Af[e] : 0.f;
     }
   }
+  auto stage_fa = [&]() {
+#pragma unroll
+    for (int q = 0; q < kFabPer; ++q) {
+      const int e = tid + q * 256 * NPH;
+      if (e < RP * RP) fal[(e / RP) * kFS + e % RP] = fa[q];
+    }
+  };
 
   double sl2 = 0.0, sl1 = 0.0, shb = 0.0;
   uint32_t nnz = 0;  // wave-uniform count of nonzero S entries
@@ -270,16 +299,7 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
       load_chunk(ring[d], min(d, nk - 1));
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (!emit_only && closed) {
-#pragma unroll
-      for (int q = 0; q < kFabPer; ++q) {
-        const int e = tid + q * 256 * NPH;
-        if (e < RP * RP) {
-          fab[0][e] = fa[q];
-          fab[1][e] = fbv[q];
-        }
-      }
-    }
+    if (!emit_only && closed) stage_fa();
     __builtin_amdgcn_sched_barrier(0);
     for (int k0 = 0; k0 < nkp; k0 += kSDepth) {
 #pragma unroll
@@ -296,23 +316,16 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
     }
   } else if (!emit_only && closed) {
     // A phase with no chunk (a client of at most 16 columns) still stages its
-    // share of A_i and B_i.
-#pragma unroll
-    for (int q = 0; q < kFabPer; ++q) {
-      const int e = tid + q * 256 * NPH;
-      if (e < RP * RP) {
-        fab[0][e] = fa[q];
-        fab[1][e] = fbv[q];
-      }
-    }
+    // share of A_i.
+    stage_fa();
   }
 
   if (emit_only) return;
-  // Epilogue: the client's U-step term for these 128 rows. U_i comes from
-  // the MFMA operand registers (rank (l/16) NS + s of row l%16; ranks from
-  // 4 NS on are zero), P from the two phases' accumulators summed in LDS.
-  // Quads: block b = l/4 summed columns 4 (b/4) + s for rows 4 (b%4) + i; the
-  // four column groups (lanes l, l ^ 16, l ^ 32, l ^ 48) are added first.
+  // Epilogue: P from the two phases' accumulators, summed in LDS in phase
+  // order; then X = P - c_i U_i and the client's U-step term for these 128
+  // rows. Quads: block b = l/4 summed columns 4 (b/4) + s for rows
+  // 4 (b%4) + i; the four column groups (lanes l, l ^ 16, l ^ 32, l ^ 48) are
+  // added first.
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -324,45 +337,45 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
         x += __shfl_xor(x, 32, 64);
         accq[rt][q][i] = x;
       }
+#pragma unroll
+  for (int q = 0; q < NPH; ++q) {
+    if (phase == q) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+        for (int ct = 0; ct < RTF; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            float& x = ptile[(w * 32 + 16 * rt + 4 * lg + v) * kPS + 16 * ct + li];
+            x = q == 0 ? accp[rt][ct][v] : x + accp[rt][ct][v];
+          }
+#pragma unroll
+        for (int qd = 0; qd < NQ; ++qd)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (lane < 16) {
+              float& x = ptile[(w * 32 + 16 * rt + 4 * (lane >> 2) + i) * kPS + 16 * RTF + 4 * qd + (lane & 3)];
+              x = q == 0 ? accq[rt][qd][i] : x + accq[rt][qd][i];
+            }
+      }
+    }
+    __syncthreads();
+  }
+  // X = P - c_i U_i, U_i from the MFMA 1 operand registers (rank
+  // (l/16) NS + s of row l%16; ranks from 4 NS on are zero in U_i and in P).
   if (phase == 0) {
+    const float cf = (float)cl.c;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < RTF; ++ct)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) ptile[w * 32 + 16 * rt + 4 * lg + v][16 * ct + li] = accp[rt][ct][v];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (lane < 16) ptile[w * 32 + 16 * rt + 4 * (lane >> 2) + i][16 * RTF + 4 * q + (lane & 3)] = accq[rt][q][i];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) utile[w * 32 + 16 * rt + li][lg * NS + s] = ub[rt][s];
-    }
-  }
-  if (phase == NPH - 1) {
-    for (int c = 4 * NS + lg; c < RP; c += 4) {
-      utile[w * 32 + li][c] = 0.f;
-      utile[w * 32 + 16 + li][c] = 0.f;
-    }
+      for (int s = 0; s < NS; ++s) {
+        float& x = ptile[(w * 32 + 16 * rt + li) * kPS + lg * NS + s];
+        x = fmaf(-cf, ub[rt][s], x);
+      }
   }
   __syncthreads();
-  if (NPH == 2 && phase == 1) {
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-#pragma unroll
-      for (int ct = 0; ct < RTF; ++ct)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) ptile[w * 32 + 16 * rt + 4 * lg + v][16 * ct + li] += accp[rt][ct][v];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (lane < 16) ptile[w * 32 + 16 * rt + 4 * (lane >> 2) + i][16 * RTF + 4 * q + (lane & 3)] += accq[rt][q][i];
-    }
-  }
-  __syncthreads();
-  spass_terms_and_stats<RP, 4 * NPH>(p, cl, b, ptile, utile, fab, closed, sl2, sl1, nnz, shb);
+  spass_terms<RT, NS, NPH, kPS, kFS>(p, cl, U, b, w, phase, ptile, fal, closed);
+  spass_stats<4 * NPH>(p, ci, b, sl2, sl1, nnz, shb);
 }
 
 // The kernel: Q = false, one work-group per tile (grid = row blocks x

@@ -151,12 +151,14 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
 }
 
 // ---------------------------------------------------------------------------
-// Per-client r x r factors for the closed-form U step:
-//   A_i = (V_i^T V_i + c_i I)^{-1},  B_i = V_i^T V_i A_i,  c_i = rho n_i / n.
-// One work-group per client; FP64 throughout.
+// Per-client r x r factor for the closed-form U step:
+//   A_i = (V_i^T V_i + c_i I)^{-1},  c_i = rho n_i / n.
+// (The step's other factor, V_i^T V_i A_i, is I - c_i A_i, which the S-pass
+// epilogue applies as U_i + (P - c_i U_i) A_i.) One work-group per client;
+// FP64 throughout.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
-  __shared__ double A[kMaxRank * kMaxRank], G[kMaxRank * kMaxRank];
+  __shared__ double A[kMaxRank * kMaxRank];
   const int r = p.r, RP = p.RP;
   const int64_t RR = (int64_t)RP * RP;
   const ClientDev cl = p.clients[blockIdx.x];
@@ -166,7 +168,6 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
     for (int e = tid; e < r * r; e += blockDim.x) {
       const int a = e / r, b = e % r;
       const double s = sum_strided(p.gv_part + (int64_t)cl.g0 * RR + a * RP + b, cl.g1 - cl.g0, RR);
-      G[e] = s;
       A[e] = s + (a == b ? cl.c : 0.0);
     }
   } else {
@@ -224,8 +225,6 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
     for (int q = 0; q < kCE; ++q)
       if (ia[q] >= 0) {
         const int a = ia[q], b = ib[q];
-        G[a * r + b] = s[q];
-        G[b * r + a] = s[q];
         A[a * r + b] = s[q] + (a == b ? cl.c : 0.0);
         A[b * r + a] = s[q] + (a == b ? cl.c : 0.0);
       }
@@ -233,16 +232,9 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
   __syncthreads();
   spd_inverse<3>(A, r, r);  // 1024 threads x 3 >= 64 x 65 / 2
   double* Af = p.Afac + (int64_t)blockIdx.x * RR;
-  double* Bf = p.Bfac + (int64_t)blockIdx.x * RR;
   for (int e = tid; e < RR; e += blockDim.x) {
     const int a = e / RP, b = e % RP;
-    double av = 0.0, bv = 0.0;
-    if (a < r && b < r) {
-      av = A[a * r + b];
-      for (int k = 0; k < r; ++k) bv += G[a * r + k] * A[k * r + b];
-    }
-    Af[e] = av;
-    Bf[e] = bv;
+    Af[e] = a < r && b < r ? A[a * r + b] : 0.0;
   }
 }
 
