@@ -190,7 +190,12 @@ def measure(M_cols, inst, r, rho, lam, U0_cols, args, precision: str, workload: 
                sparse_s=args.sparse_s and precision == "fp32")
     log(f"{precision}: warmup {args.warmup}")
     s.step(args.warmup)
-    shape = s.autotune(args.autotune) if args.autotune > 0 else s.launch_shape()
+    if args.launch_shape:
+        keys = ("row_splits", "column_groups", "spass_phases", "vpass_queue", "spass_queue")
+        s.set_launch_shape(**dict(zip(keys, (int(x) for x in args.launch_shape.split(",")))))
+        shape = s.launch_shape()
+    else:
+        shape = s.autotune(args.autotune) if args.autotune > 0 else s.launch_shape()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     log(f"{precision}: timing {args.steps} rounds")
@@ -409,6 +414,10 @@ def main() -> int:
     ap.add_argument("--autotune", type=int, default=20, metavar="ROUNDS",
                     help="before timing, pick the launch shapes with rpca_autotune (ROUNDS timed "
                          "rounds per candidate); 0 keeps the defaults")
+    ap.add_argument("--launch-shape", default="", metavar="RS,CG,PH,VQ,SQ",
+                    help="pin the launch shape instead of autotuning it: V-pass row splits, "
+                         "column groups per wave, S-pass column phases, V-pass and S-pass "
+                         "persistent launch forms (0/1)")
     ap.add_argument("--profile-rounds", type=int, default=20)
     ap.add_argument("--relerr-rounds", type=int, default=6000,
                     help="round budget of the time-to-relerr runs")

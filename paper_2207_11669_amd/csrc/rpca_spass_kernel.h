@@ -87,11 +87,13 @@ __device__ __forceinline__ void spass_terms(const DevParams& p, const ClientDev&
 // (16 consecutive rows per column per instruction).
 // The contraction index of MFMA 1 is split as k-group g = l/16 taking rank
 // indices g*NS + s, s < NS = ceil(r/4), so no padding steps run for r % 16.
+// SPLIT: the per-tile form, whose chunk body comes in a copy with and one
+// without the Huber sum (see compute_chunk).
 // SOUT: what of S the tile writes besides its statistics and U-step term:
 // kSOutNone, kSOutDense (column-major into Sout) or kSOutSparse (support
 // words and packed nonzero values per 16 x 16 tile, sparse_tile).
 // ---------------------------------------------------------------------------
-template <int RT, int NS, int SOUT, int NPH>
+template <int RT, int NS, int SOUT, int NPH, bool SPLIT>
 __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __restrict__ Ubase,
                                            int64_t u_stride, float* __restrict__ Sout,
                                            int64_t lds_out, int emit_only, int client_base,
@@ -221,7 +223,15 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
 #pragma unroll
       for (int v = 0; v < 4; ++v) c.m[rt][v] = bload(rM, vm[rt][v], 0);
   };
-  auto compute_chunk = [&](const Chunk& c, int k) {
+  // HUB: whether the body sums the Huber function at the target lambda: 0
+  // never, 1 always, 2 when the round asks for it (p.huber; the compiler
+  // if-converts the test, so the arithmetic runs on every entry). The
+  // per-tile form (SPLIT) chooses between bodies 0 and 1 per chunk, a
+  // wave-uniform branch, so that rounds at the target lambda skip it; the
+  // persistent form keeps body 2, whose loop fits the registers without
+  // spilling.
+  auto compute_chunk = [&](const Chunk& c, int k, auto hub_tag) {
+    constexpr int HUB = decltype(hub_tag)::value;
     const int j0 = (phase + NPH * k) << 4;
     float l2 = 0.f, l1 = 0.f, hb = 0.f;
     // Sparse S of this wave's two 16 x 16 tiles (consecutive tile indices):
@@ -257,7 +267,8 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
         lamv[v] = L;
         l2 = fmaf(L, L, l2);
         l1 += fabsf(Sv);
-        if (hub) hb += huber1(R, lt);
+        if constexpr (HUB == 1) hb += huber1(R, lt);
+        if constexpr (HUB == 2) if (hub) hb += huber1(R, lt);
         const uint64_t bal = __builtin_amdgcn_ballot_w64(Sv != 0.f);
         nnz += (uint32_t)__builtin_popcountll(bal);
         if constexpr (SOUT == kSOutSparse) {
@@ -305,7 +316,14 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
 #pragma unroll
       for (int d = 0; d < kSDepth; ++d) {
         const int k = k0 + d;
-        if (k < nk) compute_chunk(ring[d], k);
+        if (k < nk) {  // wave-uniform
+          if constexpr (!SPLIT)
+            compute_chunk(ring[d], k, std::integral_constant<int, 2>{});
+          else if (hub)
+            compute_chunk(ring[d], k, std::integral_constant<int, 1>{});
+          else
+            compute_chunk(ring[d], k, std::integral_constant<int, 0>{});
+        }
         // Keep the refill at this point of the program: left alone, the
         // scheduler sinks loads towards their first use and the ring
         // collapses to a single chunk in flight.
@@ -388,13 +406,13 @@ __global__ __launch_bounds__(256 * NPH) void k_spass(DevParams p, const float* _
                                                      int64_t lds_out, int emit_only,
                                                      int client_base) {
   if constexpr (!Q) {
-    spass_tile<RT, NS, SOUT, NPH>(p, Ubase, u_stride, Sout, lds_out, emit_only, client_base,
-                                   (int)blockIdx.x, (int)blockIdx.y);
+    spass_tile<RT, NS, SOUT, NPH, true>(p, Ubase, u_stride, Sout, lds_out, emit_only,
+                                         client_base, (int)blockIdx.x, (int)blockIdx.y);
   } else {
     const int ntiles = p.nrb * p.E;
     for (int t = queue_next(p.queue + 2, ntiles); t < ntiles; t = queue_next(p.queue + 2, ntiles))
-      spass_tile<RT, NS, SOUT, NPH>(p, Ubase, u_stride, Sout, lds_out, 0, 0, t % p.nrb,
-                                     t / p.nrb);
+      spass_tile<RT, NS, SOUT, NPH, false>(p, Ubase, u_stride, Sout, lds_out, 0, 0, t % p.nrb,
+                                            t / p.nrb);
   }
 }
 
