@@ -274,8 +274,9 @@ rpca_status rpca_profile(rpca_ctx* c, int32_t rounds, double* avg_ms, int64_t* l
  * deterministic for a given shape. */
 typedef struct rpca_launch_shape {
   /* V-pass row splits (the split-K of W over m): 1 .. twice the default
-   * count; rounded so that each split holds a multiple of 16 rows (32 in
-   * contexts that may run BF16 rounds), so the count in effect can be lower */
+   * count, or 8 if that is more (at most one split per 64 rows); rounded so
+   * that each split holds a multiple of 16 rows (32 in contexts that may run
+   * BF16 rounds), so the count in effect can be lower */
   int32_t vsplit;
   /* 16-column groups per FP32 V-pass wave: 1 (waves on distinct columns share
    * U operands through the cache) or 4 (a wave takes all 64 columns of its
@@ -296,8 +297,10 @@ typedef struct rpca_launch_shape {
 } rpca_launch_shape;
 
 /* Autotuner for the launch shapes. First the V-pass: candidates are the
- * default row-split count, half of it and twice it (within what the workspace
- * holds), each with 1 and 4 column groups, at the current S-pass shape. Then,
+ * default row-split count, half of it, two, three and four times it, and the
+ * most the workspace holds (the work-group count decides how full the last
+ * wave of work-groups runs), each with 1 and 4 column groups, at the current
+ * S-pass shape. Then,
  * when the rounds run in FP32, the S-pass at the chosen V-pass shape: two
  * column phases and one. Last, the launch forms (per-tile grid or tile queue)
  * of the two passes, four combinations. Each stage times its candidates in

@@ -161,8 +161,12 @@ Layout make_layout(const rpca_params* p) {
     const int64_t rows = round_up((p->m + vs - 1) / vs, L.bf16 ? 32 : 16);
     L.vsplit_rows = (int32_t)rows;
     L.vsplit = (int32_t)((p->m + rows - 1) / rows);
-    // rpca_autotune may try up to twice as many splits.
-    const int64_t vmax = 2 * L.vsplit < maxs ? 2 * L.vsplit : maxs;
+    // rpca_autotune may try up to twice as many splits, and at least 8: the
+    // work-group count decides how full the last wave of work-groups runs
+    // (at m = 20000, n = 100000 the default is 1 split, and 2 give 6.1
+    // waves of 512 resident work-groups).
+    const int64_t vwant = 2 * L.vsplit > 8 ? 2 * L.vsplit : 8;
+    const int64_t vmax = vwant < maxs ? vwant : maxs;
     L.vsplit_max = (int32_t)(vmax > L.vsplit ? vmax : L.vsplit);
   }
   L.recompute = p->K == 1 && p->inner == 1 && !(p->flags & RPCA_FLAG_STORE_S);
@@ -789,7 +793,8 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
   // Stage 1, the V-pass: (row splits, column groups per wave) at the current
   // S-pass shape.
   std::vector<rpca_launch_shape> cand;
-  for (int64_t v : {(int64_t)(start.vsplit + 1) / 2, (int64_t)start.vsplit, (int64_t)c->vsplit_max}) {
+  const int64_t v0 = start.vsplit;
+  for (int64_t v : {(v0 + 1) / 2, v0, 2 * v0, 3 * v0, 4 * v0, (int64_t)c->vsplit_max}) {
     if (v < 1 || v > c->vsplit_max) continue;
     set_vsplit(c, v);
     for (int32_t g : {1, 4}) {
