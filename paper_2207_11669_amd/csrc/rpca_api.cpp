@@ -182,11 +182,11 @@ Layout make_layout(const rpca_params* p) {
     return at;
   };
   L.S = take((size_t)L.Sfloats * f);
-  // Sparse S: per 16 x 16 tile of (row, padded column), 4 support words and
-  // room for 256 values.
+  // Sparse S: per 16 x 16 tile of (row, padded column), a slot word and room
+  // for 256 values.
   const bool sparse = (p->flags & RPCA_FLAG_SPARSE_S) != 0;
   const size_t tiles = sparse ? (size_t)(L.NVP / 16) * (size_t)(L.MP / 16) : 0;
-  L.Smask = take(tiles * 4 * sizeof(uint64_t));
+  L.Smask = take(tiles * sizeof(uint64_t));
   L.Sval = take(tiles * kSparseVals * f);
   const size_t ub = (size_t)fb_floats(L.MP, L.RP, L.NS);
   // BF16 packings (hi, then lo) follow the FP32 layouts of each U block and V

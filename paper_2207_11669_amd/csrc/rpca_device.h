@@ -80,6 +80,48 @@ typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void bstore64(rsrc_t r, uint32_t voff, uint64_t x) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, (int)voff, 0, 0);
 }
+typedef uint32_t u4s __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void bstore4(rsrc_t r, uint32_t voff, f4 x) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4s, x), r, (int)voff, 0, 0);
+}
+// Lane-pair exchanges within a quad of lanes (DPP quad permutations): the
+// value of lane l ^ 1, or of lane l ^ 2.
+__device__ __forceinline__ float quad_xor1(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float quad_xor2(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, true));
+}
+// 4 x 4 transpose within each quad of lanes: lane 4 q + e holds x[v] on
+// entry and x'[e'] = (lane 4 q + e')'s x[v] with v = its own e on exit (two
+// pair-exchange stages: 2 x 2 blocks across lanes l ^ 2, then entries across
+// lanes l ^ 1).
+__device__ __forceinline__ f4 quad_transpose(f4 x) {
+  const int e = threadIdx.x & 3;
+  {
+    const float r0 = quad_xor2((e & 2) ? x[0] : x[2]);
+    const float r1 = quad_xor2((e & 2) ? x[1] : x[3]);
+    if (e & 2) {
+      x[0] = r0;
+      x[1] = r1;
+    } else {
+      x[2] = r0;
+      x[3] = r1;
+    }
+  }
+  {
+    const float r0 = quad_xor1((e & 1) ? x[0] : x[1]);
+    const float r1 = quad_xor1((e & 1) ? x[2] : x[3]);
+    if (e & 1) {
+      x[0] = r0;
+      x[2] = r1;
+    } else {
+      x[1] = r0;
+      x[3] = r1;
+    }
+  }
+  return x;
+}
 // Tile queue of a persistent launch (a streaming pass whose grid holds only
 // as many work-groups as are resident at once). q[0] is the next tile, q[1]
 // counts the work-groups that found the queue empty. One lane takes a tile

@@ -93,9 +93,11 @@ __host__ __device__ inline int64_t hb_hB(int a, int c, int RT) {
 
 // Sparse S (RPCA_FLAG_SPARSE_S). The S-pass writes S in tiles of 16 rows by
 // 16 columns of the padded V rows: tile = (column / 16) * (MP / 16) + row / 16.
-// A tile has four 64-bit support words, word v holding bit j for the entry
-// (row j % 16, column 4 (j / 16) + v) of the tile, and room for 256 values,
-// of which the nonzero entries fill the front in (word, bit) order.
+// A tile has 64 slots of four entries, slot b = 16 a + 4 g + v holding rows
+// 4 g + e (e < 4) of column 4 a + v (the four rows one V-pass lane reads
+// together), one 64-bit slot word (bit b set: slot b has a nonzero entry),
+// and room for 64 slots of values (256 floats), of which the nonzero slots
+// fill the front, as float4, in slot order.
 constexpr int kSparseVals = 256;
 __host__ __device__ inline int64_t sparse_tile(int MP, int64_t vcol, int row) {
   return (vcol >> 4) * (int64_t)(MP >> 4) + (row >> 4);

@@ -235,9 +235,13 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
     const int j0 = (phase + NPH * k) << 4;
     float l2 = 0.f, l1 = 0.f, hb = 0.f;
     // Sparse S of this wave's two 16 x 16 tiles (consecutive tile indices):
-    // four support words each (lane 4 rt + v keeps word v of tile rt), values
-    // packed in (word, lane) order. Stores go through buffer resources; zero
-    // entries take an offset outside the range and write nothing.
+    // lane l holds rows l%16 of columns 4 (l/16) + v, so the lanes of quad
+    // q = l/4 hold rows 4 (q%4) + e of columns 4 (q/4) + v; a transpose within
+    // the quad leaves lane l with slot l (rows 4 (q%4) + e of column
+    // 4 (q/4) + l%4). The nonzero slots go to the front of the tile's region
+    // in lane order, one float4 store; lane rt keeps tile rt's slot word.
+    // Stores go through buffer resources; empty slots take an offset outside
+    // the range and write nothing.
     [[maybe_unused]] uint64_t myword = 0;
     // (The row strip via readfirstlane: wave-uniform, so the resources built
     // from it stay in scalar registers.)
@@ -251,10 +255,7 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
 #pragma unroll
       for (int s = 0; s < NS; ++s) a1 = mfma4(c.va[s], ub[rt][s], a1);
       f4 lamv;
-      [[maybe_unused]] uint32_t run = 0;  // nonzero entries of this tile so far
-      [[maybe_unused]] rsrc_t rSv;
-      if constexpr (SOUT == kSOutSparse)
-        rSv = make_rsrc(p.Sval + (tile0 + rt) * kSparseVals, kSparseVals * 4u);
+      [[maybe_unused]] f4 sv;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const float R = c.m[rt][v] - a1[v];
@@ -269,17 +270,19 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
         l1 += fabsf(Sv);
         if constexpr (HUB == 1) hb += huber1(R, lt);
         if constexpr (HUB == 2) if (hub) hb += huber1(R, lt);
-        const uint64_t bal = __builtin_amdgcn_ballot_w64(Sv != 0.f);
-        nnz += (uint32_t)__builtin_popcountll(bal);
-        if constexpr (SOUT == kSOutSparse) {
-          // This lane's value goes after every set bit before it in the
-          // tile's order: earlier words (run) and lower lanes of this one.
-          const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-              (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-          bstore(rSv, Sv != 0.f ? (run + below) * 4u : kOffNone, Sv);
-          run += (uint32_t)__builtin_popcountll(bal);
-          myword = lane == 4 * rt + v ? bal : myword;
-        }
+        nnz += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(Sv != 0.f));
+        if constexpr (SOUT == kSOutSparse) sv[v] = Sv;
+      }
+      if constexpr (SOUT == kSOutSparse) {
+        const f4 y = quad_transpose(sv);
+        const bool ne = y[0] != 0.f || y[1] != 0.f || y[2] != 0.f || y[3] != 0.f;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(ne);
+        // This slot goes after every nonzero slot of a lower lane.
+        const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        const rsrc_t rSv = make_rsrc(p.Sval + (tile0 + rt) * kSparseVals, kSparseVals * 4u);
+        bstore4(rSv, ne ? pos * 16u : kOffNone, y);
+        myword = lane == rt ? bal : myword;
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -293,9 +296,9 @@ __device__ __forceinline__ void spass_tile(const DevParams& p, const float* __re
     sl1 += (double)l1;
     shb += (double)hb;
     if constexpr (SOUT == kSOutSparse) {
-      // Lanes 0..7 write the two tiles' support words.
-      const rsrc_t rSm = make_rsrc(p.Smask + tile0 * 4, 8 * 8u);
-      bstore64(rSm, lane < 8 ? (uint32_t)lane * 8u : kOffNone, myword);
+      // Lanes 0 and 1 write the two tiles' slot words.
+      const rsrc_t rSm = make_rsrc(p.Smask + tile0, 2 * 8u);
+      bstore64(rSm, lane < 2 ? (uint32_t)lane * 8u : kOffNone, myword);
     }
   };
   // Uniform loop: every iteration loads (chunk index clamped to the wave's

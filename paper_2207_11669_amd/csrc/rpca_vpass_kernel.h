@@ -24,10 +24,11 @@ namespace rpca {
 // MODE kSRecompute rebuilds S = soft(M - Uo Vo^T) of the previous round on the
 // fly: its MFMA puts Uo rows on the A side and Vo^T on the B side, so the
 // 16x16 residual tile comes out in exactly the float4 layout of M.
-// MODE kSSparse reads the S the previous S-pass wrote in sparse form (support
-// words and packed values per 16 x 16 tile, sparse_tile): lane l's four
-// entries are bits 4 (l/16) + e + 16 ((l%16)/4) of word (l%16)%4 of the
-// chunk's tile, and sit at consecutive places among the tile's nonzeros.
+// MODE kSSparse reads the S the previous S-pass wrote in sparse form (a slot
+// word and packed float4 slots per 16 x 16 tile, sparse_tile): lane l's four
+// entries are slot b = 16 ((l%16)/4) + 4 (l/16) + (l%16)%4 of the chunk's
+// tile, stored (if bit b of the slot word is set) after the tile's nonzero
+// slots of lower index: one float4 load.
 
 
 template <int RT, int NS, int MODE, int KG>
@@ -97,25 +98,19 @@ __device__ __forceinline__ void vpass_tile(const DevParams& p, const float* __re
   const rsrc_t rUq = make_rsrc(U + fb_pq_off(p.MP, RP, NS), range32((int64_t)p.MP * 4 * NQ * 4));
   const uint32_t vq_off = (uint32_t)(((lane >> 4) * 4 + (lane & 3)) * 16);
   const rsrc_t rUa = make_rsrc(gUopa_raw, range32((int64_t)p.MP * 4 * NS * 4));
-  // Sparse S: the support words of the next chunk to load are fetched (into
+  // Sparse S: the slot words of the next chunk to load are fetched (into
   // scalar registers) one chunk ahead of the values they address.
   constexpr bool SPARSE = MODE == kSSparse;
-  const int sp_v = li & 3, sp_b0 = 4 * lg + 16 * (li >> 2);
-  const uint64_t sp_low = ((uint64_t)1 << sp_b0) - 1u;
-  uint64_t mk[SPARSE ? kG : 1][4];
+  const int sp_b = 16 * (li >> 2) + 4 * lg + (li & 3);
+  const uint64_t sp_low = ((uint64_t)1 << sp_b) - 1u;
+  uint64_t mk[SPARSE ? kG : 1];
   auto load_masks = [&](int k) {
     const int row0 = rbeg + ((ph + kPh * k) << 4);
 #pragma unroll
     for (int g = 0; g < kG; ++g) {
       const int j0 = jw + 16 * g;
-      if (j0 < cl.n) {  // wave-uniform; column groups past n_i hold no tile of this client
-        const CONSTANT uint64_t* src = cptr(p.Smask + sparse_tile(p.MP, cl.vrow0 + j0, row0) * 4);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) mk[g][q] = src[q];
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) mk[g][q] = 0;
-      }
+      // wave-uniform; column groups past n_i hold no tile of this client
+      mk[g] = j0 < cl.n ? *cptr(p.Smask + sparse_tile(p.MP, cl.vrow0 + j0, row0)) : 0;
     }
   };
 
@@ -150,27 +145,15 @@ __device__ __forceinline__ void vpass_tile(const DevParams& p, const float* __re
       for (int s = 0; s < NS; ++s) c.uo[s] = bload(rUa, (uint32_t)lane * 4u, ((chg * NS + s) * 64u) * 4u);
     }
     if constexpr (SPARSE) {
-      // mk holds this chunk's support words. The lane's value e lies after
-      // the tile's nonzeros in earlier words (pre), those of lower bits of its
-      // own word, and its own earlier set entries; unset entries read 0.
+      // mk holds this chunk's slot words; an empty slot reads 0.
 #pragma unroll
       for (int g = 0; g < kG; ++g) {
-        const uint64_t w0 = mk[g][0], w1 = mk[g][1], w2 = mk[g][2], w3 = mk[g][3];
-        const uint32_t p1 = (uint32_t)__builtin_popcountll(w0);
-        const uint32_t p2 = p1 + (uint32_t)__builtin_popcountll(w1);
-        const uint32_t p3 = p2 + (uint32_t)__builtin_popcountll(w2);
-        const uint64_t word = sp_v == 0 ? w0 : sp_v == 1 ? w1 : sp_v == 2 ? w2 : w3;
-        const uint32_t pre = sp_v == 0 ? 0u : sp_v == 1 ? p1 : sp_v == 2 ? p2 : p3;
-        const uint32_t base = pre + (uint32_t)__builtin_popcountll(word & sp_low);
-        const uint32_t nib = (uint32_t)(word >> sp_b0) & 15u;
         const int j0 = jw + 16 * g;
+        const bool ne = (mk[g] >> sp_b) & 1u;
+        const uint32_t pos = (uint32_t)__builtin_popcountll(mk[g] & sp_low);
         const rsrc_t rSv = make_rsrc(p.Sval + sparse_tile(p.MP, cl.vrow0 + j0, row0) * kSparseVals,
                                      kSparseVals * 4u);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t at = base + (uint32_t)__builtin_popcount(nib & ((1u << e) - 1u));
-          c.s[g][e] = bload(rSv, ((nib >> e) & 1u) ? at * 4u : kOffNone, 0);
-        }
+        c.s[g] = bload4(rSv, ne ? pos * 16u : kOffNone, 0);
       }
       load_masks(min(k + 1, nk - 1));
     }
