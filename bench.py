@@ -7,6 +7,9 @@ rank 64 with singular values geometric from 100 down to 1, 5% of the entries
 corrupted (Bernoulli) with magnitude U[1, 100] and a random sign, E = 50
 clients of 2000 columns, r = 64, lambda = 1/sqrt(n), rho = 0.1, closed-form U
 step, K = 1. Inputs are synthetic, seeded, and resident in HBM before timing.
+The FP32 context is created with RPCA_FLAG_SPARSE_S, so that the autotuner
+(run before timing) chooses between handing S from the S-pass to the next
+V-pass in sparse form and rebuilding it; both give bitwise the same rounds.
 
 Next to it, on the same workload: BF16 rounds (BF16 copies of M, U and V on
 BF16 MFMA) and three-product BF16 rounds (FP32 M, hi/lo splits), each with its
@@ -17,7 +20,8 @@ closing rounds.
 Time to relative error 1e-4 (where it is reachable): m = 8000, n = 32000,
 planted rank 40, 15% corruption with magnitude U[5, 20], E = 32, r = 40, for
 plain FP32 rounds, the fixed lambda continuation, the learned controller, and
-the learned controller driving three-product BF16 rounds.
+the learned controller driving three-product BF16 rounds, each with the launch
+shape the autotuner picked on a context of its own.
 
 The FP64 CPU oracle is timed on bounded samples of both workloads, on all the
 host's cores and on one.
@@ -63,10 +67,10 @@ def traffic_file(workload: str, precision: str = "fp32") -> str:
     return os.path.join(ROOT, "profiles", f"traffic_{workload}{suffix}.json")
 
 
-def kernel_costs(m: int, n: int, E: int, r: int, precision: str = "fp32") -> dict:
+def kernel_costs(m: int, n: int, E: int, r: int, precision: str = "fp32",
+                 sparse: bool = False, nnz: float = 0.0) -> dict:
     """Algorithmic HBM bytes and flops per launch of the two streaming kernels,
-    for the default round (K = 1, one V/S alternation, S rebuilt from the
-    previous factors instead of stored).
+    for the default round (K = 1, one V/S alternation, S not stored densely).
 
     V-pass: reads M once (4 B per entry; 2 B in BF16 rounds, which read their
     BF16 copy), U, the previous U and V, and writes W = (M - S)^T U (n x r);
@@ -74,9 +78,20 @@ def kernel_costs(m: int, n: int, E: int, r: int, precision: str = "fp32") -> dic
     for W.
     S-pass: reads M once (4 B, or 2 B in BF16), U and V, writes the
     per-client U-step terms (E x m x r); flops: 2r per entry for U V^T and 2r
-    for Lambda V. Factor operands count at their own width (4 B, or 2 B)."""
+    for Lambda V. Factor operands count at their own width (4 B, or 2 B).
+    With the sparse handoff (sparse, nnz = the support size of S) the S-pass
+    also writes S's nonzero values and their positions (4 B per nonzero, 8 B
+    per 256 entries) and the V-pass reads them instead of rebuilding S: no
+    previous factors, 2r flops per entry."""
     elem = m * n
     w = 2 if precision == "bf16" else 4
+    s_bytes = 4 * nnz + elem / 32
+    if sparse:
+        return {
+            "vpass": {"bytes": w * elem + w * m * r + 4 * n * r + s_bytes, "flops": 2 * r * elem},
+            "spass": {"bytes": w * elem + w * (m * r + n * r) + 4 * E * m * r + s_bytes,
+                      "flops": 4 * r * elem},
+        }
     return {
         "vpass": {"bytes": w * elem + w * (2 * m * r + n * r) + 4 * n * r, "flops": 4 * r * elem},
         "spass": {"bytes": w * elem + w * (m * r + n * r) + 4 * E * m * r, "flops": 4 * r * elem},
@@ -187,11 +202,12 @@ def measure(M_cols, inst, r, rho, lam, U0_cols, args, precision: str, workload: 
     eta0 = 0.0 if args.u_mode == "closed" else 1e-4
     s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode, eta0=eta0,
                graph=args.graph, bf16=precision == "bf16", bf16x3=precision == "bf16x3",
-               sparse_s=args.sparse_s and precision == "fp32")
+               sparse_s=not args.no_sparse_s and precision == "fp32")
     log(f"{precision}: warmup {args.warmup}")
     s.step(args.warmup)
     if args.launch_shape:
-        keys = ("row_splits", "column_groups", "spass_phases", "vpass_queue", "spass_queue")
+        keys = ("row_splits", "column_groups", "spass_phases", "vpass_queue", "spass_queue",
+                "sparse_s")
         s.set_launch_shape(**dict(zip(keys, (int(x) for x in args.launch_shape.split(",")))))
         shape = s.launch_shape()
     else:
@@ -210,7 +226,8 @@ def measure(M_cols, inst, r, rho, lam, U0_cols, args, precision: str, workload: 
     log(f"{precision}: per-kernel events over {args.profile_rounds} rounds")
     prof = s.profile(args.profile_rounds)
     s.close()
-    costs = kernel_costs(inst.m, inst.n, inst.E, r, precision)
+    sparse = bool(shape.get("sparse_s"))
+    costs = kernel_costs(inst.m, inst.n, inst.E, r, precision, sparse, st["nnz"])
     total = {k: v[0] * v[1] for k, v in prof.items()}
     dom = max(("vpass", "spass"), key=lambda k: total[k])
     roof = roofline_of(costs[dom], prof[dom][0] / 1e3, precision)
@@ -220,6 +237,7 @@ def measure(M_cols, inst, r, rho, lam, U0_cols, args, precision: str, workload: 
     if precision == "fp32":
         variant += (f":phases={shape['spass_phases']}" if dom == "spass"
                     else f":column_groups={shape['column_groups']}")
+        variant += ":sparse" if sparse else ""
     traffic = None
     path = traffic_file(workload, precision)
     if os.path.exists(path):
@@ -228,7 +246,7 @@ def measure(M_cols, inst, r, rho, lam, U0_cols, args, precision: str, workload: 
         if tr.get("kernel_source_sha256_16") == src_hash():
             per = tr.get("bytes_per_launch", {})
             traffic = per.get(variant, per.get(dom))
-    roof.update({"traffic": traffic, "kernel": variant,
+    roof.update({"traffic": traffic, "kernel": variant, "s_support": st["nnz"],
                  "algorithmic_bytes": costs[dom]["bytes"], "algorithmic_flops": costs[dom]["flops"],
                  "avg_launch_us": {k: round(v[0] * 1e3, 2) for k, v in prof.items()},
                  "launches_per_round": {k: v[1] / args.profile_rounds for k, v in prof.items()}})
@@ -281,8 +299,25 @@ def error_vs_oracle(precision: str, low_rounds: int, closing_rounds: int) -> dic
                                                             "relS": rel(S2, b.S_full())}}
 
 
+def tuned_shape(M_cols, inst, r, rho, lam, U0_cols, args, precision: str) -> dict:
+    """Launch shape picked by the autotuner on a context of its own (FP32:
+    with RPCA_FLAG_SPARSE_S, so that it also decides the sparse handoff), so
+    that the timed runs below start from U^(0) with a tuned shape."""
+    import torch
+
+    from paper_2207_11669_amd import DCFPCA
+    eta0 = 0.0 if args.u_mode == "closed" else 1e-4
+    s = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode, eta0=eta0,
+               bf16x3=precision == "bf16x3", sparse_s=precision == "fp32")
+    s.step(max(args.warmup, 5))
+    shape = s.autotune(args.autotune) if args.autotune > 0 else s.launch_shape()
+    torch.cuda.synchronize()
+    s.close()
+    return shape
+
+
 def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target, max_rounds,
-                   schedule=None, ctl=None, lam0=None, precision="fp32") -> dict:
+                   schedule=None, ctl=None, lam0=None, precision="fp32", shape=None) -> dict:
     """Wall time from U^(0) until ||U V^T - X Y^T||_F / ||X Y^T||_F <= 1e-4 for
     the target factors (X, Y), checked every 10 rounds with r x r Gram
     matrices (L is never formed) by rpca_solve. With a lambda schedule (a
@@ -293,8 +328,11 @@ def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target, max_rounds,
     from paper_2207_11669_amd import DCFPCA
     from paper_2207_11669_amd import controller as C
     eta0 = 0.0 if args.u_mode == "closed" else 1e-4
+    sparse = bool(shape and shape.get("sparse_s"))
     s2 = DCFPCA(M_cols, inst.widths, inst.m, r, rho, lam, U0_cols, u_mode=args.u_mode,
-                eta0=eta0, bf16x3=precision == "bf16x3")
+                eta0=eta0, bf16x3=precision == "bf16x3", sparse_s=sparse)
+    if shape:
+        s2.set_launch_shape(**shape)
     s2.set_target(*target)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -314,7 +352,7 @@ def time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target, max_rounds,
     s2.close()
     out = {"tol": 1e-4, "reached": bool(err <= 1e-4), "rounds": pre + done,
            "seconds": round(secs, 4), "final_relerr": err, "max_rounds": max_rounds,
-           "check_every": 10, "precision": precision}
+           "check_every": 10, "precision": precision, "launch_shape": shape}
     if ctrl is not None:
         out["control"] = {"rounds": ctrl["control_rounds"], "rejected": ctrl["rejected"],
                           "decays": [round(g, 3) for g in ctrl["gammas"]],
@@ -355,24 +393,27 @@ def relerr_suite(args, dev) -> tuple:
     lam0 = float(np.abs(inst.M).max())
     out = {"workload": EVAL_WORKLOAD, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
            "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam, "rho": rho}
+    log("launch shapes for the timed runs (autotuner, on contexts of their own)")
+    sh32 = tuned_shape(M_cols, inst, r, rho, lam, U0_cols, args, "fp32")
+    sh3 = tuned_shape(M_cols, inst, r, rho, lam, U0_cols, args, "bf16x3")
     log("time to 1e-4: plain fp32")
     out["plain_fp32"] = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target,
-                                       args.relerr_rounds)
+                                       args.relerr_rounds, shape=sh32)
     log("time to 1e-4: fixed continuation")
     sched = continuation(lam, lam0)
     out["fixed_continuation"] = dict(
         time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target, args.relerr_rounds,
-                       schedule=sched),
+                       schedule=sched, shape=sh32),
         kind="lambda_t = max(lambda, max|M| 0.8^t)", schedule_rounds=len(sched))
     ctl, info = learned_controller()
     out["controller_training"] = info
     log("time to 1e-4: learned controller")
     out["learned"] = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target,
-                                    args.relerr_rounds, ctl=ctl, lam0=lam0)
+                                    args.relerr_rounds, ctl=ctl, lam0=lam0, shape=sh32)
     log("time to 1e-4: learned controller, three-product BF16 rounds")
     out["learned_bf16x3"] = time_to_target(M_cols, inst, r, rho, lam, U0_cols, args, target,
                                            args.relerr_rounds, ctl=ctl, lam0=lam0,
-                                           precision="bf16x3")
+                                           precision="bf16x3", shape=sh3)
     base = out["plain_fp32"]["seconds"]
     out["speedup_vs_plain_fp32"] = {k: round(base / out[k]["seconds"], 3)
                                     for k in ("fixed_continuation", "learned", "learned_bf16x3")
@@ -408,16 +449,18 @@ def main() -> int:
                     help="arithmetic of the headline rounds' streaming passes")
     ap.add_argument("--graph", action="store_true",
                     help="replay steady-state rounds from HIP graphs (RPCA_FLAG_GRAPH)")
-    ap.add_argument("--sparse-s", action="store_true",
-                    help="FP32 rounds hand S from the S-pass to the next V-pass in sparse form "
-                         "(RPCA_FLAG_SPARSE_S) instead of rebuilding it")
+    ap.add_argument("--no-sparse-s", action="store_true",
+                    help="create the FP32 contexts without RPCA_FLAG_SPARSE_S (by default the "
+                         "flag is set and the autotuner decides whether FP32 rounds hand S from "
+                         "the S-pass to the next V-pass in sparse form or rebuild it)")
     ap.add_argument("--autotune", type=int, default=20, metavar="ROUNDS",
                     help="before timing, pick the launch shapes with rpca_autotune (ROUNDS timed "
                          "rounds per candidate); 0 keeps the defaults")
-    ap.add_argument("--launch-shape", default="", metavar="RS,CG,PH,VQ,SQ",
+    ap.add_argument("--launch-shape", default="", metavar="RS,CG,PH,VQ,SQ[,SP]",
                     help="pin the launch shape instead of autotuning it: V-pass row splits, "
                          "column groups per wave, S-pass column phases, V-pass and S-pass "
-                         "persistent launch forms (0/1)")
+                         "persistent launch forms (0/1), and the sparse S handoff (0/1; "
+                         "not with --no-sparse-s)")
     ap.add_argument("--profile-rounds", type=int, default=20)
     ap.add_argument("--relerr-rounds", type=int, default=6000,
                     help="round budget of the time-to-relerr runs")
@@ -492,7 +535,7 @@ def main() -> int:
         "config": {"workload": workload, "m": inst.m, "n": inst.n, "E": inst.E, "r": r,
                    "planted_rank": cfg["rstar"], "corruption": cfg["s"], "lambda": lam,
                    "rho": rho, "K": 1, "inner": 1, "u_mode": args.u_mode,
-                   "graph": bool(args.graph), "sparse_s": bool(args.sparse_s),
+                   "graph": bool(args.graph), "sparse_s_flag": not args.no_sparse_s,
                    "precision": args.precision,
                    "autotuned_launch_shape": head["autotuned_launch_shape"]},
         "roofline": head["roofline"],

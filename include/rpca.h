@@ -294,6 +294,11 @@ typedef struct rpca_launch_shape {
    * bitwise the same results. */
   int32_t vqueue;
   int32_t squeue;
+  /* With RPCA_FLAG_SPARSE_S: 1 (the default), FP32 rounds hand S from the
+   * S-pass to the next V-pass in sparse form; 0, they rebuild it as without
+   * the flag (the sparse form pays where r is large and S sparse). Always 0
+   * in a context without the flag. Both give bitwise the same results. */
+  int32_t sparse;
 } rpca_launch_shape;
 
 /* Autotuner for the launch shapes. First the V-pass: candidates are the
@@ -302,8 +307,9 @@ typedef struct rpca_launch_shape {
  * wave of work-groups runs), each with 1 and 4 column groups, at the current
  * S-pass shape. Then,
  * when the rounds run in FP32, the S-pass at the chosen V-pass shape: two
- * column phases and one. Last, the launch forms (per-tile grid or tile queue)
- * of the two passes, four combinations. Each stage times its candidates in
+ * column phases and one. Then the launch forms (per-tile grid or tile queue)
+ * of the two passes, four combinations. Last, with RPCA_FLAG_SPARSE_S and
+ * FP32 rounds, sparse S or rebuilt S, each with both V-pass launch forms. Each stage times its candidates in
  * turn, twice over, and compares the sums. Every timing runs `rounds` timed rounds (plus one
  * untimed); the fastest candidate is kept and returned in *out (optional).
  * Synchronises. The rounds are real rounds of the method; the choice depends

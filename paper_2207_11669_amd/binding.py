@@ -64,12 +64,12 @@ class RpcaStats(ctypes.Structure):
 
 class RpcaLaunchShape(ctypes.Structure):
     _fields_ = [("vsplit", c_int32), ("vcols", c_int32), ("sphases", c_int32),
-                ("vqueue", c_int32), ("squeue", c_int32)]
+                ("vqueue", c_int32), ("squeue", c_int32), ("sparse", c_int32)]
 
     def as_dict(self) -> dict:
         return {"row_splits": int(self.vsplit), "column_groups": int(self.vcols),
                 "spass_phases": int(self.sphases), "vpass_queue": int(self.vqueue),
-                "spass_queue": int(self.squeue)}
+                "spass_queue": int(self.squeue), "sparse_s": int(self.sparse)}
 
 
 class RpcaError(RuntimeError):
@@ -284,7 +284,7 @@ class DCFPCA:
     def autotune(self, rounds: int = 10) -> dict:
         """Pick the launch shapes of the V-pass and the FP32 S-pass by timing
         real rounds; returns them as {"row_splits", "column_groups",
-        "spass_phases"}."""
+        "spass_phases", "vpass_queue", "spass_queue", "sparse_s"}."""
         k = RpcaLaunchShape()
         self._check(self._lib.rpca_autotune(self.ctx, int(rounds), ctypes.byref(k)))
         return k.as_dict()
@@ -296,13 +296,13 @@ class DCFPCA:
 
     def set_launch_shape(self, row_splits: int | None = None, column_groups: int | None = None,
                          spass_phases: int | None = None, vpass_queue: int | None = None,
-                         spass_queue: int | None = None):
+                         spass_queue: int | None = None, sparse_s: int | None = None):
         """Fix the launch shapes (rpca_set_launch_shape); None keeps a value."""
         cur = self.launch_shape()
         pick = lambda key, v: cur[key] if v is None else int(v)  # noqa: E731
         k = RpcaLaunchShape(pick("row_splits", row_splits), pick("column_groups", column_groups),
                             pick("spass_phases", spass_phases), pick("vpass_queue", vpass_queue),
-                            pick("spass_queue", spass_queue))
+                            pick("spass_queue", spass_queue), pick("sparse_s", sparse_s))
         self._check(self._lib.rpca_set_launch_shape(self.ctx, ctypes.byref(k)))
 
     def copy_state_from(self, other: "DCFPCA"):

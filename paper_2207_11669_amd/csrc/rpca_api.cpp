@@ -39,6 +39,9 @@ struct rpca_ctx {
   // RPCA_FLAG_SPARSE_S: the sparse S in the workspace is that of the last
   // round's S-pass (an FP32 round); lam_rec is its lambda.
   bool sparse_valid = false;
+  // With RPCA_FLAG_SPARSE_S: 1 while the launch shape hands S over in sparse
+  // form, 0 while FP32 rounds rebuild it (the autotuner decides).
+  int32_t use_sparse = 0;
   float* V[2] = {nullptr, nullptr};  // V buffers (row-major copy + factor block)
   std::vector<VTile> vg64;
   bool poisoned = false;
@@ -313,12 +316,12 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     const bool h = c->prec != RPCA_PREC_FP32;
     // With RPCA_FLAG_SPARSE_S an FP32 round reads the S of the previous
     // round's S-pass when that was an FP32 round at this lambda.
-    const bool sparse_in = !h && c->sparse_valid && p.lam == p.lam_rec;
+    const bool sparse_in = !h && c->use_sparse && c->sparse_valid && p.lam == p.lam_rec;
     const int mode = c->rounds == 0 ? kSZero : sparse_in ? kSSparse : kSRecompute;
     const int vn = c->vcur ^ 1;
     DevParams q = with_v(c, vn);
-    // BF16 rounds write no sparse S.
-    if (h) q.Smask = nullptr, q.Sval = nullptr;
+    // BF16 rounds, and rounds whose launch shape rebuilds S, write no sparse S.
+    if (h || !c->use_sparse) q.Smask = nullptr, q.Sval = nullptr;
     double* fin = c->fin_pending ? c->Ginv : nullptr;
     c->fin_pending = false;
     const int x3 = c->prec == RPCA_PREC_BF16X3 ? 1 : 0;
@@ -533,6 +536,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.queue = reinterpret_cast<uint32_t*>(ws + L.queue);
   p.vqueue = 0;
   p.squeue = 0;
+  c->use_sparse = p.Smask ? 1 : 0;
   c->U[0] = reinterpret_cast<float*>(ws + L.U0);
   c->U[1] = reinterpret_cast<float*>(ws + L.U1);
   c->Uc[0] = reinterpret_cast<float*>(ws + L.Uc0);
@@ -711,7 +715,8 @@ rpca_status rpca_step(rpca_ctx* c, int32_t rounds) {
     // that is the lambda of every round.
     // With sparse S the graph's first round reads the sparse S, which must
     // then be there.
-    const bool sparse_ok = !c->p.Smask || c->prec != RPCA_PREC_FP32 || c->sparse_valid;
+    const bool sparse_ok =
+        !c->p.Smask || !c->use_sparse || c->prec != RPCA_PREC_FP32 || c->sparse_valid;
     if (c->use_graph && rounds - t >= 2 && c->rounds >= 1 && c->fin_pending &&
         c->p.lam_rec == c->p.lam && sparse_ok) {
       if (rpca_status s = enqueue_round_pair_graph(c)) return s;
@@ -743,7 +748,8 @@ static void set_vsplit(rpca_ctx* c, int64_t vs) {
 }
 
 static rpca_launch_shape shape_of(const rpca_ctx* c) {
-  return rpca_launch_shape{c->p.vsplit, c->p.vcols, c->p.sphases, c->p.vqueue, c->p.squeue};
+  return rpca_launch_shape{c->p.vsplit, c->p.vcols, c->p.sphases, c->p.vqueue, c->p.squeue,
+                           c->use_sparse};
 }
 
 static void apply_shape(rpca_ctx* c, const rpca_launch_shape& k) {
@@ -752,11 +758,12 @@ static void apply_shape(rpca_ctx* c, const rpca_launch_shape& k) {
   c->p.sphases = k.sphases;
   c->p.vqueue = k.vqueue;
   c->p.squeue = k.squeue;
+  c->use_sparse = c->p.Smask ? k.sparse : 0;
 }
 
 static bool same_shape(const rpca_launch_shape& a, const rpca_launch_shape& b) {
   return a.vsplit == b.vsplit && a.vcols == b.vcols && a.sphases == b.sphases &&
-         a.vqueue == b.vqueue && a.squeue == b.squeue;
+         a.vqueue == b.vqueue && a.squeue == b.squeue && a.sparse == b.sparse;
 }
 
 rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
@@ -798,7 +805,8 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
     if (v < 1 || v > c->vsplit_max) continue;
     set_vsplit(c, v);
     for (int32_t g : {1, 4}) {
-      const rpca_launch_shape k{c->p.vsplit, g, start.sphases, start.vqueue, start.squeue};
+      const rpca_launch_shape k{c->p.vsplit, g, start.sphases, start.vqueue, start.squeue,
+                                start.sparse};
       if (std::none_of(cand.begin(), cand.end(), [&](const rpca_launch_shape& x) { return same_shape(x, k); }))
         cand.push_back(k);
     }
@@ -819,8 +827,8 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
   // BF16 rounds run their own S-pass).
   if (result == RPCA_OK && c->prec == RPCA_PREC_FP32) {
     const std::vector<rpca_launch_shape> ks = {
-        {best.vsplit, best.vcols, 2, best.vqueue, best.squeue},
-        {best.vsplit, best.vcols, 1, best.vqueue, best.squeue}};
+        {best.vsplit, best.vcols, 2, best.vqueue, best.squeue, best.sparse},
+        {best.vsplit, best.vcols, 1, best.vqueue, best.squeue, best.sparse}};
     std::vector<float> ts(ks.size(), 0.f);
     for (int rep = 0; rep < 2 && result == RPCA_OK; ++rep)
       for (size_t q = 0; q < ks.size() && result == RPCA_OK; ++q) {
@@ -835,7 +843,26 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
   if (result == RPCA_OK) {
     std::vector<rpca_launch_shape> ks;
     for (int32_t vq : {0, 1})
-      for (int32_t sq : {0, 1}) ks.push_back({best.vsplit, best.vcols, best.sphases, vq, sq});
+      for (int32_t sq : {0, 1})
+        ks.push_back({best.vsplit, best.vcols, best.sphases, vq, sq, best.sparse});
+    std::vector<float> ts(ks.size(), 0.f);
+    for (int rep = 0; rep < 2 && result == RPCA_OK; ++rep)
+      for (size_t q = 0; q < ks.size() && result == RPCA_OK; ++q) {
+        const float ms = time_shape(ks[q]);
+        if (ms >= 0.f) ts[q] += ms;
+      }
+    if (result == RPCA_OK)
+      best = ks[std::min_element(ts.begin(), ts.end()) - ts.begin()];
+  }
+  // Stage 4, with RPCA_FLAG_SPARSE_S and FP32 rounds: S handed over in sparse
+  // form or rebuilt, each tuned anew for the V-pass form (which of the two
+  // pays depends on r and on how dense S is). Every timing starts with an
+  // untimed round, which also refills the sparse S after a rebuilt round.
+  if (result == RPCA_OK && c->p.Smask && c->prec == RPCA_PREC_FP32) {
+    std::vector<rpca_launch_shape> ks;
+    for (int32_t sp : {0, 1})
+      for (int32_t vq : {0, 1})
+        ks.push_back({best.vsplit, best.vcols, best.sphases, vq, best.squeue, sp});
     std::vector<float> ts(ks.size(), 0.f);
     for (int rep = 0; rep < 2 && result == RPCA_OK; ++rep)
       for (size_t q = 0; q < ks.size() && result == RPCA_OK; ++q) {
@@ -872,6 +899,10 @@ rpca_status rpca_set_launch_shape(rpca_ctx* c, const rpca_launch_shape* k) {
     return fail(c, RPCA_EINVAL, "S-pass column phases must be 1 or 2");
   if ((k->vqueue != 0 && k->vqueue != 1) || (k->squeue != 0 && k->squeue != 1))
     return fail(c, RPCA_EINVAL, "launch forms must be 0 (one work-group per tile) or 1 (tile queue)");
+  if (k->sparse != 0 && k->sparse != 1)
+    return fail(c, RPCA_EINVAL, "sparse must be 0 (rebuild S) or 1 (sparse S)");
+  if (k->sparse && !c->p.Smask)
+    return fail(c, RPCA_EINVAL, "sparse S needs a context created with RPCA_FLAG_SPARSE_S");
   apply_shape(c, *k);
   drop_graphs(c);
   return RPCA_OK;

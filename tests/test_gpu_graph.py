@@ -123,7 +123,7 @@ def test_set_launch_shape_rejects_bad_values():
         assert s.launch_shape() == before
     s.set_launch_shape(row_splits=1, column_groups=4, spass_phases=1)
     assert s.launch_shape() == {"row_splits": 1, "column_groups": 4, "spass_phases": 1,
-                                "vpass_queue": 0, "spass_queue": 0}
+                                "vpass_queue": 0, "spass_queue": 0, "sparse_s": 0}
     s.step(2)
     assert np.isfinite(s.stats()["objective"])
     s.close()

@@ -1,6 +1,6 @@
 """Sparse S between the passes (RPCA_FLAG_SPARSE_S): each FP32 S-pass also
-writes S (eq. "optS") as support words plus packed nonzero values per 16 x 16
-tile, and the next V-pass reads those instead of rebuilding S from the
+writes S (eq. "optS") as a slot word plus packed nonzero float4 slots per
+16 x 16 tile, and the next V-pass reads those instead of rebuilding S from the
 previous factors. S is the same bit for bit, so whole trajectories must be
 bitwise those without the flag: in every launch shape and form, at ranks
 that take the quad path and the full rank tiles, on ragged rows and client
@@ -48,9 +48,11 @@ def _same(a, b):
     return np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
 
 
-def _trajectory(inst, r, shape=None, rounds=9, lam=None, schedule=None, precisions=None, **kw):
+def _trajectory(inst, r, shape=None, rounds=9, lam=None, schedule=None, precisions=None,
+                sparse_per_round=None, **kw):
     """Checkpoints after rounds 1, 2 and `rounds`. schedule: lambda per round
-    (scaled from the default); precisions: precision per round."""
+    (scaled from the default); precisions: precision per round;
+    sparse_per_round: the launch shape's sparse choice per round."""
     s = _session(inst, r, lam=lam, shape=shape, **kw)
     lam0 = default_lam(inst) if lam is None else lam
     out = []
@@ -59,6 +61,8 @@ def _trajectory(inst, r, shape=None, rounds=9, lam=None, schedule=None, precisio
             s.set_lambda(lam0 * schedule[t])
         if precisions is not None:
             s.set_precision(precisions[t])
+        if sparse_per_round is not None:
+            s.set_launch_shape(sparse_s=sparse_per_round[t])
         s.step(1)
         if t in (0, 1, rounds - 1):
             out.append(_snap(s))
@@ -157,6 +161,30 @@ def test_sparse_precision_switches():
     a = _trajectory(inst, 20, precisions=prec, bf16x3=True)
     b = _trajectory(inst, 20, precisions=prec, bf16x3=True, sparse_s=True)
     _compare("precision", a, b)
+
+
+def test_sparse_shape_switches():
+    """The launch shape's sparse choice switched between rounds (as the
+    autotuner does): a round after a rebuilt one rebuilds S, and the
+    trajectory stays bitwise the rebuild's; a context without the flag refuses
+    the sparse choice."""
+    from paper_2207_11669_amd import RpcaError
+    inst = _instance(seed=68)
+    per_round = [1, 1, 0, 1, 1, 0, 0, 1, 1]
+    announce("sparse S across launch-shape switches")
+    a = _trajectory(inst, 20)
+    b = _trajectory(inst, 20, sparse_per_round=per_round, sparse_s=True)
+    _compare("switches", a, b)
+    s = _session(inst, 20)
+    assert s.launch_shape()["sparse_s"] == 0
+    with pytest.raises(RpcaError, match="RPCA_FLAG_SPARSE_S"):
+        s.set_launch_shape(sparse_s=1)
+    s.close()
+    s = _session(inst, 20, sparse_s=True)
+    assert s.launch_shape()["sparse_s"] == 1
+    with pytest.raises(RpcaError, match="sparse"):
+        s.set_launch_shape(sparse_s=2)
+    s.close()
 
 
 def test_sparse_copy_state():
