@@ -332,7 +332,10 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
 // work-groups fit on a compute unit and one's epilogue overlaps the other's
 // sweep.
 // ---------------------------------------------------------------------------
-template <int RT, int NK, bool X3>
+// HUB: 0, the Huber sum at the target lambda is left out (rounds at the
+// target lambda); 1, it is taken; 2, p.huber decides per round (the test is
+// if-converted, so its arithmetic runs on every entry).
+template <int RT, int NK, bool X3, int HUB>
 __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __restrict__ U, int b,
                                              int yi) {
   constexpr int RP = 16 * RT;
@@ -519,7 +522,8 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
         lamv[e] = L;
         l2 = fmaf(L, L, l2);
         l1 += fabsf(Sv);
-        if (hub) hb += huber1(R, lt);
+        if constexpr (HUB == 1) hb += huber1(R, lt);
+        if constexpr (HUB == 2) if (hub) hb += huber1(R, lt);
         nnz += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(Sv != 0.f));
       }
       if constexpr (X3) {
@@ -679,15 +683,17 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
 // allows it): at most 256 registers per lane, which it fits without spilling,
 // so that one work-group's epilogue overlaps the other's sweep. The queue
 // form's loop needs more registers and keeps the default bound.
-template <int RT, int NK, bool X3>
+// The per-tile form comes in two instantiations, with and without the Huber
+// sum, picked at launch; the queue form decides per round.
+template <int RT, int NK, bool X3, int HUB>
 __global__ __launch_bounds__(256, 2) void k_spass_h_tile(DevParams p, const float* __restrict__ U) {
-  spass_h_tile<RT, NK, X3>(p, U, (int)blockIdx.x, (int)blockIdx.y);
+  spass_h_tile<RT, NK, X3, HUB>(p, U, (int)blockIdx.x, (int)blockIdx.y);
 }
 template <int RT, int NK, bool X3>
 __global__ __launch_bounds__(256) void k_spass_h_queue(DevParams p, const float* __restrict__ U) {
   const int ntiles = p.nrb * p.E;
   for (int t = queue_next(p.queue + 2, ntiles); t < ntiles; t = queue_next(p.queue + 2, ntiles))
-    spass_h_tile<RT, NK, X3>(p, U, t % p.nrb, t / p.nrb);
+    spass_h_tile<RT, NK, X3, 2>(p, U, t % p.nrb, t / p.nrb);
 }
 
 hipError_t launch_m_to_bf16(const DevParams& p, hipStream_t st) {
@@ -744,18 +750,21 @@ template <int RT>
 static hipError_t launch_spass_h_t(const DevParams& p, const float* U, int x3, hipStream_t st) {
   constexpr int NK = (RT + 1) / 2;
   const int ntiles = p.nrb * p.E;
-  auto go = [&](auto persistent, auto per_tile) {
+  auto go = [&](auto persistent, auto per_tile, auto per_tile_huber) {
     if (p.squeue) {
       const int groups = pass_groups(persistent, 256, ntiles, 1);
       hipLaunchKernelGGL(persistent, dim3(groups), dim3(256), 0, st, p, U);
     } else {
-      hipLaunchKernelGGL(per_tile, dim3(p.nrb, p.E), dim3(256), 0, st, p, U);
+      hipLaunchKernelGGL(p.huber ? per_tile_huber : per_tile, dim3(p.nrb, p.E), dim3(256), 0, st,
+                         p, U);
     }
   };
   if (x3)
-    go(k_spass_h_queue<RT, NK, true>, k_spass_h_tile<RT, NK, true>);
+    go(k_spass_h_queue<RT, NK, true>, k_spass_h_tile<RT, NK, true, 0>,
+       k_spass_h_tile<RT, NK, true, 1>);
   else
-    go(k_spass_h_queue<RT, NK, false>, k_spass_h_tile<RT, NK, false>);
+    go(k_spass_h_queue<RT, NK, false>, k_spass_h_tile<RT, NK, false, 0>,
+       k_spass_h_tile<RT, NK, false, 1>);
   return hipGetLastError();
 }
 

@@ -95,32 +95,19 @@ __device__ __forceinline__ float quad_xor2(float x) {
 // 4 x 4 transpose within each quad of lanes: lane 4 q + e holds x[v] on
 // entry and x'[e'] = (lane 4 q + e')'s x[v] with v = its own e on exit (two
 // pair-exchange stages: 2 x 2 blocks across lanes l ^ 2, then entries across
-// lanes l ^ 1).
+// lanes l ^ 1; scalar selects, 16 instructions).
 __device__ __forceinline__ f4 quad_transpose(f4 x) {
   const int e = threadIdx.x & 3;
-  {
-    const float r0 = quad_xor2((e & 2) ? x[0] : x[2]);
-    const float r1 = quad_xor2((e & 2) ? x[1] : x[3]);
-    if (e & 2) {
-      x[0] = r0;
-      x[1] = r1;
-    } else {
-      x[2] = r0;
-      x[3] = r1;
-    }
-  }
-  {
-    const float r0 = quad_xor1((e & 1) ? x[0] : x[1]);
-    const float r1 = quad_xor1((e & 1) ? x[2] : x[3]);
-    if (e & 1) {
-      x[0] = r0;
-      x[2] = r1;
-    } else {
-      x[1] = r0;
-      x[3] = r1;
-    }
-  }
-  return x;
+  const bool h = (e & 2) != 0, o = (e & 1) != 0;
+  float x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
+  const float a0 = quad_xor2(h ? x0 : x2), a1 = quad_xor2(h ? x1 : x3);
+  const float y0 = h ? a0 : x0, y1 = h ? a1 : x1, y2 = h ? x2 : a0, y3 = h ? x3 : a1;
+  const float b0 = quad_xor1(o ? y0 : y1), b1 = quad_xor1(o ? y2 : y3);
+  x0 = o ? b0 : y0;
+  x1 = o ? y1 : b0;
+  x2 = o ? b1 : y2;
+  x3 = o ? y3 : b1;
+  return f4{x0, x1, x2, x3};
 }
 // Tile queue of a persistent launch (a streaming pass whose grid holds only
 // as many work-groups as are resident at once). q[0] is the next tile, q[1]
@@ -494,8 +481,10 @@ __device__ __forceinline__ void spass_stats(const DevParams& p, int ci, int b, d
 // within the threshold, lt |R| - lt^2 / 2 beyond it. By the Huber identity it
 // is the least value over S of (R - S)^2 / 2 + lt |S|.
 __device__ __forceinline__ float huber1(float R, float lt) {
-  const float a = fabsf(R);
-  return a <= lt ? 0.5f * R * R : lt * a - 0.5f * lt * lt;
+  // With c = min(|R|, lt): c (|R| - c / 2) is R^2 / 2 for |R| <= lt and
+  // lt |R| - lt^2 / 2 beyond (three instructions, no select).
+  const float a = fabsf(R), c = fminf(a, lt);
+  return c * fmaf(-0.5f, c, a);
 }
 
 // ---------------------------------------------------------------------------
