@@ -213,8 +213,9 @@ def measure(M_cols, inst, r, rho, lam, U0_cols, args, precision: str, workload: 
     else:
         shape = s.autotune(args.autotune) if args.autotune > 0 else s.launch_shape()
     torch.cuda.synchronize()
+    first = s.rounds  # rounds run before the timed ones (warm-up and autotuner)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    log(f"{precision}: timing {args.steps} rounds")
+    log(f"{precision}: timing {args.steps} rounds from round {first}")
     ev0.record(s.stream)
     s.step(args.steps)
     ev1.record(s.stream)
@@ -251,7 +252,7 @@ def measure(M_cols, inst, r, rho, lam, U0_cols, args, precision: str, workload: 
                  "avg_launch_us": {k: round(v[0] * 1e3, 2) for k, v in prof.items()},
                  "launches_per_round": {k: v[1] / args.profile_rounds for k, v in prof.items()}})
     return {"iters_per_s": round(args.steps / (ms / 1e3), 2), "ms_per_step": round(ms / args.steps, 5),
-            "autotuned_launch_shape": shape, "roofline": roof}
+            "autotuned_launch_shape": shape, "timed_from_round": first, "roofline": roof}
 
 
 def error_vs_oracle(precision: str, low_rounds: int, closing_rounds: int) -> dict:
@@ -537,7 +538,8 @@ def main() -> int:
                    "rho": rho, "K": 1, "inner": 1, "u_mode": args.u_mode,
                    "graph": bool(args.graph), "sparse_s_flag": not args.no_sparse_s,
                    "precision": args.precision,
-                   "autotuned_launch_shape": head["autotuned_launch_shape"]},
+                   "autotuned_launch_shape": head["autotuned_launch_shape"],
+                   "timed_from_round": head["timed_from_round"]},
         "roofline": head["roofline"],
         "mixed_precision": mixed,
         "time_to_relerr": relerr,
