@@ -65,7 +65,8 @@ __global__ __launch_bounds__(256) void k_m_to_bf16(DevParams p) {
 template <int RT, int NK, int MODE, bool X3>
 __device__ __forceinline__ void vpass_h_tile(const DevParams& p, const float* __restrict__ Ubase,
                                              const float* __restrict__ Uold,
-                                             const float* __restrict__ Vold, int tile) {
+                                             const float* __restrict__ Vold, int tile,
+                                             float (*red)[16 * RT]) {
   constexpr int RP = 16 * RT;
   constexpr int KG = X3 ? 2 : 4, kPh = KG;  // column groups per wave, row phases
   const int gx = tile % p.ng64, gy = tile / p.ng64;
@@ -273,9 +274,9 @@ __device__ __forceinline__ void vpass_h_tile(const DevParams& p, const float* __
       }
     }
   }
-  // Partial W of the waves, added in LDS in row-phase order; the work-group
-  // then writes its partial of the 64 columns.
-  __shared__ float red[kVStreamCols][RP];
+  // Partial W of the waves, added in LDS (red: kVStreamCols x RP) in
+  // row-phase order; the work-group then writes its partial of the 64
+  // columns.
   const int c0 = 16 * KG * cset;
   for (int q0 = 0; q0 < kPh; ++q0) {
     if (ph == q0) {
@@ -302,17 +303,21 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
                                                  const float* __restrict__ Uold,
                                                  const float* __restrict__ Vold,
                                                  double* __restrict__ fin_Ginv, int fin) {
+  // One LDS pool for both roles (sized for this rank, not the largest).
+  constexpr int RP = 16 * RT;
+  __shared__ double pool[vpass_pool_doubles(RP)];
+  float(*red)[RP] = reinterpret_cast<float(*)[RP]>(pool);
   if constexpr (!Q) {
     if (fin && blockIdx.x < 2) {
-      finalize_role(p, fin_Ginv, (int)blockIdx.x);
+      finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
       return;
     }
-    vpass_h_tile<RT, NK, MODE, X3>(p, Ubase, Uold, Vold, (int)blockIdx.x - (fin ? 2 : 0));
+    vpass_h_tile<RT, NK, MODE, X3>(p, Ubase, Uold, Vold, (int)blockIdx.x - (fin ? 2 : 0), red);
   } else {
-    if (fin && blockIdx.x < 2) finalize_role(p, fin_Ginv, (int)blockIdx.x);
+    if (fin && blockIdx.x < 2) finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
     const int ntiles = p.ng64 * p.vsplit;
     for (int t = queue_next(p.queue, ntiles); t < ntiles; t = queue_next(p.queue, ntiles))
-      vpass_h_tile<RT, NK, MODE, X3>(p, Ubase, Uold, Vold, t);
+      vpass_h_tile<RT, NK, MODE, X3>(p, Ubase, Uold, Vold, t, red);
   }
 }
 

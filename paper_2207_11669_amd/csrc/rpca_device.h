@@ -611,10 +611,12 @@ static __device__ void fin_record(const DevParams& p, const double* stats, doubl
 // The same work folded into a V-pass launch, by work-group role: role 0 forms
 // the Gram and its inverse (into Ginv slot 0, trace into dstate->u_sq_next),
 // role 1 the statistics (into p.stat_part). Neither reads what the other or
-// the streaming work-groups write; the V finish records the round.
-static __device__ void finalize_role(const DevParams& p, double* Ginv, int role) {
+// the streaming work-groups write; the V finish records the round. A: LDS
+// of at least r x r doubles, which the launch shares with the streaming
+// work-groups' own LDS (a work-group takes one role at a time, and a
+// persistent one passes a barrier before its first tile).
+static __device__ void finalize_role(const DevParams& p, double* Ginv, int role, double* A) {
   if (role == 0) {
-    __shared__ double A[kMaxRank * kMaxRank];
     fin_gram(p, 0, A);
     __syncthreads();
     const double tr = fin_inverse(p, A, Ginv, 0, 0);
@@ -625,6 +627,12 @@ static __device__ void finalize_role(const DevParams& p, double* Ginv, int role)
     if (threadIdx.x == 0)
       for (int q = 0; q < 7; ++q) p.stat_part[q] = st[q];
   }
+}
+
+// LDS pool of a V-pass launch (doubles): the folded finalize's r x r Gram
+// (r <= RP) or a streaming work-group's 64 x RP FP32 partial of W.
+constexpr int vpass_pool_doubles(int RP) {
+  return RP * RP > kVStreamCols * RP / 2 ? RP * RP : kVStreamCols * RP / 2;
 }
 
 // ===========================================================================

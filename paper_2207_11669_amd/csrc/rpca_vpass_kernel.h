@@ -34,7 +34,8 @@ namespace rpca {
 template <int RT, int NS, int MODE, int KG>
 __device__ __forceinline__ void vpass_tile(const DevParams& p, const float* __restrict__ Ubase,
                                            int64_t u_stride, const float* __restrict__ Uold,
-                                           const float* __restrict__ Vold, int tile) {
+                                           const float* __restrict__ Vold, int tile,
+                                           float (*red)[16 * RT]) {
   constexpr int RP = 16 * RT;
   static_assert(NS >= 1 && NS <= 4 * RT, "NS = ceil(r / 4) must fit the rank tiles");
   // W's last rank tile in 4x4 blocks when it holds at most 12 ranks.
@@ -236,9 +237,9 @@ __device__ __forceinline__ void vpass_tile(const DevParams& p, const float* __re
         x += __shfl_xor(x, 32, 64);
         accq[g][q][i] = x;
       }
-  // Partial W of the waves, added in LDS in row-phase order; the
-  // work-group then writes its partial of the 64 columns.
-  __shared__ float red[kVStreamCols][RP];
+  // Partial W of the waves, added in LDS (red: kVStreamCols x RP) in
+  // row-phase order; the work-group then writes its partial of the 64
+  // columns.
   const int c0 = 16 * kG * cset;
   for (int q0 = 0; q0 < kPh; ++q0) {
     if (ph == q0) {
@@ -284,17 +285,22 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
                                                int64_t u_stride, const float* __restrict__ Uold,
                                                const float* __restrict__ Vold,
                                                double* __restrict__ fin_Ginv, int fin) {
+  // One LDS pool for both roles (sized for this rank, not the largest).
+  constexpr int RP = 16 * RT;
+  __shared__ double pool[vpass_pool_doubles(RP)];
+  float(*red)[RP] = reinterpret_cast<float(*)[RP]>(pool);
   if constexpr (!Q) {
     if (fin && blockIdx.x < 2) {
-      finalize_role(p, fin_Ginv, (int)blockIdx.x);
+      finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
       return;
     }
-    vpass_tile<RT, NS, MODE, KG>(p, Ubase, u_stride, Uold, Vold, (int)blockIdx.x - (fin ? 2 : 0));
+    vpass_tile<RT, NS, MODE, KG>(p, Ubase, u_stride, Uold, Vold, (int)blockIdx.x - (fin ? 2 : 0),
+                                 red);
   } else {
-    if (fin && blockIdx.x < 2) finalize_role(p, fin_Ginv, (int)blockIdx.x);
+    if (fin && blockIdx.x < 2) finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
     const int ntiles = p.ng64 * p.vsplit;
     for (int t = queue_next(p.queue, ntiles); t < ntiles; t = queue_next(p.queue, ntiles))
-      vpass_tile<RT, NS, MODE, KG>(p, Ubase, u_stride, Uold, Vold, t);
+      vpass_tile<RT, NS, MODE, KG>(p, Ubase, u_stride, Uold, Vold, t, red);
   }
 }
 
