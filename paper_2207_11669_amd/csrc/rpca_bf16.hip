@@ -369,6 +369,16 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
         ub[rt][kb] = UhA[o];
         if constexpr (X3) ubl[rt][kb] = UhA[uhl + o];
       }
+    // Negated once: MFMA 1 then accumulates M - U V^T onto M (the residual
+    // needs no subtraction per entry; the pass is VALU-bound).
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt)
+#pragma unroll
+      for (int kb = 0; kb < NK; ++kb) {
+        ub[rt][kb] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4, ub[rt][kb]) ^ 0x80008000u);
+        if constexpr (X3)
+          ubl[rt][kb] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4, ubl[rt][kb]) ^ 0x80008000u);
+      }
   }
   f4 accp[kRT][RT];
 #pragma unroll
@@ -471,13 +481,26 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
       if constexpr (X3) c.vbl[ct] = VhB[vhl + o];
     }
   };
-  // MFMA 1 for every row tile: (U V^T)^T, two 16x16 halves per tile.
+  // MFMA 1 for every row tile: the residual's transpose M^T - (U V^T)^T in
+  // two 16x16 halves per tile, the accumulators starting from the lane's
+  // entries of M (rows 8 (l/16) + e of the chunk's columns) and the U
+  // operand negated.
   f4 o[kRT][2];
-  auto mfma1 = [&](const OpA& a) {
+  auto init_o = [&](const MChunk& c, int rt) {
+    float x[8];
+    if constexpr (X3) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = c.mf[rt][e];
+    } else {
+      unpack8(c.m[rt], x);
+    }
+    o[rt][0] = f4{x[0], x[1], x[2], x[3]};
+    o[rt][1] = f4{x[4], x[5], x[6], x[7]};
+  };
+  auto mfma1 = [&](const MChunk& c, const OpA& a) {
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) {
-      o[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
-      o[rt][1] = f4{0.f, 0.f, 0.f, 0.f};
+      init_o(c, rt);
 #pragma unroll
       for (int kb = 0; kb < NK; ++kb) {
 #pragma unroll
@@ -499,8 +522,7 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) {
       if constexpr (FUSED) {
-        o[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
-        o[rt][1] = f4{0.f, 0.f, 0.f, 0.f};
+        init_o(c, rt);
 #pragma unroll
         for (int kb = 0; kb < NK; ++kb) {
 #pragma unroll
@@ -512,16 +534,10 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
           }
         }
       }
-      float x[8], lamv[8];
-      if constexpr (X3) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = c.mf[rt][e];
-      } else {
-        unpack8(c.m[rt], x);
-      }
+      float lamv[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float R = x[e] - o[rt][e >> 2][e & 3];
+        const float R = o[rt][e >> 2][e & 3];
         const float L = __builtin_amdgcn_fmed3f(R, -lam, lam);  // clip(R, -lam, lam)
         const float Sv = R - L;
         lamv[e] = L;
@@ -564,7 +580,7 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
         for (int d = 0; d < kDepth; ++d) {
           const int k = k0 + d;
           const int kn = min(k + 1, nk - 1);
-          if (k < nk) mfma1(oa[0]);  // wave-uniform
+          if (k < nk) mfma1(ring[d], oa[0]);  // wave-uniform
           __builtin_amdgcn_sched_barrier(0);
           load_a(oa[0], kn);
           __builtin_amdgcn_sched_barrier(0);
