@@ -61,12 +61,18 @@ typedef enum {
  * byte ranges, so with RP = r rounded up to 16:
  *   (m rounded up to 128) * RP * 4 < 2^31          (m < 2^23 at r = 64), and
  *   (sum of the n_i each rounded up to 64) * RP * 4 < 2^31
- *                                                   (n < 2^23 at r = 64). */
+ *                                                   (n < 2^23 at r = 64).
+ * Ranks above 64 (the upper-bound rank experiments of Section 4.2 and Table 1
+ * fit up to 0.2 n) run in FP32 only: RPCA_FLAG_BF16 and RPCA_FLAG_BF16X3
+ * need r <= 64, and the launch shape keeps one column group per V-pass wave
+ * and one S-pass column phase. A client narrower than r makes V_i^T V_i
+ * singular; the closed-form U step then amplifies the FP32 rounding of
+ * (M_i - S_i) V_i by up to n / (rho n_i). */
 typedef struct {
   int64_t m;               /* rows of M (all clients share them), 1 <= m < 2^26 */
   int32_t E;               /* number of clients, 1 <= E <= 4096 */
   const int64_t* n_cols;   /* host array [E]: 1 <= n_i <= 2^30 columns of client i */
-  int32_t r;               /* factor rank, 1 <= r <= 64 */
+  int32_t r;               /* factor rank, 1 <= r <= 128 */
   double rho;              /* rho > 0 (Frobenius penalty on U and V) */
   double lambda;           /* lambda >= 0 (l1 penalty on S) */
   int32_t K;               /* local steps per round, K >= 1 (Algorithm 1) */
@@ -228,7 +234,7 @@ rpca_status rpca_solve(rpca_ctx* c, int32_t max_rounds, double tol, int32_t chec
 /* Register a planted low-rank target L* = Ustar Vstar^T for the solve metric
  * (Section 4.1 evaluation). Ustar: device m x rstar column-major (ld ldus);
  * Vstar: device n x rstar column-major (ld ldvs), rows ordered as the
- * clients' columns. Copied into the workspace. 1 <= rstar <= 64. */
+ * clients' columns. Copied into the workspace. 1 <= rstar <= 128. */
 rpca_status rpca_set_target(rpca_ctx* c, const float* Ustar, int64_t ldus,
                             const float* Vstar, int64_t ldvs, int32_t rstar);
 
@@ -280,11 +286,11 @@ typedef struct rpca_launch_shape {
   int32_t vsplit;
   /* 16-column groups per FP32 V-pass wave: 1 (waves on distinct columns share
    * U operands through the cache) or 4 (a wave takes all 64 columns of its
-   * tile, the waves splitting the rows) */
+   * tile, the waves splitting the rows); 1 only for r > 64 */
   int32_t vcols;
   /* FP32 S-pass column phases: 2 (work-groups of 8 waves, two per 32-row
    * strip taking alternate 16-column chunks, their partial P summed at the
-   * end) or 1 (4 waves, one per strip) */
+   * end) or 1 (4 waves, one per strip); 1 only for r > 64 */
   int32_t sphases;
   /* Launch forms of the V-pass and the S-pass: 0, one work-group per tile
    * (a 64-column group by row split, or a 128-row block of a client); 1, a
@@ -313,7 +319,7 @@ typedef struct rpca_launch_shape {
  * turn, twice over, and compares the sums. Every timing runs `rounds` timed rounds (plus one
  * untimed); the fastest candidate is kept and returned in *out (optional).
  * Synchronises. The rounds are real rounds of the method; the choice depends
- * on timing. */
+ * on timing. For r > 64 the column groups and S-pass phases stay at 1. */
 rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out);
 
 /* The launch shapes in effect. */

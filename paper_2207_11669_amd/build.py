@@ -1,7 +1,7 @@
 """Build the HIP library librpca.so for gfx950 in-tree with hipcc.
 
-The library is the whole DCF-PCA hot path: kernels (rpca_vpass.hip,
-rpca_spass.hip, rpca_bf16.hip, rpca_tail.hip, rpca_mlp.hip, with their shared
+The library is the whole DCF-PCA hot path: kernels (rpca_vpass*.hip,
+rpca_spass*.hip, rpca_bf16.hip, rpca_tail.hip, rpca_mlp.hip, with their shared
 device helpers in rpca_device.h) and the C ABI (rpca_api.cpp, declared in include/rpca.h). Each
 source is compiled to an object of its own, in parallel, and the objects are
 linked into one shared library. Packed-FP32 instruction selection is disabled
@@ -20,9 +20,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "librpca.so")
-SOURCES = ["rpca_vpass.hip", "rpca_vpass_q.hip", "rpca_vpass_s.hip", "rpca_spass.hip",
-           "rpca_spass_q.hip", "rpca_spass_s.hip", "rpca_bf16.hip", "rpca_tail.hip",
-           "rpca_api.cpp", "rpca_mlp.hip"]
+SOURCES = ["rpca_vpass.hip", "rpca_vpass_q.hip", "rpca_vpass_s.hip", "rpca_vpass_w.hip",
+           "rpca_spass.hip", "rpca_spass_q.hip", "rpca_spass_s.hip", "rpca_spass_w.hip",
+           "rpca_bf16.hip", "rpca_tail.hip", "rpca_api.cpp", "rpca_mlp.hip"]
 ARCH = "gfx950"
 # hipcc's host pass warns that it does not know the packed-fp32 feature.
 _NOISE = "packed-fp32-ops"

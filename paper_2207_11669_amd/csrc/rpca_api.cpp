@@ -96,7 +96,7 @@ const char* check_params(const rpca_params* p) {
     n += p->n_cols[i];
   }
   if (n > (int64_t)1 << 31) return "total columns n must be <= 2^31";
-  if (p->r < 1 || p->r > kMaxRank) return "r must be in [1, 64]";
+  if (p->r < 1 || p->r > kMaxRank) return "r must be in [1, 128]";
   {
     // The kernels address whole factor layouts through buffer resources with
     // 32-bit byte ranges: (m rounded up to 128) x (r rounded up to 16) and
@@ -128,6 +128,8 @@ const char* check_params(const rpca_params* p) {
   if ((p->flags & (RPCA_FLAG_BF16 | RPCA_FLAG_BF16X3)) &&
       (p->K != 1 || p->inner != 1 || (p->flags & RPCA_FLAG_STORE_S)))
     return "RPCA_FLAG_BF16 and RPCA_FLAG_BF16X3 need K = 1, inner = 1 and no RPCA_FLAG_STORE_S";
+  if ((p->flags & (RPCA_FLAG_BF16 | RPCA_FLAG_BF16X3)) && p->r > kFoldMaxRP)
+    return "RPCA_FLAG_BF16 and RPCA_FLAG_BF16X3 need r <= 64";
   return nullptr;
 }
 
@@ -135,7 +137,9 @@ Layout make_layout(const rpca_params* p) {
   Layout L{};
   L.MP = (int32_t)round_up(p->m, kSRows);
   L.RP = (int32_t)round_up(p->r, 16);
-  L.NS = (p->r + 3) / 4;
+  // Rank steps of the packed A operands: ceil(r/4) up to r = 64; beyond,
+  // whole rank tiles (the padding ranks are zero).
+  L.NS = L.RP <= kFoldMaxRP ? (p->r + 3) / 4 : L.RP / 4;
   L.lds = round_up(p->m, 4);
   L.RK = (int32_t)round_up(p->r, 32);
   L.bf16 = (p->flags & (RPCA_FLAG_BF16 | RPCA_FLAG_BF16X3)) != 0;
@@ -225,8 +229,8 @@ Layout make_layout(const rpca_params* p) {
   L.Vprev = take((size_t)L.NVP * L.RP * f);
   L.Ut = take((size_t)kMaxRank * L.MP * f);
   L.Vt = take((size_t)L.NVP * kMaxRank * f);
-  L.dpart = take((size_t)2 * kDistBlocks * 3 * kMaxRank * kMaxRank * d);
-  L.dpart2 = take((size_t)48 * d);
+  L.dpart = take((size_t)kDistPartDoubles * d);
+  L.dpart2 = take((size_t)kDistPart2Doubles * d);
   L.dout = take((size_t)2 * d);
   L.queue = take(4 * sizeof(uint32_t));
   L.total = o;
@@ -299,6 +303,18 @@ DevParams with_v(const rpca_ctx* c, int v) {
   return q;
 }
 
+// Ranks above 64 fold no finalize into the V-pass (its r x r FP64 matrix
+// would not share the V-pass LDS): a pending one runs as its own launch,
+// recording the previous round, before the round's first V-pass.
+hipError_t unfold_finalize(rpca_ctx* c, Profiler* prof) {
+  if (!c->fin_pending || c->p.RP <= kFoldMaxRP) return hipSuccess;
+  hipError_t e = prof ? prof->begin(c->stream, RPCA_PHASE_FINALIZE) : hipSuccess;
+  if (e == hipSuccess) e = launch_finalize(c->p, c->Ginv, 0, 0, 1, c->stream);
+  if (e == hipSuccess && prof) e = prof->end(c->stream);
+  if (e == hipSuccess) c->fin_pending = false;
+  return e;
+}
+
 // One round of Algorithm 1: K local steps (each: `inner` V/S alternations,
 // then the U step) and the consensus mean at the last one.
 rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
@@ -322,6 +338,7 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     DevParams q = with_v(c, vn);
     // BF16 rounds, and rounds whose launch shape rebuilds S, write no sparse S.
     if (h || !c->use_sparse) q.Smask = nullptr, q.Sval = nullptr;
+    RPCA_HIP(c, unfold_finalize(c, prof), "finalize launch");
     double* fin = c->fin_pending ? c->Ginv : nullptr;
     c->fin_pending = false;
     const int x3 = c->prec == RPCA_PREC_BF16X3 ? 1 : 0;
@@ -354,6 +371,7 @@ rpca_status enqueue_round(rpca_ctx* c, Profiler* prof = nullptr) {
     for (int qi = 0; qi < c->inner; ++qi) {
       const int vn = c->vcur ^ 1;
       const DevParams q = with_v(c, vn);
+      RPCA_HIP(c, unfold_finalize(c, prof), "finalize launch");
       double* fin = c->fin_pending ? c->Ginv : nullptr;
       c->fin_pending = false;
       RPCA_LAUNCH(c, prof, RPCA_PHASE_VPASS,
@@ -487,10 +505,12 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   // Shared-operand V-pass waves pay off once a chunk's U operands cost more
   // loads than its M (the rebuild's NS packed rank steps); the autotuner
   // revisits this.
-  p.vcols = L.NS > 5 ? 4 : 1;
+  // (Ranks above 64 take one group per wave.)
+  p.vcols = L.NS > 5 && L.RP <= kFoldMaxRP ? 4 : 1;
   // S-pass work-groups of 8 waves, two per 32-row strip taking alternate
-  // column chunks; the autotuner also tries one wave per strip.
-  p.sphases = 2;
+  // column chunks; the autotuner also tries one wave per strip. (Ranks above
+  // 64 take one wave per strip.)
+  p.sphases = L.RP <= kFoldMaxRP ? 2 : 1;
   c->vsplit_max = L.vsplit_max;
   p.u_mode = prm->u_mode;
   p.eta_sched = prm->eta_sched;
@@ -805,6 +825,7 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
     if (v < 1 || v > c->vsplit_max) continue;
     set_vsplit(c, v);
     for (int32_t g : {1, 4}) {
+      if (g == 4 && c->p.RP > kFoldMaxRP) continue;
       const rpca_launch_shape k{c->p.vsplit, g, start.sphases, start.vqueue, start.squeue,
                                 start.sparse};
       if (std::none_of(cand.begin(), cand.end(), [&](const rpca_launch_shape& x) { return same_shape(x, k); }))
@@ -825,7 +846,7 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
   // Stage 2, the FP32 S-pass at the chosen V-pass shape: two column phases
   // and one, timed in turn twice each (the gap is a few percent of a round;
   // BF16 rounds run their own S-pass).
-  if (result == RPCA_OK && c->prec == RPCA_PREC_FP32) {
+  if (result == RPCA_OK && c->prec == RPCA_PREC_FP32 && c->p.RP <= kFoldMaxRP) {
     const std::vector<rpca_launch_shape> ks = {
         {best.vsplit, best.vcols, 2, best.vqueue, best.squeue, best.sparse},
         {best.vsplit, best.vcols, 1, best.vqueue, best.squeue, best.sparse}};
@@ -903,6 +924,9 @@ rpca_status rpca_set_launch_shape(rpca_ctx* c, const rpca_launch_shape* k) {
     return fail(c, RPCA_EINVAL, "sparse must be 0 (rebuild S) or 1 (sparse S)");
   if (k->sparse && !c->p.Smask)
     return fail(c, RPCA_EINVAL, "sparse S needs a context created with RPCA_FLAG_SPARSE_S");
+  if (c->p.RP > kFoldMaxRP && (k->vcols != 1 || k->sphases != 1))
+    return fail(c, RPCA_EINVAL,
+                "ranks above 64 take 1 column group per V-pass wave and 1 S-pass column phase");
   apply_shape(c, *k);
   drop_graphs(c);
   return RPCA_OK;

@@ -173,7 +173,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 constexpr int kFinThreads = 256;                             // finalize work-groups
-constexpr int kFinEPT = (kMaxRank * (kMaxRank + 1) / 2 + kFinThreads - 1) / kFinThreads;  // sweep entries per thread
+// Lower-triangle entries per finalize thread for ranks up to R.
+constexpr int fin_ept(int R) { return (R * (R + 1) / 2 + kFinThreads - 1) / kFinThreads; }
+constexpr int kFinEPT = fin_ept(kFoldMaxRP);  // ranks up to 64 (the folded finalize)
 
 // 1/x for x > 0 without the correctly rounded division sequence: the
 // hardware reciprocal estimate refined by two Newton steps (each squares the
@@ -564,6 +566,7 @@ static __device__ void fin_stats(const DevParams& p, double* out) {
 
 // G^{-1} of the Gram in LDS A (adds rho I) into Ginv slot gi; returns
 // tr(U^T U) (valid in every thread).
+template <int EPT>
 static __device__ double fin_inverse(const DevParams& p, double* A, double* Ginv, int64_t g_stride, int gi) {
   __shared__ double tr_sh;
   const int tid = threadIdx.x, r = p.r, RP = p.RP;
@@ -576,7 +579,7 @@ static __device__ double fin_inverse(const DevParams& p, double* A, double* Ginv
   __syncthreads();
   for (int k = tid; k < r; k += blockDim.x) A[k * r + k] += p.rho;
   __syncthreads();
-  spd_inverse<kFinEPT>(A, r, r);
+  spd_inverse<EPT>(A, r, r);
   double* Gout = Ginv + (int64_t)gi * g_stride;
   for (int e = tid; e < RR; e += blockDim.x) {
     const int a = e / RP, b = e % RP;
@@ -619,7 +622,7 @@ static __device__ void finalize_role(const DevParams& p, double* Ginv, int role,
   if (role == 0) {
     fin_gram(p, 0, A);
     __syncthreads();
-    const double tr = fin_inverse(p, A, Ginv, 0, 0);
+    const double tr = fin_inverse<kFinEPT>(p, A, Ginv, 0, 0);
     if (threadIdx.x == 0) p.dstate->u_sq_next = tr;
   } else {
     __shared__ double st[7];
@@ -630,9 +633,10 @@ static __device__ void finalize_role(const DevParams& p, double* Ginv, int role,
 }
 
 // LDS pool of a V-pass launch (doubles): the folded finalize's r x r Gram
-// (r <= RP) or a streaming work-group's 64 x RP FP32 partial of W.
+// (r <= RP <= kFoldMaxRP) or a streaming work-group's 64 x RP FP32 partial
+// of W (wider ranks fold no finalize).
 constexpr int vpass_pool_doubles(int RP) {
-  return RP * RP > kVStreamCols * RP / 2 ? RP * RP : kVStreamCols * RP / 2;
+  return RP <= kFoldMaxRP && RP * RP > kVStreamCols * RP / 2 ? RP * RP : kVStreamCols * RP / 2;
 }
 
 // ===========================================================================
@@ -713,12 +717,30 @@ static int pass_groups(K kernel, int block, int ntiles, int persistent) {
   return res > 0 && res < ntiles ? res : ntiles;
 }
 
-// Compile-time (RT, NS) dispatch: NS = ceil(r/4) lies in [4 RT - 3, 4 RT].
+// Compile-time (RT, NS) dispatch for ranks up to kFoldMaxRP: NS = ceil(r/4)
+// lies in [4 RT - 3, 4 RT]. (Wider ranks have launchers of their own, with
+// NS = 4 RT.)
 template <int RT, int NS, class F>
 static hipError_t with_ns(int ns, F&& f) {
   if (ns == NS) return f(std::integral_constant<int, RT>{}, std::integral_constant<int, NS>{});
   if constexpr (NS < 4 * RT) return with_ns<RT, NS + 1>(ns, f);
   return hipErrorInvalidValue;
+}
+// Rank-tile dispatch (one to eight 16-rank tiles) for kernels whose code does
+// not depend on NS.
+template <class F>
+static hipError_t with_rt(int RP, F&& f) {
+  switch (RP / 16) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 7: return f(std::integral_constant<int, 7>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    default: return hipErrorInvalidValue;
+  }
 }
 template <class F>
 static hipError_t with_rank(const DevParams& p, F&& f) {

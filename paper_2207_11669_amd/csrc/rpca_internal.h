@@ -6,7 +6,13 @@
 
 namespace rpca {
 
-constexpr int kMaxRank = 64;     // largest supported factor rank r
+constexpr int kMaxRank = 128;    // largest supported factor rank r
+// Ranks up to kFoldMaxRP (four 16-rank tiles) take every launch shape, the
+// BF16 passes, and the finalize folded into the V-pass; wider ones (five to
+// eight rank tiles) run the FP32 passes with one column group per V-pass wave
+// and one S-pass column phase, full rank tiles (NS = RP / 4), and a
+// standalone finalize.
+constexpr int kFoldMaxRP = 64;
 constexpr int kHist = 4096;      // per-round statistics kept in a ring
 constexpr int kVCols = 32;       // columns per V-finalize work-group
 constexpr int kVPad = 64;        // client V blocks are padded to multiples of 64 rows
@@ -214,7 +220,13 @@ __host__ __device__ inline const uint16_t* v_hb(const float* V, const DevParams&
 
 // Launch helpers (kernels live in rpca_vpass.hip, rpca_spass.hip, rpca_bf16.hip
 // and rpca_tail.hip).
-constexpr int kDistBlocks = 64;  // work-groups per side of the factor-distance kernel
+// Factor distance: work-groups per side (64 at widths up to 64, 16 at 128),
+// Gram entries per work-group, and the doubles of its two workspaces (the
+// same at both widths).
+constexpr int dist_blocks(int W) { return W <= 64 ? 64 : 16; }
+constexpr int kDistSlice = 3 * 64 * 64;
+constexpr int64_t kDistPartDoubles = 2 * 64 * (int64_t)kDistSlice;
+constexpr int kDistPart2Doubles = 3 * kMaxRank * kMaxRank / 256;
 // S source for the V-pass: zero, the stored S buffer, recomputed from the
 // previous round's factors, or the sparse S the previous S-pass wrote.
 enum VMode { kSZero = 0, kSStored = 1, kSRecompute = 2, kSSparse = 3 };
@@ -261,8 +273,8 @@ hipError_t launch_pack_target(const DevParams& p, const ClientDev* host_clients,
                               int RPT, hipStream_t st);
 // ||X1 Y1^T - X2 Y2^T||_F^2 -> out2[0] and ||X2 Y2^T||_F^2 -> out2[1], from
 // Gram matrices (FP64). X*: column-major, MP rows (ld MP); Y*: column-major,
-// NVP rows (ld NVP); widths rp1, rp2 <= 64. part: 2*kDistBlocks*3*64*64
-// doubles; part2: 48 doubles.
+// NVP rows (ld NVP); widths rp1, rp2 <= kMaxRank. part: kDistPartDoubles
+// doubles; part2: kDistPart2Doubles doubles.
 // Mixed precision (rpca_bf16.hip). The BF16 copies of M from the borrowed
 // FP32 blocks (zero padded).
 hipError_t launch_m_to_bf16(const DevParams& p, hipStream_t st);

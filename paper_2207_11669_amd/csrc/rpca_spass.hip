@@ -34,6 +34,9 @@ static hipError_t launch_spass_t(const DevParams& p, const float* U, int64_t u_s
 hipError_t launch_spass(const DevParams& p, const float* U, int64_t u_stride, float* Sout,
                         int64_t lds_out, int emit_only, int client_base, int client_count,
                         hipStream_t st) {
+  if (p.RP > kFoldMaxRP)
+    return launch_spass_wide(p, U, u_stride, Sout, lds_out, emit_only, client_base, client_count,
+                             st);
   const bool all = !emit_only && client_base == 0 && client_count == p.E;
   if (all && !Sout && p.Smask) return launch_spass_sparse(p, U, u_stride, st);
   if (p.squeue && all) return launch_spass_queue(p, U, u_stride, Sout, lds_out, st);

@@ -419,6 +419,11 @@ __global__ __launch_bounds__(256 * NPH) void k_spass(DevParams p, const float* _
   }
 }
 
+// S-pass at ranks above kFoldMaxRP, every launch form and output
+// (rpca_spass_w.hip).
+hipError_t launch_spass_wide(const DevParams& p, const float* U, int64_t u_stride, float* Sout,
+                             int64_t lds_out, int emit_only, int client_base, int client_count,
+                             hipStream_t st);
 // Persistent S-pass launches over all clients from the tile queue
 // (rpca_spass_q.hip).
 hipError_t launch_spass_queue(const DevParams& p, const float* U, int64_t u_stride,

@@ -20,30 +20,34 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
     for (int q = 0; q < 7; ++q) st[q] = p.stat_part[q];
     fin_record(p, st, p.dstate->u_sq_next);
   }
+  // G^{-1} is staged in LDS kKB rows at a time: all of it up to four rank
+  // tiles, half of it beyond (the whole of it and W would not fit the LDS at
+  // r = 128); the products still run over k in increasing order.
+  constexpr int kKB = RT <= 4 ? RP : RP / 2;
   __shared__ double wd[kVCols][RP + 1];
-  __shared__ double gl[RP * RP];
+  __shared__ double gl[kKB * RP];
   const VGroup vg = p.vgroups[blockIdx.x];
   const double* __restrict__ Gi = Gbase + (int64_t)vg.client * g_stride;
   const int tid = threadIdx.x;
   const int vrow = vg.vrow;
   const int64_t split_stride = (int64_t)p.NVP * RP;
   constexpr int kPer = (kVCols * RP + 255) / 256;
-  constexpr int kGPer = (RP * RP + 255) / 256;
+  constexpr int kGPer = (kKB * RP + 255) / 256;
   {
     // All of a thread's loads (kWB row splits of each of its W entries, and
-    // its share of G^{-1}) are issued before any is used; splits are summed
-    // in increasing order. Wider ranks batch fewer splits, which keeps the
-    // batch's addresses within the register file.
+    // its share of G^{-1}'s first kKB rows) are issued before any is used;
+    // splits are summed in increasing order. Wider ranks batch fewer splits,
+    // which keeps the batch's addresses within the register file.
     double gv_[kGPer];
 #pragma unroll
     for (int q = 0; q < kGPer; ++q) {
       const int e = tid + q * 256;
-      gv_[q] = Gi[e];  // RP^2 is a multiple of 256
+      gv_[q] = Gi[e];  // e < RP^2: a multiple of 256 is read, kKB RP kept
     }
     double acc[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
-    constexpr int kWB = RT <= 2 ? 8 : 4;
+    constexpr int kWB = RT <= 2 ? 8 : RT <= 4 ? 4 : 2;
     for (int s0 = 0; s0 < p.vsplit; s0 += kWB) {
       float wv[kPer][kWB];
 #pragma unroll
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
 #pragma unroll
     for (int q = 0; q < kGPer; ++q) {
       const int e = tid + q * 256;
-      if (e < RP * RP) gl[e] = gv_[q];
+      if (e < kKB * RP) gl[e] = gv_[q];
     }
   }
   __syncthreads();
@@ -87,17 +91,26 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
     double sv[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) sv[q] = 0.0;
+    for (int kb = 0; kb < RP; kb += kKB) {
+      if (kb > 0) {  // (wide ranks) the next kKB rows of G^{-1}
+        __syncthreads();
+        for (int e = tid; e < kKB * RP; e += 256) gl[e] = Gi[(int64_t)kb * RP + e];
+        __syncthreads();
+      }
+      const int kend = min(p.r, kb + kKB);
 #pragma unroll 2
-    for (int k = 0; k < p.r; ++k) {
-      if constexpr (256 % RP == 0) {
-        const double g = gl[k * RP + tid % RP];
+      for (int k = kb; k < kend; ++k) {
+        const double* gk = gl + (k - kb) * RP;
+        if constexpr (256 % RP == 0) {
+          const double g = gk[tid % RP];
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) sv[q] += wd[(tid + 256 * q) / RP][k] * g;
-      } else {
+          for (int q = 0; q < kPer; ++q) sv[q] += wd[(tid + 256 * q) / RP][k] * g;
+        } else {
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-          const int e = tid + 256 * q;
-          sv[q] += wd[e / RP][k] * gl[k * RP + e % RP];
+          for (int q = 0; q < kPer; ++q) {
+            const int e = tid + 256 * q;
+            sv[q] += wd[e / RP][k] * gk[e % RP];
+          }
         }
       }
     }
@@ -122,31 +135,35 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
   // Partial V^T V of these columns: thread (ta, tb) = (tid / 16, tid % 16)
   // forms the RT x RT block of entries (RT ta + x, RT tb + y), each a sum over
   // the 32 columns in order (each LDS read feeds RT FMAs).
+  // (Beyond four rank tiles the block's rows go in sweeps of four, which
+  // keeps its sums within the registers; same sums.)
   double* gv = p.gv_part + (int64_t)blockIdx.x * RP * RP;
-  {
-    const int a0 = RT * (tid >> 4), b0 = RT * (tid & 15);
-    double sg[RT][RT];
+  constexpr int kXB = RT <= 4 ? RT : 4;
 #pragma unroll
-    for (int x = 0; x < RT; ++x)
+  for (int x0 = 0; x0 < RT; x0 += kXB) {
+    const int a0 = RT * (tid >> 4) + x0, b0 = RT * (tid & 15);
+    double sg[kXB][RT];
+#pragma unroll
+    for (int x = 0; x < kXB; ++x)
 #pragma unroll
       for (int y = 0; y < RT; ++y) sg[x][y] = 0.0;
 #pragma unroll 2
     for (int j = 0; j < kVCols; ++j) {
-      double va[RT], vb[RT];
+      double va[kXB], vb[RT];
 #pragma unroll
-      for (int x = 0; x < RT; ++x) {
-        va[x] = wd[j][a0 + x];
-        vb[x] = wd[j][b0 + x];
-      }
+      for (int x = 0; x < kXB; ++x) va[x] = x0 + x < RT ? wd[j][a0 + x] : 0.0;
 #pragma unroll
-      for (int x = 0; x < RT; ++x)
+      for (int y = 0; y < RT; ++y) vb[y] = wd[j][b0 + y];
+#pragma unroll
+      for (int x = 0; x < kXB; ++x)
 #pragma unroll
         for (int y = 0; y < RT; ++y) sg[x][y] += va[x] * vb[y];
     }
 #pragma unroll
-    for (int x = 0; x < RT; ++x)
+    for (int x = 0; x < kXB; ++x)
+      if (x0 + x < RT)
 #pragma unroll
-      for (int y = 0; y < RT; ++y) gv[(a0 + x) * RP + b0 + y] = sg[x][y];
+        for (int y = 0; y < RT; ++y) gv[(a0 + x) * RP + b0 + y] = sg[x][y];
   }
 }
 
@@ -157,9 +174,14 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
 // epilogue applies as U_i + (P - c_i U_i) A_i.) One work-group per client;
 // FP64 throughout.
 // ---------------------------------------------------------------------------
+template <int RT>
 __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
-  __shared__ double A[kMaxRank * kMaxRank];
-  const int r = p.r, RP = p.RP;
+  constexpr int RP = 16 * RT;
+  // Lower-triangle entries per thread: three up to r = 64 (1024 x 3 >= 64 x
+  // 65 / 2), nine at r = 128.
+  constexpr int kCE = RT <= 4 ? 3 : (RP * (RP + 1) / 2 + 1023) / 1024;
+  __shared__ double A[RP * RP];
+  const int r = p.r;
   const int64_t RR = (int64_t)RP * RP;
   const ClientDev cl = p.clients[blockIdx.x];
   const int tid = threadIdx.x;
@@ -179,7 +201,6 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
     // under a branch: out-of-range groups and entries re-read a valid,
     // finite partial and are multiplied by 0 (a select would let the
     // compiler move the load into a branch of its own, with its own wait).
-    constexpr int kCE = 3;  // 1024 threads x 3 >= 64 x 65 / 2
     const int nl = r * (r + 1) / 2, ng = cl.g1 - cl.g0;
     const double* __restrict__ gp = p.gv_part + (int64_t)cl.g0 * RR;
     int ia[kCE], ib[kCE];
@@ -198,17 +219,20 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
       ib[q] = b;
       s[q] = 0.0;
     }
+    // (Beyond four rank tiles, with three times the entries per thread, 2
+    // groups at a time: same sums.)
+    constexpr int kGB = RT <= 4 ? 8 : 2;
     for (int g0 = 0; g0 < ng; g0 += 16) {
       double t[kCE];
 #pragma unroll
       for (int q = 0; q < kCE; ++q) t[q] = 0.0;
 #pragma unroll
-      for (int h = 0; h < 16; h += 8) {
-        double v[kCE][8];
+      for (int h = 0; h < 16; h += kGB) {
+        double v[kCE][kGB];
 #pragma unroll
         for (int q = 0; q < kCE; ++q)
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < kGB; ++u) {
             const int g = g0 + h + u;
             const double x = gp[(int64_t)min(g, ng - 1) * RR + max(ia[q], 0) * RP + ib[q]];
             v[q][u] = x * (double)(ia[q] >= 0 && g < ng);
@@ -216,7 +240,7 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
 #pragma unroll
         for (int q = 0; q < kCE; ++q)
 #pragma unroll
-          for (int u = 0; u < 8; ++u) t[q] += v[q][u];
+          for (int u = 0; u < kGB; ++u) t[q] += v[q][u];
       }
 #pragma unroll
       for (int q = 0; q < kCE; ++q) s[q] += t[q];
@@ -230,7 +254,7 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
       }
   }
   __syncthreads();
-  spd_inverse<3>(A, r, r);  // 1024 threads x 3 >= 64 x 65 / 2
+  spd_inverse<kCE>(A, r, r);
   double* Af = p.Afac + (int64_t)blockIdx.x * RR;
   for (int e = tid; e < RR; e += blockDim.x) {
     const int a = e / RP, b = e % RP;
@@ -239,42 +263,51 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
 }
 
 
-// Partial Gram of kURows rows held in LDS (FP64, row stride kMaxRank), by a
+// Partial Gram of kURows rows held in LDS (FP64, row stride RP), by a
 // 256-thread work-group: thread (ta, tb) = (tid / 16, tid % 16) forms the
 // RT x RT block of entries (RT ta + x, RT tb + y), so each LDS read feeds RT
-// FMAs. Every entry is summed as two chains, even rows and odd rows, each in
-// row order, then added.
+// FMAs (beyond four rank tiles, the block's rows x in sweeps of two, which
+// keeps the sums within the registers). Every entry is summed as two chains,
+// even rows and odd rows, each in row order, then added.
 template <int RT>
 __device__ void gram_rows_partial(const double* ul, double* out) {
   constexpr int RP = 16 * RT;
-  const int a0 = RT * (threadIdx.x >> 4), b0 = RT * (threadIdx.x & 15);
-  double s0[RT][RT], s1[RT][RT];
+  constexpr int kXB = RT <= 4 ? RT : 2;
 #pragma unroll
-  for (int x = 0; x < RT; ++x)
+  for (int x0 = 0; x0 < RT; x0 += kXB) {
+    const int a0 = RT * (threadIdx.x >> 4) + x0, b0 = RT * (threadIdx.x & 15);
+    double s0[kXB][RT], s1[kXB][RT];
 #pragma unroll
-    for (int y = 0; y < RT; ++y) s0[x][y] = s1[x][y] = 0.0;
+    for (int x = 0; x < kXB; ++x)
+#pragma unroll
+      for (int y = 0; y < RT; ++y) s0[x][y] = s1[x][y] = 0.0;
 #pragma unroll 4
-  for (int j = 0; j < kURows; j += 2) {
-    double va0[RT], vb0[RT], va1[RT], vb1[RT];
+    for (int j = 0; j < kURows; j += 2) {
+      double va0[kXB], vb0[RT], va1[kXB], vb1[RT];
 #pragma unroll
-    for (int x = 0; x < RT; ++x) {
-      va0[x] = ul[j * kMaxRank + a0 + x];
-      vb0[x] = ul[j * kMaxRank + b0 + x];
-      va1[x] = ul[(j + 1) * kMaxRank + a0 + x];
-      vb1[x] = ul[(j + 1) * kMaxRank + b0 + x];
-    }
-#pragma unroll
-    for (int x = 0; x < RT; ++x)
+      for (int x = 0; x < kXB; ++x) {
+        va0[x] = x0 + x < RT ? ul[j * RP + a0 + x] : 0.0;
+        va1[x] = x0 + x < RT ? ul[(j + 1) * RP + a0 + x] : 0.0;
+      }
 #pragma unroll
       for (int y = 0; y < RT; ++y) {
-        s0[x][y] += va0[x] * vb0[y];
-        s1[x][y] += va1[x] * vb1[y];
+        vb0[y] = ul[j * RP + b0 + y];
+        vb1[y] = ul[(j + 1) * RP + b0 + y];
       }
+#pragma unroll
+      for (int x = 0; x < kXB; ++x)
+#pragma unroll
+        for (int y = 0; y < RT; ++y) {
+          s0[x][y] += va0[x] * vb0[y];
+          s1[x][y] += va1[x] * vb1[y];
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < kXB; ++x)
+      if (x0 + x < RT)
+#pragma unroll
+        for (int y = 0; y < RT; ++y) out[(a0 + x) * RP + b0 + y] = s0[x][y] + s1[x][y];
   }
-#pragma unroll
-  for (int x = 0; x < RT; ++x)
-#pragma unroll
-    for (int y = 0; y < RT; ++y) out[(a0 + x) * RP + b0 + y] = s0[x][y] + s1[x][y];
 }
 
 // ---------------------------------------------------------------------------
@@ -290,7 +323,7 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
                                                  int64_t uout_stride,
                                                  const float* __restrict__ Uprev, int final_step) {
   constexpr int RP = 16 * RT, NQ = RP / 4;
-  __shared__ double ul[kURows * kMaxRank];
+  __shared__ double ul[kURows * RP];
   __shared__ double dred[4];
   const int MP = p.MP, r = p.r;
   const int tid = threadIdx.x, al = tid & 63, cq = tid >> 6;
@@ -302,7 +335,7 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
   // Clients are summed in order, kUB at a time so that their loads are in
   // flight together.
-  constexpr int kUB = RT <= 2 ? 8 : 4;
+  constexpr int kUB = RT <= 2 ? 8 : RT <= 4 ? 4 : 2;
   int i = i_first;
   for (; i + kUB <= i_last; i += kUB) {
     float tv[kUB][NQ];
@@ -348,7 +381,7 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
     const float v = (a < p.m && c < r) ? (float)x : 0.f;
     fb_store(Uo, MP, RP, p.NS, a, c, v);
     if (p.bf16) hb_store(u_hb(Uo, p), MP, p, a, c, v);
-    ul[al * kMaxRank + c] = (double)v;
+    ul[al * RP + c] = (double)v;
     if (final_step) {
       const double d = (double)v - (double)uprev[q];
       dsq += d * d;
@@ -363,35 +396,32 @@ __global__ __launch_bounds__(256) void k_uupdate(DevParams p, float* __restrict_
 }
 
 // Gram partials of the consensus U (start of the run).
+template <int RT>
 __global__ __launch_bounds__(256) void k_gram_init(DevParams p, const float* __restrict__ U) {
-  __shared__ double ul[kURows * kMaxRank];
-  const int RP = p.RP;
+  constexpr int RP = 16 * RT;
+  __shared__ double ul[kURows * RP];
   for (int e = threadIdx.x; e < kURows * RP; e += blockDim.x) {
     const int al = e % kURows, c = e / kURows;
-    ul[al * kMaxRank + c] = (double)U[(int64_t)c * p.MP + blockIdx.x * kURows + al];
+    ul[al * RP + c] = (double)U[(int64_t)c * p.MP + blockIdx.x * kURows + al];
   }
   __syncthreads();
-  double* out = p.gram_part + (int64_t)blockIdx.x * RP * RP;
-  switch (RP / 16) {
-    case 1: gram_rows_partial<1>(ul, out); break;
-    case 2: gram_rows_partial<2>(ul, out); break;
-    case 3: gram_rows_partial<3>(ul, out); break;
-    default: gram_rows_partial<4>(ul, out); break;
-  }
+  gram_rows_partial<RT>(ul, p.gram_part + (int64_t)blockIdx.x * RP * RP);
 }
 
 
-// Standalone finalize: one work-group per Gram slot (grid = per_client ? E : 1).
+// Standalone finalize: one work-group per Gram slot (grid = per_client ? E : 1),
+// for ranks up to RMAX (64, or 128 for the wider ones).
+template <int RMAX>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(DevParams p, double* Ginv,
                                                           int64_t g_stride, int per_client,
                                                           int record) {
-  __shared__ double A[kMaxRank * kMaxRank];
-  __shared__ double st[6];
+  __shared__ double A[RMAX * RMAX];
+  __shared__ double st[7];
   const int gi = (int)blockIdx.x;
   fin_gram(p, gi, A);
   if (record && !per_client) fin_stats(p, st);
   __syncthreads();
-  const double tr = fin_inverse(p, A, Ginv, g_stride, gi);
+  const double tr = fin_inverse<fin_ept(RMAX)>(p, A, Ginv, g_stride, gi);
   if (threadIdx.x != 0) return;
   if (per_client)
     p.ucl_sq[gi] = tr;
@@ -499,31 +529,35 @@ __global__ void k_pack_target_V(DevParams p, const float* __restrict__ Vs, int64
   Vt[(int64_t)c * p.NVP + cl.vrow0 + j] = (j < cl.n && c < rs) ? Vs[(int64_t)c * ldvs + col0 + j] : 0.f;
 }
 
-// Partial cross-Gram matrices for ||X1 Y1^T - X2 Y2^T||_F^2. Work-groups
-// [0, kDistBlocks) sweep the X side (MP rows), [kDistBlocks, 2 kDistBlocks) the
-// Y side (NVP rows), 64 rows at a time. part[blk] holds [Z1^T Z1 | Z1^T Z2 |
-// Z2^T Z2] as 64x64 FP64 tiles; each thread keeps 48 entries in registers.
+// Partial cross-Gram matrices for ||X1 Y1^T - X2 Y2^T||_F^2 over widths up to
+// W (64, or 128 beyond). Work-groups blockIdx.x in [0, NB) sweep the X side
+// (MP rows), [NB, 2 NB) the Y side (NVP rows), 64 rows at a time; blockIdx.y
+// takes a slice of kDistSlice of the 3 W^2 entries of [Z1^T Z1 | Z1^T Z2 |
+// Z2^T Z2] (W x W FP64 each), 48 per thread in registers. part[blockIdx.x]
+// holds the 3 W^2 entries; 2 NB 3 W^2 is kDistPartDoubles at both widths.
 constexpr int kDistRows = 64;
-constexpr int kDistEntries = 3 * kMaxRank * kMaxRank;
+template <int W>
 __global__ __launch_bounds__(256) void k_dist_partial(DevParams p, const float* __restrict__ X1,
                                                       const float* __restrict__ Y1, int rp1,
                                                       const float* __restrict__ X2,
                                                       const float* __restrict__ Y2, int rp2,
                                                       double* __restrict__ part) {
-  __shared__ float z1[kDistRows][kMaxRank + 1];
-  __shared__ float z2[kDistRows][kMaxRank + 1];
-  constexpr int kPer = kDistEntries / 256;
-  const bool xside = (int)blockIdx.x < kDistBlocks;
-  const int blk = xside ? blockIdx.x : blockIdx.x - kDistBlocks;
+  constexpr int NB = dist_blocks(W), ET = 3 * W * W;
+  __shared__ float z1[kDistRows][W + 1];
+  __shared__ float z2[kDistRows][W + 1];
+  constexpr int kPer = kDistSlice / 256;
+  const bool xside = (int)blockIdx.x < NB;
+  const int blk = xside ? blockIdx.x : blockIdx.x - NB;
   const int ld = xside ? p.MP : p.NVP;
   const float* A = xside ? X1 : Y1;
   const float* B = xside ? X2 : Y2;
+  const int e0 = (int)blockIdx.y * kDistSlice;
   double acc[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
-  for (int row0 = blk * kDistRows; row0 < ld; row0 += kDistBlocks * kDistRows) {
+  for (int row0 = blk * kDistRows; row0 < ld; row0 += NB * kDistRows) {
     __syncthreads();
-    for (int e = threadIdx.x; e < kDistRows * kMaxRank; e += blockDim.x) {
+    for (int e = threadIdx.x; e < kDistRows * W; e += blockDim.x) {
       const int j = e % kDistRows, c = e / kDistRows;
       const int row = row0 + j;
       z1[j][c] = (row < ld && c < rp1) ? A[(int64_t)c * ld + row] : 0.f;
@@ -532,43 +566,46 @@ __global__ __launch_bounds__(256) void k_dist_partial(DevParams p, const float* 
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const int e = threadIdx.x + q * 256;
-      const int which = e / (kMaxRank * kMaxRank);
-      const int a = (e / kMaxRank) % kMaxRank, b = e % kMaxRank;
+      const int e = e0 + threadIdx.x + q * 256;
+      const int which = e / (W * W);
+      const int a = (e / W) % W, b = e % W;
       const int ra = which == 2 ? rp2 : rp1;
       const int rb = which == 0 ? rp1 : rp2;
       if (a < ra && b < rb) {
-        const float(*za)[kMaxRank + 1] = which == 2 ? z2 : z1;
-        const float(*zb)[kMaxRank + 1] = which == 0 ? z1 : z2;
+        const float(*za)[W + 1] = which == 2 ? z2 : z1;
+        const float(*zb)[W + 1] = which == 0 ? z1 : z2;
         double s = 0.0;
         for (int j = 0; j < kDistRows; ++j) s += (double)za[j][a] * (double)zb[j][b];
         acc[q] += s;
       }
     }
   }
-  double* o = part + (int64_t)blockIdx.x * kDistEntries;
+  double* o = part + (int64_t)blockIdx.x * ET + e0;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) o[threadIdx.x + q * 256] = acc[q];
 }
 
-// Level 1: 48 work-groups x 256 entries; each entry's X- and Y-side Grams are
-// summed over the partials and multiplied; part2[blk][which] = block sum.
+// Level 1: 3 W^2 / 256 work-groups x 256 entries; each entry's X- and Y-side
+// Grams are summed over the partials and multiplied; part2[blk] = block sum.
+template <int W>
 __global__ __launch_bounds__(256) void k_dist_reduce(const double* __restrict__ part,
                                                      double* __restrict__ part2) {
+  constexpr int NB = dist_blocks(W), ET = 3 * W * W;
   __shared__ double red[4];
   const int e = blockIdx.x * 256 + threadIdx.x;
   double gx = 0.0, gy = 0.0;
-  for (int k = 0; k < kDistBlocks; ++k) gx += part[(int64_t)k * kDistEntries + e];
-  for (int k = 0; k < kDistBlocks; ++k) gy += part[(int64_t)(kDistBlocks + k) * kDistEntries + e];
+  for (int k = 0; k < NB; ++k) gx += part[(int64_t)k * ET + e];
+  for (int k = 0; k < NB; ++k) gy += part[(int64_t)(NB + k) * ET + e];
   double t = wave_sum(gx * gy);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
   __syncthreads();
   if (threadIdx.x == 0) part2[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+template <int W>
 __global__ void k_dist_final(const double* __restrict__ part2, double* __restrict__ out2) {
   if (threadIdx.x != 0) return;
-  constexpr int per = (kMaxRank * kMaxRank) / 256;  // level-1 blocks per Gram pair
+  constexpr int per = (W * W) / 256;  // level-1 blocks per Gram pair
   double s[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < 3 * per; ++k) s[k / per] += part2[k];
   out2[0] = s[0] - 2.0 * s[1] + s[2];
@@ -584,39 +621,45 @@ static hipError_t launch_vfinal_t(const DevParams& p, const double* Ginv, int64_
 
 hipError_t launch_vfinal(const DevParams& p, const double* Ginv, int64_t g_stride, int rec,
                          hipStream_t st) {
-  return with_rank(p, [&](auto rt, auto) {
+  return with_rt(p.RP, [&](auto rt) {
     return launch_vfinal_t<decltype(rt)::value>(p, Ginv, g_stride, rec, st);
   });
 }
 
 hipError_t launch_client_factor(const DevParams& p, hipStream_t st) {
-  hipLaunchKernelGGL(k_client_factor, dim3(p.E), dim3(1024), 0, st, p);
-  return hipGetLastError();
+  return with_rt(p.RP, [&](auto rt) {
+    hipLaunchKernelGGL(k_client_factor<decltype(rt)::value>, dim3(p.E), dim3(1024), 0, st, p);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_uupdate(const DevParams& p, float* Uout, int64_t uout_stride,
                           const float* Uprev_cons, int final_step, hipStream_t st) {
   dim3 grid(p.nub, final_step ? 1 : p.E), block(256);
-  switch (p.RP / 16) {
-    case 1: hipLaunchKernelGGL(k_uupdate<1>, grid, block, 0, st, p, Uout, uout_stride, Uprev_cons, final_step); break;
-    case 2: hipLaunchKernelGGL(k_uupdate<2>, grid, block, 0, st, p, Uout, uout_stride, Uprev_cons, final_step); break;
-    case 3: hipLaunchKernelGGL(k_uupdate<3>, grid, block, 0, st, p, Uout, uout_stride, Uprev_cons, final_step); break;
-    case 4: hipLaunchKernelGGL(k_uupdate<4>, grid, block, 0, st, p, Uout, uout_stride, Uprev_cons, final_step); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return with_rt(p.RP, [&](auto rt) {
+    hipLaunchKernelGGL(k_uupdate<decltype(rt)::value>, grid, block, 0, st, p, Uout, uout_stride,
+                       Uprev_cons, final_step);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_finalize(const DevParams& p, double* Ginv, int64_t g_stride, int per_client,
                            int record, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(per_client ? p.E : 1), dim3(kFinThreads), 0, st, p, Ginv,
-                     g_stride, per_client, record);
+  const dim3 grid(per_client ? p.E : 1), block(kFinThreads);
+  if (p.RP <= kFoldMaxRP)
+    hipLaunchKernelGGL(k_finalize<kFoldMaxRP>, grid, block, 0, st, p, Ginv, g_stride, per_client,
+                       record);
+  else
+    hipLaunchKernelGGL(k_finalize<kMaxRank>, grid, block, 0, st, p, Ginv, g_stride, per_client,
+                       record);
   return hipGetLastError();
 }
 
 hipError_t launch_gram_init(const DevParams& p, const float* U, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_init, dim3(p.nub), dim3(256), 0, st, p, U);
-  return hipGetLastError();
+  return with_rt(p.RP, [&](auto rt) {
+    hipLaunchKernelGGL(k_gram_init<decltype(rt)::value>, dim3(p.nub), dim3(256), 0, st, p, U);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_copy_in_U(const DevParams& p, const float* U0, int64_t ldu, float* Ufb,
@@ -682,14 +725,25 @@ hipError_t launch_pack_target(const DevParams& p, const ClientDev* host_clients,
   return hipGetLastError();
 }
 
+template <int W>
+static hipError_t launch_distance_t(const DevParams& p, const float* X1, const float* Y1,
+                                    int rp1, const float* X2, const float* Y2, int rp2,
+                                    double* part, double* part2, double* out2, hipStream_t st) {
+  constexpr int ET = 3 * W * W;
+  hipLaunchKernelGGL(k_dist_partial<W>, dim3(2 * dist_blocks(W), ET / kDistSlice), dim3(256), 0,
+                     st, p, X1, Y1, rp1, X2, Y2, rp2, part);
+  hipLaunchKernelGGL(k_dist_reduce<W>, dim3(ET / 256), dim3(256), 0, st, part, part2);
+  hipLaunchKernelGGL(k_dist_final<W>, dim3(1), dim3(64), 0, st, part2, out2);
+  return hipGetLastError();
+}
+
 hipError_t launch_factor_distance(const DevParams& p, const float* X1, const float* Y1, int rp1,
                                   const float* X2, const float* Y2, int rp2, double* part,
                                   double* part2, double* out2, hipStream_t st) {
-  hipLaunchKernelGGL(k_dist_partial, dim3(2 * kDistBlocks), dim3(256), 0, st, p, X1, Y1, rp1, X2,
-                     Y2, rp2, part);
-  hipLaunchKernelGGL(k_dist_reduce, dim3(kDistEntries / 256), dim3(256), 0, st, part, part2);
-  hipLaunchKernelGGL(k_dist_final, dim3(1), dim3(64), 0, st, part2, out2);
-  return hipGetLastError();
+  if (rp1 < 1 || rp2 < 1 || rp1 > kMaxRank || rp2 > kMaxRank) return hipErrorInvalidValue;
+  if (rp1 <= 64 && rp2 <= 64)
+    return launch_distance_t<64>(p, X1, Y1, rp1, X2, Y2, rp2, part, part2, out2, st);
+  return launch_distance_t<kMaxRank>(p, X1, Y1, rp1, X2, Y2, rp2, part, part2, out2, st);
 }
 
 

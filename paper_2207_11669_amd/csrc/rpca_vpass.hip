@@ -32,6 +32,8 @@ static hipError_t launch_vpass_t(const DevParams& p, int mode, const float* U, i
 // The first round (S = 0) always runs one work-group per tile.
 hipError_t launch_vpass(const DevParams& p, int mode, const float* U, int64_t u_stride,
                         const float* Uold, const float* Vold, double* fin_Ginv, hipStream_t st) {
+  if (p.RP > kFoldMaxRP)
+    return fin_Ginv ? hipErrorInvalidValue : launch_vpass_wide(p, mode, U, u_stride, Uold, Vold, st);
   if (mode == kSSparse) return launch_vpass_sparse(p, U, u_stride, fin_Ginv, st);
   if (p.vqueue && mode != kSZero)
     return launch_vpass_queue(p, mode, U, u_stride, Uold, Vold, fin_Ginv, st);

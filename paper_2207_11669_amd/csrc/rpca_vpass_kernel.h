@@ -289,21 +289,30 @@ __global__ __launch_bounds__(256) void k_vpass(DevParams p, const float* __restr
   constexpr int RP = 16 * RT;
   __shared__ double pool[vpass_pool_doubles(RP)];
   float(*red)[RP] = reinterpret_cast<float(*)[RP]>(pool);
+  // Ranks above kFoldMaxRP fold no finalize (their launchers pass fin = 0).
+  constexpr bool kFold = RP <= kFoldMaxRP;
   if constexpr (!Q) {
-    if (fin && blockIdx.x < 2) {
-      finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
-      return;
+    if constexpr (kFold) {
+      if (fin && blockIdx.x < 2) {
+        finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
+        return;
+      }
     }
-    vpass_tile<RT, NS, MODE, KG>(p, Ubase, u_stride, Uold, Vold, (int)blockIdx.x - (fin ? 2 : 0),
-                                 red);
+    vpass_tile<RT, NS, MODE, KG>(p, Ubase, u_stride, Uold, Vold,
+                                 (int)blockIdx.x - (kFold && fin ? 2 : 0), red);
   } else {
-    if (fin && blockIdx.x < 2) finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
+    if constexpr (kFold)
+      if (fin && blockIdx.x < 2) finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
     const int ntiles = p.ng64 * p.vsplit;
     for (int t = queue_next(p.queue, ntiles); t < ntiles; t = queue_next(p.queue, ntiles))
       vpass_tile<RT, NS, MODE, KG>(p, Ubase, u_stride, Uold, Vold, t, red);
   }
 }
 
+// V-pass at ranks above kFoldMaxRP, every launch form (rpca_vpass_w.hip);
+// the previous round's finalize has run standalone.
+hipError_t launch_vpass_wide(const DevParams& p, int mode, const float* U, int64_t u_stride,
+                             const float* Uold, const float* Vold, hipStream_t st);
 // Persistent V-pass launches over the tile queue (rpca_vpass_q.hip).
 hipError_t launch_vpass_queue(const DevParams& p, int mode, const float* U, int64_t u_stride,
                               const float* Uold, const float* Vold, double* fin_Ginv,

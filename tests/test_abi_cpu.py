@@ -30,12 +30,20 @@ def test_parameter_validation_messages(lib):
     from paper_2207_11669_amd import make_params, params_error
     ok, _k = make_params(100, [30, 70], 5, 0.1, 0.1)
     assert params_error(ok) is None
+    # Ranks up to 128 in FP32; the mixed-precision flags up to 64.
+    for r in (64, 65, 100, 128):
+        ok, _k = make_params(100, [30, 70], r, 0.1, 0.1)
+        assert params_error(ok) is None, r
+    ok, _k = make_params(100, [30, 70], 64, 0.1, 0.1, bf16=True)
+    assert params_error(ok) is None
     cases = [
         (dict(m=0, widths=[3], r=1, rho=0.1, lam=0.1), "m must"),
         (dict(m=1 << 26, widths=[3], r=1, rho=0.1, lam=0.1), "m must"),
         (dict(m=10, widths=[3, 0], r=1, rho=0.1, lam=0.1), "n_i"),
         (dict(m=10, widths=[3], r=0, rho=0.1, lam=0.1), "r must"),
-        (dict(m=10, widths=[3], r=65, rho=0.1, lam=0.1), "r must"),
+        (dict(m=10, widths=[3], r=129, rho=0.1, lam=0.1), "r must"),
+        (dict(m=10, widths=[3], r=65, rho=0.1, lam=0.1, bf16=True), "r <= 64"),
+        (dict(m=10, widths=[3], r=65, rho=0.1, lam=0.1, bf16x3=True), "r <= 64"),
         (dict(m=10, widths=[3], r=2, rho=0.0, lam=0.1), "rho"),
         (dict(m=10, widths=[3], r=2, rho=0.1, lam=-1.0), "lambda"),
         (dict(m=10, widths=[3], r=2, rho=0.1, lam=0.1, K=0), "K must"),
