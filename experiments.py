@@ -13,9 +13,10 @@ sign. The paper leaves lambda and rho unstated; these runs use lambda =
 the section's setting where it names one (the gradient step with K local
 steps and eta0 / sqrt(t + 1), the paper's decaying rate); --u-mode closed and
 --continuation (lambda_t = max(lambda, max|M| 0.8^t)) are offered beside it.
-Ranks are limited to 64 by the library, so the rank-level grid runs at
-m = n = 320 (ranks 16 .. 64 = 0.05 n .. 0.2 n) instead of 500. Each command
-prints one JSON line.
+The library fits ranks up to 128, so the rank-level grid runs at the paper's
+m = n = 500 (ranks 25 .. 100 = 0.05 n .. 0.2 n) and the upper-bound-rank
+table up to its n = 1000 row (p = 100); its n = 5000 row (p = 500) is beyond
+that range. Each command prints one JSON line.
 """
 from __future__ import annotations
 
@@ -94,14 +95,14 @@ def phase(args) -> dict:
 def rank(args) -> dict:
     """Fit rank p = 2 r with r = 0.05 n, s = 0.05: relative singular-value
     error max_i |sigma_i(L) - sigma_i(L*)| / sigma_r(L*) over i <= p (the
-    paper's table of relative singular value errors). Fits above rank 64 are
-    outside the library's range."""
+    paper's table of relative singular value errors). Fits above rank 128
+    are outside the library's range."""
     rows = []
     for n in args.sizes:
         r = round(0.05 * n)
         p = 2 * r
-        if p > 64:
-            rows.append({"n": n, "r": r, "p": p, "skipped": "p > 64"})
+        if p > 128:
+            rows.append({"n": n, "r": r, "p": p, "skipped": "p > 128"})
             continue
         inst = _instance(n, r, 0.05, args.clients, seed=n)
         t0 = time.perf_counter()
@@ -266,7 +267,7 @@ def main() -> int:
         p.add_argument("--rounds", type=int, default=rounds)
         p.add_argument("--continuation", action="store_true")
     a = sub.add_parser("phase")
-    a.add_argument("--n", type=int, default=320)
+    a.add_argument("--n", type=int, default=500)
     a.add_argument("--clients", type=int, default=5)
     solver_args(a, 2, 0.05, 200)
     b = sub.add_parser("rank")
