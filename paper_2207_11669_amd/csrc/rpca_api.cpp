@@ -77,7 +77,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t S, Smask, Sval, U0, U1, Uc0, Uc1, V0, V1, Mbv, Mbs, Wpart, P, gv, Af, gram, spart, upart,
+  size_t S, Smask, Sval, U0, U1, Uc0, Uc1, V0, V1, Mbv, Mbs, Wpart, P, gv, gvtr, Af, gram, spart, upart,
       ucl, Ginv, dstate, hist, stat_part, clients, clients_lpt, vgroups, vg64, Uprev, Vprev, Ut, Vt, dpart, dpart2, dout,
       queue, total;
   int32_t MP, RP, NS, NVP, nrb, nub, ngroups, ng64, vsplit, vsplit_rows, vsplit_max, RK;
@@ -212,6 +212,7 @@ Layout make_layout(const rpca_params* p) {
   L.Wpart = take((size_t)(L.vsplit_max + 1) * L.NVP * L.RP * f);
   L.P = take((size_t)E * L.RP * L.MP * f);
   L.gv = take((size_t)L.ngroups * RR * d);
+  L.gvtr = take((size_t)L.ngroups * d);
   L.Af = take((size_t)E * RR * d);
   L.gram = take((size_t)(multi ? E : 1) * L.nub * RR * d);
   L.spart = take((size_t)E * L.nrb * 4 * d);
@@ -545,6 +546,7 @@ rpca_status rpca_init(rpca_ctx** out, const rpca_params* prm, const float* const
   p.Wpart = reinterpret_cast<float*>(ws + L.Wpart);
   p.P = reinterpret_cast<float*>(ws + L.P);
   p.gv_part = reinterpret_cast<double*>(ws + L.gv);
+  p.gv_tr = reinterpret_cast<double*>(ws + L.gvtr);
   p.Afac = reinterpret_cast<double*>(ws + L.Af);
   p.gram_part = reinterpret_cast<double*>(ws + L.gram);
   p.spart = reinterpret_cast<double*>(ws + L.spart);

@@ -203,14 +203,20 @@ __device__ __forceinline__ double recip_pos(double x) {
 // i >= k, -x_i for i < k. The threads owning the next step's cross publish it
 // during this step into a second LDS vector (double-buffered by step parity),
 // so each step costs one barrier. Each thread owns up to EPT lower-triangle
-// entries, indexed once. A pivot that is not positive (non-SPD or NaN input)
-// turns the result into NaN, which the round statistics then expose.
-template <int EPT>
+// entries, indexed once and held in registers through the sweep (no other
+// thread reads or writes them; the LDS carries the cross vector only), then
+// written back with the mirror. A pivot that is not positive (non-SPD or NaN
+// input) turns the result into NaN, which the round statistics then expose.
+// BATCH: a step's cross reads all go out before the pivot's reciprocal (the
+// default up to four entries per thread; the standalone kernels at ranks
+// above 64 ask for it with nine). Same values either way.
+template <int EPT, bool BATCH = (EPT <= 4)>
 __device__ void spd_inverse(double* A, int r, int ld) {
   __shared__ double xb[2][kMaxRank];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int nl = r * (r + 1) / 2;
   int ei[EPT], ej[EPT];
+  double a[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int e = tid + q * nt;
@@ -223,23 +229,24 @@ __device__ void spd_inverse(double* A, int r, int ld) {
     }
     ei[q] = i;
     ej[q] = j;
+    a[q] = i >= 0 ? A[i * ld + j] : 0.0;
   }
   if (tid < r) xb[0][tid] = A[tid * ld];
   __syncthreads();
   for (int k = 0; k < r; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
     const double pv = xb[cur][k];
-    if constexpr (EPT <= 4) {
-      // The step's LDS reads go out together, before the pivot's reciprocal;
-      // the three cases are then selects. (With many entries per thread the
-      // held reads would cost more registers than the latency they save.)
-      double xi[EPT], xj[EPT], aa[EPT];
+    if constexpr (BATCH) {
+      // The step's cross reads go out together, before the pivot's
+      // reciprocal; the three cases are then selects. (With many entries per
+      // thread in the folded finalize the held reads would cost more
+      // registers than the latency they save.)
+      double xi[EPT], xj[EPT];
 #pragma unroll
       for (int q = 0; q < EPT; ++q)
         if (ei[q] >= 0) {
           xi[q] = xb[cur][ei[q]];
           xj[q] = xb[cur][ej[q]];
-          aa[q] = A[ei[q] * ld + ej[q]];
         }
       const double pinv = pv > 0.0 ? recip_pos(pv) : NAN;
 #pragma unroll
@@ -247,10 +254,10 @@ __device__ void spd_inverse(double* A, int r, int ld) {
         const int i = ei[q], j = ej[q];
         if (i >= 0) {
           const double ci = i < k ? -xi[q] : xi[q];
-          double v = aa[q] - ci * xj[q] * pinv;
+          double v = a[q] - ci * xj[q] * pinv;
           v = j == k ? -xi[q] * pinv : v;
           v = i == k ? (j == k ? pinv : xj[q] * pinv) : v;
-          A[i * ld + j] = v;
+          a[q] = v;
           if (i == k + 1) xb[nxt][j] = v;
           if (j == k + 1) xb[nxt][i] = v;
         }
@@ -268,9 +275,9 @@ __device__ void spd_inverse(double* A, int r, int ld) {
             v = -xb[cur][i] * pinv;
           else {
             const double ci = i < k ? -xb[cur][i] : xb[cur][i];
-            v = A[i * ld + j] - ci * xb[cur][j] * pinv;
+            v = a[q] - ci * xb[cur][j] * pinv;
           }
-          A[i * ld + j] = v;
+          a[q] = v;
           if (i == k + 1) xb[nxt][j] = v;
           if (j == k + 1) xb[nxt][i] = v;
         }
@@ -280,7 +287,10 @@ __device__ void spd_inverse(double* A, int r, int ld) {
   }
 #pragma unroll
   for (int q = 0; q < EPT; ++q)
-    if (ei[q] > ej[q]) A[ej[q] * ld + ei[q]] = A[ei[q] * ld + ej[q]];
+    if (ei[q] >= 0) {
+      A[ei[q] * ld + ej[q]] = a[q];
+      if (ei[q] > ej[q]) A[ej[q] * ld + ei[q]] = a[q];
+    }
   __syncthreads();
 }
 
@@ -515,18 +525,14 @@ static __device__ void fin_gram(const DevParams& p, int gi, double* A) {
 // the target lambda (rounds at another lambda only).
 static __device__ void fin_stats(const DevParams& p, double* out) {
   __shared__ double red[kFinThreads / 64][6];
-  const int tid = threadIdx.x, r = p.r, RP = p.RP;
-  const int64_t RR = (int64_t)RP * RP;
+  const int tid = threadIdx.x;
   if (tid < kFinThreads) {
     const int nsp = p.E * p.nrb;
     double l2 = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 0]; }, kFinThreads);
     double l1 = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 1]; }, kFinThreads);
     double nz = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 2]; }, kFinThreads);
     double hb = block_strided_sum(nsp, [&](int k) { return p.spart[(int64_t)k * 4 + 3]; }, kFinThreads);
-    double vsq = block_strided_sum(p.ngroups * r, [&](int k) {
-      const int g = k / r, d = k - g * r;
-      return p.gv_part[(int64_t)g * RR + d * RP + d];
-    }, kFinThreads);
+    double vsq = block_strided_sum(p.ngroups, [&](int k) { return p.gv_tr[k]; }, kFinThreads);
     double du = block_strided_sum(p.nub, [&](int k) { return p.upart[k]; }, kFinThreads);
     l2 = wave_sum(l2);
     l1 = wave_sum(l1);
@@ -566,7 +572,7 @@ static __device__ void fin_stats(const DevParams& p, double* out) {
 
 // G^{-1} of the Gram in LDS A (adds rho I) into Ginv slot gi; returns
 // tr(U^T U) (valid in every thread).
-template <int EPT>
+template <int EPT, bool BATCH = (EPT <= 4)>
 static __device__ double fin_inverse(const DevParams& p, double* A, double* Ginv, int64_t g_stride, int gi) {
   __shared__ double tr_sh;
   const int tid = threadIdx.x, r = p.r, RP = p.RP;
@@ -579,7 +585,7 @@ static __device__ double fin_inverse(const DevParams& p, double* A, double* Ginv
   __syncthreads();
   for (int k = tid; k < r; k += blockDim.x) A[k * r + k] += p.rho;
   __syncthreads();
-  spd_inverse<EPT>(A, r, r);
+  spd_inverse<EPT, BATCH>(A, r, r);
   double* Gout = Ginv + (int64_t)gi * g_stride;
   for (int e = tid; e < RR; e += blockDim.x) {
     const int a = e / RP, b = e % RP;

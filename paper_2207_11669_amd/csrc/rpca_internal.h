@@ -184,6 +184,7 @@ struct DevParams {
   float* Wpart;          // V-pass partial W per row split, [vsplit][NVP][RP]
   float* P;              // per-client U-step term T_i, column-major MP x RP
   double* gv_part;       // per V-finalize group partial V^T V, RP x RP
+  double* gv_tr;         // per V-finalize group trace of its partial V^T V
   double* Afac;          // per-client (V_i^T V_i + c_i I)^{-1}, RP x RP
   double* gram_part;     // per (client,) U row block partial U^T U, RP x RP
   double* spart;         // per S-pass work-group: sums of Lambda^2, |S|, nnz(S)

@@ -8,7 +8,7 @@ namespace rpca {
 // V-pass, finalize: one work-group per 32 columns. W = sum of the row-split
 // partials (fixed order, FP64), V = W (U^T U + rho I)^{-1} (eq. "condition1"),
 // rounded to FP32 once and written in both layouts, plus the partial V^T V of
-// these columns.
+// these columns and its trace (the group's share of ||V||_F^2).
 // ---------------------------------------------------------------------------
 template <int RT>
 __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __restrict__ Gbase,
@@ -136,9 +136,12 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
   // forms the RT x RT block of entries (RT ta + x, RT tb + y), each a sum over
   // the 32 columns in order (each LDS read feeds RT FMAs).
   // (Beyond four rank tiles the block's rows go in sweeps of four, which
-  // keeps its sums within the registers; same sums.)
+  // keeps its sums within the registers; same sums.) The threads on the
+  // diagonal (ta = tb) add their diagonal entries in rank order for the trace.
   double* gv = p.gv_part + (int64_t)blockIdx.x * RP * RP;
   constexpr int kXB = RT <= 4 ? RT : 4;
+  const bool on_diag = (tid >> 4) == (tid & 15);
+  double dtr = 0.0;
 #pragma unroll
   for (int x0 = 0; x0 < RT; x0 += kXB) {
     const int a0 = RT * (tid >> 4) + x0, b0 = RT * (tid & 15);
@@ -161,9 +164,19 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
     }
 #pragma unroll
     for (int x = 0; x < kXB; ++x)
-      if (x0 + x < RT)
+      if (x0 + x < RT) {
 #pragma unroll
         for (int y = 0; y < RT; ++y) gv[(a0 + x) * RP + b0 + y] = sg[x][y];
+        if (on_diag) dtr += sg[x][x0 + x];
+      }
+  }
+  __shared__ double trs[16];
+  if (on_diag) trs[tid >> 4] = dtr;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += trs[k];
+    p.gv_tr[blockIdx.x] = t;
   }
 }
 
@@ -174,12 +187,14 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
 // epilogue applies as U_i + (P - c_i U_i) A_i.) One work-group per client;
 // FP64 throughout.
 // ---------------------------------------------------------------------------
+// Threads of a client-factor work-group.
+constexpr int cf_threads(int) { return 1024; }
 template <int RT>
-__global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
-  constexpr int RP = 16 * RT;
+__global__ __launch_bounds__(cf_threads(RT)) void k_client_factor(DevParams p) {
+  constexpr int RP = 16 * RT, NT = cf_threads(RT);
   // Lower-triangle entries per thread: three up to r = 64 (1024 x 3 >= 64 x
   // 65 / 2), nine at r = 128.
-  constexpr int kCE = RT <= 4 ? 3 : (RP * (RP + 1) / 2 + 1023) / 1024;
+  constexpr int kCE = RT <= 4 ? 3 : (RP * (RP + 1) / 2 + NT - 1) / NT;
   __shared__ double A[RP * RP];
   const int r = p.r;
   const int64_t RR = (int64_t)RP * RP;
@@ -207,7 +222,7 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
     double s[kCE];
 #pragma unroll
     for (int q = 0; q < kCE; ++q) {
-      const int e = tid + q * 1024;
+      const int e = tid + q * NT;
       int a = -1, b = 0;
       if (e < nl) {
         a = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
@@ -219,9 +234,9 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
       ib[q] = b;
       s[q] = 0.0;
     }
-    // (Beyond four rank tiles, with three times the entries per thread, 2
-    // groups at a time: same sums.)
-    constexpr int kGB = RT <= 4 ? 8 : 2;
+    // (Beyond four rank tiles, with up to three times the entries per
+    // thread, one group at a time: same sums.)
+    constexpr int kGB = RT <= 4 ? 8 : 1;
     for (int g0 = 0; g0 < ng; g0 += 16) {
       double t[kCE];
 #pragma unroll
@@ -254,7 +269,7 @@ __global__ __launch_bounds__(1024) void k_client_factor(DevParams p) {
       }
   }
   __syncthreads();
-  spd_inverse<kCE>(A, r, r);
+  spd_inverse<kCE, true>(A, r, r);
   double* Af = p.Afac + (int64_t)blockIdx.x * RR;
   for (int e = tid; e < RR; e += blockDim.x) {
     const int a = e / RP, b = e % RP;
@@ -409,19 +424,41 @@ __global__ __launch_bounds__(256) void k_gram_init(DevParams p, const float* __r
 }
 
 
-// Standalone finalize: one work-group per Gram slot (grid = per_client ? E : 1),
-// for ranks up to RMAX (64, or 128 for the wider ones).
-template <int RMAX>
-__global__ __launch_bounds__(kFinThreads) void k_finalize(DevParams p, double* Ginv,
-                                                          int64_t g_stride, int per_client,
-                                                          int record) {
+// Gram sums for the finalize at ranks above kFoldMaxRP: entry e < r^2 of
+// slot blockIdx.y over the slot's row-block partials, in the order fin_gram
+// sums them, into Ginv slot blockIdx.y (row stride r), which the finalize
+// then reads and overwrites with the inverse. Spread over r^2 / 256
+// work-groups per slot: the sums read nub r^2 doubles (16 MB at m = 8000,
+// r = 128), which the finalize's one work-group would read at the latency
+// of a single compute unit.
+__global__ __launch_bounds__(256) void k_gram_sum(DevParams p, double* Ginv, int64_t g_stride) {
+  const int gi = (int)blockIdx.y, e = (int)blockIdx.x * 256 + (int)threadIdx.x, r = p.r;
+  if (e >= r * r) return;
+  const int a = e / r, b = e - a * r;
+  const int64_t RR = (int64_t)p.RP * p.RP;
+  Ginv[(int64_t)gi * g_stride + e] =
+      sum_strided(p.gram_part + (int64_t)gi * p.nub * RR + a * p.RP + b, p.nub, RR);
+}
+
+// Standalone finalize: one work-group of NT threads per Gram slot (grid =
+// per_client ? E : 1), for ranks up to RMAX: 64 (Gram summed here), or 128
+// (Gram summed by k_gram_sum into the slot; 1024 threads share the sweep).
+template <int RMAX, int NT>
+__global__ __launch_bounds__(NT) void k_finalize(DevParams p, double* Ginv, int64_t g_stride,
+                                                 int per_client, int record) {
   __shared__ double A[RMAX * RMAX];
   __shared__ double st[7];
   const int gi = (int)blockIdx.x;
-  fin_gram(p, gi, A);
+  if constexpr (RMAX > kFoldMaxRP) {
+    const double* g = Ginv + (int64_t)gi * g_stride;
+    for (int e = threadIdx.x; e < p.r * p.r; e += NT) A[e] = g[e];
+  } else {
+    fin_gram(p, gi, A);
+  }
   if (record && !per_client) fin_stats(p, st);
   __syncthreads();
-  const double tr = fin_inverse<fin_ept(RMAX)>(p, A, Ginv, g_stride, gi);
+  constexpr int kEPT = (RMAX * (RMAX + 1) / 2 + NT - 1) / NT;
+  const double tr = fin_inverse<kEPT, (RMAX > kFoldMaxRP || kEPT <= 4)>(p, A, Ginv, g_stride, gi);
   if (threadIdx.x != 0) return;
   if (per_client)
     p.ucl_sq[gi] = tr;
@@ -628,7 +665,8 @@ hipError_t launch_vfinal(const DevParams& p, const double* Ginv, int64_t g_strid
 
 hipError_t launch_client_factor(const DevParams& p, hipStream_t st) {
   return with_rt(p.RP, [&](auto rt) {
-    hipLaunchKernelGGL(k_client_factor<decltype(rt)::value>, dim3(p.E), dim3(1024), 0, st, p);
+    constexpr int RT = decltype(rt)::value;
+    hipLaunchKernelGGL(k_client_factor<RT>, dim3(p.E), dim3(cf_threads(RT)), 0, st, p);
     return hipGetLastError();
   });
 }
@@ -645,13 +683,16 @@ hipError_t launch_uupdate(const DevParams& p, float* Uout, int64_t uout_stride,
 
 hipError_t launch_finalize(const DevParams& p, double* Ginv, int64_t g_stride, int per_client,
                            int record, hipStream_t st) {
-  const dim3 grid(per_client ? p.E : 1), block(kFinThreads);
-  if (p.RP <= kFoldMaxRP)
-    hipLaunchKernelGGL(k_finalize<kFoldMaxRP>, grid, block, 0, st, p, Ginv, g_stride, per_client,
-                       record);
-  else
-    hipLaunchKernelGGL(k_finalize<kMaxRank>, grid, block, 0, st, p, Ginv, g_stride, per_client,
-                       record);
+  const int slots = per_client ? p.E : 1;
+  if (p.RP <= kFoldMaxRP) {
+    hipLaunchKernelGGL((k_finalize<kFoldMaxRP, kFinThreads>), dim3(slots), dim3(kFinThreads), 0,
+                       st, p, Ginv, g_stride, per_client, record);
+  } else {
+    hipLaunchKernelGGL(k_gram_sum, dim3((p.r * p.r + 255) / 256, slots), dim3(256), 0, st, p,
+                       Ginv, g_stride);
+    hipLaunchKernelGGL((k_finalize<kMaxRank, 1024>), dim3(slots), dim3(1024), 0, st, p, Ginv,
+                       g_stride, per_client, record);
+  }
   return hipGetLastError();
 }
 
