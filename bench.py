@@ -26,6 +26,10 @@ shape the autotuner picked on a context of its own.
 The FP64 CPU oracle is timed on bounded samples of both workloads, on all the
 host's cores and on one.
 
+--rank fits another rank than the workload's (up to 128; the BF16 legs need
+64 or less), for the upper-bound rank setting of Section 4.2; the line then
+names the fitted rank and reads the byte counters of that fit.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -195,7 +199,9 @@ def continuation(lam: float, lam0: float, gamma: float = 0.8) -> list:
 def measure(M_cols, inst, r, rho, lam, U0_cols, args, precision: str, workload: str) -> dict:
     """Rounds/s of one precision on a resident instance: warm-up rounds, the
     autotuner, then `steps` rounds between HIP events on the library's stream,
-    and per-kernel HIP events over `profile_rounds` more rounds."""
+    and per-kernel HIP events over `profile_rounds` more rounds. `workload`
+    names the counter file (the workload, with the fitted rank when it is
+    not the workload's)."""
     import torch
 
     from paper_2207_11669_amd import DCFPCA
@@ -443,6 +449,8 @@ def main() -> int:
     ap.add_argument("--workload", default=WORKLOAD, choices=WORKLOADS,
                     help="workload of the timed rounds (default: the 20000 x 100000, r = 64 "
                          "geometric-spectrum workload)")
+    ap.add_argument("--rank", type=int, default=0,
+                    help="fitted rank r instead of the workload's (1 .. 128)")
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--u-mode", default="closed", choices=["closed", "grad"])
@@ -490,7 +498,9 @@ def main() -> int:
 
     workload = args.workload
     cfg = RECIPES[workload]
-    r, rho = cfg["r"], cfg["rho"]
+    r, rho = (args.rank or cfg["r"]), cfg["rho"]
+    # Counters of a fit at another rank live in a file of their own.
+    tag = workload if r == cfg["r"] else f"{workload}_fit{r}"
     log(f"generating {workload}")
     inst = recipe(workload, seed=0)
     lam = 1.0 / math.sqrt(inst.n)
@@ -501,12 +511,12 @@ def main() -> int:
     U0_cols = colmajor(U0, device=dev)
     torch.cuda.synchronize()
 
-    head = measure(M_cols, inst, r, rho, lam, U0_cols, args, args.precision, workload)
+    head = measure(M_cols, inst, r, rho, lam, U0_cols, args, args.precision, tag)
     mixed = None
-    if not args.no_mixed and args.precision == "fp32":
+    if not args.no_mixed and args.precision == "fp32" and r <= 64:
         mixed = {}
         for prec in ("bf16", "bf16x3"):
-            mixed[prec] = measure(M_cols, inst, r, rho, lam, U0_cols, args, prec, workload)
+            mixed[prec] = measure(M_cols, inst, r, rho, lam, U0_cols, args, prec, tag)
             mixed[prec]["speedup_vs_fp32"] = round(mixed[prec]["iters_per_s"] /
                                                    head["iters_per_s"], 3)
             log(f"{prec}: error against the FP64 oracle on the 2000 x 2000 sub-instance")
