@@ -442,6 +442,39 @@ def copy_calibration() -> int:
     return 0
 
 
+def hbm_ceiling() -> int:
+    """What plain streaming kernels of the runtime reach on this GPU, as a
+    practical HBM ceiling beside the 8 TB/s peak: torch's device copy (read
+    and write), sum (read) and fill (write) of 4 GiB, each timed over 10
+    launches with HIP events after one untimed launch."""
+    import torch
+    n = 1 << 30
+    x = torch.empty(n, dtype=torch.float32, device="cuda:0").normal_()
+    y = torch.empty_like(x)
+    z = torch.empty((), dtype=torch.float32, device="cuda:0")
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps / 1e3
+
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: y.copy_(x), 8 * n),
+                             ("sum", lambda: torch.sum(x, dim=0, out=z), 4 * n),
+                             ("fill", lambda: x.fill_(1.0), 4 * n)):
+        sec = timed(fn)
+        out[name] = {"bytes": nbytes, "ms": round(sec * 1e3, 4),
+                     "GB_per_s": round(nbytes / sec / 1e9, 1)}
+    print(json.dumps({"hbm_ceiling": out}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -482,9 +515,14 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device three times (a kernel of known "
                          "traffic, to scale hardware byte counters) and exit")
+    ap.add_argument("--hbm-ceiling", action="store_true",
+                    help="time torch's copy, sum and fill of 4 GiB (a practical HBM ceiling) "
+                         "and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
+    if args.hbm_ceiling:
+        return hbm_ceiling()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the DCF-PCA path here runs every client on a "
