@@ -232,10 +232,27 @@ __device__ void spd_inverse(double* A, int r, int ld) {
     a[q] = i >= 0 ? A[i * ld + j] : 0.0;
   }
   if (tid < r) xb[0][tid] = A[tid * ld];
+  // Slots q with an entry in some lane of this wave: tid0 + q nt < nl.
+  const int tid0 = __builtin_amdgcn_readfirstlane(tid & ~63);
+  const int wq = nl > tid0 ? (nl - tid0 + nt - 1) / nt : 0;
   __syncthreads();
   for (int k = 0; k < r; ++k) {
     const int cur = k & 1, nxt = cur ^ 1;
     const double pv = xb[cur][k];
+    // A lane's slot without an entry (ei = ej = -1) reads the cross at 0 and
+    // never matches a pivot or a publication index, so no per-lane entry test
+    // is needed before the write-back; slots past the wave's last entry
+    // (wave-uniform) are skipped.
+    auto update = [&](int q, double xi, double xj, double pinv) {
+      const int i = ei[q], j = ej[q];
+      const double ci = i < k ? -xi : xi;
+      double v = a[q] - ci * xj * pinv;
+      v = j == k ? -xi * pinv : v;
+      v = i == k ? (j == k ? pinv : xj * pinv) : v;
+      a[q] = v;
+      if (i == k + 1) xb[nxt][j] = v;
+      if (j == k + 1) xb[nxt][i] = v;
+    };
     if constexpr (BATCH) {
       // The step's cross reads go out together, before the pivot's
       // reciprocal; the three cases are then selects. (With many entries per
@@ -244,44 +261,19 @@ __device__ void spd_inverse(double* A, int r, int ld) {
       double xi[EPT], xj[EPT];
 #pragma unroll
       for (int q = 0; q < EPT; ++q)
-        if (ei[q] >= 0) {
-          xi[q] = xb[cur][ei[q]];
-          xj[q] = xb[cur][ej[q]];
+        if (q < wq) {
+          xi[q] = xb[cur][max(ei[q], 0)];
+          xj[q] = xb[cur][max(ej[q], 0)];
         }
       const double pinv = pv > 0.0 ? recip_pos(pv) : NAN;
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int i = ei[q], j = ej[q];
-        if (i >= 0) {
-          const double ci = i < k ? -xi[q] : xi[q];
-          double v = a[q] - ci * xj[q] * pinv;
-          v = j == k ? -xi[q] * pinv : v;
-          v = i == k ? (j == k ? pinv : xj[q] * pinv) : v;
-          a[q] = v;
-          if (i == k + 1) xb[nxt][j] = v;
-          if (j == k + 1) xb[nxt][i] = v;
-        }
-      }
+      for (int q = 0; q < EPT; ++q)
+        if (q < wq) update(q, xi[q], xj[q], pinv);
     } else {
       const double pinv = pv > 0.0 ? recip_pos(pv) : NAN;
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int i = ei[q], j = ej[q];
-        if (i >= 0) {
-          double v;
-          if (i == k)
-            v = (j == k) ? pinv : xb[cur][j] * pinv;
-          else if (j == k)
-            v = -xb[cur][i] * pinv;
-          else {
-            const double ci = i < k ? -xb[cur][i] : xb[cur][i];
-            v = a[q] - ci * xb[cur][j] * pinv;
-          }
-          a[q] = v;
-          if (i == k + 1) xb[nxt][j] = v;
-          if (j == k + 1) xb[nxt][i] = v;
-        }
-      }
+      for (int q = 0; q < EPT; ++q)
+        if (q < wq) update(q, xb[cur][max(ei[q], 0)], xb[cur][max(ej[q], 0)], pinv);
     }
     __syncthreads();
   }
