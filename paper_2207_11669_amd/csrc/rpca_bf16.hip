@@ -142,7 +142,9 @@ __device__ __forceinline__ void vpass_h_tile(const DevParams& p, const float* __
   struct OpB {
     bf8 u[RT], ul[X3 ? RT : 1];          // U, hB (hi, lo)
   };
-  constexpr int kDepth = 2;
+  // Three-product rounds up to three rank tiles keep M three chunks ahead
+  // (the registers allow it at two waves per SIMD).
+  constexpr int kDepth = X3 && RT <= 3 ? 3 : 2;
   MChunk ring[kDepth];
   OpA oa;
   OpB ob;
@@ -255,8 +257,11 @@ __device__ __forceinline__ void vpass_h_tile(const DevParams& p, const float* __
     load_a(oa, 0);
     load_b(ob, 0);
     __builtin_amdgcn_sched_barrier(0);
-    load_m(ring[1], min(1, nk - 1));
-    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int d = 1; d < kDepth; ++d) {
+      load_m(ring[d], min(d, nk - 1));
+      __builtin_amdgcn_sched_barrier(0);
+    }
     for (int k0 = 0; k0 < nkp; k0 += kDepth) {
 #pragma unroll
       for (int d = 0; d < kDepth; ++d) {
