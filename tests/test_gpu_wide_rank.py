@@ -203,3 +203,64 @@ def test_wide_rank_target_error(r, rstar):
     announce(f"r={r} rstar={rstar}: target error {got:.9e} vs FP64 {want:.9e}")
     assert abs(got - want) <= 1e-9 * want
     s.close()
+
+
+def test_wide_rank_schedule_stored_s_and_copy():
+    """Rank 100: a lambda continuation with the sparse S handoff (rounds after
+    a lambda change rebuild S) against the oracle run with the same schedule,
+    each round's objective included; stored S (RPCA_FLAG_STORE_S) bitwise equal
+    to rebuilt S; and rpca_copy_state mid-run continuing bitwise."""
+    import math
+
+    import torch
+
+    from paper_2207_11669_amd import DCFPCA, colmajor
+    inst = planted_instance(400, [150, 130, 120], 10, 0.08, values="signed", lo=5.0, hi=20.0,
+                            seed=97)
+    r = 100
+    lam = float(np.float32(1.0 / math.sqrt(inst.n)))
+    U0 = init_for(inst, r, 8)
+    lam0 = float(np.abs(inst.M).max())
+    sched = [max(lam, lam0 * 0.8 ** t) for t in range(30)] + [lam] * 6
+    s = DCFPCA(colmajor(inst.M), inst.widths, inst.m, r, 0.1, lam, colmajor(U0), sparse_s=True)
+    for lt in sched:
+        s.set_lambda(lt)
+        s.step(1)
+    L, S = s.get_LS(-1)
+    torch.cuda.synchronize()
+    Lg = L[:, :inst.m].T.double().cpu().numpy()
+    Sg = S[:, :inst.m].T.double().cpu().numpy()
+    res = O.dcfpca(inst.blocks(), r, 0.1, lam, len(sched), U0, lam_schedule=sched)
+    eL, eS = rel(Lg, res.L_full()), rel(Sg, res.S_full())
+    hist = [s.stats(t) for t in range(len(sched))]
+    ef = max(abs(g["objective"] - o["objective"]) / abs(o["objective"])
+             for g, o in zip(hist, res.history))
+    announce(f"r={r} continuation with sparse S: relL={eL:.3e} relS={eS:.3e} "
+             f"max objective rel={ef:.3e}")
+    assert eL <= TOL and eS <= TOL and ef <= TOL
+    s.close()
+
+    lam_d = default_lam(inst)
+    _, L1, S1, _ = run_gpu(inst, U0, r, 0.1, lam_d, 12)
+    _, L2, S2, _ = run_gpu(inst, U0, r, 0.1, lam_d, 12, store_s=True)
+    same = np.array_equal(L1, L2) and np.array_equal(S1, S2)
+    announce(f"r={r} rebuilt vs stored S: bitwise={same}")
+    assert same
+
+    a = DCFPCA(colmajor(inst.M), inst.widths, inst.m, r, 0.1, lam_d, colmajor(U0), sparse_s=True)
+    b = DCFPCA(colmajor(inst.M), inst.widths, inst.m, r, 0.1, lam_d, colmajor(U0), sparse_s=True)
+    a.step(5)
+    b.copy_state_from(a)
+    a.step(4)
+    b.step(4)
+    snaps = []
+    for x in (a, b):
+        L, S = x.get_LS(-1)
+        torch.cuda.synchronize()
+        snaps.append((L.cpu().numpy(), S.cpu().numpy(), x.stats()))
+    a.close()
+    b.close()
+    same = (np.array_equal(snaps[0][0], snaps[1][0]) and np.array_equal(snaps[0][1], snaps[1][1])
+            and snaps[0][2] == snaps[1][2])
+    announce(f"r={r} copy_state mid-run: bitwise={same}")
+    assert same
