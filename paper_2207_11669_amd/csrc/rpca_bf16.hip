@@ -340,12 +340,20 @@ __device__ __forceinline__ rsrc_t uniform_rsrc(const void* base, uint32_t bytes)
                    __builtin_amdgcn_readfirstlane(bytes));
 }
 
+// Tiles per work-group of the staged V-pass: kVTiles consecutive 64-column
+// tiles over the same rows (clients may differ; the U operands are the same),
+// so that each wave streams kVTiles column groups of M against one copy of a
+// chunk's U operands.
+constexpr int kVTiles = 2;
+__host__ __device__ inline int vpass_h3_groups(int ng64) { return (ng64 + kVTiles - 1) / kVTiles; }
+
 template <int RT, int NK, int MODE>
 __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* __restrict__ Ubase,
                                               const float* __restrict__ Uold,
                                               const float* __restrict__ Vold, int tile,
                                               float (*red)[16 * RT], void* stage_mem) {
   constexpr int RP = 16 * RT;
+  constexpr int KT = kVTiles;
   constexpr bool kA = MODE == kSRecompute;
   constexpr int kUA = kA ? 4 * NK : 0;   // 1 KiB units of the previous U (hP hi, hP lo)
   constexpr int kUnits = vpass_h3_units<RT, NK, MODE>();  // and of U (hB hi, hB lo)
@@ -353,37 +361,56 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
   constexpr int kStage = vpass_h3_stage_bytes<RT, NK, MODE>();
   static_assert(kStage == 4 * kPerWave * 1024, "one padded unit per wave and copy");
   constexpr int kD = kLdsStages - 1;     // chunks ahead (M ring depth)
-  const int gx = tile % p.ng64, gy = tile / p.ng64;
-  const VTile vt = p.vg64[gx];
-  const ClientDev& cl = vt.cl;
+  const int ngr = vpass_h3_groups(p.ng64);
+  const int gx0 = (tile % ngr) * KT, gy = tile / ngr;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int jw = vt.j0 + 16 * w;  // this wave's column group
   const float lam = p.lam;
   const int MP = p.MP;
+  // Tile t of the group (past the last tile: the last again, reading 0 and
+  // writing nothing); wave w takes its column group w.
+  bool valid[KT];
+  int jw[KT];
+  const ClientDev* clp[KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    valid[t] = gx0 + t < p.ng64;
+    const VTile& vt = p.vg64[min(gx0 + t, p.ng64 - 1)];
+    clp[t] = &vt.cl;
+    jw[t] = vt.j0 + 16 * w;
+  }
 
   const int64_t uhl = hb_elems(MP, p.RK, p.RP) / 8, vhl = hb_elems(p.NVP, p.RK, p.RP) / 8;
   const GLOBAL bf8* UhB = reinterpret_cast<const GLOBAL bf8*>(gptr(u_hb(Ubase, p))) +
                           2 * (int64_t)MP * p.RK / 8;
   const GLOBAL bf8* UohP = reinterpret_cast<const GLOBAL bf8*>(gptr(u_hb(Uold, p))) +
                            (int64_t)MP * p.RK / 8;
-  bf8 vb[NK], vbl[NK];  // S rebuild B operand (hi, lo): Vo[col][rank 32 kb + 8 (l/16) + e]
+  bf8 vb[KT][NK], vbl[KT][NK];  // S rebuild B operand (hi, lo): Vo[col][rank 32 kb + 8 (l/16) + e]
   if (kA) {
     const GLOBAL bf8* VohA = reinterpret_cast<const GLOBAL bf8*>(gptr(v_hb(Vold, p)));
-    const int vch = (cl.vrow0 + jw) >> 4;
 #pragma unroll
-    for (int kb = 0; kb < NK; ++kb) {
-      vb[kb] = VohA[((int64_t)vch * NK + kb) * 64 + lane];
-      vbl[kb] = VohA[vhl + ((int64_t)vch * NK + kb) * 64 + lane];
+    for (int t = 0; t < KT; ++t) {
+      const int vch = (clp[t]->vrow0 + jw[t]) >> 4;
+#pragma unroll
+      for (int kb = 0; kb < NK; ++kb) {
+        vb[t][kb] = VohA[((int64_t)vch * NK + kb) * 64 + lane];
+        vbl[t][kb] = VohA[vhl + ((int64_t)vch * NK + kb) * 64 + lane];
+      }
     }
   }
   const int rbeg = gy * p.vsplit_rows;
   const int rend = min(p.m, rbeg + p.vsplit_rows);
   const int ch0 = rbeg >> 5;
   const int nk = (rend - rbeg + 31) >> 5;  // chunks of the row split (the same for every wave)
-  const rsrc_t rM =
-      uniform_rsrc(cl.M + (int64_t)min(jw, cl.n) * cl.ldm, block_bytes_from(cl.n, jw, cl.ldm));
-  const uint32_t vM = (uint32_t)(li * cl.ldm) * 4u;
+  rsrc_t rM[KT];
+  uint32_t vM[KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const ClientDev& cl = *clp[t];
+    rM[t] = uniform_rsrc(cl.M + (int64_t)min(jw[t], cl.n) * cl.ldm,
+                         valid[t] ? block_bytes_from(cl.n, jw[t], cl.ldm) : 0u);
+    vM[t] = (uint32_t)(li * cl.ldm) * 4u;
+  }
 
   // The units this wave copies (u = w, w + 4, ...): source of chunk 0 and
   // the stride between chunks, in 16-byte elements. Unit u of a stage is
@@ -422,64 +449,77 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
       __builtin_amdgcn_global_load_lds((GLOBAL void*)(src[i] + (int64_t)ch * cstr[i]),
                                        (lds_void*)(st + (w + 4 * i) * 1024), 16, 0, 0);
   };
-  f4 ring[kD][2];  // M rows 32 ch + 8 (l/16) + e of column jw + l%16, FP32
-  auto load_m = [&](f4* c, int k) {
+  f4 ring[kD][KT][2];  // M rows 32 ch + 8 (l/16) + e of column jw[t] + l%16, FP32
+  auto load_m = [&](f4 (*c)[2], int k) {
     const int ch = ch0 + min(k, nk - 1);
     const uint32_t rowb = (uint32_t)(32 * ch + 8 * lg) * 4u;
-    c[0] = bload4(rM, vM + rowb, 0);
-    c[1] = bload4(rM, vM + rowb + 16u, 0);
-  };
-  f4 acc[RT];
 #pragma unroll
-  for (int ct = 0; ct < RT; ++ct) acc[ct] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < KT; ++t) {
+      c[t][0] = bload4(rM[t], vM[t] + rowb, 0);
+      c[t][1] = bload4(rM[t], vM[t] + rowb + 16u, 0);
+    }
+  };
+  f4 acc[KT][RT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t)
+#pragma unroll
+    for (int ct = 0; ct < RT; ++ct) acc[t][ct] = f4{0.f, 0.f, 0.f, 0.f};
 
-  auto chunk = [&](const f4* c, int k) {
+  auto chunk = [&](const f4 (*c)[2], int k) {
     const uint32_t sa = stage_lds + (uint32_t)((k % kLdsStages) * kStage);
-    f4 o[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+    f4 o[KT][2];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) o[t][0] = o[t][1] = f4{0.f, 0.f, 0.f, 0.f};
     if constexpr (kA) {
       // (Uo Vo^T) rows 8 (l/16) + e of the wave's column, two 16x16 halves.
       u4 a[4 * NK];
       lds_read_1k<4 * NK>(a, sa);
 #pragma unroll
-      for (int kb = 0; kb < NK; ++kb)
+      for (int t = 0; t < KT; ++t)
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
-          o[t] = mfma3(__builtin_bit_cast(bf8, a[t * NK + kb]),
-                       __builtin_bit_cast(bf8, a[2 * NK + t * NK + kb]), vb[kb], vbl[kb], o[t]);
+        for (int kb = 0; kb < NK; ++kb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            o[t][h] = mfma3(__builtin_bit_cast(bf8, a[h * NK + kb]),
+                            __builtin_bit_cast(bf8, a[2 * NK + h * NK + kb]), vb[t][kb], vbl[t][kb],
+                            o[t][h]);
     }
     u4 b[2 * RT];
     lds_read_1k<2 * RT>(b, sa + kUA * 1024);
     const int row0 = 32 * (ch0 + k) + 8 * lg;
     const bool tail = 32 * (ch0 + k) + 32 > p.m;  // wave-uniform
-    float x[8], d[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) x[e] = c[e >> 2][e & 3];
-    if (tail) {
+    for (int t = 0; t < KT; ++t) {
+      float x[8], d[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) x[e] = row0 + e < p.m ? x[e] : 0.f;
-    }
+      for (int e = 0; e < 8; ++e) x[e] = c[t][e >> 2][e & 3];
+      if (tail) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if constexpr (kA) {
-        const float a1 = o[e >> 2][e & 3];
-        // M - S = Uo Vo^T + clip(M - Uo Vo^T, -lambda, lambda)
-        d[e] = a1 + __builtin_amdgcn_fmed3f(x[e] - a1, -lam, lam);
-      } else {
-        d[e] = x[e];
+        for (int e = 0; e < 8; ++e) x[e] = row0 + e < p.m ? x[e] : 0.f;
       }
-    }
-    bf8 dh, dl;
-    split8(d, dh, dl);
 #pragma unroll
-    for (int ct = 0; ct < RT; ++ct)
-      acc[ct] = mfma3(dh, dl, __builtin_bit_cast(bf8, b[ct]), __builtin_bit_cast(bf8, b[RT + ct]),
-                      acc[ct]);
+      for (int e = 0; e < 8; ++e) {
+        if constexpr (kA) {
+          const float a1 = o[t][e >> 2][e & 3];
+          // M - S = Uo Vo^T + clip(M - Uo Vo^T, -lambda, lambda)
+          d[e] = a1 + __builtin_amdgcn_fmed3f(x[e] - a1, -lam, lam);
+        } else {
+          d[e] = x[e];
+        }
+      }
+      bf8 dh, dl;
+      split8(d, dh, dl);
+#pragma unroll
+      for (int ct = 0; ct < RT; ++ct)
+        acc[t][ct] = mfma3(dh, dl, __builtin_bit_cast(bf8, b[ct]),
+                           __builtin_bit_cast(bf8, b[RT + ct]), acc[t][ct]);
+    }
   };
 
   // Groups of loads: chunk g's copies, then its M loads; groups are issued
   // in chunk order, so at chunk k the kD - 1 newer groups may stay in
   // flight. Every wave runs the same count of iterations and barriers.
-  constexpr int kInFlight = (kD - 1) * (kPerWave + 2);
+  constexpr int kInFlight = (kD - 1) * (kPerWave + 2 * KT);
 #pragma unroll
   for (int g = 0; g < kD; ++g) {
     copy_u(g);
@@ -502,15 +542,25 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  // Drain the copies of the chunks past the end before the LDS is reused.
+  // Drain the copies of the chunks past the end before the LDS is reused;
+  // then each tile's partial W (red: KT blocks of kVStreamCols x RP).
   __syncthreads();
 #pragma unroll
-  for (int ct = 0; ct < RT; ++ct)
+  for (int t = 0; t < KT; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[16 * w + 4 * lg + v][16 * ct + li] = acc[ct][v];
+    for (int ct = 0; ct < RT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        red[kVStreamCols * t + 16 * w + 4 * lg + v][16 * ct + li] = acc[t][ct][v];
   __syncthreads();
-  GLOBAL float* wp = gptr_w(p.Wpart) + ((int64_t)gy * p.NVP + cl.vrow0 + vt.j0) * RP;
-  for (int e = tid; e < kVStreamCols * RP; e += blockDim.x) wp[e] = red[e / RP][e % RP];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    if (!valid[t]) continue;  // work-group-uniform
+    const VTile& vt = p.vg64[gx0 + t];
+    GLOBAL float* wp = gptr_w(p.Wpart) + ((int64_t)gy * p.NVP + vt.cl.vrow0 + vt.j0) * RP;
+    for (int e = tid; e < kVStreamCols * RP; e += blockDim.x)
+      wp[e] = red[kVStreamCols * t + e / RP][e % RP];
+  }
 }
 
 // Work-group roles and tiles as in k_vpass (Q: persistent launch over the
@@ -524,6 +574,7 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
   constexpr int RP = 16 * RT;
   constexpr int kPool = vpass_pool_doubles(RP);
   constexpr int kStaged = X3 ? kLdsStages * vpass_h3_stage_bytes<RT, NK, MODE>() / 8 : 0;
+  static_assert(!X3 || kVTiles * kVStreamCols * RP / 2 <= kStaged, "the staging block holds every tile's W");
   __shared__ double pool[kPool > kStaged ? kPool : kStaged];
   float(*red)[RP] = reinterpret_cast<float(*)[RP]>(pool);
   auto run = [&](int t) {
@@ -540,7 +591,7 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
     run((int)blockIdx.x - (fin ? 2 : 0));
   } else {
     if (fin && blockIdx.x < 2) finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
-    const int ntiles = p.ng64 * p.vsplit;
+    const int ntiles = (X3 ? vpass_h3_groups(p.ng64) : p.ng64) * p.vsplit;
     for (int t = queue_next(p.queue, ntiles); t < ntiles; t = queue_next(p.queue, ntiles)) run(t);
   }
 }
@@ -1105,8 +1156,9 @@ static hipError_t launch_vpass_h_t(const DevParams& p, int mode, const float* U,
                                    const float* Vold, double* fin_Ginv, int x3, hipStream_t st) {
   constexpr int NK = (RT + 1) / 2;
   const int fin = fin_Ginv ? 1 : 0;
-  const int ntiles = p.ng64 * p.vsplit;
-  // The first round (S = 0) always runs one work-group per tile.
+  // Three-product rounds: one work-group per kVTiles tiles over the same rows.
+  const int ntiles = (x3 ? vpass_h3_groups(p.ng64) : p.ng64) * p.vsplit;
+  // The first round (S = 0) always runs one work-group per tile (group).
   auto go = [&](auto m, auto x) {
     constexpr int kMode = decltype(m)::value;
     constexpr bool kX3 = decltype(x)::value;
