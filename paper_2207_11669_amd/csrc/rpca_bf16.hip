@@ -246,16 +246,17 @@ __device__ __forceinline__ void vpass_h_tile(const DevParams& p, const float* __
 // copies and 4NK + 2RT 16-byte LDS reads.
 // ---------------------------------------------------------------------------
 constexpr int kLdsStages = 4;
-// 1 KiB units of a chunk's U operands: the previous U's hP hi and lo
-// halves (S rebuild only), then U's hB hi and lo; and the bytes of one stage,
-// the units rounded up to a multiple of the four waves.
-template <int RT, int NK, int MODE>
+// 1 KiB units of a chunk's U operands: the previous U's hP halves (S rebuild
+// only; hi, then lo in three-product rounds), then U's hB (hi, then lo); and
+// the bytes of one stage, the units rounded up to a multiple of the four
+// waves.
+template <int RT, int NK, int MODE, bool X3>
 constexpr int vpass_h3_units() {
-  return (MODE == kSRecompute ? 4 * NK : 0) + 2 * RT;
+  return ((MODE == kSRecompute ? 2 * NK : 0) + RT) * (X3 ? 2 : 1);
 }
-template <int RT, int NK, int MODE>
+template <int RT, int NK, int MODE, bool X3>
 constexpr int vpass_h3_stage_bytes() {
-  return (vpass_h3_units<RT, NK, MODE>() + 3) / 4 * 4 * 1024;
+  return (vpass_h3_units<RT, NK, MODE, X3>() + 3) / 4 * 4 * 1024;
 }
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -267,6 +268,26 @@ __device__ __forceinline__ uint32_t lds_addr(void* p) {
 // LDS copies of later chunks in front of them.
 template <int N>
 __device__ __forceinline__ void lds_read_1k(u4* o, uint32_t a);
+template <>
+__device__ __forceinline__ void lds_read_1k<1>(u4* o, uint32_t a) {
+  asm volatile(
+      "ds_read_b128 %0, %1\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(o[0])
+      : "v"(a)
+      : "memory");
+}
+template <>
+__device__ __forceinline__ void lds_read_1k<3>(u4* o, uint32_t a) {
+  asm volatile(
+      "ds_read_b128 %0, %3\n\t"
+      "ds_read_b128 %1, %3 offset:1024\n\t"
+      "ds_read_b128 %2, %3 offset:2048\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2])
+      : "v"(a)
+      : "memory");
+}
 template <>
 __device__ __forceinline__ void lds_read_1k<2>(u4* o, uint32_t a) {
   asm volatile(
@@ -340,28 +361,32 @@ __device__ __forceinline__ rsrc_t uniform_rsrc(const void* base, uint32_t bytes)
                    __builtin_amdgcn_readfirstlane(bytes));
 }
 
-// Tiles per work-group of the staged V-pass: kVTiles consecutive 64-column
-// tiles over the same rows (clients may differ; the U operands are the same),
-// so that each wave streams kVTiles column groups of M against one copy of a
-// chunk's U operands.
-constexpr int kVTiles = 2;
-__host__ __device__ inline int vpass_h3_groups(int ng64) { return (ng64 + kVTiles - 1) / kVTiles; }
+// Tiles per work-group of the staged V-pass: vtiles(X3) consecutive
+// 64-column tiles over the same rows (clients may differ; the U operands are
+// the same), so that each wave streams that many column groups of M against
+// one copy of a chunk's U operands: two in three-product rounds (FP32 M, hi
+// and lo operands), four in one-product rounds (the BF16 copy of M).
+__host__ __device__ constexpr int vtiles(bool x3) { return x3 ? 2 : 4; }
+__host__ __device__ inline int vpass_h3_groups(int ng64, bool x3) {
+  return (ng64 + vtiles(x3) - 1) / vtiles(x3);
+}
 
-template <int RT, int NK, int MODE>
+template <int RT, int NK, int MODE, bool X3>
 __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* __restrict__ Ubase,
                                               const float* __restrict__ Uold,
                                               const float* __restrict__ Vold, int tile,
                                               float (*red)[16 * RT], void* stage_mem) {
   constexpr int RP = 16 * RT;
-  constexpr int KT = kVTiles;
+  constexpr int KT = vtiles(X3);
+  constexpr int kX = X3 ? 2 : 1;          // hi, and lo in three-product rounds
   constexpr bool kA = MODE == kSRecompute;
-  constexpr int kUA = kA ? 4 * NK : 0;   // 1 KiB units of the previous U (hP hi, hP lo)
-  constexpr int kUnits = vpass_h3_units<RT, NK, MODE>();  // and of U (hB hi, hB lo)
+  constexpr int kUA = kA ? 2 * NK * kX : 0;  // 1 KiB units of the previous U (hP)
+  constexpr int kUnits = vpass_h3_units<RT, NK, MODE, X3>();  // and of U (hB)
   constexpr int kPerWave = (kUnits + 3) / 4;
-  constexpr int kStage = vpass_h3_stage_bytes<RT, NK, MODE>();
+  constexpr int kStage = vpass_h3_stage_bytes<RT, NK, MODE, X3>();
   static_assert(kStage == 4 * kPerWave * 1024, "one padded unit per wave and copy");
   constexpr int kD = kLdsStages - 1;     // chunks ahead (M ring depth)
-  const int ngr = vpass_h3_groups(p.ng64);
+  const int ngr = vpass_h3_groups(p.ng64, X3);
   const int gx0 = (tile % ngr) * KT, gy = tile / ngr;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -385,7 +410,8 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
                           2 * (int64_t)MP * p.RK / 8;
   const GLOBAL bf8* UohP = reinterpret_cast<const GLOBAL bf8*>(gptr(u_hb(Uold, p))) +
                            (int64_t)MP * p.RK / 8;
-  bf8 vb[KT][NK], vbl[KT][NK];  // S rebuild B operand (hi, lo): Vo[col][rank 32 kb + 8 (l/16) + e]
+  // S rebuild B operand (hi, lo): Vo[col][rank 32 kb + 8 (l/16) + e]
+  bf8 vb[KT][NK], vbl[X3 ? KT : 1][NK];
   if (kA) {
     const GLOBAL bf8* VohA = reinterpret_cast<const GLOBAL bf8*>(gptr(v_hb(Vold, p)));
 #pragma unroll
@@ -394,7 +420,7 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
 #pragma unroll
       for (int kb = 0; kb < NK; ++kb) {
         vb[t][kb] = VohA[((int64_t)vch * NK + kb) * 64 + lane];
-        vbl[t][kb] = VohA[vhl + ((int64_t)vch * NK + kb) * 64 + lane];
+        if constexpr (X3) vbl[t][kb] = VohA[vhl + ((int64_t)vch * NK + kb) * 64 + lane];
       }
     }
   }
@@ -402,14 +428,25 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
   const int rend = min(p.m, rbeg + p.vsplit_rows);
   const int ch0 = rbeg >> 5;
   const int nk = (rend - rbeg + 31) >> 5;  // chunks of the row split (the same for every wave)
-  rsrc_t rM[KT];
-  uint32_t vM[KT];
+  // M: (X3) the caller's FP32 block through one buffer resource per tile
+  // (columns past n_i, and every column of a tile past the last, read 0;
+  // rows past m are masked in the last chunk), or the V-pass BF16 copy, one
+  // 16-byte load per lane (zero past m and n_i; a tile past the last reads
+  // the last tile's and its W is not written).
+  rsrc_t rM[X3 ? KT : 1];
+  uint32_t vM[X3 ? KT : 1];
+  const GLOBAL u4* Mv[X3 ? 1 : KT];
 #pragma unroll
   for (int t = 0; t < KT; ++t) {
     const ClientDev& cl = *clp[t];
-    rM[t] = uniform_rsrc(cl.M + (int64_t)min(jw[t], cl.n) * cl.ldm,
-                         valid[t] ? block_bytes_from(cl.n, jw[t], cl.ldm) : 0u);
-    vM[t] = (uint32_t)(li * cl.ldm) * 4u;
+    if constexpr (X3) {
+      rM[t] = uniform_rsrc(cl.M + (int64_t)min(jw[t], cl.n) * cl.ldm,
+                           valid[t] ? block_bytes_from(cl.n, jw[t], cl.ldm) : 0u);
+      vM[t] = (uint32_t)(li * cl.ldm) * 4u;
+    } else {
+      Mv[t] = reinterpret_cast<const GLOBAL u4*>(gptr(p.Mbv)) + (int64_t)cl.vrow0 * MP / 8 +
+              (int64_t)(jw[t] >> 4) * (MP >> 5) * 64 + lane;
+    }
   }
 
   // The units this wave copies (u = w, w + 4, ...): source of chunk 0 and
@@ -426,7 +463,7 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
     if (kA && u < 2 * NK) {
       src[i] = UohP + u * 64 + lane;
       cstr[i] = 2 * NK * 64;
-    } else if (kA && u < 4 * NK) {
+    } else if (kA && u < kUA) {
       src[i] = UohP + uhl + (u - 2 * NK) * 64 + lane;
       cstr[i] = 2 * NK * 64;
     } else if (u < kUA + RT) {
@@ -449,14 +486,21 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
       __builtin_amdgcn_global_load_lds((GLOBAL void*)(src[i] + (int64_t)ch * cstr[i]),
                                        (lds_void*)(st + (w + 4 * i) * 1024), 16, 0, 0);
   };
-  f4 ring[kD][KT][2];  // M rows 32 ch + 8 (l/16) + e of column jw[t] + l%16, FP32
-  auto load_m = [&](f4 (*c)[2], int k) {
+  // M rows 32 ch + 8 (l/16) + e of column jw[t] + l%16: FP32 (X3, two
+  // 16-byte loads) or BF16 (one).
+  u4 ring[kD][KT][kX];
+  auto load_m = [&](u4 (*c)[kX], int k) {
     const int ch = ch0 + min(k, nk - 1);
-    const uint32_t rowb = (uint32_t)(32 * ch + 8 * lg) * 4u;
+    if constexpr (X3) {
+      const uint32_t rowb = (uint32_t)(32 * ch + 8 * lg) * 4u;
 #pragma unroll
-    for (int t = 0; t < KT; ++t) {
-      c[t][0] = bload4(rM[t], vM[t] + rowb, 0);
-      c[t][1] = bload4(rM[t], vM[t] + rowb + 16u, 0);
+      for (int t = 0; t < KT; ++t) {
+        c[t][0] = __builtin_bit_cast(u4, bload4(rM[t], vM[t] + rowb, 0));
+        c[t][kX - 1] = __builtin_bit_cast(u4, bload4(rM[t], vM[t] + rowb + 16u, 0));
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < KT; ++t) c[t][0] = Mv[t][(int64_t)ch * 64];
     }
   };
   f4 acc[KT][RT];
@@ -465,34 +509,46 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
 #pragma unroll
     for (int ct = 0; ct < RT; ++ct) acc[t][ct] = f4{0.f, 0.f, 0.f, 0.f};
 
-  auto chunk = [&](const f4 (*c)[2], int k) {
+  auto chunk = [&](const u4 (*c)[kX], int k) {
     const uint32_t sa = stage_lds + (uint32_t)((k % kLdsStages) * kStage);
     f4 o[KT][2];
 #pragma unroll
     for (int t = 0; t < KT; ++t) o[t][0] = o[t][1] = f4{0.f, 0.f, 0.f, 0.f};
     if constexpr (kA) {
       // (Uo Vo^T) rows 8 (l/16) + e of the wave's column, two 16x16 halves.
-      u4 a[4 * NK];
-      lds_read_1k<4 * NK>(a, sa);
+      u4 a[kUA];
+      lds_read_1k<kUA>(a, sa);
 #pragma unroll
       for (int t = 0; t < KT; ++t)
 #pragma unroll
         for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
-          for (int h = 0; h < 2; ++h)
-            o[t][h] = mfma3(__builtin_bit_cast(bf8, a[h * NK + kb]),
-                            __builtin_bit_cast(bf8, a[2 * NK + h * NK + kb]), vb[t][kb], vbl[t][kb],
-                            o[t][h]);
+          for (int h = 0; h < 2; ++h) {
+            const bf8 ah = __builtin_bit_cast(bf8, a[h * NK + kb]);
+            if constexpr (X3)
+              o[t][h] = mfma3(ah, __builtin_bit_cast(bf8, a[2 * NK + h * NK + kb]), vb[t][kb],
+                              vbl[t][kb], o[t][h]);
+            else
+              o[t][h] = mfma_bf16(ah, vb[t][kb], o[t][h]);
+          }
     }
-    u4 b[2 * RT];
-    lds_read_1k<2 * RT>(b, sa + kUA * 1024);
+    u4 b[RT * kX];
+    lds_read_1k<RT * kX>(b, sa + kUA * 1024);
     const int row0 = 32 * (ch0 + k) + 8 * lg;
-    const bool tail = 32 * (ch0 + k) + 32 > p.m;  // wave-uniform
+    const bool tail = X3 && 32 * (ch0 + k) + 32 > p.m;  // wave-uniform
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
       float x[8], d[8];
+      if constexpr (X3) {
+        const f4 m0 = __builtin_bit_cast(f4, c[t][0]), m1 = __builtin_bit_cast(f4, c[t][kX - 1]);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) x[e] = c[t][e >> 2][e & 3];
+        for (int e = 0; e < 4; ++e) {
+          x[e] = m0[e];
+          x[4 + e] = m1[e];
+        }
+      } else {
+        unpack8(c[t][0], x);
+      }
       if (tail) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = row0 + e < p.m ? x[e] : 0.f;
@@ -507,19 +563,26 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
           d[e] = x[e];
         }
       }
-      bf8 dh, dl;
-      split8(d, dh, dl);
+      if constexpr (X3) {
+        bf8 dh, dl;
+        split8(d, dh, dl);
 #pragma unroll
-      for (int ct = 0; ct < RT; ++ct)
-        acc[t][ct] = mfma3(dh, dl, __builtin_bit_cast(bf8, b[ct]),
-                           __builtin_bit_cast(bf8, b[RT + ct]), acc[t][ct]);
+        for (int ct = 0; ct < RT; ++ct)
+          acc[t][ct] = mfma3(dh, dl, __builtin_bit_cast(bf8, b[ct]),
+                             __builtin_bit_cast(bf8, b[RT + ct]), acc[t][ct]);
+      } else {
+        const bf8 dh = pack8(d);
+#pragma unroll
+        for (int ct = 0; ct < RT; ++ct)
+          acc[t][ct] = mfma_bf16(dh, __builtin_bit_cast(bf8, b[ct]), acc[t][ct]);
+      }
     }
   };
 
   // Groups of loads: chunk g's copies, then its M loads; groups are issued
   // in chunk order, so at chunk k the kD - 1 newer groups may stay in
   // flight. Every wave runs the same count of iterations and barriers.
-  constexpr int kInFlight = (kD - 1) * (kPerWave + 2 * KT);
+  constexpr int kInFlight = (kD - 1) * (kPerWave + kX * KT);
 #pragma unroll
   for (int g = 0; g < kD; ++g) {
     copy_u(g);
@@ -564,22 +627,26 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
 }
 
 // Work-group roles and tiles as in k_vpass (Q: persistent launch over the
-// tile queue).
-template <int RT, int NK, int MODE, bool X3, bool Q>
+// tile queue). ST: the U operands staged in LDS (vpass_h3_tile; always in
+// three-product rounds, picked by the column-group knob = 1 in one-product
+// rounds), else the one-product register form (vpass_h_tile).
+template <int RT, int NK, int MODE, bool X3, bool Q, bool ST>
 __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __restrict__ Ubase,
                                                  const float* __restrict__ Uold,
                                                  const float* __restrict__ Vold,
                                                  double* __restrict__ fin_Ginv, int fin) {
+  static_assert(ST || !X3, "three-product rounds run the staged form");
   // One LDS pool for both roles (sized for this rank, not the largest).
   constexpr int RP = 16 * RT;
   constexpr int kPool = vpass_pool_doubles(RP);
-  constexpr int kStaged = X3 ? kLdsStages * vpass_h3_stage_bytes<RT, NK, MODE>() / 8 : 0;
-  static_assert(!X3 || kVTiles * kVStreamCols * RP / 2 <= kStaged, "the staging block holds every tile's W");
+  constexpr int kStages = ST ? kLdsStages * vpass_h3_stage_bytes<RT, NK, MODE, X3>() / 8 : 0;
+  constexpr int kRed = ST ? vtiles(X3) * kVStreamCols * RP / 2 : 0;  // every tile's W
+  constexpr int kStaged = kStages > kRed ? kStages : kRed;
   __shared__ double pool[kPool > kStaged ? kPool : kStaged];
   float(*red)[RP] = reinterpret_cast<float(*)[RP]>(pool);
   auto run = [&](int t) {
-    if constexpr (X3)
-      vpass_h3_tile<RT, NK, MODE>(p, Ubase, Uold, Vold, t, red, pool);
+    if constexpr (ST)
+      vpass_h3_tile<RT, NK, MODE, X3>(p, Ubase, Uold, Vold, t, red, pool);
     else
       vpass_h_tile<RT, NK, MODE>(p, Ubase, Uold, Vold, t, red);
   };
@@ -591,7 +658,7 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
     run((int)blockIdx.x - (fin ? 2 : 0));
   } else {
     if (fin && blockIdx.x < 2) finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
-    const int ntiles = (X3 ? vpass_h3_groups(p.ng64) : p.ng64) * p.vsplit;
+    const int ntiles = (ST ? vpass_h3_groups(p.ng64, X3) : p.ng64) * p.vsplit;
     for (int t = queue_next(p.queue, ntiles); t < ntiles; t = queue_next(p.queue, ntiles)) run(t);
   }
 }
@@ -1156,30 +1223,34 @@ static hipError_t launch_vpass_h_t(const DevParams& p, int mode, const float* U,
                                    const float* Vold, double* fin_Ginv, int x3, hipStream_t st) {
   constexpr int NK = (RT + 1) / 2;
   const int fin = fin_Ginv ? 1 : 0;
-  // Three-product rounds: one work-group per kVTiles tiles over the same rows.
-  const int ntiles = (x3 ? vpass_h3_groups(p.ng64) : p.ng64) * p.vsplit;
+  // The staged form: one work-group per vtiles tiles over the same rows.
+  const bool staged = x3 || p.vcols == 1;
+  const int ntiles = (staged ? vpass_h3_groups(p.ng64, x3 != 0) : p.ng64) * p.vsplit;
   // The first round (S = 0) always runs one work-group per tile (group).
-  auto go = [&](auto m, auto x) {
+  auto go = [&](auto m, auto x, auto sg) {
     constexpr int kMode = decltype(m)::value;
-    constexpr bool kX3 = decltype(x)::value;
+    constexpr bool kX3 = decltype(x)::value, kST = decltype(sg)::value;
     if (kMode == kSRecompute && p.vqueue) {
-      auto kernel = k_vpass_h<RT, NK, kSRecompute, kX3, true>;
+      auto kernel = k_vpass_h<RT, NK, kSRecompute, kX3, true, kST>;
       const int groups = pass_groups(kernel, 256, ntiles, 1);
       hipLaunchKernelGGL(kernel, dim3((unsigned)(groups + 2 * fin)), dim3(256), 0, st, p, U, Uold,
                          Vold, fin_Ginv, fin);
     } else {
-      hipLaunchKernelGGL((k_vpass_h<RT, NK, kMode, kX3, false>), dim3((unsigned)(ntiles + 2 * fin)),
-                         dim3(256), 0, st, p, U, Uold, Vold, fin_Ginv, fin);
+      hipLaunchKernelGGL((k_vpass_h<RT, NK, kMode, kX3, false, kST>),
+                         dim3((unsigned)(ntiles + 2 * fin)), dim3(256), 0, st, p, U, Uold, Vold,
+                         fin_Ginv, fin);
     }
   };
   using Z = std::integral_constant<int, kSZero>;
   using R = std::integral_constant<int, kSRecompute>;
   using F = std::false_type;
   using T = std::true_type;
-  if (mode == kSRecompute)
-    x3 ? go(R{}, T{}) : go(R{}, F{});
+  if (x3)
+    mode == kSRecompute ? go(R{}, T{}, T{}) : go(Z{}, T{}, T{});
+  else if (staged)
+    mode == kSRecompute ? go(R{}, F{}, T{}) : go(Z{}, F{}, T{});
   else
-    x3 ? go(Z{}, T{}) : go(Z{}, F{});
+    mode == kSRecompute ? go(R{}, F{}, F{}) : go(Z{}, F{}, F{});
   return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@
 #include "rpca_internal.h"
 
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 namespace rpca {
@@ -689,20 +690,33 @@ __device__ __forceinline__ f4 mfma3(bf8 ah, bf8 al, bf8 bh, bf8 bl, f4 c) {
 
 // Work-groups of `kernel` (block threads, no dynamic LDS) that are resident
 // on the current device at once, for the grid of a persistent launch; kept
-// per device after the first query (0 if the runtime cannot tell).
+// per kernel and device after the first query (0 if the runtime cannot
+// tell). Kernels of one signature differ in their register and LDS use, so
+// the cache is keyed by the kernel's address, not its type.
 template <class K>
 static int resident_groups(K kernel, int block) {
-  constexpr int kDevs = 64;
-  static int cache[kDevs] = {};
+  struct Entry {
+    const void* k;
+    int dev, block, groups;
+  };
+  constexpr int kSlots = 256;
+  static Entry cache[kSlots];
+  static int used = 0;
+  static std::mutex mu;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
-  if (dev < kDevs && cache[dev] > 0) return cache[dev];
+  const void* kp = reinterpret_cast<const void*>(kernel);
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < used; ++i)
+      if (cache[i].k == kp && cache[i].dev == dev && cache[i].block == block) return cache[i].groups;
+  }
   int cus = 0, nb = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kernel), block,
-                                                    0) != hipSuccess)
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kp, block, 0) != hipSuccess)
     return 0;
-  if (dev < kDevs) cache[dev] = nb * cus;
+  std::lock_guard<std::mutex> lock(mu);
+  if (used < kSlots) cache[used++] = Entry{kp, dev, block, nb * cus};
   return nb * cus;
 }
 

@@ -109,6 +109,34 @@ def test_narrow_client_closed_step(r, widths):
     assert hL <= BF16_TOL and hS <= BF16_TOL
 
 
+@pytest.mark.parametrize("r", [20, 40, 64])
+def test_bf16_vpass_forms_follow_oracle(r):
+    """One-product BF16 rounds with either V-pass form -- the U operands in
+    each wave's registers (column groups 4) or staged in LDS with four
+    64-column tiles per work-group (column groups 1) -- on ragged m (301),
+    clients of 1-3 tiles and a last work-group with two tiles stay within 5u
+    of the FP64 trajectory after 20 rounds; the staged form gives the same
+    bits from one work-group per tile group and from the tile queue."""
+    import torch
+    inst = planted_instance(301, [70, 190, 130, 96], 4, 0.05, values="uniform", lo=5.0, hi=10.0,
+                            seed=29)
+    U0 = init_for(inst, r, 7)
+    lam, T = 0.1, 20
+    res = run_oracle(inst, U0, r, 0.1, lam, T)
+    out = {}
+    for cg, vq in ((4, 0), (1, 0), (1, 1)):
+        s, Lg, Sg, _ = run_gpu(inst, U0, r, 0.1, lam, T, bf16=True,
+                               shape=dict(column_groups=cg, vpass_queue=vq))
+        out[(cg, vq)] = (Lg, Sg)
+        eL, eS = rel(Lg, res.L_full()), rel(Sg, res.S_full())
+        announce(f"bf16 r={r} column_groups={cg} vpass_queue={vq}: relL={eL:.3e} relS={eS:.3e}")
+        assert eL <= BF16_TOL and eS <= BF16_TOL
+        del s
+        torch.cuda.synchronize()
+    assert np.array_equal(out[(1, 0)][0], out[(1, 1)][0])
+    assert np.array_equal(out[(1, 0)][1], out[(1, 1)][1])
+
+
 def test_bf16_deterministic_and_switchable():
     """BF16 rounds are bitwise reproducible; precision can go BF16 -> FP32 ->
     BF16; a context created without the flag refuses BF16."""
