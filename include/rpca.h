@@ -286,7 +286,12 @@ typedef struct rpca_launch_shape {
   int32_t vsplit;
   /* 16-column groups per FP32 V-pass wave: 1 (waves on distinct columns share
    * U operands through the cache) or 4 (a wave takes all 64 columns of its
-   * tile, the waves splitting the rows); 1 only for r > 64 */
+   * tile, the waves splitting the rows); 1 only for r > 64. In BF16 rounds
+   * it picks the V-pass form: 4, the U operands in each wave's registers
+   * (waves split the rows of a 64-column tile); 1, a work-group takes four
+   * 64-column tiles over the same rows and copies a chunk's U operands into
+   * LDS once for its four waves. Three-product rounds always run the LDS
+   * form (two tiles per work-group). */
   int32_t vcols;
   /* FP32 S-pass column phases: 2 (work-groups of 8 waves, two per 32-row
    * strip taking alternate 16-column chunks, their partial P summed at the
