@@ -295,7 +295,11 @@ typedef struct rpca_launch_shape {
   int32_t vcols;
   /* FP32 S-pass column phases: 2 (work-groups of 8 waves, two per 32-row
    * strip taking alternate 16-column chunks, their partial P summed at the
-   * end) or 1 (4 waves, one per strip); 1 only for r > 64 */
+   * end) or 1 (4 waves, one per strip); 1 only for r > 64. In BF16 rounds it
+   * picks the S-pass form: 2, the V operands in each wave's registers (waves
+   * of 64 rows, two column phases); 1, four waves of 32 rows over the same
+   * chunks, which copy a chunk's V operands into LDS once. Three-product
+   * rounds always run the LDS form. */
   int32_t sphases;
   /* Launch forms of the V-pass and the S-pass: 0, one work-group per tile
    * (a 64-column group by row split, or a 128-row block of a client); 1, a
@@ -317,8 +321,8 @@ typedef struct rpca_launch_shape {
  * most the workspace holds (the work-group count decides how full the last
  * wave of work-groups runs), each with 1 and 4 column groups, at the current
  * S-pass shape. Then,
- * when the rounds run in FP32, the S-pass at the chosen V-pass shape: two
- * column phases and one. Then the launch forms (per-tile grid or tile queue)
+ * when the rounds run in FP32 or BF16, the S-pass at the chosen V-pass
+ * shape: two column phases and one. Then the launch forms (per-tile grid or tile queue)
  * of the two passes, four combinations. Last, with RPCA_FLAG_SPARSE_S and
  * FP32 rounds, sparse S or rebuilt S, each with both V-pass launch forms. Each stage times its candidates in
  * turn, twice over, and compares the sums. Every timing runs `rounds` timed rounds (plus one

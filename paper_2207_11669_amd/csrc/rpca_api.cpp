@@ -845,10 +845,12 @@ rpca_status rpca_autotune(rpca_ctx* c, int32_t rounds, rpca_launch_shape* out) {
     }
   if (result == RPCA_OK && !cand.empty())
     best = cand[std::min_element(tot.begin(), tot.end()) - tot.begin()];
-  // Stage 2, the FP32 S-pass at the chosen V-pass shape: two column phases
-  // and one, timed in turn twice each (the gap is a few percent of a round;
-  // BF16 rounds run their own S-pass).
-  if (result == RPCA_OK && c->prec == RPCA_PREC_FP32 && c->p.RP <= kFoldMaxRP) {
+  // Stage 2, the S-pass at the chosen V-pass shape: in FP32 rounds two
+  // column phases and one; in BF16 rounds the register form (two phases)
+  // and the LDS-staged form (one). Timed in turn twice each (the gap is a
+  // few percent of a round; three-product rounds have one form).
+  if (result == RPCA_OK && (c->prec == RPCA_PREC_FP32 || c->prec == RPCA_PREC_BF16) &&
+      c->p.RP <= kFoldMaxRP) {
     const std::vector<rpca_launch_shape> ks = {
         {best.vsplit, best.vcols, 2, best.vqueue, best.squeue, best.sparse},
         {best.vsplit, best.vcols, 1, best.vqueue, best.squeue, best.sparse}};

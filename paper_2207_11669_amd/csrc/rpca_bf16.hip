@@ -959,24 +959,26 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
 // entry are those of the register form.
 // ---------------------------------------------------------------------------
 constexpr int kSpStages = 3;
-template <int RT, int NK>
+template <int RT, int NK, bool X3>
 constexpr int spass_h3_units() {
-  return 4 * NK + 2 * RT;
+  return (2 * NK + RT) * (X3 ? 2 : 1);
 }
-template <int RT, int NK>
+template <int RT, int NK, bool X3>
 constexpr int spass_h3_stage_bytes() {
-  return (spass_h3_units<RT, NK>() + 3) / 4 * 4 * 1024;
+  return (spass_h3_units<RT, NK, X3>() + 3) / 4 * 4 * 1024;
 }
 
-template <int RT, int NK, int HUB>
+template <int RT, int NK, int HUB, bool X3>
 __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* __restrict__ U, int b,
                                               int yi) {
   constexpr int RP = 16 * RT;
   constexpr int kRT = 2;  // 16-row tiles per wave
   static_assert(4 * 16 * kRT == kSRows, "four waves cover the work-group's rows");
-  constexpr int kUnits = spass_h3_units<RT, NK>();
+  constexpr int kX = X3 ? 2 : 1;  // hi, and lo in three-product rounds
+  constexpr int kVA = 2 * NK * kX;  // 1 KiB units of V's hP halves, then of V's hB
+  constexpr int kUnits = spass_h3_units<RT, NK, X3>();
   constexpr int kPerWave = (kUnits + 3) / 4;
-  constexpr int kStage = spass_h3_stage_bytes<RT, NK>();
+  constexpr int kStage = spass_h3_stage_bytes<RT, NK, X3>();
   static_assert(kStage == 4 * kPerWave * 1024, "one padded unit per wave and copy");
   constexpr int kD = kSpStages - 1;  // chunks ahead (M ring depth)
   const ClientDev cl = p.clients_lpt[yi];
@@ -988,7 +990,8 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
   const int MP = p.MP;
 
   const int64_t uhl = hb_elems(MP, p.RK, p.RP) / 8, vhl = hb_elems(p.NVP, p.RK, p.RP) / 8;
-  bf8 ub[kRT][NK], ubl[kRT][NK];  // MFMA 1 B operand (hi, lo): U[row][rank 32 kb + 8 (l/16) + e]
+  // MFMA 1 B operand (hi, lo): U[row][rank 32 kb + 8 (l/16) + e]
+  bf8 ub[kRT][NK], ubl[X3 ? kRT : 1][NK];
   {
     const GLOBAL bf8* UhA = reinterpret_cast<const GLOBAL bf8*>(gptr(u_hb(U, p)));
 #pragma unroll
@@ -997,7 +1000,7 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
       for (int kb = 0; kb < NK; ++kb) {
         const int64_t o = ((int64_t)((arow0 >> 4) + rt) * NK + kb) * 64 + lane;
         ub[rt][kb] = UhA[o];
-        ubl[rt][kb] = UhA[uhl + o];
+        if constexpr (X3) ubl[rt][kb] = UhA[uhl + o];
       }
     // Negated once: MFMA 1 then accumulates M - U V^T onto M.
 #pragma unroll
@@ -1005,7 +1008,8 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
 #pragma unroll
       for (int kb = 0; kb < NK; ++kb) {
         ub[rt][kb] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4, ub[rt][kb]) ^ 0x80008000u);
-        ubl[rt][kb] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4, ubl[rt][kb]) ^ 0x80008000u);
+        if constexpr (X3)
+          ubl[rt][kb] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4, ubl[rt][kb]) ^ 0x80008000u);
       }
   }
   f4 accp[kRT][RT];
@@ -1018,7 +1022,7 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
   // and then P share one LDS block.
   constexpr int kFS = 16 * ((RP / 16) | 1);
   __shared__ float fal[RP * kFS];
-  constexpr int kPBytes = kSRows * (RP + 1) * 4;
+  constexpr int kPBytes = kSRows * (RP + 1) * 4;  // P after the sweep
   constexpr int kSBytes = kSpStages * kStage;
   __shared__ float4 spool[(kPBytes > kSBytes ? kPBytes : kSBytes) / 16];
   float(*ptile)[RP + 1] = reinterpret_cast<float(*)[RP + 1]>(spool);
@@ -1035,17 +1039,24 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
   const GLOBAL bf8* Vh = reinterpret_cast<const GLOBAL bf8*>(gptr(v_hb(p.V, p)));
   const GLOBAL bf8* VhP = Vh + (int64_t)p.NVP * p.RK / 8;
   const GLOBAL bf8* VhB = Vh + 2 * (int64_t)p.NVP * p.RK / 8;
-  // The caller's FP32 block, one buffer resource per chunk (base at its
-  // first column), fixed per-lane offsets; columns past n_i are out of range
-  // and rows past m get an offset beyond any range, so both read 0.
-  uint32_t vm[kRT][8];
+  // M: (X3) the caller's FP32 block, one buffer resource per chunk (base at
+  // its first column), fixed per-lane offsets; columns past n_i are out of
+  // range and rows past m get an offset beyond any range, so both read 0.
+  // Otherwise the S-pass BF16 copy of M, one 16-byte load per lane and row
+  // tile (zero past m and n_i).
+  uint32_t vm[X3 ? kRT : 1][8];
+  if constexpr (X3) {
 #pragma unroll
-  for (int rt = 0; rt < kRT; ++rt) {
-    const int row = arow0 + 16 * rt + li;
+    for (int rt = 0; rt < kRT; ++rt) {
+      const int row = arow0 + 16 * rt + li;
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      vm[rt][e] = row < p.m ? ((uint32_t)((8 * lg + e) * cl.ldm) + (uint32_t)row) * 4u : kOffNone;
+      for (int e = 0; e < 8; ++e)
+        vm[rt][e] = row < p.m ? ((uint32_t)((8 * lg + e) * cl.ldm) + (uint32_t)row) * 4u : kOffNone;
+    }
   }
+  const int nvc32 = (cl.n + kVPad - 1) / kVPad * (kVPad / 32);
+  const GLOBAL u4* Ms = reinterpret_cast<const GLOBAL u4*>(gptr(p.Mbs)) +
+                        (int64_t)cl.vrow0 * MP / 8 + (int64_t)(arow0 >> 4) * nvc32 * 64 + lane;
   const int nk = (cl.n + 31) >> 5;  // chunks (the same for every wave)
 
   // Units this wave copies (u = wv, wv + 4, ...; past the last: the last
@@ -1060,14 +1071,14 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
     if (u < 2 * NK) {
       src[i] = VhP + u * 64 + lane;
       cstr[i] = 2 * NK * 64;
-    } else if (u < 4 * NK) {
+    } else if (u < kVA) {
       src[i] = VhP + vhl + (u - 2 * NK) * 64 + lane;
       cstr[i] = 2 * NK * 64;
-    } else if (u < 4 * NK + RT) {
-      src[i] = VhB + (u - 4 * NK) * 64 + lane;
+    } else if (u < kVA + RT) {
+      src[i] = VhB + (u - kVA) * 64 + lane;
       cstr[i] = RT * 64;
     } else {
-      src[i] = VhB + vhl + (u - 4 * NK - RT) * 64 + lane;
+      src[i] = VhB + vhl + (u - kVA - RT) * 64 + lane;
       cstr[i] = RT * 64;
     }
   }
@@ -1083,17 +1094,23 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
                                        (lds_void*)(st + (wv + 4 * i) * 1024), 16, 0, 0);
   };
   struct MChunk {
-    float mf[kRT][8];  // M[row arow0 + 16 rt + l%16][col 32 cc + 8 (l/16) + e]
+    float mf[X3 ? kRT : 1][8];  // M[row arow0 + 16 rt + l%16][col 32 cc + 8 (l/16) + e]
+    u4 m[X3 ? 1 : kRT];         // the same entries in BF16
   };
   MChunk ring[kD];
   auto load_m = [&](MChunk& c, int k) {
     const int cc = min(k, nk - 1);
-    const rsrc_t rM =
-        uniform_rsrc(cl.M + (int64_t)32 * cc * cl.ldm, chunk_bytes_from(cl.n, 32 * cc, cl.ldm));
+    if constexpr (X3) {
+      const rsrc_t rM =
+          uniform_rsrc(cl.M + (int64_t)32 * cc * cl.ldm, chunk_bytes_from(cl.n, 32 * cc, cl.ldm));
 #pragma unroll
-    for (int rt = 0; rt < kRT; ++rt)
+      for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) c.mf[rt][e] = bload(rM, vm[rt][e], 0);
+        for (int e = 0; e < 8; ++e) c.mf[rt][e] = bload(rM, vm[rt][e], 0);
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < kRT; ++rt) c.m[rt] = Ms[((int64_t)rt * nvc32 + cc) * 64];
+    }
   };
   auto chunk = [&](const MChunk& c, int k) {
     const uint32_t sa = stage_lds + (uint32_t)((k % kSpStages) * kStage);
@@ -1101,23 +1118,34 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
     // tile, starting from the lane's entries of M.
     f4 o[kRT][2];
     {
-      u4 a[4 * NK];
-      lds_read_1k<4 * NK>(a, sa);
+      u4 a[kVA];
+      lds_read_1k<kVA>(a, sa);
 #pragma unroll
       for (int rt = 0; rt < kRT; ++rt) {
-        o[rt][0] = f4{c.mf[rt][0], c.mf[rt][1], c.mf[rt][2], c.mf[rt][3]};
-        o[rt][1] = f4{c.mf[rt][4], c.mf[rt][5], c.mf[rt][6], c.mf[rt][7]};
+        float x[8];
+        if constexpr (X3) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) x[e] = c.mf[rt][e];
+        } else {
+          unpack8(c.m[rt], x);
+        }
+        o[rt][0] = f4{x[0], x[1], x[2], x[3]};
+        o[rt][1] = f4{x[4], x[5], x[6], x[7]};
 #pragma unroll
         for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
-          for (int t = 0; t < 2; ++t)
-            o[rt][t] = mfma3(__builtin_bit_cast(bf8, a[t * NK + kb]),
-                             __builtin_bit_cast(bf8, a[2 * NK + t * NK + kb]), ub[rt][kb],
-                             ubl[rt][kb], o[rt][t]);
+          for (int t = 0; t < 2; ++t) {
+            const bf8 ah = __builtin_bit_cast(bf8, a[t * NK + kb]);
+            if constexpr (X3)
+              o[rt][t] = mfma3(ah, __builtin_bit_cast(bf8, a[2 * NK + t * NK + kb]), ub[rt][kb],
+                               ubl[rt][kb], o[rt][t]);
+            else
+              o[rt][t] = mfma_bf16(ah, ub[rt][kb], o[rt][t]);
+          }
       }
     }
-    u4 vb[2 * RT];
-    lds_read_1k<2 * RT>(vb, sa + 4 * NK * 1024);
+    u4 vb[RT * kX];
+    lds_read_1k<RT * kX>(vb, sa + kVA * 1024);
     // Residual, soft-threshold and statistics per row tile, then MFMA 2.
     float l2 = 0.f, l1 = 0.f, hb = 0.f;
 #pragma unroll
@@ -1135,12 +1163,19 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
         if constexpr (HUB == 2) if (hub) hb += huber1(R, lt);
         nnz += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(Sv != 0.f));
       }
-      bf8 lh, ll;
-      split8(lamv, lh, ll);
+      if constexpr (X3) {
+        bf8 lh, ll;
+        split8(lamv, lh, ll);
 #pragma unroll
-      for (int ct = 0; ct < RT; ++ct)
-        accp[rt][ct] = mfma3(lh, ll, __builtin_bit_cast(bf8, vb[ct]),
-                             __builtin_bit_cast(bf8, vb[RT + ct]), accp[rt][ct]);
+        for (int ct = 0; ct < RT; ++ct)
+          accp[rt][ct] = mfma3(lh, ll, __builtin_bit_cast(bf8, vb[ct]),
+                               __builtin_bit_cast(bf8, vb[RT + ct]), accp[rt][ct]);
+      } else {
+        const bf8 lh = pack8(lamv);
+#pragma unroll
+        for (int ct = 0; ct < RT; ++ct)
+          accp[rt][ct] = mfma_bf16(lh, __builtin_bit_cast(bf8, vb[ct]), accp[rt][ct]);
+      }
     }
     sl2 += (double)l2;
     sl1 += (double)l1;
@@ -1150,7 +1185,7 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
   // Groups of loads: chunk g's copies, then its M loads, in chunk order; at
   // chunk k the kD - 1 newer groups may stay in flight. Every wave runs the
   // same count of iterations and barriers.
-  constexpr int kInFlight = (kD - 1) * (kPerWave + 8 * kRT);
+  constexpr int kInFlight = (kD - 1) * (kPerWave + (X3 ? 8 : 1) * kRT);
 #pragma unroll
   for (int g = 0; g < kD; ++g) {
     copy_v(g);
@@ -1193,19 +1228,24 @@ __device__ __forceinline__ void spass_h3_tile(const DevParams& p, const float* _
 // form's loop needs more registers and keeps the default bound.
 // The per-tile form comes in two instantiations, with and without the Huber
 // sum, picked at launch; the queue form decides per round.
-template <int RT, int NK, bool X3, int HUB>
+// ST: the V operands staged in LDS (spass_h3_tile; always in three-product
+// rounds, picked by one S-pass phase in one-product rounds), else the
+// one-product register form (spass_h_tile).
+template <int RT, int NK, bool X3, int HUB, bool ST>
 __global__ __launch_bounds__(256, 2) void k_spass_h_tile(DevParams p, const float* __restrict__ U) {
-  if constexpr (X3)
-    spass_h3_tile<RT, NK, HUB>(p, U, (int)blockIdx.x, (int)blockIdx.y);
+  static_assert(ST || !X3, "three-product rounds run the staged form");
+  if constexpr (ST)
+    spass_h3_tile<RT, NK, HUB, X3>(p, U, (int)blockIdx.x, (int)blockIdx.y);
   else
     spass_h_tile<RT, NK, HUB>(p, U, (int)blockIdx.x, (int)blockIdx.y);
 }
-template <int RT, int NK, bool X3>
+template <int RT, int NK, bool X3, bool ST>
 __global__ __launch_bounds__(256) void k_spass_h_queue(DevParams p, const float* __restrict__ U) {
+  static_assert(ST || !X3, "three-product rounds run the staged form");
   const int ntiles = p.nrb * p.E;
   for (int t = queue_next(p.queue + 2, ntiles); t < ntiles; t = queue_next(p.queue + 2, ntiles)) {
-    if constexpr (X3)
-      spass_h3_tile<RT, NK, 2>(p, U, t % p.nrb, t / p.nrb);
+    if constexpr (ST)
+      spass_h3_tile<RT, NK, 2, X3>(p, U, t % p.nrb, t / p.nrb);
     else
       spass_h_tile<RT, NK, 2>(p, U, t % p.nrb, t / p.nrb);
   }
@@ -1280,11 +1320,14 @@ static hipError_t launch_spass_h_t(const DevParams& p, const float* U, int x3, h
     }
   };
   if (x3)
-    go(k_spass_h_queue<RT, NK, true>, k_spass_h_tile<RT, NK, true, 0>,
-       k_spass_h_tile<RT, NK, true, 1>);
+    go(k_spass_h_queue<RT, NK, true, true>, k_spass_h_tile<RT, NK, true, 0, true>,
+       k_spass_h_tile<RT, NK, true, 1, true>);
+  else if (p.sphases == 1)
+    go(k_spass_h_queue<RT, NK, false, true>, k_spass_h_tile<RT, NK, false, 0, true>,
+       k_spass_h_tile<RT, NK, false, 1, true>);
   else
-    go(k_spass_h_queue<RT, NK, false>, k_spass_h_tile<RT, NK, false, 0>,
-       k_spass_h_tile<RT, NK, false, 1>);
+    go(k_spass_h_queue<RT, NK, false, false>, k_spass_h_tile<RT, NK, false, 0, false>,
+       k_spass_h_tile<RT, NK, false, 1, false>);
   return hipGetLastError();
 }
 

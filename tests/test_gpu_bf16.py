@@ -110,13 +110,15 @@ def test_narrow_client_closed_step(r, widths):
 
 
 @pytest.mark.parametrize("r", [20, 40, 64])
-def test_bf16_vpass_forms_follow_oracle(r):
-    """One-product BF16 rounds with either V-pass form -- the U operands in
-    each wave's registers (column groups 4) or staged in LDS with four
-    64-column tiles per work-group (column groups 1) -- on ragged m (301),
-    clients of 1-3 tiles and a last work-group with two tiles stay within 5u
-    of the FP64 trajectory after 20 rounds; the staged form gives the same
-    bits from one work-group per tile group and from the tile queue."""
+def test_bf16_pass_forms_follow_oracle(r):
+    """One-product BF16 rounds with either form of each pass -- the factor
+    operands in each wave's registers (V-pass column groups 4, S-pass phases
+    2) or staged in LDS (column groups 1: four 64-column tiles per V-pass
+    work-group; phases 1: four waves of 32 rows over the same S-pass chunks)
+    -- on ragged m (301), clients of 1-3 tiles and a last V-pass work-group
+    with two tiles stay within 5u of the FP64 trajectory after 20 rounds; the
+    staged forms give the same bits from one work-group per tile and from
+    the tile queues."""
     import torch
     inst = planted_instance(301, [70, 190, 130, 96], 4, 0.05, values="uniform", lo=5.0, hi=10.0,
                             seed=29)
@@ -124,17 +126,19 @@ def test_bf16_vpass_forms_follow_oracle(r):
     lam, T = 0.1, 20
     res = run_oracle(inst, U0, r, 0.1, lam, T)
     out = {}
-    for cg, vq in ((4, 0), (1, 0), (1, 1)):
+    for cg, ph, q in ((4, 2, 0), (1, 2, 0), (4, 1, 0), (1, 1, 0), (1, 1, 1)):
         s, Lg, Sg, _ = run_gpu(inst, U0, r, 0.1, lam, T, bf16=True,
-                               shape=dict(column_groups=cg, vpass_queue=vq))
-        out[(cg, vq)] = (Lg, Sg)
+                               shape=dict(column_groups=cg, spass_phases=ph, vpass_queue=q,
+                                          spass_queue=q))
+        out[(cg, ph, q)] = (Lg, Sg)
         eL, eS = rel(Lg, res.L_full()), rel(Sg, res.S_full())
-        announce(f"bf16 r={r} column_groups={cg} vpass_queue={vq}: relL={eL:.3e} relS={eS:.3e}")
+        announce(f"bf16 r={r} column_groups={cg} spass_phases={ph} queues={q}: "
+                 f"relL={eL:.3e} relS={eS:.3e}")
         assert eL <= BF16_TOL and eS <= BF16_TOL
         del s
         torch.cuda.synchronize()
-    assert np.array_equal(out[(1, 0)][0], out[(1, 1)][0])
-    assert np.array_equal(out[(1, 0)][1], out[(1, 1)][1])
+    assert np.array_equal(out[(1, 1, 0)][0], out[(1, 1, 1)][0])
+    assert np.array_equal(out[(1, 1, 0)][1], out[(1, 1, 1)][1])
 
 
 def test_bf16_deterministic_and_switchable():
