@@ -230,20 +230,23 @@ __device__ __forceinline__ void vpass_h_tile(const DevParams& p, const float* __
 }
 
 // ---------------------------------------------------------------------------
-// Three-product BF16 V-pass with the U operands staged in LDS. Loads of one
-// wave complete in issue order, so in vpass_h_tile every wait for a U
+// BF16 V-pass with the U operands staged in LDS (three-product rounds
+// always; one-product rounds with one column group). Loads of one wave
+// complete in issue order, so in the register form every wait for a U
 // operand (an L2 hit, fetched one chunk ahead) also waits for the M chunks
 // issued before it, and M effectively streams one chunk ahead whatever the
-// ring depth. Here the four waves take one 16-column group each and share
-// the rows, so a chunk's U operands (previous U hP hi/lo, U hB hi/lo: 14-16
-// KiB) are needed once per work-group: the waves copy them from L2 straight
-// into LDS (global_load_lds, 1 KiB per instruction, no registers), kLdsStages
-// chunks ahead, and issue each chunk's M loads beside its copies. A chunk's
-// group of loads is waited for as a whole, kLdsStages - 2 groups behind the
-// newest, so both M and U stream kLdsStages - 1 chunks ahead. One barrier
-// per chunk makes the other waves' copies visible and frees the stage read
-// in the chunk before. Per wave and chunk: 2 FP32 loads of M, 14-16 / 4
-// copies and 4NK + 2RT 16-byte LDS reads.
+// ring depth. Here a work-group takes vtiles 64-column tiles over the same
+// rows, each of its four waves one 16-column group of every tile, so a
+// chunk's U operands (previous U hP, U hB, hi and in three-product rounds lo:
+// 8-16 KiB) are needed once per work-group: the waves copy them from L2
+// straight into LDS (global_load_lds, 1 KiB per instruction, no registers),
+// kLdsStages chunks ahead, and issue each chunk's M loads beside its copies.
+// A chunk's group of loads is waited for as a whole, kLdsStages - 2 groups
+// behind the newest, so both M and U stream kLdsStages - 1 chunks ahead. One
+// barrier per chunk makes the other waves' copies visible and frees the
+// stage read in the chunk before. Per wave and chunk: one or two 16-byte
+// loads of M per tile, a quarter of the copies, and one 16-byte LDS read per
+// U operand.
 // ---------------------------------------------------------------------------
 constexpr int kLdsStages = 4;
 // 1 KiB units of a chunk's U operands: the previous U's hP halves (S rebuild
@@ -949,14 +952,17 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
 }
 
 // ---------------------------------------------------------------------------
-// Three-product BF16 S-pass with the V operands staged in LDS (the V-pass's
-// scheme with the roles of U and V exchanged). The four waves take 32 rows
-// each (two 16-row tiles) and every 32-column chunk of the client, so a
-// chunk's V operands (hP hi/lo halves for MFMA 1, hB hi/lo for MFMA 2) are
-// the same for all of them: the waves copy them from L2 into LDS, kSpStages
-// - 1 chunks ahead, beside the chunk's FP32 M loads (16 per wave), and each
-// wave reads them from LDS at its use. The arithmetic and its order per
-// entry are those of the register form.
+// BF16 S-pass with the V operands staged in LDS (three-product rounds
+// always; one-product rounds with one S-pass phase), the V-pass's scheme with
+// the roles of U and V exchanged. The four waves take 32 rows each (two
+// 16-row tiles) and every 32-column chunk of the client, so a chunk's V
+// operands (hP halves for MFMA 1, hB for MFMA 2; hi, and lo in three-product
+// rounds) are the same for all of them: the waves copy them from L2 into
+// LDS, kSpStages - 1 chunks ahead, beside the chunk's M loads (16 FP32 loads
+// or 2 BF16 loads per wave), and each wave reads them from LDS at its use.
+// Per entry of S and P the arithmetic and its order are those of the
+// one-product register form (spass_h_tile); only the statistics' partial
+// sums group the entries differently.
 // ---------------------------------------------------------------------------
 constexpr int kSpStages = 3;
 template <int RT, int NK, bool X3>
