@@ -960,9 +960,9 @@ __device__ __forceinline__ void spass_h_tile(const DevParams& p, const float* __
 // rounds) are the same for all of them: the waves copy them from L2 into
 // LDS, kSpStages - 1 chunks ahead, beside the chunk's M loads (16 FP32 loads
 // or 2 BF16 loads per wave), and each wave reads them from LDS at its use.
-// Per entry of S and P the arithmetic and its order are those of the
-// one-product register form (spass_h_tile); only the statistics' partial
-// sums group the entries differently.
+// S per entry is computed as in the register form; P sums a row's chunks in
+// chunk order in one accumulator (the one-product register form adds two
+// column phases' partial sums at the end).
 // ---------------------------------------------------------------------------
 constexpr int kSpStages = 3;
 template <int RT, int NK, bool X3>
