@@ -291,7 +291,7 @@ typedef struct rpca_launch_shape {
    * (waves split the rows of a 64-column tile); 1, a work-group takes four
    * 64-column tiles over the same rows and copies a chunk's U operands into
    * LDS once for its four waves. Three-product rounds always run the LDS
-   * form (two tiles per work-group). */
+   * form: 4, two tiles per work-group; 1, one. */
   int32_t vcols;
   /* FP32 S-pass column phases: 2 (work-groups of 8 waves, two per 32-row
    * strip taking alternate 16-column chunks, their partial P summed at the

@@ -235,7 +235,7 @@ __device__ __forceinline__ void vpass_h_tile(const DevParams& p, const float* __
 // complete in issue order, so in the register form every wait for a U
 // operand (an L2 hit, fetched one chunk ahead) also waits for the M chunks
 // issued before it, and M effectively streams one chunk ahead whatever the
-// ring depth. Here a work-group takes vtiles 64-column tiles over the same
+// ring depth. Here a work-group takes KT 64-column tiles over the same
 // rows, each of its four waves one 16-column group of every tile, so a
 // chunk's U operands (previous U hP, U hB, hi and in three-product rounds lo:
 // 8-16 KiB) are needed once per work-group: the waves copy them from L2
@@ -364,23 +364,20 @@ __device__ __forceinline__ rsrc_t uniform_rsrc(const void* base, uint32_t bytes)
                    __builtin_amdgcn_readfirstlane(bytes));
 }
 
-// Tiles per work-group of the staged V-pass: vtiles(X3) consecutive
-// 64-column tiles over the same rows (clients may differ; the U operands are
-// the same), so that each wave streams that many column groups of M against
-// one copy of a chunk's U operands: two in three-product rounds (FP32 M, hi
-// and lo operands), four in one-product rounds (the BF16 copy of M).
-__host__ __device__ constexpr int vtiles(bool x3) { return x3 ? 2 : 4; }
-__host__ __device__ inline int vpass_h3_groups(int ng64, bool x3) {
-  return (ng64 + vtiles(x3) - 1) / vtiles(x3);
-}
+// Tiles per work-group of the staged V-pass: KT consecutive 64-column tiles
+// over the same rows (clients may differ; the U operands are the same), so
+// that each wave streams KT column groups of M against one copy of a chunk's
+// U operands. The launch picks KT from the column-group knob: one-product
+// rounds 4; three-product rounds (FP32 M, hi and lo operands) 2, or 1 with
+// one column group.
+__host__ __device__ inline int vpass_h3_groups(int ng64, int kt) { return (ng64 + kt - 1) / kt; }
 
-template <int RT, int NK, int MODE, bool X3>
+template <int RT, int NK, int MODE, bool X3, int KT>
 __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* __restrict__ Ubase,
                                               const float* __restrict__ Uold,
                                               const float* __restrict__ Vold, int tile,
                                               float (*red)[16 * RT], void* stage_mem) {
   constexpr int RP = 16 * RT;
-  constexpr int KT = vtiles(X3);
   constexpr int kX = X3 ? 2 : 1;          // hi, and lo in three-product rounds
   constexpr bool kA = MODE == kSRecompute;
   constexpr int kUA = kA ? 2 * NK * kX : 0;  // 1 KiB units of the previous U (hP)
@@ -389,7 +386,7 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
   constexpr int kStage = vpass_h3_stage_bytes<RT, NK, MODE, X3>();
   static_assert(kStage == 4 * kPerWave * 1024, "one padded unit per wave and copy");
   constexpr int kD = kLdsStages - 1;     // chunks ahead (M ring depth)
-  const int ngr = vpass_h3_groups(p.ng64, X3);
+  const int ngr = vpass_h3_groups(p.ng64, KT);
   const int gx0 = (tile % ngr) * KT, gy = tile / ngr;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -630,26 +627,28 @@ __device__ __forceinline__ void vpass_h3_tile(const DevParams& p, const float* _
 }
 
 // Work-group roles and tiles as in k_vpass (Q: persistent launch over the
-// tile queue). ST: the U operands staged in LDS (vpass_h3_tile; always in
-// three-product rounds, picked by the column-group knob = 1 in one-product
-// rounds), else the one-product register form (vpass_h_tile).
-template <int RT, int NK, int MODE, bool X3, bool Q, bool ST>
+// tile queue). KT > 0: the U operands staged in LDS, KT tiles per
+// work-group (vpass_h3_tile; always in three-product rounds, picked by the
+// column-group knob = 1 in one-product rounds); KT = 0, the one-product
+// register form (vpass_h_tile).
+template <int RT, int NK, int MODE, bool X3, bool Q, int KT>
 __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __restrict__ Ubase,
                                                  const float* __restrict__ Uold,
                                                  const float* __restrict__ Vold,
                                                  double* __restrict__ fin_Ginv, int fin) {
+  constexpr bool ST = KT > 0;
   static_assert(ST || !X3, "three-product rounds run the staged form");
   // One LDS pool for both roles (sized for this rank, not the largest).
   constexpr int RP = 16 * RT;
   constexpr int kPool = vpass_pool_doubles(RP);
   constexpr int kStages = ST ? kLdsStages * vpass_h3_stage_bytes<RT, NK, MODE, X3>() / 8 : 0;
-  constexpr int kRed = ST ? vtiles(X3) * kVStreamCols * RP / 2 : 0;  // every tile's W
+  constexpr int kRed = KT * kVStreamCols * RP / 2;  // every tile's W
   constexpr int kStaged = kStages > kRed ? kStages : kRed;
   __shared__ double pool[kPool > kStaged ? kPool : kStaged];
   float(*red)[RP] = reinterpret_cast<float(*)[RP]>(pool);
   auto run = [&](int t) {
     if constexpr (ST)
-      vpass_h3_tile<RT, NK, MODE, X3>(p, Ubase, Uold, Vold, t, red, pool);
+      vpass_h3_tile<RT, NK, MODE, X3, KT>(p, Ubase, Uold, Vold, t, red, pool);
     else
       vpass_h_tile<RT, NK, MODE>(p, Ubase, Uold, Vold, t, red);
   };
@@ -661,7 +660,7 @@ __global__ __launch_bounds__(256) void k_vpass_h(DevParams p, const float* __res
     run((int)blockIdx.x - (fin ? 2 : 0));
   } else {
     if (fin && blockIdx.x < 2) finalize_role(p, fin_Ginv, (int)blockIdx.x, pool);
-    const int ntiles = (ST ? vpass_h3_groups(p.ng64, X3) : p.ng64) * p.vsplit;
+    const int ntiles = (ST ? vpass_h3_groups(p.ng64, KT) : p.ng64) * p.vsplit;
     for (int t = queue_next(p.queue, ntiles); t < ntiles; t = queue_next(p.queue, ntiles)) run(t);
   }
 }
@@ -1269,20 +1268,21 @@ static hipError_t launch_vpass_h_t(const DevParams& p, int mode, const float* U,
                                    const float* Vold, double* fin_Ginv, int x3, hipStream_t st) {
   constexpr int NK = (RT + 1) / 2;
   const int fin = fin_Ginv ? 1 : 0;
-  // The staged form: one work-group per vtiles tiles over the same rows.
-  const bool staged = x3 || p.vcols == 1;
-  const int ntiles = (staged ? vpass_h3_groups(p.ng64, x3 != 0) : p.ng64) * p.vsplit;
+  // Tiles per work-group of the staged form (0: the register form).
+  const int kt = x3 ? (p.vcols == 1 ? 1 : 2) : (p.vcols == 1 ? 4 : 0);
+  const int ntiles = (kt ? vpass_h3_groups(p.ng64, kt) : p.ng64) * p.vsplit;
   // The first round (S = 0) always runs one work-group per tile (group).
-  auto go = [&](auto m, auto x, auto sg) {
+  auto go = [&](auto m, auto x, auto ktc) {
     constexpr int kMode = decltype(m)::value;
-    constexpr bool kX3 = decltype(x)::value, kST = decltype(sg)::value;
+    constexpr bool kX3 = decltype(x)::value;
+    constexpr int kKT = decltype(ktc)::value;
     if (kMode == kSRecompute && p.vqueue) {
-      auto kernel = k_vpass_h<RT, NK, kSRecompute, kX3, true, kST>;
+      auto kernel = k_vpass_h<RT, NK, kSRecompute, kX3, true, kKT>;
       const int groups = pass_groups(kernel, 256, ntiles, 1);
       hipLaunchKernelGGL(kernel, dim3((unsigned)(groups + 2 * fin)), dim3(256), 0, st, p, U, Uold,
                          Vold, fin_Ginv, fin);
     } else {
-      hipLaunchKernelGGL((k_vpass_h<RT, NK, kMode, kX3, false, kST>),
+      hipLaunchKernelGGL((k_vpass_h<RT, NK, kMode, kX3, false, kKT>),
                          dim3((unsigned)(ntiles + 2 * fin)), dim3(256), 0, st, p, U, Uold, Vold,
                          fin_Ginv, fin);
     }
@@ -1291,12 +1291,17 @@ static hipError_t launch_vpass_h_t(const DevParams& p, int mode, const float* U,
   using R = std::integral_constant<int, kSRecompute>;
   using F = std::false_type;
   using T = std::true_type;
-  if (x3)
-    mode == kSRecompute ? go(R{}, T{}, T{}) : go(Z{}, T{}, T{});
-  else if (staged)
-    mode == kSRecompute ? go(R{}, F{}, T{}) : go(Z{}, F{}, T{});
-  else
-    mode == kSRecompute ? go(R{}, F{}, F{}) : go(Z{}, F{}, F{});
+  using K0 = std::integral_constant<int, 0>;
+  using K1 = std::integral_constant<int, 1>;
+  using K2 = std::integral_constant<int, 2>;
+  using K4 = std::integral_constant<int, 4>;
+  const bool rec = mode == kSRecompute;
+  switch (kt) {
+    case 1: rec ? go(R{}, T{}, K1{}) : go(Z{}, T{}, K1{}); break;
+    case 2: rec ? go(R{}, T{}, K2{}) : go(Z{}, T{}, K2{}); break;
+    case 4: rec ? go(R{}, F{}, K4{}) : go(Z{}, F{}, K4{}); break;
+    default: rec ? go(R{}, F{}, K0{}) : go(Z{}, F{}, K0{}); break;
+  }
   return hipGetLastError();
 }
 

@@ -215,6 +215,34 @@ def test_bf16x3_ragged_and_rank_tiles(r, widths):
     assert hL <= X3_TOL and hS <= X3_TOL
 
 
+@pytest.mark.parametrize("r", [20, 64])
+def test_bf16x3_vpass_tiles_follow_oracle(r):
+    """Three-product rounds with one and with two 64-column tiles per V-pass
+    work-group (column groups 1 and 4) on ragged m, clients of 1-3 tiles and
+    an odd tile count stay within the three-product bar of the FP64
+    trajectory (rho = 1 keeps the closed-form step well conditioned for
+    clients of 70 columns at r = 64); each gives the same bits from the
+    per-group grid and from the tile queue."""
+    import torch
+    from gpu_helpers import run_gpu
+    inst = planted_instance(301, [70, 190, 130, 96], 4, 0.05, values="uniform", hi=10.0, seed=31)
+    U0 = init_for(inst, r, 7)
+    res = run_oracle(inst, U0, r, 1.0, 0.1, 10)
+    out = {}
+    for cg in (1, 4):
+        for q in (0, 1):
+            s, Lg, Sg, _ = run_gpu(inst, U0, r, 1.0, 0.1, 10, bf16x3=True,
+                                   shape=dict(column_groups=cg, vpass_queue=q))
+            out[(cg, q)] = (Lg, Sg)
+            eL, eS = rel(Lg, res.L_full()), rel(Sg, res.S_full())
+            announce(f"bf16x3 r={r} column_groups={cg} vpass_queue={q}: relL={eL:.3e} relS={eS:.3e}")
+            assert eL <= X3_TOL and eS <= X3_TOL
+            del s
+            torch.cuda.synchronize()
+        assert np.array_equal(out[(cg, 0)][0], out[(cg, 1)][0])
+        assert np.array_equal(out[(cg, 0)][1], out[(cg, 1)][1])
+
+
 def test_precision_rules_and_switching():
     """A context made with RPCA_FLAG_BF16X3 alone starts in three-product
     rounds, refuses plain BF16 (it holds no BF16 copy of M), and switches to
