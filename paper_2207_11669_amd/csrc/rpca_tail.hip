@@ -138,12 +138,17 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
   // (Beyond four rank tiles the block's rows go in sweeps of four, which
   // keeps its sums within the registers; same sums.) The threads on the
   // diagonal (ta = tb) add their diagonal entries in rank order for the trace.
+  // Only the lower triangle is written: the partial is symmetric bit for bit
+  // (each entry multiplies the same two factors both ways round), and
+  // k_client_factor reads entry (a, b) with a >= b.
   double* gv = p.gv_part + (int64_t)blockIdx.x * RP * RP;
   constexpr int kXB = RT <= 4 ? RT : 4;
   const bool on_diag = (tid >> 4) == (tid & 15);
+  const bool lower = (tid >> 4) >= (tid & 15);
   double dtr = 0.0;
 #pragma unroll
   for (int x0 = 0; x0 < RT; x0 += kXB) {
+    if (!lower) break;
     const int a0 = RT * (tid >> 4) + x0, b0 = RT * (tid & 15);
     double sg[kXB][RT];
 #pragma unroll
@@ -166,7 +171,8 @@ __global__ __launch_bounds__(256) void k_vfinal(DevParams p, const double* __res
     for (int x = 0; x < kXB; ++x)
       if (x0 + x < RT) {
 #pragma unroll
-        for (int y = 0; y < RT; ++y) gv[(a0 + x) * RP + b0 + y] = sg[x][y];
+        for (int y = 0; y < RT; ++y)
+          if (a0 + x >= b0 + y) gv[(a0 + x) * RP + b0 + y] = sg[x][y];
         if (on_diag) dtr += sg[x][x0 + x];
       }
   }
@@ -201,10 +207,12 @@ __global__ __launch_bounds__(cf_threads(RT)) void k_client_factor(DevParams p) {
   const ClientDev cl = p.clients[blockIdx.x];
   const int tid = threadIdx.x;
   if (cl.g1 - cl.g0 <= 16) {
-    // One block of groups: one batch of loads per entry.
+    // One block of groups: one batch of loads per entry; the partials hold
+    // the lower triangle, so (a, b) reads (max, min).
     for (int e = tid; e < r * r; e += blockDim.x) {
       const int a = e / r, b = e % r;
-      const double s = sum_strided(p.gv_part + (int64_t)cl.g0 * RR + a * RP + b, cl.g1 - cl.g0, RR);
+      const int hi = a > b ? a : b, lo = a > b ? b : a;
+      const double s = sum_strided(p.gv_part + (int64_t)cl.g0 * RR + hi * RP + lo, cl.g1 - cl.g0, RR);
       A[e] = s + (a == b ? cl.c : 0.0);
     }
   } else {
